@@ -1,0 +1,609 @@
+/*
+ * dem_oracle.cpp -- plain, slow FP64 CPU reference of one soft-sphere DEM
+ * contact step.  TEST INFRASTRUCTURE ONLY: the GPU library never links,
+ * loads or calls this code, and this code shares nothing with it.
+ *
+ * What it computes (Queteschiner et al., "Adaptive Coarse-Graining for
+ * Large-Scale DEM Simulations", CFD2017; cited by section and equation):
+ *
+ *   Newton's equations for translation and rotation          Sec. 2.1, Eq. (1)-(2)
+ *   total force = gravity + sum of binary contact forces     Sec. 2.1, text after Eq. (2)
+ *   normal spring-dashpot  f_n = k_n d_n - g_n d(d_n)/dt     Sec. 2.1, Eq. (3)
+ *   tangential spring-dashpot with overlap history            Sec. 2.1, Eq. (4)
+ *   truncation of the tangential overlap, f_t <= mu f_n       Sec. 2.1, Eq. (5)
+ *   damped Hertz coefficients k_n, g_n, k_t, g_t, beta(e)     Sec. 2.1, Eq. (6)
+ *   coarse-grain rule: E, nu, rho, e, mu fixed, r scaled      Sec. 2.2 (no explicit
+ *       alpha appears: k ~ alpha and g ~ alpha^2 follow from the scaled radius)
+ *
+ * Readings where the paper is silent (each is also listed in the design
+ * notes of the repository):
+ *   - effective properties are the Hertz-Mindlin harmonic combinations
+ *       1/R = 1/r_i + 1/r_j, 1/m = 1/m_i + 1/m_j,
+ *       1/E* = (1-nu_i^2)/E_i + (1-nu_j^2)/E_j,
+ *       1/G* = 2(2-nu_i)(1+nu_i)/E_i + 2(2-nu_j)(1+nu_j)/E_j;
+ *     the flat wall has the contacting particle's material and R, m of the particle;
+ *     a pair of two types uses e = (e_i+e_j)/2 and mu = (mu_i+mu_j)/2;
+ *   - n points from j to i; F_n = (k_n delta - g_n v_n) n, not clamped at zero;
+ *     contact while d^2 < (r_i+r_j)^2 (strict);
+ *   - the tangential history xi starts at zero, is reset when the pair is out of
+ *     contact, is projected onto the current tangent plane (no rescaling) and then
+ *     incremented by v_t dt; F_t* = -k_t xi - g_t v_t;
+ *   - Coulomb: if |F_t*|^2 > (mu |f_n|)^2 the total tangential force is scaled to
+ *     mu |f_n| and xi is solved back so that -k_t xi - g_t v_t equals it;
+ *   - the contact lever arm is the radius r (v_t and the torque);
+ *   - solid spheres, m = (4/3) pi rho r^3, I = (2/5) m r^2;
+ *   - velocity Verlet (kick 1/2, drift, force, kick 1/2), forces evaluated with
+ *     half-step velocities; a force evaluation may leave the history untouched
+ *     (used once at the start of a run);
+ *   - periodic images by minimum image; positions wrapped into [lo, hi).
+ *
+ * Every particle's force is accumulated gravity first, then its pair terms in
+ * ascending partner id, then the wall.  Pairs are visited once (lower id
+ * first); the lower id's side holds the history.
+ *
+ * The scalar type is a template parameter so the same code also runs with
+ * forward-mode dual numbers (derivatives with respect to per-type E, e, mu).
+ *
+ * Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared dem_oracle.cpp -o liboracle.so
+ */
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+namespace {
+
+constexpr int NDIR = 6;  // tangent directions: E_0, E_1, e_0, e_1, mu_0, mu_1
+
+/* ---------------------------------------------------------------- scalars */
+
+struct Dual {
+    double v;
+    double d[NDIR];
+    Dual() : v(0.0) { for (double &q : d) q = 0.0; }
+    Dual(double x) : v(x) { for (double &q : d) q = 0.0; }  // NOLINT(implicit)
+};
+inline double val(double x) { return x; }
+inline double val(const Dual &x) { return x.v; }
+inline Dual operator+(const Dual &a, const Dual &b) { Dual c(a.v + b.v); for (int k = 0; k < NDIR; ++k) c.d[k] = a.d[k] + b.d[k]; return c; }
+inline Dual operator-(const Dual &a, const Dual &b) { Dual c(a.v - b.v); for (int k = 0; k < NDIR; ++k) c.d[k] = a.d[k] - b.d[k]; return c; }
+inline Dual operator-(const Dual &a) { Dual c(-a.v); for (int k = 0; k < NDIR; ++k) c.d[k] = -a.d[k]; return c; }
+inline Dual operator*(const Dual &a, const Dual &b) { Dual c(a.v * b.v); for (int k = 0; k < NDIR; ++k) c.d[k] = a.d[k] * b.v + a.v * b.d[k]; return c; }
+inline Dual operator/(const Dual &a, const Dual &b) {
+    Dual c(a.v / b.v);
+    for (int k = 0; k < NDIR; ++k) c.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+    return c;
+}
+inline Dual operator+(const Dual &a, double b) { return a + Dual(b); }
+inline Dual operator+(double a, const Dual &b) { return Dual(a) + b; }
+inline Dual operator-(const Dual &a, double b) { return a - Dual(b); }
+inline Dual operator-(double a, const Dual &b) { return Dual(a) - b; }
+inline Dual operator*(const Dual &a, double b) { Dual c(a.v * b); for (int k = 0; k < NDIR; ++k) c.d[k] = a.d[k] * b; return c; }
+inline Dual operator*(double a, const Dual &b) { return b * a; }
+inline Dual operator/(const Dual &a, double b) { return a / Dual(b); }
+inline Dual operator/(double a, const Dual &b) { return Dual(a) / b; }
+inline Dual &operator+=(Dual &a, const Dual &b) { a = a + b; return a; }
+inline Dual &operator-=(Dual &a, const Dual &b) { a = a - b; return a; }
+inline Dual sqrt(const Dual &a) {
+    double s = std::sqrt(a.v);
+    Dual c(s);
+    for (int k = 0; k < NDIR; ++k) c.d[k] = a.d[k] / (2.0 * s);
+    return c;
+}
+inline Dual log(const Dual &a) { Dual c(std::log(a.v)); for (int k = 0; k < NDIR; ++k) c.d[k] = a.d[k] / a.v; return c; }
+inline Dual fabs(const Dual &a) { return a.v < 0.0 ? -a : a; }
+using std::sqrt;
+using std::log;
+using std::fabs;
+
+template <class S> struct V3 { S x, y, z; };
+
+/* ------------------------------------------------------------ parameters */
+
+struct Config {
+    int ntypes;
+    double E[4], nu[4], rho[4], e[4], mu[4];
+    double dt, g[3], lo[3], hi[3];
+    int periodic[3], wall_z0;
+};
+
+template <class S> struct PairCoef { S Es, Gs, beta, mu; };
+
+template <class S> struct Particle {
+    int id, type;
+    double r, m, I, inv_m, inv_I;
+    V3<S> x, v, w, f, t;
+};
+
+template <class S> struct PairRecord { int lo, hi; double fn_mag, f_mag, ft_mag, fncap; };
+
+template <class S> struct Sim {
+    Config cfg;
+    S E[4], e[4], mu[4];  // material parameters as scalars (seeded for tangents)
+    std::vector<Particle<S>> p;
+    std::unordered_map<int, int> idx;                        // id -> index
+    std::map<std::pair<int, int>, V3<S>> hist;               // (id_lo, id_hi) -> xi seen from id_lo
+    std::map<int, V3<S>> whist;                              // id -> wall xi
+    std::vector<PairRecord<S>> records;                      // last force evaluation
+    double rmax = 0.0;
+};
+
+/* Effective pair coefficients, Eq. (6) with the harmonic combinations above. */
+template <class S> PairCoef<S> coef(const Sim<S> &s, int ti, int tj) {
+    const Config &c = s.cfg;
+    S inv_E = (1.0 - c.nu[ti] * c.nu[ti]) / s.E[ti] + (1.0 - c.nu[tj] * c.nu[tj]) / s.E[tj];
+    S inv_G = 2.0 * (2.0 - c.nu[ti]) * (1.0 + c.nu[ti]) / s.E[ti] + 2.0 * (2.0 - c.nu[tj]) * (1.0 + c.nu[tj]) / s.E[tj];
+    S e = (s.e[ti] + s.e[tj]) / 2.0;
+    S mu = (s.mu[ti] + s.mu[tj]) / 2.0;
+    S le = log(e);
+    PairCoef<S> k;
+    k.Es = 1.0 / inv_E;
+    k.Gs = 1.0 / inv_G;
+    k.beta = le / sqrt(le * le + M_PI * M_PI);
+    k.mu = mu;
+    return k;
+}
+
+inline double min_image(double d, double L, int periodic) {
+    if (!periodic) return d;
+    double hL = 0.5 * L;
+    if (d > hL) d -= L;
+    else if (d < -hL) d += L;
+    return d;
+}
+template <class S> S min_image_s(const S &d, double L, int periodic) {
+    if (!periodic) return d;
+    double hL = 0.5 * L;
+    if (val(d) > hL) return d - L;
+    if (val(d) < -hL) return d + L;
+    return d;
+}
+
+/*
+ * One contact between particle a ("self") and b.  Computes the force on a
+ * (f_out) and the tangential force ft (for the torques), updating xi in place
+ * when update is set.  Wall: b == nullptr, normal +z, R = r_a, m* = m_a.
+ * Returns false when not in contact.
+ */
+template <class S>
+bool contact(const Sim<S> &s, const Particle<S> &a, const Particle<S> *b, V3<S> &xi, bool update, V3<S> &f_out,
+             V3<S> &ft_out, V3<S> &n_out, PairRecord<S> *rec) {
+    const Config &c = s.cfg;
+    V3<S> d;
+    S dist;
+    double rs;
+    if (b) {
+        d.x = min_image_s(a.x.x - b->x.x, c.hi[0] - c.lo[0], c.periodic[0]);
+        d.y = min_image_s(a.x.y - b->x.y, c.hi[1] - c.lo[1], c.periodic[1]);
+        d.z = min_image_s(a.x.z - b->x.z, c.hi[2] - c.lo[2], c.periodic[2]);
+        S d2 = d.x * d.x + d.y * d.y + d.z * d.z;
+        rs = a.r + b->r;
+        if (!(val(d2) < rs * rs)) return false;
+        dist = sqrt(d2);
+    } else {
+        rs = a.r;
+        if (!(val(a.x.z) < a.r)) return false;
+        d.x = 0.0; d.y = 0.0; d.z = a.x.z;
+        dist = a.x.z;
+    }
+    S delta = rs - dist;
+    if (!(val(delta) > 0.0)) return false;
+    V3<S> n;
+    if (b) {
+        n.x = d.x / dist; n.y = d.y / dist; n.z = d.z / dist;
+    } else {
+        n.x = 0.0; n.y = 0.0; n.z = 1.0;
+    }
+    /* effective radius and mass */
+    double R = b ? a.r * b->r / (a.r + b->r) : a.r;
+    double M = b ? a.m * b->m / (a.m + b->m) : a.m;
+    PairCoef<S> k = coef(s, a.type, b ? b->type : a.type);
+    /* Eq. (6) */
+    S sq = sqrt(R * delta);
+    S kn = 4.0 / 3.0 * k.Es * sq;
+    S kt = 8.0 * k.Gs * sq;
+    S gn = -k.beta * sqrt(5.0 * M * kn);
+    S gt = -k.beta * sqrt(10.0 / 3.0 * M * kt);
+    /* relative velocity of the contact point (lever arm r) */
+    V3<S> vr = b ? V3<S>{a.v.x - b->v.x, a.v.y - b->v.y, a.v.z - b->v.z} : a.v;
+    S vn = vr.x * n.x + vr.y * n.y + vr.z * n.z;
+    V3<S> ws;
+    if (b) {
+        ws = {a.r * a.w.x + b->r * b->w.x, a.r * a.w.y + b->r * b->w.y, a.r * a.w.z + b->r * b->w.z};
+    } else {
+        ws = {a.r * a.w.x, a.r * a.w.y, a.r * a.w.z};
+    }
+    V3<S> wxn = {ws.y * n.z - ws.z * n.y, ws.z * n.x - ws.x * n.z, ws.x * n.y - ws.y * n.x};
+    V3<S> vt = {vr.x - vn * n.x - wxn.x, vr.y - vn * n.y - wxn.y, vr.z - vn * n.z - wxn.z};
+    /* Eq. (3) */
+    S fn = kn * delta - gn * vn;
+    /* Eq. (4): history projected onto the tangent plane, then advanced */
+    S xn = xi.x * n.x + xi.y * n.y + xi.z * n.z;
+    V3<S> z = {xi.x - xn * n.x, xi.y - xn * n.y, xi.z - xn * n.z};
+    if (update) {
+        z.x = z.x + vt.x * c.dt;
+        z.y = z.y + vt.y * c.dt;
+        z.z = z.z + vt.z * c.dt;
+    }
+    V3<S> ft = {-kt * z.x - gt * vt.x, -kt * z.y - gt * vt.y, -kt * z.z - gt * vt.z};
+    /* Eq. (5): Coulomb truncation of the total tangential force */
+    S ft2 = ft.x * ft.x + ft.y * ft.y + ft.z * ft.z;
+    S cap = k.mu * fabs(fn);
+    if (val(ft2) > val(cap * cap)) {
+        S scale = cap / sqrt(ft2);
+        ft = {scale * ft.x, scale * ft.y, scale * ft.z};
+        z = {-(ft.x + gt * vt.x) / kt, -(ft.y + gt * vt.y) / kt, -(ft.z + gt * vt.z) / kt};
+    }
+    if (update) xi = z;
+    f_out = {fn * n.x + ft.x, fn * n.y + ft.y, fn * n.z + ft.z};
+    ft_out = ft;
+    n_out = n;
+    if (rec) {
+        double fx = val(f_out.x), fy = val(f_out.y), fz = val(f_out.z);
+        rec->fn_mag = std::fabs(val(fn));
+        rec->f_mag = std::sqrt(fx * fx + fy * fy + fz * fz);
+        rec->ft_mag = std::sqrt(val(ft.x) * val(ft.x) + val(ft.y) * val(ft.y) + val(ft.z) * val(ft.z));
+        rec->fncap = val(cap);
+    }
+    return true;
+}
+
+/* Candidate pairs (i < j by id) within d^2 < (r_i + r_j + extra)^2, visiting a
+ * uniform grid of cells no smaller than the largest cut-off. */
+template <class S> void grid_pairs(const Sim<S> &s, double extra, std::vector<std::pair<int, int>> &out) {
+    const Config &c = s.cfg;
+    double h = 2.0 * s.rmax + extra;
+    int nc[3];
+    for (int d = 0; d < 3; ++d) {
+        double L = c.hi[d] - c.lo[d];
+        nc[d] = std::max(1, (int)std::floor(L / h));
+    }
+    auto cell_of = [&](const Particle<S> &q, int ci[3]) {
+        double xs[3] = {val(q.x.x), val(q.x.y), val(q.x.z)};
+        for (int d = 0; d < 3; ++d) {
+            double L = c.hi[d] - c.lo[d];
+            int k = (int)std::floor((xs[d] - c.lo[d]) / L * nc[d]);
+            if (c.periodic[d]) k = ((k % nc[d]) + nc[d]) % nc[d];
+            else k = std::min(std::max(k, 0), nc[d] - 1);
+            ci[d] = k;
+        }
+    };
+    std::unordered_map<long long, std::vector<int>> cells;
+    std::vector<std::array<int, 3>> pc(s.p.size());
+    for (size_t i = 0; i < s.p.size(); ++i) {
+        int ci[3];
+        cell_of(s.p[i], ci);
+        pc[i] = {ci[0], ci[1], ci[2]};
+        cells[((long long)ci[2] * nc[1] + ci[1]) * nc[0] + ci[0]].push_back((int)i);
+    }
+    std::vector<int> order(s.p.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return s.p[a].id < s.p[b].id; });
+    std::vector<int> cand;
+    for (int i : order) {
+        cand.clear();
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int cc[3] = {pc[i][0] + dx, pc[i][1] + dy, pc[i][2] + dz};
+                    bool skip = false;
+                    for (int d = 0; d < 3; ++d) {
+                        if (c.periodic[d]) cc[d] = ((cc[d] % nc[d]) + nc[d]) % nc[d];
+                        else if (cc[d] < 0 || cc[d] >= nc[d]) skip = true;
+                    }
+                    if (skip) continue;
+                    auto it = cells.find(((long long)cc[2] * nc[1] + cc[1]) * nc[0] + cc[0]);
+                    if (it == cells.end()) continue;
+                    for (int j : it->second)
+                        if (s.p[j].id > s.p[i].id) cand.push_back(j);
+                }
+        std::sort(cand.begin(), cand.end(), [&](int a, int b) { return s.p[a].id < s.p[b].id; });
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        for (int j : cand) {
+            double dx = min_image(val(s.p[i].x.x) - val(s.p[j].x.x), c.hi[0] - c.lo[0], c.periodic[0]);
+            double dy = min_image(val(s.p[i].x.y) - val(s.p[j].x.y), c.hi[1] - c.lo[1], c.periodic[1]);
+            double dz = min_image(val(s.p[i].x.z) - val(s.p[j].x.z), c.hi[2] - c.lo[2], c.periodic[2]);
+            double d2 = dx * dx + dy * dy + dz * dz;
+            double cut = s.p[i].r + s.p[j].r + extra;
+            if (d2 < cut * cut) out.push_back({i, j});
+        }
+    }
+}
+
+/* The same set by checking every pair: O(N^2), the definition itself. */
+template <class S> void brute_pairs(const Sim<S> &s, double extra, std::vector<std::pair<int, int>> &out) {
+    const Config &c = s.cfg;
+    for (size_t i = 0; i < s.p.size(); ++i)
+        for (size_t j = 0; j < s.p.size(); ++j) {
+            if (s.p[j].id <= s.p[i].id) continue;
+            double dx = min_image(val(s.p[i].x.x) - val(s.p[j].x.x), c.hi[0] - c.lo[0], c.periodic[0]);
+            double dy = min_image(val(s.p[i].x.y) - val(s.p[j].x.y), c.hi[1] - c.lo[1], c.periodic[1]);
+            double dz = min_image(val(s.p[i].x.z) - val(s.p[j].x.z), c.hi[2] - c.lo[2], c.periodic[2]);
+            double d2 = dx * dx + dy * dy + dz * dz;
+            double cut = s.p[i].r + s.p[j].r + extra;
+            if (d2 < cut * cut) out.push_back({(int)i, (int)j});
+        }
+    std::sort(out.begin(), out.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+        if (s.p[a.first].id != s.p[b.first].id) return s.p[a.first].id < s.p[b.first].id;
+        return s.p[a.second].id < s.p[b.second].id;
+    });
+}
+
+/* Total force and torque on every particle (Sec. 2.1). */
+template <class S> void forces(Sim<S> &s, bool update) {
+    const Config &c = s.cfg;
+    for (auto &q : s.p) {
+        q.f = {q.m * c.g[0], q.m * c.g[1], q.m * c.g[2]};
+        q.t = {0.0, 0.0, 0.0};
+    }
+    s.records.clear();
+    std::vector<std::pair<int, int>> cand;
+    grid_pairs(s, 0.0, cand);  // ordered by the lower id, then ascending partner id
+    std::map<std::pair<int, int>, V3<S>> next;
+    for (auto &pr : cand) {
+        Particle<S> &a = s.p[pr.first];
+        Particle<S> &b = s.p[pr.second];
+        std::pair<int, int> key{a.id, b.id};
+        auto it = s.hist.find(key);
+        V3<S> xi = it == s.hist.end() ? V3<S>{0.0, 0.0, 0.0} : it->second;
+        V3<S> f, ft, n;
+        PairRecord<S> rec{a.id, b.id, 0, 0, 0, 0};
+        if (!contact(s, a, &b, xi, update, f, ft, n, &rec)) continue;
+        s.records.push_back(rec);
+        if (update) next[key] = xi;
+        a.f = {a.f.x + f.x, a.f.y + f.y, a.f.z + f.z};
+        b.f = {b.f.x - f.x, b.f.y - f.y, b.f.z - f.z};
+        V3<S> nxf = {n.y * ft.z - n.z * ft.y, n.z * ft.x - n.x * ft.z, n.x * ft.y - n.y * ft.x};
+        a.t = {a.t.x - a.r * nxf.x, a.t.y - a.r * nxf.y, a.t.z - a.r * nxf.z};
+        b.t = {b.t.x - b.r * nxf.x, b.t.y - b.r * nxf.y, b.t.z - b.r * nxf.z};
+    }
+    if (update) s.hist.swap(next);
+    if (c.wall_z0) {
+        std::map<int, V3<S>> wnext;
+        for (auto &a : s.p) {
+            auto it = s.whist.find(a.id);
+            V3<S> xi = it == s.whist.end() ? V3<S>{0.0, 0.0, 0.0} : it->second;
+            V3<S> f, ft, n;
+            if (!contact(s, a, (const Particle<S> *)nullptr, xi, update, f, ft, n, (PairRecord<S> *)nullptr)) continue;
+            if (update) wnext[a.id] = xi;
+            a.f = {a.f.x + f.x, a.f.y + f.y, a.f.z + f.z};
+            V3<S> nxf = {n.y * ft.z - n.z * ft.y, n.z * ft.x - n.x * ft.z, n.x * ft.y - n.y * ft.x};
+            a.t = {a.t.x - a.r * nxf.x, a.t.y - a.r * nxf.y, a.t.z - a.r * nxf.z};
+        }
+        if (update) s.whist.swap(wnext);
+    }
+}
+
+template <class S> S wrap(S x, double lo, double hi, int periodic) {
+    if (!periodic) return x;
+    double L = hi - lo;
+    if (val(x) >= hi) x = x - L;
+    if (val(x) < lo) x = x + L;
+    if (val(x) >= hi) x = S(lo);
+    return x;
+}
+
+/* Velocity Verlet for Eq. (1)-(2): kick 1/2, drift, forces, kick 1/2. */
+template <class S> void kick(Sim<S> &s) {
+    double h = 0.5 * s.cfg.dt;
+    for (auto &q : s.p) {
+        q.v = {q.v.x + h * (q.f.x * q.inv_m), q.v.y + h * (q.f.y * q.inv_m), q.v.z + h * (q.f.z * q.inv_m)};
+        q.w = {q.w.x + h * (q.t.x * q.inv_I), q.w.y + h * (q.t.y * q.inv_I), q.w.z + h * (q.t.z * q.inv_I)};
+    }
+}
+template <class S> void drift(Sim<S> &s) {
+    const Config &c = s.cfg;
+    for (auto &q : s.p) {
+        q.x = {q.x.x + c.dt * q.v.x, q.x.y + c.dt * q.v.y, q.x.z + c.dt * q.v.z};
+        q.x.x = wrap(q.x.x, c.lo[0], c.hi[0], c.periodic[0]);
+        q.x.y = wrap(q.x.y, c.lo[1], c.hi[1], c.periodic[1]);
+        q.x.z = wrap(q.x.z, c.lo[2], c.hi[2], c.periodic[2]);
+    }
+}
+template <class S> void step(Sim<S> &s, int n) {
+    for (int k = 0; k < n; ++k) {
+        kick(s);
+        drift(s);
+        forces(s, true);
+        kick(s);
+    }
+}
+
+template <class S>
+Sim<S> *make(const Config *cfg, int n, const double *x, const double *v, const double *w, const double *r,
+             const int *type, const int *id) {
+    Sim<S> *s = new Sim<S>();
+    s->cfg = *cfg;
+    for (int t = 0; t < cfg->ntypes; ++t) { s->E[t] = cfg->E[t]; s->e[t] = cfg->e[t]; s->mu[t] = cfg->mu[t]; }
+    s->p.resize(n);
+    for (int i = 0; i < n; ++i) {
+        Particle<S> &q = s->p[i];
+        q.id = id[i];
+        q.type = type[i];
+        q.r = r[i];
+        q.m = 4.0 / 3.0 * M_PI * cfg->rho[q.type] * q.r * q.r * q.r;
+        q.I = 0.4 * q.m * q.r * q.r;
+        q.inv_m = 1.0 / q.m;
+        q.inv_I = 1.0 / q.I;
+        q.x = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+        q.v = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
+        q.w = {w[3 * i], w[3 * i + 1], w[3 * i + 2]};
+        q.f = {0.0, 0.0, 0.0};
+        q.t = {0.0, 0.0, 0.0};
+        s->idx[q.id] = i;
+        s->rmax = std::max(s->rmax, q.r);
+    }
+    return s;
+}
+
+using SimD = Sim<double>;
+using SimT = Sim<Dual>;
+
+}  // namespace
+
+extern "C" {
+
+typedef Config orc_config;
+
+void *orc_new(const orc_config *cfg, int n, const double *x, const double *v, const double *w, const double *r,
+              const int *type, const int *id) {
+    return make<double>(cfg, n, x, v, w, r, type, id);
+}
+
+void orc_free(void *h) { delete (SimD *)h; }
+
+int orc_n(void *h) { return (int)((SimD *)h)->p.size(); }
+
+/* State in input order, (n, 3) row-major. Any pointer may be null. */
+void orc_get(void *h, double *x, double *v, double *w, double *f, double *t) {
+    SimD *s = (SimD *)h;
+    for (size_t i = 0; i < s->p.size(); ++i) {
+        const Particle<double> &q = s->p[i];
+        if (x) { x[3 * i] = q.x.x; x[3 * i + 1] = q.x.y; x[3 * i + 2] = q.x.z; }
+        if (v) { v[3 * i] = q.v.x; v[3 * i + 1] = q.v.y; v[3 * i + 2] = q.v.z; }
+        if (w) { w[3 * i] = q.w.x; w[3 * i + 1] = q.w.y; w[3 * i + 2] = q.w.z; }
+        if (f) { f[3 * i] = q.f.x; f[3 * i + 1] = q.f.y; f[3 * i + 2] = q.f.z; }
+        if (t) { t[3 * i] = q.t.x; t[3 * i + 1] = q.t.y; t[3 * i + 2] = q.t.z; }
+    }
+}
+
+void orc_set(void *h, const double *x, const double *v, const double *w, const double *f, const double *t) {
+    SimD *s = (SimD *)h;
+    for (size_t i = 0; i < s->p.size(); ++i) {
+        Particle<double> &q = s->p[i];
+        if (x) q.x = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+        if (v) q.v = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
+        if (w) q.w = {w[3 * i], w[3 * i + 1], w[3 * i + 2]};
+        if (f) q.f = {f[3 * i], f[3 * i + 1], f[3 * i + 2]};
+        if (t) q.t = {t[3 * i], t[3 * i + 1], t[3 * i + 2]};
+    }
+}
+
+/* Masses and inertias as the oracle computes them, input order. */
+void orc_get_mass(void *h, double *m, double *I) {
+    SimD *s = (SimD *)h;
+    for (size_t i = 0; i < s->p.size(); ++i) { m[i] = s->p[i].m; I[i] = s->p[i].I; }
+}
+
+void orc_forces(void *h, int update_history) { forces(*(SimD *)h, update_history != 0); }
+
+void orc_step(void *h, int nsteps) { step(*(SimD *)h, nsteps); }
+
+void orc_kick(void *h) { kick(*(SimD *)h); }
+void orc_drift(void *h) { drift(*(SimD *)h); }
+
+/* Pair history, (id_lo, id_hi) ascending; xi is seen from id_lo. */
+long orc_history(void *h, int *lo, int *hi, double *xi, long cap) {
+    SimD *s = (SimD *)h;
+    long k = 0;
+    for (auto &kv : s->hist) {
+        if (k < cap) {
+            lo[k] = kv.first.first; hi[k] = kv.first.second;
+            xi[3 * k] = kv.second.x; xi[3 * k + 1] = kv.second.y; xi[3 * k + 2] = kv.second.z;
+        }
+        ++k;
+    }
+    return k;
+}
+
+void orc_set_history(void *h, long count, const int *lo, const int *hi, const double *xi) {
+    SimD *s = (SimD *)h;
+    s->hist.clear();
+    for (long k = 0; k < count; ++k) {
+        int a = lo[k], b = hi[k];
+        V3<double> z = {xi[3 * k], xi[3 * k + 1], xi[3 * k + 2]};
+        if (a > b) { std::swap(a, b); z = {-z.x, -z.y, -z.z}; }
+        s->hist[{a, b}] = z;
+    }
+}
+
+long orc_wall_history(void *h, int *id, double *xi, long cap) {
+    SimD *s = (SimD *)h;
+    long k = 0;
+    for (auto &kv : s->whist) {
+        if (k < cap) {
+            id[k] = kv.first;
+            xi[3 * k] = kv.second.x; xi[3 * k + 1] = kv.second.y; xi[3 * k + 2] = kv.second.z;
+        }
+        ++k;
+    }
+    return k;
+}
+
+void orc_set_wall_history(void *h, long count, const int *id, const double *xi) {
+    SimD *s = (SimD *)h;
+    s->whist.clear();
+    for (long k = 0; k < count; ++k) s->whist[id[k]] = {xi[3 * k], xi[3 * k + 1], xi[3 * k + 2]};
+}
+
+/* Unordered pairs (id_lo < id_hi), ascending, with d^2 < (r_i + r_j + extra)^2.
+ * brute != 0 checks all N^2 pairs; otherwise a uniform cell grid is used. */
+long orc_pairs(void *h, double extra, int brute, int *lo, int *hi, long cap) {
+    SimD *s = (SimD *)h;
+    std::vector<std::pair<int, int>> out;
+    if (brute) brute_pairs(*s, extra, out);
+    else grid_pairs(*s, extra, out);
+    long k = 0;
+    for (auto &pr : out) {
+        if (k < cap) { lo[k] = s->p[pr.first].id; hi[k] = s->p[pr.second].id; }
+        ++k;
+    }
+    return k;
+}
+
+/* Per-pair records of the last force evaluation: ids and magnitudes
+ * |f_n| (scalar normal force), |F_ij|, |F_t| and the Coulomb cap mu |f_n|. */
+long orc_records(void *h, int *lo, int *hi, double *fn, double *fmag, double *ftmag, double *cap, long capn) {
+    SimD *s = (SimD *)h;
+    long k = 0;
+    for (auto &r : s->records) {
+        if (k < capn) {
+            lo[k] = r.lo; hi[k] = r.hi; fn[k] = r.fn_mag; fmag[k] = r.f_mag; ftmag[k] = r.ft_mag; cap[k] = r.fncap;
+        }
+        ++k;
+    }
+    return k;
+}
+
+/* ------------------------------------------------ forward-mode tangents */
+
+/* Same simulation with dual numbers: derivative directions are
+ * (E_0, E_1, e_0, e_1, mu_0, mu_1); types beyond 2 carry no tangent. */
+void *orc_tan_new(const orc_config *cfg, int n, const double *x, const double *v, const double *w, const double *r,
+                  const int *type, const int *id) {
+    SimT *s = make<Dual>(cfg, n, x, v, w, r, type, id);
+    for (int t = 0; t < cfg->ntypes && t < 2; ++t) {
+        s->E[t].d[0 + t] = 1.0;
+        s->e[t].d[2 + t] = 1.0;
+        s->mu[t].d[4 + t] = 1.0;
+    }
+    return s;
+}
+void orc_tan_free(void *h) { delete (SimT *)h; }
+void orc_tan_forces(void *h, int update_history) { forces(*(SimT *)h, update_history != 0); }
+void orc_tan_step(void *h, int nsteps) { step(*(SimT *)h, nsteps); }
+
+/* Values and tangents of x and v: val[n*3], tan[n*3*6] (direction fastest). */
+void orc_tan_get(void *h, double *xv, double *xt, double *vv, double *vt) {
+    SimT *s = (SimT *)h;
+    for (size_t i = 0; i < s->p.size(); ++i) {
+        const Particle<Dual> &q = s->p[i];
+        const Dual *X[3] = {&q.x.x, &q.x.y, &q.x.z};
+        const Dual *Vv[3] = {&q.v.x, &q.v.y, &q.v.z};
+        for (int c = 0; c < 3; ++c) {
+            if (xv) xv[3 * i + c] = X[c]->v;
+            if (vv) vv[3 * i + c] = Vv[c]->v;
+            for (int k = 0; k < NDIR; ++k) {
+                if (xt) xt[(3 * i + c) * NDIR + k] = X[c]->d[k];
+                if (vt) vt[(3 * i + c) * NDIR + k] = Vv[c]->d[k];
+            }
+        }
+    }
+}
+
+}  // extern "C"

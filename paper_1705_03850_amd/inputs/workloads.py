@@ -1,0 +1,312 @@
+"""Seeded synthetic workloads for the DEM contact pipeline.
+
+This module only *places* particles and draws their sizes, velocities and
+types; it contains no contact mechanics and no time stepping.  Both the CPU
+oracle and the GPU library are fed from here, so neither side generates its
+own inputs.
+
+Workloads (all lengths in metres, SI units throughout):
+
+* ``plain_fcc``      -- 2,000 monodisperse spheres (r = 1 mm) on a jittered FCC
+                        subset in a 20 x 20 mm footprint periodic in x and y,
+                        wall at z = 0, vertical gravity (the small plain case).
+* ``settled_bed``    -- N polydisperse spheres, r ~ U[0.8, 1.2] mm, deposited
+                        by the geometric drop-and-roll construction on an
+                        80 x 80 mm periodic footprint, then compacted
+                        vertically (the at-scale plain case, N = 1e6).
+* ``chute_two_level``-- a coarse (alpha = 4) and a fine (alpha = 1) bed on a
+                        30 degree chute, as one two-system batch.
+* ``batch_systems``  -- 64 independent deposited beds with log-uniform
+                        particle counts and coarse-grain factors in {1,2,4,8}.
+* ``chute_adjoint``  -- 50,000 spheres of two material types on a 30 degree
+                        chute with a sheared initial velocity profile.
+
+The material sets are the ones the workloads are quoted with: E = 5e6 Pa,
+nu = 0.25, rho = 2500 kg/m^3, e = 0.9, mu = 0.5 (and a second type with
+E = 1e7 Pa, e = 0.7, mu = 0.3 for the two-type chute).  The coarse-grain rule
+of the paper (Sec. 2.2) keeps E, nu, rho, e and mu fixed and scales only the
+radius, so a coarse system differs from a fine one only in r.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libdeposit.so")
+
+G0 = 9.81
+
+
+@dataclass
+class Material:
+    E: float
+    nu: float
+    rho: float
+    e: float
+    mu: float
+
+
+MAT_A = Material(E=5e6, nu=0.25, rho=2500.0, e=0.9, mu=0.5)
+MAT_B = Material(E=1e7, nu=0.25, rho=2500.0, e=0.7, mu=0.3)
+
+
+@dataclass
+class System:
+    """One DEM system: particle arrays (row i = one particle) plus its setup."""
+
+    x: np.ndarray          # (n, 3) float64 positions
+    v: np.ndarray          # (n, 3) float64 velocities
+    w: np.ndarray          # (n, 3) float64 angular velocities
+    r: np.ndarray          # (n,)   float64 radii
+    type: np.ndarray       # (n,)   int32 material index
+    id: np.ndarray         # (n,)   int32 particle id (unique within the system)
+    materials: list        # [Material]
+    lo: tuple              # box lower corner
+    hi: tuple              # box upper corner (z: top of the binning grid)
+    periodic: tuple        # (px, py, pz) 0/1
+    wall_z0: int           # flat wall at z = 0
+    g: tuple               # gravity vector
+    dt: float
+    skin: float
+    steps: int
+    name: str = ""
+    alpha: float = 1.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.r.shape[0])
+
+    def copy(self) -> "System":
+        return System(self.x.copy(), self.v.copy(), self.w.copy(), self.r.copy(), self.type.copy(),
+                      self.id.copy(), list(self.materials), tuple(self.lo), tuple(self.hi),
+                      tuple(self.periodic), self.wall_z0, tuple(self.g), self.dt, self.skin, self.steps,
+                      self.name, self.alpha, dict(self.meta))
+
+
+def _deposit_lib():
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(os.path.join(_HERE, "deposit.c")):
+        build_deposit()
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.deposit.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            dp, dp, dp]
+    lib.deposit.restype = ctypes.c_int
+    return lib
+
+
+def build_deposit() -> str:
+    """Compile the deposition helper in place (plain gcc, no GPU code)."""
+    src = os.path.join(_HERE, "deposit.c")
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", src, "-o", tmp, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def deposit(r: np.ndarray, Lx: float, Ly: float, rng: np.random.Generator, zcap: float | None = None):
+    """Drop-and-roll deposition of spheres with radii ``r`` (in that order).
+
+    Returns (n, 3) centres.  Random drop points and tie-break azimuths come from
+    ``rng``; the geometry itself is deterministic.
+    """
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    n = r.shape[0]
+    dx = rng.uniform(0.0, Lx, n)
+    dy = rng.uniform(0.0, Ly, n)
+    az = rng.uniform(0.0, 2.0 * math.pi, n)
+    if zcap is None:
+        zcap = 1.3 * float(np.sum(4.0 / 3.0 * math.pi * r ** 3)) / (0.55 * Lx * Ly) + 4.0 * float(r.max())
+    x = np.empty(n); y = np.empty(n); z = np.empty(n)
+    lib = _deposit_lib()
+    stuck = lib.deposit(n, _ptr(r), _ptr(dx), _ptr(dy), _ptr(az), Lx, Ly, float(zcap), _ptr(x), _ptr(y), _ptr(z))
+    return np.stack([x, y, z], axis=1), int(stuck)
+
+
+def compact(z: np.ndarray, strain_bottom: float) -> np.ndarray:
+    """Vertical compaction z -> z - int_0^z eps(s) ds with eps(s) = eps_b (1 - s/H)^(2/3).
+
+    A heuristic stand-in for the load a settled bed carries: the strain is
+    largest at the floor and vanishes at the free surface (H = max z).
+    """
+    H = float(z.max())
+    if H <= 0.0 or strain_bottom == 0.0:
+        return z.copy()
+    # int_0^z (1 - s/H)^(2/3) ds = (3H/5) (1 - (1 - z/H)^(5/3))
+    u = np.clip(1.0 - z / H, 0.0, 1.0)
+    return z - strain_bottom * 0.6 * H * (1.0 - u ** (5.0 / 3.0))
+
+
+# ----------------------------------------------------------------------------
+# Workload 1: 2,000 spheres, jittered FCC subset
+# ----------------------------------------------------------------------------
+
+def plain_fcc(seed: int = 1, e: float | None = None, mu: float | None = None) -> System:
+    """2,000 spheres, r = 1 mm, in a 20 x 20 mm footprint periodic in x/y.
+
+    2,000 random non-overlapping spheres at packing fraction pi/6 cannot be
+    produced by random sequential insertion (its jamming limit is ~0.38), so
+    the positions are a seeded subset of an FCC lattice: lattice constant
+    a = 20/7 mm (7 x 7 cubic cells span the footprint exactly; nearest
+    neighbours at 2.0203 mm), 21 close-packed-direction planes at
+    z = 1.01 mm + k a/2 (2,058 sites), 2,000 sites chosen at random, each
+    coordinate jittered by U(-5, 5) um.  Velocities N(0, 0.1 m/s) per component
+    with the mean removed; zero spin.
+    """
+    rng = np.random.default_rng(seed)
+    a = 20e-3 / 7.0
+    sites = []
+    for k in range(21):
+        z = 1.01e-3 + k * a / 2.0
+        offs = [(0.0, 0.0), (0.5, 0.5)] if k % 2 == 0 else [(0.5, 0.0), (0.0, 0.5)]
+        for cy in range(7):
+            for cx in range(7):
+                for ox, oy in offs:
+                    sites.append(((cx + ox) * a, (cy + oy) * a, z))
+    sites = np.asarray(sites, dtype=np.float64)
+    pick = rng.choice(sites.shape[0], 2000, replace=False)
+    x = sites[pick] + rng.uniform(-5e-6, 5e-6, (2000, 3))
+    x[:, 0] = np.mod(x[:, 0], 20e-3)
+    x[:, 1] = np.mod(x[:, 1], 20e-3)
+    v = rng.normal(0.0, 0.1, (2000, 3))
+    v -= v.mean(axis=0)
+    mat = Material(MAT_A.E, MAT_A.nu, MAT_A.rho, MAT_A.e if e is None else e, MAT_A.mu if mu is None else mu)
+    return System(x=x, v=v, w=np.zeros((2000, 3)), r=np.full(2000, 1e-3), type=np.zeros(2000, np.int32),
+                  id=np.arange(2000, dtype=np.int32), materials=[mat], lo=(0.0, 0.0, 0.0),
+                  hi=(20e-3, 20e-3, 60e-3), periodic=(1, 1, 0), wall_z0=1, g=(0.0, 0.0, -G0), dt=1e-6,
+                  skin=0.1e-3, steps=1000, name="plain_fcc_2000")
+
+
+# ----------------------------------------------------------------------------
+# Workload 2: settled polydisperse bed
+# ----------------------------------------------------------------------------
+
+def bed(n: int, r: np.ndarray, Lx: float, Ly: float, rng: np.random.Generator, overlap_frac: float = 2.5e-4,
+        strain_bottom: float = 0.02):
+    """Deposit ``n`` spheres, then shrink all gaps slightly and compact vertically.
+
+    Deposition uses radii r (1 - overlap_frac) so that every touching pair of
+    the construction overlaps by overlap_frac (r_i + r_j) at the true radii;
+    the vertical compaction adds the depth-dependent strain.
+    """
+    pos, stuck = deposit(r * (1.0 - overlap_frac), Lx, Ly, rng)
+    pos[:, 2] = compact(pos[:, 2], strain_bottom)
+    return pos, stuck
+
+
+def settled_bed(seed: int = 2, n: int = 1_000_000, footprint: float = 80e-3) -> System:
+    """N spheres, r ~ U[0.8, 1.2] mm, on a periodic square footprint, settled by deposition."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.8e-3, 1.2e-3, n)
+    pos, stuck = bed(n, r, footprint, footprint, rng)
+    order = np.argsort(pos[:, 2], kind="stable")  # ids follow height, like a filled bed
+    pos = pos[order]; r = r[order]
+    # shuffle the storage order so that no code can rely on input sorting
+    perm = rng.permutation(n)
+    pos = pos[perm]; r = r[perm]
+    ids = perm.astype(np.int32)
+    rmax = 1.2e-3
+    top = float(pos[:, 2].max()) + 4.0 * rmax
+    return System(x=pos, v=np.zeros((n, 3)), w=np.zeros((n, 3)), r=r, type=np.zeros(n, np.int32), id=ids,
+                  materials=[MAT_A], lo=(0.0, 0.0, 0.0), hi=(footprint, footprint, top), periodic=(1, 1, 0),
+                  wall_z0=1, g=(0.0, 0.0, -G0), dt=1e-6, skin=0.1 * rmax, steps=10_000,
+                  name=f"settled_bed_{n}", meta={"deposit_stuck": stuck})
+
+
+# ----------------------------------------------------------------------------
+# Chutes and batches
+# ----------------------------------------------------------------------------
+
+def chute_gravity(angle_deg: float = 30.0):
+    a = math.radians(angle_deg)
+    return (G0 * math.sin(a), 0.0, -G0 * math.cos(a))
+
+
+def _system_from_bed(pos, r, types, materials, Lx, Ly, g, dt, skin, steps, name, alpha, v=None, rng=None):
+    n = r.shape[0]
+    rmax = float(r.max())
+    top = float(pos[:, 2].max()) + 4.0 * rmax
+    return System(x=pos, v=np.zeros((n, 3)) if v is None else v, w=np.zeros((n, 3)), r=r, type=types,
+                  id=np.arange(n, dtype=np.int32), materials=materials, lo=(0.0, 0.0, 0.0), hi=(Lx, Ly, top),
+                  periodic=(1, 1, 0), wall_z0=1, g=g, dt=dt, skin=skin, steps=steps, name=name, alpha=alpha)
+
+
+def chute_two_level(seed: int = 3, n_fine: int = 500_000, n_coarse: int = 200_000):
+    """Two systems of one batch: coarse (alpha = 4, r = 4 mm, 1000 x 400 mm) and
+    fine (r = 1 mm, 200 x 100 mm), both on a periodic 30 degree chute.
+
+    The fine particles within 10 mm of the fine block's top face form the
+    coupling shell; their indices are returned in ``meta['shell']`` (the shell
+    receives an external-force array that stays zero until the coupling
+    controllers exist).
+    """
+    rng = np.random.default_rng(seed)
+    g = chute_gravity(30.0)
+    rc = np.full(n_coarse, 4e-3)
+    Lc = (1000e-3 * math.sqrt(n_coarse / 200_000), 400e-3 * math.sqrt(n_coarse / 200_000))
+    pc, _ = bed(n_coarse, rc, Lc[0], Lc[1], rng, strain_bottom=0.01)
+    coarse = _system_from_bed(pc, rc, np.zeros(n_coarse, np.int32), [MAT_A], Lc[0], Lc[1], g, 1e-6,
+                              0.1 * 4e-3, 5000, "chute_coarse", 4.0)
+    rf = np.full(n_fine, 1e-3)
+    Lf = (200e-3 * math.sqrt(n_fine / 500_000), 100e-3 * math.sqrt(n_fine / 500_000))
+    pf, _ = bed(n_fine, rf, Lf[0], Lf[1], rng, strain_bottom=0.01)
+    fine = _system_from_bed(pf, rf, np.zeros(n_fine, np.int32), [MAT_A], Lf[0], Lf[1], g, 1e-6, 0.1e-3, 5000,
+                            "chute_fine", 1.0)
+    fine.meta["shell"] = np.nonzero(pf[:, 2] > pf[:, 2].max() - 10e-3)[0].astype(np.int64)
+    return [coarse, fine]
+
+
+def batch_systems(seed: int = 4, count: int = 64, n_lo: int = 5_000, n_hi: int = 200_000,
+                  dt_scaled: bool = True):
+    """``count`` independent beds: N log-uniform in [n_lo, n_hi], alpha in {1,2,4,8},
+    r = alpha U[1-p, 1+p] mm with p ~ U(0, 0.2), footprint aspect U(1, 4), bed
+    depth about 20 alpha mm; dt = alpha * 1e-6 s when ``dt_scaled``."""
+    rng = np.random.default_rng(seed)
+    systems = []
+    for s in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        alpha = float(rng.choice([1, 2, 4, 8]))
+        p = rng.uniform(0.0, 0.2)
+        r = alpha * 1e-3 * rng.uniform(1.0 - p, 1.0 + p, n)
+        aspect = rng.uniform(1.0, 4.0)
+        depth = 20e-3 * alpha
+        area = float(np.sum(4.0 / 3.0 * math.pi * r ** 3)) / (0.58 * depth)
+        Lx = math.sqrt(area * aspect)
+        Ly = area / Lx
+        rmax = float(r.max())
+        cut = 2.0 * rmax * 1.1
+        Lx = max(Lx, 3.0 * cut); Ly = max(Ly, 3.0 * cut)
+        pos, _ = bed(n, r, Lx, Ly, rng, strain_bottom=0.005)
+        dt = alpha * 1e-6 if dt_scaled else 1e-6
+        systems.append(_system_from_bed(pos, r, np.zeros(n, np.int32), [MAT_A], Lx, Ly, (0.0, 0.0, -G0), dt,
+                                        0.1 * rmax, 2000, f"batch_{s}", alpha))
+    return systems
+
+
+def chute_adjoint(seed: int = 5, n: int = 50_000, Lx: float = 100e-3, Ly: float = 50e-3) -> System:
+    """Two-type chute (50/50 by seeded draw), r ~ U[0.9, 1.1] mm, 30 degrees.
+
+    The initial velocity is a synthetic sheared flow profile
+    v_x(z) = U (1 - (1 - z/H)^(3/2)) with U = 0.2 m/s plus N(0, 0.01 m/s) noise.
+    """
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.9e-3, 1.1e-3, n)
+    pos, _ = bed(n, r, Lx, Ly, rng, strain_bottom=0.005)
+    types = (rng.uniform(size=n) < 0.5).astype(np.int32)
+    H = float(pos[:, 2].max())
+    v = rng.normal(0.0, 0.01, (n, 3))
+    v[:, 0] += 0.2 * (1.0 - np.clip(1.0 - pos[:, 2] / H, 0.0, 1.0) ** 1.5)
+    sysm = _system_from_bed(pos, r, types, [MAT_A, MAT_B], Lx, Ly, chute_gravity(30.0), 1e-6, 0.1 * 1.1e-3,
+                            200, "chute_adjoint", 1.0, v=v)
+    sysm.meta["H0"] = H
+    return sysm

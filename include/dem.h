@@ -1,0 +1,213 @@
+/*
+ * dem.h -- C-ABI of libdem.so, the MI355X (gfx950) DEM contact pipeline.
+ *
+ * One call of dem_step advances soft spheres by velocity Verlet under the
+ * contact law of Queteschiner et al., "Adaptive Coarse-Graining for
+ * Large-Scale DEM Simulations" (CFD2017):
+ *   Newton's equations for translation and rotation ............ Sec. 2.1, Eq. (1)-(2)
+ *   force = gravity + binary contact forces ..................... Sec. 2.1
+ *   damped Hertz normal force .................................... Eq. (3), Eq. (6)
+ *   tangential spring-dashpot with overlap history ............... Eq. (4), Eq. (6)
+ *   Coulomb truncation f_t <= mu f_n ............................. Eq. (5)
+ *   coarse-grain rule (E, nu, rho, e, mu fixed, radius scaled) .... Sec. 2.2
+ *   several coarse-grain levels as one batch of systems ........... Sec. 2.3
+ * The readings where the paper is silent (effective properties, sign
+ * conventions, history rules, the integrator) are the same as the CPU
+ * oracle's and are listed in the repository's design notes.
+ *
+ * Conventions
+ *   - Units are SI.  All floating point is IEEE binary64.
+ *   - Particle arrays are device memory owned by the caller, structure of
+ *     arrays: a vector field V of n particles is V[0..n) = x components,
+ *     V[n..2n) = y, V[2n..3n) = z.
+ *   - A batch of S systems concatenates the systems' particles: system s owns
+ *     the index range [off_s, off_s + n_s) with off_0 = 0 in the order of the
+ *     configurations passed to dem_batch_init.  Every call below acts on all
+ *     systems of the context.
+ *   - Ids must be unique across the whole context (all systems of a batch)
+ *     and non-negative.  dem_bin permutes the caller's particle arrays (within
+ *     each system); compare results by id.
+ *   - The library never allocates device memory.  Its device storage is one
+ *     caller-provided workspace of dem_workspace_size() bytes that must stay
+ *     allocated and untouched until dem_destroy.
+ *   - Calls are enqueued on the stream given to dem_init (a hipStream_t passed
+ *     as void*) and return before the GPU finishes, except where a call is
+ *     documented as synchronising.
+ *   - Every call returns DEM_OK or a DEM_ERR_* code; nothing aborts or throws
+ *     across this boundary.  dem_last_error() gives a message for the last
+ *     failing call on a context.  Errors found by kernels (list capacity,
+ *     non-finite values) are sticky device flags that dem_check, dem_step and
+ *     the export calls report.
+ */
+#ifndef DEM_H
+#define DEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DEM_OK = 0,
+    DEM_ERR_ARG = 1,        /* invalid argument or configuration              */
+    DEM_ERR_CAPACITY = 2,   /* a neighbour row needs more than k_max slots    */
+    DEM_ERR_DOMAIN = 3,     /* box too small for the cut-off, or bad geometry */
+    DEM_ERR_NONFINITE = 4,  /* NaN or infinity in positions or velocities      */
+    DEM_ERR_HIP = 5,        /* a HIP runtime call failed                       */
+    DEM_ERR_STATE = 6       /* call out of order (e.g. forces before a list)   */
+};
+
+#define DEM_MAX_TYPES 4
+
+/* Material of one particle type (Sec. 2.1 and Sec. 2.2).  A pair of two
+ * types uses the harmonic effective modulus and shear modulus of the two
+ * materials, e = (e_i + e_j)/2 and mu = (mu_i + mu_j)/2; the flat wall is
+ * treated as the contacting particle's own material. */
+typedef struct dem_material {
+    double E;    /* Young's modulus (Pa), > 0                 */
+    double nu;   /* Poisson ratio, in (-1, 0.5)               */
+    double rho;  /* density (kg/m^3), > 0                     */
+    double e;    /* coefficient of restitution, in (0, 1]     */
+    double mu;   /* Coulomb friction coefficient, >= 0        */
+} dem_material;
+
+/* One system.  The box [lo, hi) is the periodic cell along periodic axes and
+ * the extent of the binning grid along open axes (particles outside an open
+ * axis are still handled correctly, they share the edge cells). */
+typedef struct dem_config {
+    int32_t ntypes;                    /* 1..DEM_MAX_TYPES                              */
+    dem_material mat[DEM_MAX_TYPES];
+    double dt;                         /* time step (s), > 0                            */
+    double g[3];                       /* gravity (m/s^2)                               */
+    double lo[3], hi[3];               /* box corners (m), hi > lo                      */
+    int32_t periodic[3];               /* 1 = periodic axis                              */
+    int32_t wall_z0;                   /* 1 = flat frictional wall at z = 0, normal +z  */
+    double skin;                       /* neighbour-list skin s (m), > 0                */
+    double cell;                       /* cell edge (m); 0 = smallest valid, 2 r_max + s */
+    double r_max;                      /* largest particle radius in this system (m)    */
+    int64_t n;                         /* particle count, >= 0                          */
+    int32_t k_max;                     /* neighbour slots per particle, 1..63           */
+    int32_t block;                     /* threads per block: 64, 128, 256; 0 = 128      */
+} dem_config;
+
+/* Caller-owned device arrays of the particles (see Conventions). */
+typedef struct dem_state {
+    double *x;       /* [3][n] positions (m); kept wrapped into [lo, hi) on periodic axes */
+    double *v;       /* [3][n] velocities (m/s)                                        */
+    double *w;       /* [3][n] angular velocities (rad/s)                              */
+    double *f;       /* [3][n] force of the last force evaluation (N)                  */
+    double *t;       /* [3][n] torque of the last force evaluation (N m)               */
+    double *r;       /* [n] radius (m)                                                 */
+    int32_t *type;   /* [n] material index into dem_config.mat                         */
+    int32_t *id;     /* [n] particle id, unique within the context, >= 0                */
+} dem_state;
+
+typedef struct dem_ctx dem_ctx;
+
+/* Device workspace bytes for one system (host only, no device work). */
+int dem_workspace_size(const dem_config *cfg, size_t *bytes);
+
+/* Same for a batch of nsys systems (Sec. 2.3: levels of different coarse-grain
+ * factor as independent systems of one launch). */
+int dem_batch_workspace_size(int32_t nsys, const dem_config *cfgs, size_t *bytes);
+
+/* Create a context over a caller-owned device workspace (at least the size
+ * returned above, 256-byte aligned).  stream: hipStream_t as void* (NULL =
+ * the default stream).  Validates the configuration: DEM_ERR_ARG for bad
+ * materials, dt, skin, k_max or block, DEM_ERR_DOMAIN when a periodic box is
+ * shorter than two cut-offs (2 (2 r_max + skin)).  Synchronises once. */
+int dem_init(dem_ctx **ctx, const dem_config *cfg, void *workspace, size_t ws_bytes, void *stream);
+int dem_batch_init(dem_ctx **ctx, int32_t nsys, const dem_config *cfgs, void *workspace, size_t ws_bytes,
+                   void *stream);
+
+/* Start from the particles in *s: computes masses m = (4/3) pi rho r^3 and
+ * inertias I = (2/5) m r^2 (solid spheres, Eq. (1)-(2)), clears the tangential
+ * history of all pairs and of the wall, and marks the neighbour list invalid.
+ * Synchronises; DEM_ERR_ARG when a type is out of range, an id negative or a
+ * radius not positive. */
+int dem_reset(dem_ctx *ctx, const dem_state *s);
+
+/* Binning: sorts every system's particles by cell (cell index major, id minor)
+ * with a counting sort and permutes all caller arrays and the library's
+ * per-particle data in place.  The stored history is kept and re-attached to
+ * the particles by the next dem_neighbors. */
+int dem_bin(dem_ctx *ctx, const dem_state *s);
+
+/* Neighbour list: for every particle i all j with d^2 < (r_i + r_j + skin)^2
+ * (minimum image), one row per particle sorted by neighbour id.  The
+ * tangential history of every pair still listed is carried over from the
+ * previous list by id; new pairs start with zero history.  Requires dem_bin
+ * on the current positions (DEM_ERR_STATE otherwise). */
+int dem_neighbors(dem_ctx *ctx, const dem_state *s);
+
+/* Force and torque on every particle (Eq. (3)-(6), gravity, the wall) at the
+ * current positions and velocities, written to s->f and s->t.  With
+ * update_history != 0 the tangential overlaps are advanced by v_t dt and
+ * truncated (Eq. (5)) and stored; with 0 they are only read (the first force
+ * evaluation of a run).  Uses no atomics: each particle sums its own row
+ * (gravity, then neighbours by ascending id, then the wall), so results do
+ * not depend on the particle order.  Requires a list (DEM_ERR_STATE). */
+int dem_forces(dem_ctx *ctx, const dem_state *s, int update_history);
+
+/* Velocity Verlet halves.  phase 0: v += dt/2 f/m, w += dt/2 t/I, x += dt v,
+ * wrap periodic axes, accumulate the displacement since the last list build.
+ * phase 1: v += dt/2 f/m, w += dt/2 t/I.  DEM_ERR_ARG for another phase. */
+int dem_integrate(dem_ctx *ctx, const dem_state *s, int phase);
+
+/* nsteps velocity-Verlet steps: phase 0, rebuild (bin + list) when some
+ * particle moved more than skin/2 since the last build, forces with history
+ * update, phase 1.  The forces in s->f, s->t must belong to the current state
+ * (call dem_forces(ctx, s, 0) once after dem_reset, or provide them); the
+ * library cannot check this.  The rebuild decision is
+ * taken on the device; the host learns of it at a synchronisation every few
+ * dozen steps, so this call synchronises the stream.  Returns the sticky
+ * device errors (DEM_ERR_CAPACITY, DEM_ERR_NONFINITE). */
+int dem_step(dem_ctx *ctx, const dem_state *s, int64_t nsteps);
+
+/* Step-loop options: use_graph != 0 replays the per-step kernels as one
+ * captured HIP graph of `chunk` steps (chunk even, 2..1024; default 64). */
+int dem_set_step_options(dem_ctx *ctx, int use_graph, int32_t chunk);
+
+/* Synchronise and report the sticky device flags.  info[0] = error bits
+ * (1 capacity, 2 non-finite), info[1] = largest neighbour row seen (the k_max
+ * a retry needs), info[2] = list builds so far, info[3] = steps so far.
+ * Returns DEM_ERR_CAPACITY / DEM_ERR_NONFINITE when flagged. */
+int dem_check(dem_ctx *ctx, int64_t info[4]);
+
+/* Counters (synchronises): out[0] steps, out[1] list builds, out[2] sum over
+ * force evaluations of directed contacts (each unordered pair counts twice),
+ * out[3] sum of wall contacts, out[4] listed directed slots of the current
+ * list. */
+int dem_stats(dem_ctx *ctx, int64_t out[5]);
+
+/* Host copies for checking (synchronise).  Output arrays are host memory of
+ * `cap` entries; *count receives the total even when it exceeds cap.
+ *   dem_export_neighbors: directed list entries (id_i, id_j), sorted.
+ *   dem_export_contacts:  directed pairs in contact at the current positions
+ *                         with their tangential history xi_ij [count][3].
+ *   dem_export_wall:      particles touching the wall and their history. */
+int dem_export_neighbors(dem_ctx *ctx, const dem_state *s, int32_t *id_i, int32_t *id_j, int64_t cap,
+                         int64_t *count);
+int dem_export_contacts(dem_ctx *ctx, const dem_state *s, int32_t *id_i, int32_t *id_j, double *xi, int64_t cap,
+                        int64_t *count);
+int dem_export_wall(dem_ctx *ctx, const dem_state *s, int32_t *id, double *xi, int64_t cap, int64_t *count);
+
+/* Set the tangential history from host arrays (synchronises): npairs directed
+ * entries (id_i, id_j, xi[3]) and nwall wall entries (id, xi[3]).  Pairs in the
+ * current list that are not given get zero history.  Requires a list
+ * (DEM_ERR_STATE). */
+int dem_import_history(dem_ctx *ctx, const dem_state *s, int64_t npairs, const int32_t *id_i, const int32_t *id_j,
+                       const double *xi, int64_t nwall, const int32_t *wall_id, const double *wall_xi);
+
+const char *dem_last_error(const dem_ctx *ctx);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+int dem_destroy(dem_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEM_H */

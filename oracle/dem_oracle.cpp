@@ -369,7 +369,9 @@ template <class S> void forces(Sim<S> &s, bool update) {
             auto it = s.whist.find(a.id);
             V3<S> xi = it == s.whist.end() ? V3<S>{0.0, 0.0, 0.0} : it->second;
             V3<S> f, ft, n;
-            if (!contact(s, a, (const Particle<S> *)nullptr, xi, update, f, ft, n, (PairRecord<S> *)nullptr)) continue;
+            PairRecord<S> rec{a.id, -1, 0, 0, 0, 0};
+            if (!contact(s, a, (const Particle<S> *)nullptr, xi, update, f, ft, n, &rec)) continue;
+            s.records.push_back(rec);
             if (update) wnext[a.id] = xi;
             a.f = {a.f.x + f.x, a.f.y + f.y, a.f.z + f.z};
             V3<S> nxf = {n.y * ft.z - n.z * ft.y, n.z * ft.x - n.x * ft.z, n.x * ft.y - n.y * ft.x};
@@ -556,8 +558,9 @@ long orc_pairs(void *h, double extra, int brute, int *lo, int *hi, long cap) {
     return k;
 }
 
-/* Per-pair records of the last force evaluation: ids and magnitudes
- * |f_n| (scalar normal force), |F_ij|, |F_t| and the Coulomb cap mu |f_n|. */
+/* Per-contact records of the last force evaluation: ids (hi = -1 for the
+ * wall) and magnitudes |f_n| (scalar normal force), |F_ij|, |F_t| and the
+ * Coulomb cap mu |f_n|. */
 long orc_records(void *h, int *lo, int *hi, double *fn, double *fmag, double *ftmag, double *cap, long capn) {
     SimD *s = (SimD *)h;
     long k = 0;

@@ -1,0 +1,720 @@
+// dem_api.hip -- host side of libdem.so: validation, workspace layout, the
+// step driver and the C-ABI declared in include/dem.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dem.h"
+#include "dem_kernels.h"
+
+using namespace dem;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame;
+    size_t nbr[2], cnt[2], xi[2], mask[2], ids[2];
+    size_t cell_of, rank, order, cell_count, cell_start, scan_partial, shadow_d, shadow_i;
+    size_t total;
+};
+
+struct Geometry {
+    std::vector<SysDesc> sys;
+    std::vector<PairCoef> coef;
+    std::vector<double> rho;
+    int64_t n = 0, ncell = 0;
+    int32_t kmax = 0, block = 128;
+};
+
+double cutoff_of(const dem_config &c) { return 2.0 * c.r_max + c.skin; }
+
+// Validates the configurations and derives the device descriptors.
+int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::string &err) {
+    if (nsys < 1 || !cfgs) { err = "need at least one system"; return DEM_ERR_ARG; }
+    g = Geometry();
+    g.block = cfgs[0].block == 0 ? 128 : cfgs[0].block;
+    if (g.block != 64 && g.block != 128 && g.block != 256) { err = "block must be 64, 128 or 256"; return DEM_ERR_ARG; }
+    for (int s = 0; s < nsys; ++s) {
+        const dem_config &c = cfgs[s];
+        char buf[256];
+        if (c.ntypes < 1 || c.ntypes > DEM_MAX_TYPES) { err = "ntypes out of range"; return DEM_ERR_ARG; }
+        for (int t = 0; t < c.ntypes; ++t) {
+            const dem_material &m = c.mat[t];
+            if (!(m.E > 0.0) || !(m.nu > -1.0 && m.nu < 0.5) || !(m.rho > 0.0) || !(m.e > 0.0 && m.e <= 1.0) ||
+                !(m.mu >= 0.0) || !std::isfinite(m.E) || !std::isfinite(m.mu)) {
+                snprintf(buf, sizeof buf, "system %d type %d: need E > 0, -1 < nu < 0.5, rho > 0, 0 < e <= 1, mu >= 0", s, t);
+                err = buf;
+                return DEM_ERR_ARG;
+            }
+        }
+        if (!(c.dt > 0.0) || !std::isfinite(c.dt)) { err = "dt must be > 0"; return DEM_ERR_ARG; }
+        if (!(c.skin > 0.0)) { err = "skin must be > 0"; return DEM_ERR_ARG; }
+        if (!(c.r_max > 0.0)) { err = "r_max must be > 0"; return DEM_ERR_ARG; }
+        if (c.n < 0) { err = "n must be >= 0"; return DEM_ERR_ARG; }
+        if (c.k_max < 1 || c.k_max > kMaxSlots) { err = "k_max must be in 1..63"; return DEM_ERR_ARG; }
+        if ((c.block == 0 ? 128 : c.block) != g.block) { err = "all systems of a batch need the same block size"; return DEM_ERR_ARG; }
+        const double cut = cutoff_of(c);
+        double h = c.cell > 0.0 ? c.cell : cut;
+        if (h < cut) { err = "cell must be >= 2 r_max + skin"; return DEM_ERR_ARG; }
+        SysDesc d;
+        memset(&d, 0, sizeof d);
+        int64_t cells = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (!(c.hi[a] > c.lo[a])) { err = "box needs hi > lo"; return DEM_ERR_ARG; }
+            d.lo[a] = c.lo[a];
+            d.hi[a] = c.hi[a];
+            d.L[a] = c.hi[a] - c.lo[a];
+            d.hL[a] = 0.5 * d.L[a];
+            d.periodic[a] = c.periodic[a] ? 1 : 0;
+            d.g[a] = c.g[a];
+            double want = d.L[a] / (h * (1.0 + 1e-9));
+            int64_t nc = (int64_t)std::floor(want);
+            if (nc < 1) nc = 1;
+            if (d.periodic[a]) {
+                if (d.L[a] < 2.0 * cut || nc < 2) {
+                    snprintf(buf, sizeof buf, "system %d: periodic axis %d shorter than two cut-offs (or two cells)", s, a);
+                    err = buf;
+                    return DEM_ERR_DOMAIN;
+                }
+            }
+            if (nc > (1 << 20)) { err = "too many cells along an axis"; return DEM_ERR_DOMAIN; }
+            d.nc[a] = (int32_t)nc;
+            d.inv_w[a] = (double)nc / d.L[a];
+            cells *= nc;
+        }
+        d.dt = c.dt;
+        d.hdt = 0.5 * c.dt;
+        d.skin = c.skin;
+        d.disp_thr2 = (0.5 * c.skin) * (0.5 * c.skin);
+        d.p0 = g.n;
+        d.p1 = g.n + c.n;
+        d.c0 = g.ncell;
+        d.wall = c.wall_z0 ? 1 : 0;
+        d.ntypes = c.ntypes;
+        d.coef0 = (int32_t)g.coef.size();
+        d.type0 = (int32_t)g.rho.size();
+        for (int ti = 0; ti < c.ntypes; ++ti)
+            for (int tj = 0; tj < c.ntypes; ++tj) {
+                const dem_material &a = c.mat[ti], &b = c.mat[tj];
+                double inv_E = (1.0 - a.nu * a.nu) / a.E + (1.0 - b.nu * b.nu) / b.E;
+                double inv_G = 2.0 * (2.0 - a.nu) * (1.0 + a.nu) / a.E + 2.0 * (2.0 - b.nu) * (1.0 + b.nu) / b.E;
+                double e = (a.e + b.e) / 2.0;
+                double mu = (a.mu + b.mu) / 2.0;
+                double le = std::log(e);
+                PairCoef k;
+                k.Es = 1.0 / inv_E;
+                k.Gs = 1.0 / inv_G;
+                k.beta = le / std::sqrt(le * le + M_PI * M_PI);
+                k.mu = mu;
+                g.coef.push_back(k);
+            }
+        for (int t = 0; t < c.ntypes; ++t) g.rho.push_back(c.mat[t].rho);
+        g.sys.push_back(d);
+        g.n += c.n;
+        g.ncell += cells;
+        g.kmax = std::max(g.kmax, c.k_max);
+    }
+    if (g.n > INT32_MAX / 2 || g.ncell > INT32_MAX / 2) { err = "problem too large for 32-bit indices"; return DEM_ERR_ARG; }
+    return DEM_OK;
+}
+
+Layout make_layout(const Geometry &g) {
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    const size_t n = (size_t)g.n, K = (size_t)g.kmax, C = (size_t)g.ncell;
+    L.sys = take(g.sys.size() * sizeof(SysDesc));
+    L.coef = take(g.coef.size() * sizeof(PairCoef));
+    L.rho = take(g.rho.size() * sizeof(double));
+    L.flags = take(sizeof(Flags));
+    L.m = take(n * 8);
+    L.inv_m = take(n * 8);
+    L.inv_I = take(n * 8);
+    L.disp = take(3 * n * 8);
+    L.xiw = take(3 * n * 8);
+    L.frame = take(n * 4);
+    for (int b = 0; b < 2; ++b) {
+        L.nbr[b] = take(K * n * 4);
+        L.cnt[b] = take(n * 4);
+        L.xi[b] = take(3 * K * n * 8);
+        L.mask[b] = take(n * 8);
+        L.ids[b] = take(n * 4);
+    }
+    L.cell_of = take(n * 4);
+    L.rank = take(n * 4);
+    L.order = take(n * 4);
+    L.cell_count = take((C + 1) * 4);
+    L.cell_start = take((C + 1) * 4);
+    L.scan_partial = take(((C + 1023) / 1024 + 1) * 4);
+    L.shadow_d = take(25 * n * 8);
+    L.shadow_i = take(3 * n * 4);
+    L.total = o;
+    return L;
+}
+
+struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    const void *key[10] = {nullptr};
+    int chunk = 0;
+    int count = 0;
+};
+
+}  // namespace
+
+struct dem_ctx {
+    Geometry geo;
+    Layout lay;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    SysDesc *d_sys = nullptr;
+    PairCoef *d_coef = nullptr;
+    double *d_rho = nullptr;
+    Flags *d_flags = nullptr;
+    List lists[2];
+    int cur = 0;
+    // host-side state machine
+    bool masses = false, have_list = false, list_current = false, binned = false, frame_identity = true;
+    bool forces_valid = false;
+    int64_t step_counter = 0;
+    // options
+    bool use_graph = false, count = true;
+    int chunk = 64;
+    GraphSlot graphs[2];
+    std::string err;
+};
+
+namespace {
+
+int fail(dem_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(dem_ctx *c, hipError_t e, const char *what) {
+    return fail(c, DEM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCALL(c, expr)                                            \
+    do {                                                            \
+        hipError_t _e = (expr);                                     \
+        if (_e != hipSuccess) return hip_fail((c), _e, #expr);      \
+    } while (0)
+
+KArgs kargs(dem_ctx *c, const dem_state *s) {
+    KArgs a;
+    memset(&a, 0, sizeof a);
+    a.x = s->x; a.v = s->v; a.w = s->w; a.f = s->f; a.t = s->t; a.r = s->r;
+    a.type = s->type; a.id = s->id;
+    char *w = c->ws;
+    const Layout &L = c->lay;
+    a.m = (double *)(w + L.m);
+    a.inv_m = (double *)(w + L.inv_m);
+    a.inv_I = (double *)(w + L.inv_I);
+    a.disp = (double *)(w + L.disp);
+    a.xiw = (double *)(w + L.xiw);
+    a.frame = (int32_t *)(w + L.frame);
+    a.sys = c->d_sys;
+    a.coef = c->d_coef;
+    a.rho = c->d_rho;
+    a.nsys = (int32_t)c->geo.sys.size();
+    a.kmax = c->geo.kmax;
+    a.block = c->geo.block;
+    a.n = c->geo.n;
+    a.ncell = c->geo.ncell;
+    a.flags = c->d_flags;
+    a.cur = c->lists[c->cur];
+    a.old = c->lists[1 - c->cur];
+    a.cell_of = (int32_t *)(w + L.cell_of);
+    a.rank = (int32_t *)(w + L.rank);
+    a.order = (int32_t *)(w + L.order);
+    a.cell_count = (int32_t *)(w + L.cell_count);
+    a.cell_start = (int32_t *)(w + L.cell_start);
+    a.scan_partial = (int32_t *)(w + L.scan_partial);
+    a.shadow_d = (double *)(w + L.shadow_d);
+    a.shadow_i = (int32_t *)(w + L.shadow_i);
+    return a;
+}
+
+int check_state(dem_ctx *c, const dem_state *s) {
+    if (!c) return DEM_ERR_ARG;
+    if (!s) return fail(c, DEM_ERR_ARG, "state is NULL");
+    if (c->geo.n > 0 && (!s->x || !s->v || !s->w || !s->f || !s->t || !s->r || !s->type || !s->id))
+        return fail(c, DEM_ERR_ARG, "a state array is NULL");
+    return DEM_OK;
+}
+
+int read_flags(dem_ctx *c, Flags &h) {
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    HIPCALL(c, hipMemcpy(&h, c->d_flags, sizeof(Flags), hipMemcpyDeviceToHost));
+    return DEM_OK;
+}
+
+int flag_error(dem_ctx *c, const Flags &h) {
+    if (h.err & kErrNonFinite) return fail(c, DEM_ERR_NONFINITE, "non-finite position or velocity");
+    if (h.err & kErrCapacity) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "neighbour row of %d entries exceeds k_max = %d", h.max_row, c->geo.kmax);
+        return fail(c, DEM_ERR_CAPACITY, buf);
+    }
+    if (h.err & kErrCellOverflow) return fail(c, DEM_ERR_CAPACITY, "a cell holds more than 64 particles");
+    if (h.err & kErrBadInput) return fail(c, DEM_ERR_ARG, "a particle has a type out of range, a negative id or r <= 0");
+    return DEM_OK;
+}
+
+int do_bin(dem_ctx *c, const dem_state *s) {
+    KArgs a = kargs(c, s);
+    HIPCALL(c, launch_bin(a, c->frame_identity ? 1 : 0, c->stream));
+    c->binned = true;
+    c->frame_identity = false;
+    c->list_current = false;
+    return DEM_OK;
+}
+
+int do_neighbors(dem_ctx *c, const dem_state *s) {
+    if (!c->binned) return fail(c, DEM_ERR_STATE, "dem_neighbors needs dem_bin on the current positions");
+    int have_old = c->have_list ? 1 : 0;
+    c->cur = 1 - c->cur;  // build into the other buffer; the previous list becomes `old`
+    KArgs a = kargs(c, s);
+    HIPCALL(c, launch_neighbors(a, have_old, c->stream));
+    HIPCALL(c, launch_ctrl(c->d_flags, 4, 1, c->stream));
+    c->have_list = true;
+    c->list_current = true;
+    c->frame_identity = true;
+    return DEM_OK;
+}
+
+int capture_graph(dem_ctx *c, const dem_state *s, GraphSlot &gs) {
+    if (gs.exec) { (void)hipGraphExecDestroy(gs.exec); gs.exec = nullptr; }
+    KArgs a = kargs(c, s);
+    hipGraph_t graph = nullptr;
+    HIPCALL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < c->chunk && e == hipSuccess; ++k) {
+        e = launch_phase(a, 0, k, 1, c->stream);
+        if (e == hipSuccess) e = launch_forces(a, 1, k, 1, c->count ? 1 : 0, c->stream);
+        if (e == hipSuccess) e = launch_phase(a, 1, k, 1, c->stream);
+    }
+    hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch during graph capture");
+    if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+    hipError_t e3 = hipGraphInstantiate(&gs.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) { gs.exec = nullptr; return hip_fail(c, e3, "hipGraphInstantiate"); }
+    const void *key[10] = {s->x, s->v, s->w, s->f, s->t, s->r, s->type, s->id, c->lists[c->cur].nbr, nullptr};
+    memcpy(gs.key, key, sizeof key);
+    gs.chunk = c->chunk;
+    gs.count = c->count ? 1 : 0;
+    return DEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dem_batch_workspace_size(int32_t nsys, const dem_config *cfgs, size_t *bytes) {
+    if (!bytes) return DEM_ERR_ARG;
+    Geometry g;
+    std::string err;
+    int rc = build_geometry(nsys, cfgs, g, err);
+    if (rc) return rc;
+    *bytes = make_layout(g).total;
+    return DEM_OK;
+}
+
+int dem_workspace_size(const dem_config *cfg, size_t *bytes) { return dem_batch_workspace_size(1, cfg, bytes); }
+
+static std::string g_init_error;
+
+int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *workspace, size_t ws_bytes,
+                   void *stream) {
+    if (!out) return DEM_ERR_ARG;
+    *out = nullptr;
+    Geometry g;
+    std::string err;
+    int rc = build_geometry(nsys, cfgs, g, err);
+    if (rc) { g_init_error = err; return rc; }
+    Layout lay = make_layout(g);
+    if (!workspace || ws_bytes < lay.total) { g_init_error = "workspace too small"; return DEM_ERR_ARG; }
+    if ((uintptr_t)workspace % kAlign) { g_init_error = "workspace must be 256-byte aligned"; return DEM_ERR_ARG; }
+    dem_ctx *c = new dem_ctx();
+    c->geo = g;
+    c->lay = lay;
+    c->ws = (char *)workspace;
+    c->stream = (hipStream_t)stream;
+    c->d_sys = (SysDesc *)(c->ws + lay.sys);
+    c->d_coef = (PairCoef *)(c->ws + lay.coef);
+    c->d_rho = (double *)(c->ws + lay.rho);
+    c->d_flags = (Flags *)(c->ws + lay.flags);
+    for (int b = 0; b < 2; ++b) {
+        c->lists[b].nbr = (int32_t *)(c->ws + lay.nbr[b]);
+        c->lists[b].cnt = (int32_t *)(c->ws + lay.cnt[b]);
+        c->lists[b].xi = (double *)(c->ws + lay.xi[b]);
+        c->lists[b].mask = (uint64_t *)(c->ws + lay.mask[b]);
+        c->lists[b].ids = (int32_t *)(c->ws + lay.ids[b]);
+    }
+    hipError_t e = hipMemcpyAsync(c->d_sys, g.sys.data(), g.sys.size() * sizeof(SysDesc), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_coef, g.coef.data(), g.coef.size() * sizeof(PairCoef), hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_rho, g.rho.data(), g.rho.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_ctrl(c->d_flags, 2, 0, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        g_init_error = std::string("HIP error during init: ") + hipGetErrorString(e);
+        delete c;
+        return DEM_ERR_HIP;
+    }
+    *out = c;
+    return DEM_OK;
+}
+
+int dem_init(dem_ctx **ctx, const dem_config *cfg, void *workspace, size_t ws_bytes, void *stream) {
+    return dem_batch_init(ctx, 1, cfg, workspace, ws_bytes, stream);
+}
+
+int dem_reset(dem_ctx *c, const dem_state *s) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    KArgs a = kargs(c, s);
+    HIPCALL(c, launch_init_mass(a, c->stream));
+    HIPCALL(c, launch_fill_f64(a.disp, 3 * c->geo.n, 0.0, c->stream));
+    HIPCALL(c, launch_fill_f64(a.xiw, 3 * c->geo.n, 0.0, c->stream));
+    Flags h;
+    if ((rc = read_flags(c, h))) return rc;
+    if ((rc = flag_error(c, h))) return rc;
+    c->masses = true;
+    c->have_list = false;
+    c->list_current = false;
+    c->binned = false;
+    c->frame_identity = true;
+    c->forces_valid = false;
+    return DEM_OK;
+}
+
+int dem_bin(dem_ctx *c, const dem_state *s) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first");
+    return do_bin(c, s);
+}
+
+int dem_neighbors(dem_ctx *c, const dem_state *s) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first");
+    return do_neighbors(c, s);
+}
+
+int dem_forces(dem_ctx *c, const dem_state *s, int update_history) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_forces needs a neighbour list for the current order");
+    KArgs a = kargs(c, s);
+    HIPCALL(c, launch_forces(a, update_history ? 1 : 0, 0, 0, 0, c->stream));
+    c->forces_valid = true;
+    return DEM_OK;
+}
+
+int dem_integrate(dem_ctx *c, const dem_state *s, int phase) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (phase != 0 && phase != 1) return fail(c, DEM_ERR_ARG, "phase must be 0 or 1");
+    if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first");
+    KArgs a = kargs(c, s);
+    HIPCALL(c, launch_phase(a, phase, 0, 0, c->stream));
+    if (phase == 0) {
+        c->binned = false;
+        c->forces_valid = false;
+    }
+    return DEM_OK;
+}
+
+int dem_set_step_options(dem_ctx *c, int use_graph, int32_t chunk) {
+    if (!c) return DEM_ERR_ARG;
+    if (chunk < 2 || chunk > 1024 || (chunk & 1)) return fail(c, DEM_ERR_ARG, "chunk must be even, 2..1024");
+    c->use_graph = use_graph != 0;
+    c->chunk = chunk;
+    return DEM_OK;
+}
+
+int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(c, DEM_ERR_ARG, "nsteps < 0");
+    if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first");
+    if (nsteps == 0 || c->geo.n == 0) return DEM_OK;
+    if (!c->list_current) {
+        // binned but no list yet: build it (f and t were permuted with the particles)
+        if ((rc = do_bin(c, s)) || (rc = do_neighbors(c, s))) return rc;
+    }
+    int64_t done = 0;
+    Flags h;
+    while (done < nsteps) {
+        const int64_t m = std::min<int64_t>(c->chunk, nsteps - done);
+        HIPCALL(c, launch_ctrl(c->d_flags, 0, c->step_counter, c->stream));
+        KArgs a = kargs(c, s);
+        if (c->use_graph && m == c->chunk) {
+            GraphSlot &gs = c->graphs[c->cur];
+            const void *key[10] = {s->x, s->v, s->w, s->f, s->t, s->r, s->type, s->id, c->lists[c->cur].nbr, nullptr};
+            if (!gs.exec || memcmp(gs.key, key, sizeof key) || gs.chunk != c->chunk || gs.count != (c->count ? 1 : 0)) {
+                if ((rc = capture_graph(c, s, gs))) return rc;
+            }
+            HIPCALL(c, hipGraphLaunch(gs.exec, c->stream));
+        } else {
+            for (int64_t k = 0; k < m; ++k) {
+                HIPCALL(c, launch_phase(a, 0, (int)k, 1, c->stream));
+                HIPCALL(c, launch_forces(a, 1, (int)k, 1, c->count ? 1 : 0, c->stream));
+                HIPCALL(c, launch_phase(a, 1, (int)k, 1, c->stream));
+            }
+        }
+        if ((rc = read_flags(c, h))) return rc;
+        if ((rc = flag_error(c, h))) return rc;
+        if (h.abort_at != INT64_MAX) {
+            // step abort_at has drifted; rebuild, then finish it
+            const int64_t k = h.abort_at - c->step_counter;
+            c->binned = false;
+            if ((rc = do_bin(c, s)) || (rc = do_neighbors(c, s))) return rc;
+            KArgs b = kargs(c, s);
+            HIPCALL(c, launch_forces(b, 1, 0, 0, c->count ? 1 : 0, c->stream));
+            HIPCALL(c, launch_phase(b, 1, 0, 0, c->stream));
+            HIPCALL(c, launch_ctrl(c->d_flags, 3, 1, c->stream));
+            done += k + 1;
+            c->step_counter += k + 1;
+        } else {
+            done += m;
+            c->step_counter += m;
+        }
+    }
+    if ((rc = read_flags(c, h))) return rc;
+    c->binned = false;
+    c->forces_valid = true;
+    return flag_error(c, h);
+}
+
+int dem_check(dem_ctx *c, int64_t info[4]) {
+    if (!c) return DEM_ERR_ARG;
+    Flags h;
+    int rc = read_flags(c, h);
+    if (rc) return rc;
+    if (info) {
+        info[0] = h.err;
+        info[1] = h.max_row;
+        info[2] = h.builds;
+        info[3] = h.steps;
+    }
+    return flag_error(c, h);
+}
+
+int dem_stats(dem_ctx *c, int64_t out[5]) {
+    if (!c || !out) return DEM_ERR_ARG;
+    Flags h;
+    int rc = read_flags(c, h);
+    if (rc) return rc;
+    out[0] = h.steps;
+    out[1] = h.builds;
+    out[2] = (int64_t)h.contacts;
+    out[3] = (int64_t)h.wall_contacts;
+    int64_t slots = 0;
+    if (c->have_list && c->geo.n > 0) {
+        std::vector<int32_t> cnt(c->geo.n);
+        HIPCALL(c, hipMemcpy(cnt.data(), c->lists[c->cur].cnt, c->geo.n * 4, hipMemcpyDeviceToHost));
+        for (int32_t q : cnt) slots += q;
+    }
+    out[4] = slots;
+    return DEM_OK;
+}
+
+// ------------------------------------------------------------ host exports
+
+namespace {
+
+struct HostList {
+    std::vector<int32_t> nbr, cnt, ids, id_now;
+    std::vector<uint64_t> mask;
+    std::vector<double> xi, x, r, xiw;
+};
+
+int fetch_list(dem_ctx *c, const dem_state *s, HostList &H, bool with_xi, bool with_pos) {
+    const int64_t n = c->geo.n, K = c->geo.kmax;
+    const List &L = c->lists[c->cur];
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    H.nbr.resize(K * n);
+    H.cnt.resize(n);
+    H.ids.resize(n);
+    H.mask.resize(n);
+    HIPCALL(c, hipMemcpy(H.nbr.data(), L.nbr, K * n * 4, hipMemcpyDeviceToHost));
+    HIPCALL(c, hipMemcpy(H.cnt.data(), L.cnt, n * 4, hipMemcpyDeviceToHost));
+    HIPCALL(c, hipMemcpy(H.ids.data(), L.ids, n * 4, hipMemcpyDeviceToHost));
+    HIPCALL(c, hipMemcpy(H.mask.data(), L.mask, n * 8, hipMemcpyDeviceToHost));
+    if (with_xi) {
+        H.xi.resize(3 * K * n);
+        H.xiw.resize(3 * n);
+        HIPCALL(c, hipMemcpy(H.xi.data(), L.xi, 3 * K * n * 8, hipMemcpyDeviceToHost));
+        HIPCALL(c, hipMemcpy(H.xiw.data(), c->ws + c->lay.xiw, 3 * n * 8, hipMemcpyDeviceToHost));
+    }
+    if (with_pos) {
+        H.x.resize(3 * n);
+        H.r.resize(n);
+        HIPCALL(c, hipMemcpy(H.x.data(), s->x, 3 * n * 8, hipMemcpyDeviceToHost));
+        HIPCALL(c, hipMemcpy(H.r.data(), s->r, n * 8, hipMemcpyDeviceToHost));
+    }
+    return DEM_OK;
+}
+
+int sys_index(const Geometry &g, int64_t i) {
+    for (size_t s = 0; s < g.sys.size(); ++s)
+        if (i < g.sys[s].p1) return (int)s;
+    return (int)g.sys.size() - 1;
+}
+
+}  // namespace
+
+int dem_export_neighbors(dem_ctx *c, const dem_state *s, int32_t *id_i, int32_t *id_j, int64_t cap, int64_t *count) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!count) return fail(c, DEM_ERR_ARG, "count is NULL");
+    if (!c->list_current) return fail(c, DEM_ERR_STATE, "no neighbour list for the current order");
+    HostList H;
+    if ((rc = fetch_list(c, s, H, false, false))) return rc;
+    const int64_t n = c->geo.n;
+    std::vector<std::pair<int32_t, int32_t>> out;
+    for (int64_t i = 0; i < n; ++i)
+        for (int q = 0; q < H.cnt[i]; ++q) out.push_back({H.ids[i], H.ids[H.nbr[(int64_t)q * n + i]]});
+    std::sort(out.begin(), out.end());
+    *count = (int64_t)out.size();
+    for (int64_t k = 0; k < *count && k < cap; ++k) {
+        if (id_i) id_i[k] = out[k].first;
+        if (id_j) id_j[k] = out[k].second;
+    }
+    Flags h;
+    if ((rc = read_flags(c, h))) return rc;
+    return flag_error(c, h);
+}
+
+int dem_export_contacts(dem_ctx *c, const dem_state *s, int32_t *id_i, int32_t *id_j, double *xi, int64_t cap,
+                        int64_t *count) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!count) return fail(c, DEM_ERR_ARG, "count is NULL");
+    if (!c->list_current) return fail(c, DEM_ERR_STATE, "no neighbour list for the current order");
+    HostList H;
+    if ((rc = fetch_list(c, s, H, true, true))) return rc;
+    const int64_t n = c->geo.n, K = c->geo.kmax;
+    struct Rec { int32_t a, b; double x, y, z; };
+    std::vector<Rec> out;
+    for (int64_t i = 0; i < n; ++i) {
+        const SysDesc &sd = c->geo.sys[sys_index(c->geo, i)];
+        for (int q = 0; q < H.cnt[i]; ++q) {
+            const int64_t j = H.nbr[(int64_t)q * n + i];
+            double dx = min_image(H.x[i] - H.x[j], sd.L[0], sd.hL[0], sd.periodic[0]);
+            double dy = min_image(H.x[n + i] - H.x[n + j], sd.L[1], sd.hL[1], sd.periodic[1]);
+            double dz = min_image(H.x[2 * n + i] - H.x[2 * n + j], sd.L[2], sd.hL[2], sd.periodic[2]);
+            double d2 = dx * dx + dy * dy + dz * dz;
+            double rs = H.r[i] + H.r[j];
+            if (!(d2 < rs * rs)) continue;
+            const int64_t slot = (int64_t)q * n + i, plane = K * n;
+            Rec r{H.ids[i], H.ids[j], 0.0, 0.0, 0.0};
+            if ((H.mask[i] >> q) & 1ull) { r.x = H.xi[slot]; r.y = H.xi[plane + slot]; r.z = H.xi[2 * plane + slot]; }
+            out.push_back(r);
+        }
+    }
+    std::sort(out.begin(), out.end(), [](const Rec &p, const Rec &q) { return p.a != q.a ? p.a < q.a : p.b < q.b; });
+    *count = (int64_t)out.size();
+    for (int64_t k = 0; k < *count && k < cap; ++k) {
+        if (id_i) id_i[k] = out[k].a;
+        if (id_j) id_j[k] = out[k].b;
+        if (xi) { xi[3 * k] = out[k].x; xi[3 * k + 1] = out[k].y; xi[3 * k + 2] = out[k].z; }
+    }
+    Flags h;
+    if ((rc = read_flags(c, h))) return rc;
+    return flag_error(c, h);
+}
+
+int dem_export_wall(dem_ctx *c, const dem_state *s, int32_t *id, double *xi, int64_t cap, int64_t *count) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!count) return fail(c, DEM_ERR_ARG, "count is NULL");
+    if (!c->list_current) return fail(c, DEM_ERR_STATE, "no neighbour list for the current order");
+    HostList H;
+    if ((rc = fetch_list(c, s, H, true, true))) return rc;
+    const int64_t n = c->geo.n;
+    struct Rec { int32_t a; double x, y, z; };
+    std::vector<Rec> out;
+    for (int64_t i = 0; i < n; ++i) {
+        const SysDesc &sd = c->geo.sys[sys_index(c->geo, i)];
+        if (!sd.wall || !(H.x[2 * n + i] < H.r[i])) continue;
+        Rec r{H.ids[i], 0.0, 0.0, 0.0};
+        if (H.mask[i] & kWallBit) { r.x = H.xiw[i]; r.y = H.xiw[n + i]; r.z = H.xiw[2 * n + i]; }
+        out.push_back(r);
+    }
+    std::sort(out.begin(), out.end(), [](const Rec &p, const Rec &q) { return p.a < q.a; });
+    *count = (int64_t)out.size();
+    for (int64_t k = 0; k < *count && k < cap; ++k) {
+        if (id) id[k] = out[k].a;
+        if (xi) { xi[3 * k] = out[k].x; xi[3 * k + 1] = out[k].y; xi[3 * k + 2] = out[k].z; }
+    }
+    return DEM_OK;
+}
+
+int dem_import_history(dem_ctx *c, const dem_state *s, int64_t npairs, const int32_t *id_i, const int32_t *id_j,
+                       const double *xi, int64_t nwall, const int32_t *wall_id, const double *wall_xi) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (npairs < 0 || nwall < 0 || (npairs && (!id_i || !id_j || !xi)) || (nwall && (!wall_id || !wall_xi)))
+        return fail(c, DEM_ERR_ARG, "bad history arrays");
+    if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_import_history needs a neighbour list");
+    HostList H;
+    if ((rc = fetch_list(c, s, H, true, false))) return rc;
+    const int64_t n = c->geo.n, K = c->geo.kmax, plane = K * n;
+    std::unordered_map<uint64_t, int64_t> pairs;
+    pairs.reserve((size_t)npairs * 2);
+    for (int64_t k = 0; k < npairs; ++k)
+        pairs[((uint64_t)(uint32_t)id_i[k] << 32) | (uint32_t)id_j[k]] = k;
+    std::unordered_map<int32_t, int64_t> walls;
+    for (int64_t k = 0; k < nwall; ++k) walls[wall_id[k]] = k;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t m = 0;
+        for (int q = 0; q < H.cnt[i]; ++q) {
+            const int64_t slot = (int64_t)q * n + i;
+            const int32_t a = H.ids[i], b = H.ids[H.nbr[slot]];
+            auto it = pairs.find(((uint64_t)(uint32_t)a << 32) | (uint32_t)b);
+            double v[3] = {0.0, 0.0, 0.0};
+            if (it != pairs.end()) for (int d = 0; d < 3; ++d) v[d] = xi[3 * it->second + d];
+            for (int d = 0; d < 3; ++d) H.xi[d * plane + slot] = v[d];
+            if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) m |= 1ull << q;
+        }
+        auto w = walls.find(H.ids[i]);
+        double v[3] = {0.0, 0.0, 0.0};
+        if (w != walls.end()) for (int d = 0; d < 3; ++d) v[d] = wall_xi[3 * w->second + d];
+        for (int d = 0; d < 3; ++d) H.xiw[d * n + i] = v[d];
+        if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) m |= kWallBit;
+        H.mask[i] = m;
+    }
+    const List &L = c->lists[c->cur];
+    HIPCALL(c, hipMemcpy(L.xi, H.xi.data(), 3 * K * n * 8, hipMemcpyHostToDevice));
+    HIPCALL(c, hipMemcpy(L.mask, H.mask.data(), n * 8, hipMemcpyHostToDevice));
+    HIPCALL(c, hipMemcpy(c->ws + c->lay.xiw, H.xiw.data(), 3 * n * 8, hipMemcpyHostToDevice));
+    return DEM_OK;
+}
+
+const char *dem_last_error(const dem_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+int dem_destroy(dem_ctx *c) {
+    if (!c) return DEM_ERR_ARG;
+    for (GraphSlot &g : c->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    delete c;
+    return DEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,44 @@
+// dem_kernels.h -- kernel arguments and launchers of libdem.so (internal).
+#pragma once
+
+#include "dem_core.h"
+
+namespace dem {
+
+// Everything a kernel may touch, passed by value.
+struct KArgs {
+    // caller-owned particle arrays
+    double *x, *v, *w, *f, *t, *r;
+    int32_t *type, *id;
+    // library-owned per-particle arrays (workspace)
+    double *m, *inv_m, *inv_I, *disp, *xiw;
+    int32_t *frame;        // index of each particle in the order of the last list build
+    // systems
+    const SysDesc *sys;
+    const PairCoef *coef;
+    const double *rho;     // per type, all systems
+    int32_t nsys;
+    int32_t kmax;
+    int32_t block;
+    int32_t pad;
+    int64_t n;             // particles, all systems
+    int64_t ncell;         // cells, all systems
+    Flags *flags;
+    List cur, old;         // current list and the one before it
+    // binning scratch
+    int32_t *cell_of, *rank, *cell_count, *cell_start, *scan_partial, *order;
+    double *shadow_d;      // [25][n]
+    int32_t *shadow_i;     // [3][n]
+};
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t st);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
+hipError_t launch_ctrl(Flags *f, int op, int64_t value, hipStream_t st);
+hipError_t launch_init_mass(const KArgs &a, hipStream_t st);
+hipError_t launch_phase(const KArgs &a, int phase, int k, int gate, hipStream_t st);
+hipError_t launch_forces(const KArgs &a, int update, int k, int gate, int count, hipStream_t st);
+hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st);
+hipError_t launch_neighbors(const KArgs &a, int have_old, hipStream_t st);
+
+}  // namespace dem

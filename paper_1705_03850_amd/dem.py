@@ -1,0 +1,304 @@
+"""ctypes binding of libdem.so (include/dem.h).
+
+Argument marshalling only: every step of the DEM pipeline runs in the HIP
+kernels of ``libdem.so``.  PyTorch provides the device memory (particle
+arrays and the one workspace buffer) and the stream.  Loading fails loudly
+when the library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdem.so")
+
+DEM_OK, DEM_ERR_ARG, DEM_ERR_CAPACITY, DEM_ERR_DOMAIN, DEM_ERR_NONFINITE, DEM_ERR_HIP, DEM_ERR_STATE = range(7)
+ERROR_NAMES = {1: "DEM_ERR_ARG", 2: "DEM_ERR_CAPACITY", 3: "DEM_ERR_DOMAIN", 4: "DEM_ERR_NONFINITE",
+               5: "DEM_ERR_HIP", 6: "DEM_ERR_STATE"}
+MAX_TYPES = 4
+
+
+class DemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("nu", ctypes.c_double), ("rho", ctypes.c_double),
+                ("e", ctypes.c_double), ("mu", ctypes.c_double)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("ntypes", ctypes.c_int32), ("mat", Material * MAX_TYPES), ("dt", ctypes.c_double),
+                ("g", ctypes.c_double * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("periodic", ctypes.c_int32 * 3), ("wall_z0", ctypes.c_int32), ("skin", ctypes.c_double),
+                ("cell", ctypes.c_double), ("r_max", ctypes.c_double), ("n", ctypes.c_int64),
+                ("k_max", ctypes.c_int32), ("block", ctypes.c_int32)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "v", "w", "f", "t", "r", "type", "id")]
+
+
+_lib = None
+_SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_batch_init", "dem_reset", "dem_bin",
+            "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_set_step_options", "dem_check",
+            "dem_stats", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
+            "dem_last_error", "dem_destroy"]
+
+
+def load(path: str = LIB_PATH):
+    """Load libdem.so and declare its C signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() or paper_1705_03850_amd/build.py")
+    L = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER
+    L.dem_workspace_size.argtypes = [P(Config), P(ctypes.c_size_t)]
+    L.dem_batch_workspace_size.argtypes = [i32, P(Config), P(ctypes.c_size_t)]
+    L.dem_init.argtypes = [P(vp), P(Config), vp, ctypes.c_size_t, vp]
+    L.dem_batch_init.argtypes = [P(vp), i32, P(Config), vp, ctypes.c_size_t, vp]
+    for name in ("dem_reset", "dem_bin", "dem_neighbors"):
+        getattr(L, name).argtypes = [vp, P(State)]
+    L.dem_forces.argtypes = [vp, P(State), ctypes.c_int]
+    L.dem_integrate.argtypes = [vp, P(State), ctypes.c_int]
+    L.dem_step.argtypes = [vp, P(State), i64]
+    L.dem_set_step_options.argtypes = [vp, ctypes.c_int, i32]
+    L.dem_check.argtypes = [vp, P(i64)]
+    L.dem_stats.argtypes = [vp, P(i64)]
+    ip, dp = P(i32), P(ctypes.c_double)
+    L.dem_export_neighbors.argtypes = [vp, P(State), ip, ip, i64, P(i64)]
+    L.dem_export_contacts.argtypes = [vp, P(State), ip, ip, dp, i64, P(i64)]
+    L.dem_export_wall.argtypes = [vp, P(State), ip, dp, i64, P(i64)]
+    L.dem_import_history.argtypes = [vp, P(State), i64, ip, ip, dp, i64, ip, dp]
+    L.dem_last_error.argtypes = [vp]
+    L.dem_last_error.restype = ctypes.c_char_p
+    L.dem_destroy.argtypes = [vp]
+    for name in _SYMBOLS:
+        if name != "dem_last_error":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def symbols():
+    return list(_SYMBOLS)
+
+
+def make_config(system, k_max: int = 32, block: int = 0, cell: float = 0.0, skin: float | None = None) -> Config:
+    """dem_config of one workload system (inputs.workloads.System)."""
+    c = Config()
+    mats = system.materials
+    if not 1 <= len(mats) <= MAX_TYPES:
+        raise ValueError("1..4 material types")
+    c.ntypes = len(mats)
+    for t, m in enumerate(mats):
+        c.mat[t].E, c.mat[t].nu, c.mat[t].rho, c.mat[t].e, c.mat[t].mu = m.E, m.nu, m.rho, m.e, m.mu
+    c.dt = system.dt
+    for a in range(3):
+        c.g[a] = system.g[a]
+        c.lo[a] = system.lo[a]
+        c.hi[a] = system.hi[a]
+        c.periodic[a] = int(system.periodic[a])
+    c.wall_z0 = int(system.wall_z0)
+    c.skin = system.skin if skin is None else skin
+    c.cell = cell
+    c.r_max = float(np.max(system.r)) if system.n else 1e-3
+    c.n = system.n
+    c.k_max = k_max
+    c.block = block
+    return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _i32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class DemSystem:
+    """Particles of one or several systems on the GPU plus a libdem context.
+
+    ``systems``: one ``System`` or a list (a batch; the systems are concatenated
+    and ids are made unique by adding each system's offset).
+    """
+
+    def __init__(self, systems, k_max: int = 32, block: int = 0, cell=0.0, skin=None, device: str = "cuda",
+                 use_graph: bool = False, chunk: int = 64):
+        import torch
+
+        self.torch = torch
+        self.L = load()
+        if not isinstance(systems, (list, tuple)):
+            systems = [systems]
+        self.systems = list(systems)
+        self.nsys = len(self.systems)
+        cells = cell if isinstance(cell, (list, tuple)) else [cell] * self.nsys
+        skins = skin if isinstance(skin, (list, tuple)) else [skin] * self.nsys
+        self.cfgs = (Config * self.nsys)(*[make_config(s, k_max, block, cells[k], skins[k])
+                                          for k, s in enumerate(self.systems)])
+        self.counts = [s.n for s in self.systems]
+        self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
+        self.n = int(self.offsets[-1])
+        self.id_offset = np.repeat(self.offsets[:-1], self.counts).astype(np.int64)
+        self.device = torch.device(device)
+        # a stream of our own (default priority): graph capture needs a non-default stream
+        self.stream = torch.cuda.Stream(self.device)
+        ws = ctypes.c_size_t()
+        self._rc(self.L.dem_batch_workspace_size(self.nsys, self.cfgs, ctypes.byref(ws)))
+        self.ws_bytes = ws.value
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.ctx = ctypes.c_void_p()
+        self._rc(self.L.dem_batch_init(ctypes.byref(self.ctx), self.nsys, self.cfgs, ctypes.c_void_p(self.ws_ptr),
+                                       ctypes.c_size_t(self.ws_bytes), ctypes.c_void_p(self.stream.cuda_stream)))
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.x = torch.empty((3, self.n), **f64)
+        self.v = torch.empty((3, self.n), **f64)
+        self.w = torch.empty((3, self.n), **f64)
+        self.f = torch.zeros((3, self.n), **f64)
+        self.t = torch.zeros((3, self.n), **f64)
+        self.r = torch.empty(self.n, **f64)
+        self.type = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        self.id = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        self.load_state()
+        self._state = State(*[_ptr(t) for t in (self.x, self.v, self.w, self.f, self.t, self.r, self.type, self.id)])
+        self._rc(self.L.dem_set_step_options(self.ctx, int(use_graph), int(chunk)))
+        self.reset()
+
+    # ------------------------------------------------------------ helpers
+    def _rc(self, rc):
+        if rc != DEM_OK:
+            msg = self.L.dem_last_error(getattr(self, "ctx", None) or None)
+            raise DemError(rc, (msg or b"").decode())
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                self.torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            self.L.dem_destroy(ctx)
+            self.ctx = None
+
+    def load_state(self, x=None, v=None, w=None, f=None, t=None):
+        """Copy host arrays ((n,3) rows in system order, ids from the systems) to the device."""
+        torch = self.torch
+        cat = lambda k: np.concatenate([getattr(s, k) for s in self.systems])  # noqa: E731
+        x = cat("x") if x is None else x
+        v = cat("v") if v is None else v
+        w = cat("w") if w is None else w
+        self.x.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(x, np.float64).T)))
+        self.v.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(v, np.float64).T)))
+        self.w.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(w, np.float64).T)))
+        if f is not None:
+            self.f.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(f, np.float64).T)))
+        if t is not None:
+            self.t.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(t, np.float64).T)))
+        self.r.copy_(torch.from_numpy(cat("r").astype(np.float64)))
+        self.type.copy_(torch.from_numpy(cat("type").astype(np.int32)))
+        gid = cat("id").astype(np.int64) + self.id_offset
+        self.id.copy_(torch.from_numpy(gid.astype(np.int32)))
+        torch.cuda.synchronize(self.device)
+
+    @property
+    def state(self):
+        return self._state
+
+    # ------------------------------------------------------------ the ABI
+    def reset(self):
+        self._rc(self.L.dem_reset(self.ctx, self._state))
+
+    def bin(self):
+        self._rc(self.L.dem_bin(self.ctx, self._state))
+
+    def neighbors(self):
+        self._rc(self.L.dem_neighbors(self.ctx, self._state))
+
+    def build_list(self):
+        self.bin()
+        self.neighbors()
+
+    def forces(self, update_history: bool = False):
+        self._rc(self.L.dem_forces(self.ctx, self._state, int(update_history)))
+
+    def integrate(self, phase: int):
+        self._rc(self.L.dem_integrate(self.ctx, self._state, int(phase)))
+
+    def step(self, nsteps: int):
+        self._rc(self.L.dem_step(self.ctx, self._state, int(nsteps)))
+
+    def set_step_options(self, use_graph: bool, chunk: int = 64):
+        self._rc(self.L.dem_set_step_options(self.ctx, int(use_graph), int(chunk)))
+
+    def prime(self):
+        """Bin, build the list and evaluate the initial forces (history untouched)."""
+        self.build_list()
+        self.forces(False)
+
+    def check(self):
+        info = (ctypes.c_int64 * 4)()
+        rc = self.L.dem_check(self.ctx, info)
+        return rc, list(info)
+
+    def stats(self):
+        out = (ctypes.c_int64 * 5)()
+        self._rc(self.L.dem_stats(self.ctx, out))
+        return dict(steps=out[0], builds=out[1], contacts=out[2], wall_contacts=out[3], slots=out[4])
+
+    # ------------------------------------------------------------ host views (by id)
+    def host(self):
+        """Current state as numpy, rows sorted by (global) id: x, v, w, f, t (n,3), id (n,)."""
+        self.torch.cuda.synchronize(self.device)
+        ids = self.id.cpu().numpy()
+        order = np.argsort(ids, kind="stable")
+        out = {"id": ids[order]}
+        for k in ("x", "v", "w", "f", "t"):
+            out[k] = getattr(self, k).cpu().numpy().T[order].copy()
+        out["r"] = self.r.cpu().numpy()[order]
+        return out
+
+    def export_neighbors(self):
+        cnt = ctypes.c_int64()
+        self._rc(self.L.dem_export_neighbors(self.ctx, self._state, None, None, 0, ctypes.byref(cnt)))
+        a = np.empty(cnt.value, np.int32); b = np.empty(cnt.value, np.int32)
+        self._rc(self.L.dem_export_neighbors(self.ctx, self._state, _i32p(a), _i32p(b), cnt.value, ctypes.byref(cnt)))
+        return a, b
+
+    def export_contacts(self):
+        cnt = ctypes.c_int64()
+        self._rc(self.L.dem_export_contacts(self.ctx, self._state, None, None, None, 0, ctypes.byref(cnt)))
+        a = np.empty(cnt.value, np.int32); b = np.empty(cnt.value, np.int32); xi = np.empty((cnt.value, 3))
+        self._rc(self.L.dem_export_contacts(self.ctx, self._state, _i32p(a), _i32p(b), _dp(xi), cnt.value,
+                                            ctypes.byref(cnt)))
+        return a, b, xi
+
+    def export_wall(self):
+        cnt = ctypes.c_int64()
+        self._rc(self.L.dem_export_wall(self.ctx, self._state, None, None, 0, ctypes.byref(cnt)))
+        a = np.empty(cnt.value, np.int32); xi = np.empty((cnt.value, 3))
+        self._rc(self.L.dem_export_wall(self.ctx, self._state, _i32p(a), _dp(xi), cnt.value, ctypes.byref(cnt)))
+        return a, xi
+
+    def import_history(self, id_i, id_j, xi, wall_id=None, wall_xi=None):
+        id_i = np.ascontiguousarray(id_i, np.int32); id_j = np.ascontiguousarray(id_j, np.int32)
+        xi = np.ascontiguousarray(xi, np.float64).reshape(-1, 3)
+        wall_id = np.zeros(0, np.int32) if wall_id is None else np.ascontiguousarray(wall_id, np.int32)
+        wall_xi = np.zeros((0, 3)) if wall_xi is None else np.ascontiguousarray(wall_xi, np.float64).reshape(-1, 3)
+        self._rc(self.L.dem_import_history(self.ctx, self._state, len(id_i), _i32p(id_i), _i32p(id_j), _dp(xi),
+                                           len(wall_id), _i32p(wall_id), _dp(wall_xi)))

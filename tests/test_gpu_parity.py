@@ -1,0 +1,296 @@
+"""GPU (HIP, gfx950) against the FP64 CPU oracle on the same seeded inputs.
+
+Bars (from the method's arithmetic, see the design notes):
+  * neighbour list and contact set: identical (bit-exact) sets of directed pairs;
+  * history-slot mapping: identical pair sets, xi_ji == -xi_ij bit for bit;
+  * forces after one evaluation: |dF_i| <= 1e-12 sum_j |F_ij| per particle;
+  * positions after 100 steps: max |dx| <= 1e-9 max(L).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1705_03850_amd.inputs import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gpu(system, **kw):
+    from paper_1705_03850_amd import dem
+    return dem.DemSystem(system, **kw)
+
+
+def directed(lo, hi, xi=None):
+    a = np.concatenate([lo, hi]); b = np.concatenate([hi, lo])
+    order = np.lexsort((b, a))
+    if xi is None:
+        return a[order], b[order]
+    x = np.concatenate([xi, -xi])
+    return a[order], b[order], x[order]
+
+
+def force_scale(o, n, ids, mass):
+    """Per particle: m|g| + sum over its contacts of |F_ij| (oracle records)."""
+    rec = o.records()
+    pos = {int(v): k for k, v in enumerate(ids)}
+    s = mass * 9.81
+    for lo, hi, fm in zip(rec["lo"], rec["hi"], rec["fmag"]):
+        s[pos[int(lo)]] += fm
+        if hi >= 0:
+            s[pos[int(hi)]] += fm
+    return s
+
+
+def by_id(system, arr):
+    order = np.argsort(system.id, kind="stable")
+    return arr[order]
+
+
+def load_oracle_state(g, system, o):
+    """Put the oracle's state and history into the GPU context."""
+    st = o.state()
+    g.load_state(x=st["x"], v=st["v"], w=st["w"], f=st["f"], t=st["t"])
+    g.reset()
+    g.build_list()
+    lo, hi, xi = o.history()
+    a, b, x = directed(lo, hi, xi)
+    wid, wxi = o.wall_history()
+    g.import_history(a, b, x, wid, wxi)
+
+
+def compare_forces(g, system, o, tol=1e-12):
+    h = g.host()
+    st = o.state()
+    m, _ = o.mass()
+    scale = by_id(system, force_scale(o, system.n, system.id, m.copy()))
+    F = by_id(system, st["f"]); T = by_id(system, st["t"])
+    dF = np.linalg.norm(h["f"] - F, axis=1)
+    dT = np.linalg.norm(h["t"] - T, axis=1)
+    r = by_id(system, system.r)
+    assert np.all(dF <= tol * scale), (dF / scale).max()
+    assert np.all(dT <= tol * scale * r), (dT / (scale * r)).max()
+    return float(np.mean(dF == 0.0))
+
+
+# --------------------------------------------------------------------------
+
+def test_neighbor_list_bitexact_plain():
+    s = W.plain_fcc()
+    g = gpu(s)
+    g.build_list()
+    a, b = g.export_neighbors()
+    o = O.Oracle(s)
+    lo, hi = o.pairs(s.skin, brute=True)
+    ea, eb = directed(lo, hi)
+    assert len(a) > 20000
+    assert np.array_equal(a, ea) and np.array_equal(b, eb)
+
+
+def test_neighbor_list_bitexact_bed():
+    s = W.settled_bed(seed=7, n=20000, footprint=80e-3 * np.sqrt(0.02))
+    g = gpu(s)
+    g.build_list()
+    a, b = g.export_neighbors()
+    o = O.Oracle(s)
+    lo, hi = o.pairs(s.skin, brute=False)
+    ea, eb = directed(lo, hi)
+    assert np.array_equal(a, ea) and np.array_equal(b, eb)
+
+
+def test_forces_first_evaluation_bed():
+    """Settled bed: contacts from the start, zero history; one force evaluation."""
+    s = W.settled_bed(seed=8, n=20000, footprint=80e-3 * np.sqrt(0.02))
+    g = gpu(s)
+    g.prime()
+    o = O.Oracle(s)
+    o.forces(False)
+    exact = compare_forces(g, s, o)
+    print("bitwise-equal force fraction", exact)
+
+
+@pytest.mark.parametrize("k", [10, 50, 100])
+def test_resumed_step_parity(k):
+    """From oracle-dumped states (positions, velocities, forces, history) one more
+    step on both sides: forces, contact set and history mapping."""
+    s = W.plain_fcc()
+    o = O.Oracle(s)
+    o.forces(False)
+    o.step(k)
+    g = gpu(s)
+    load_oracle_state(g, s, o)
+    # the imported history is the oracle's, slot for slot
+    ca, cb, cx = g.export_contacts()
+    lo, hi, xi = o.history()
+    ea, eb, ex = directed(lo, hi, xi)
+    assert np.array_equal(ca, ea) and np.array_equal(cb, eb)
+    assert np.array_equal(cx, ex)
+    g.step(1)
+    o.step(1)
+    compare_forces(g, s, o)
+    ca, cb, cx = g.export_contacts()
+    lo, hi, xi = o.history()
+    ea, eb, ex = directed(lo, hi, xi)
+    assert len(ca) > 100
+    assert np.array_equal(ca, ea) and np.array_equal(cb, eb)
+    scale = np.maximum(np.abs(ex).max(), 1e-300)
+    assert np.max(np.abs(cx - ex)) <= 1e-12 * scale
+    wa, wx = g.export_wall()
+    wo, wox = o.wall_history()
+    assert np.array_equal(wa, wo)
+    if len(wo):
+        assert np.max(np.abs(wx - wox)) <= 1e-12 * max(np.abs(wox).max(), 1e-300)
+
+
+@pytest.mark.parametrize("skin", [0.1e-3, 2e-6])
+def test_hundred_steps_positions(skin):
+    """100 independent steps from the same start.  The small skin forces list
+    rebuilds (history carried by id) every few steps; the result may not depend
+    on when the list is rebuilt."""
+    s = W.plain_fcc()
+    s.skin = skin
+    g = gpu(s)
+    g.prime()
+    g.step(100)
+    o = O.Oracle(s)
+    o.forces(False)
+    o.step(100)
+    h = g.host()
+    st = o.state()
+    X = by_id(s, st["x"])
+    d = h["x"] - X
+    d[:, :2] -= 20e-3 * np.round(d[:, :2] / 20e-3)
+    assert np.max(np.abs(d)) <= 1e-9 * 60e-3
+    stats = g.stats()
+    if skin < 1e-5:
+        assert stats["builds"] > 5
+    ca, cb, cx = g.export_contacts()
+    lo, hi, xi = o.history()
+    ea, eb, ex = directed(lo, hi, xi)
+    assert np.array_equal(ca, ea) and np.array_equal(cb, eb)
+    assert np.max(np.abs(cx - ex)) <= 1e-9 * max(np.abs(ex).max(), 1e-300)
+
+
+def test_history_antisymmetric_bitwise():
+    s = W.plain_fcc()
+    g = gpu(s)
+    g.prime()
+    g.step(300)
+    a, b, x = g.export_contacts()
+    assert len(a) > 100
+    key = {(int(p), int(q)): k for k, (p, q) in enumerate(zip(a, b))}
+    for k, (p, q) in enumerate(zip(a, b)):
+        j = key[(int(q), int(p))]
+        assert np.array_equal(x[j], -x[k])
+
+
+def test_momentum_conserved_gpu():
+    s = W.plain_fcc()
+    s.periodic = (1, 1, 1); s.hi = (20e-3, 20e-3, 40e-3); s.wall_z0 = 0; s.g = (0.0, 0.0, 0.0)
+    g = gpu(s)
+    g.prime()
+    h0 = g.host()
+    m = 4.0 / 3.0 * np.pi * 2500.0 * 1e-9
+    p0 = (m * h0["v"]).sum(axis=0)
+    g.step(1000)
+    h1 = g.host()
+    p1 = (m * h1["v"]).sum(axis=0)
+    scale = np.sum(m * np.linalg.norm(h1["v"], axis=1))
+    assert np.max(np.abs(p1 - p0)) < 1e-14 * scale
+
+
+def test_deterministic_and_order_independent():
+    """Same input twice, and the same particles in another storage order: the
+    physics (by id) is identical bit for bit."""
+    s = W.plain_fcc()
+    outs = []
+    for perm_seed in (None, None, 5):
+        t = s.copy()
+        if perm_seed is not None:
+            p = np.random.default_rng(perm_seed).permutation(s.n)
+            t.x, t.v, t.w, t.r, t.type, t.id = t.x[p], t.v[p], t.w[p], t.r[p], t.type[p], t.id[p]
+        g = gpu(t)
+        g.prime()
+        g.step(200)
+        outs.append(g.host())
+    for o in outs[1:]:
+        for k in ("x", "v", "w", "f", "t"):
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
+def test_launch_options_do_not_change_results():
+    """Block size, cell size, skin and graph replay change the schedule, not the
+    results (rows are summed in id order, history follows ids)."""
+    s = W.plain_fcc()
+    ref = None
+    for kw in (dict(), dict(block=64), dict(block=256, cell=5e-3), dict(skin=30e-6),
+               dict(use_graph=True, chunk=16)):
+        g = gpu(s, **kw)
+        g.prime()
+        g.step(150)
+        h = g.host()
+        if ref is None:
+            ref = h
+        for k in ("x", "v", "w", "f", "t"):
+            assert np.array_equal(h[k], ref[k]), (kw, k)
+
+
+def test_batch_equals_separate_systems():
+    """Two systems of different coarse-grain factor in one context evolve exactly
+    as each alone (Sec. 2.3 levels as a batch)."""
+    a = W.plain_fcc()
+    b = W.plain_fcc(seed=9)
+    b.x = b.x * 2.0; b.r = b.r * 2.0; b.hi = tuple(2 * q for q in b.hi); b.skin *= 2; b.dt *= 2
+    bg = gpu([a, b])
+    bg.prime()
+    bg.step(120)
+    hb = bg.host()
+    for k, s in enumerate((a, b)):
+        g = gpu(s)
+        g.prime()
+        g.step(120)
+        h = g.host()
+        sl = slice(int(bg.offsets[k]), int(bg.offsets[k + 1]))
+        for key in ("x", "v", "w", "f", "t"):
+            assert np.array_equal(hb[key][sl], h[key]), (k, key)
+
+
+def test_capacity_error_reported():
+    from paper_1705_03850_amd import dem
+    s = W.plain_fcc()
+    g = gpu(s, k_max=4)
+    with pytest.raises(dem.DemError) as e:
+        g.build_list()
+        g.forces(False)
+        rc, info = g.check()
+        g._rc(rc)
+    assert e.value.code == dem.DEM_ERR_CAPACITY
+    rc, info = g.check()
+    assert info[1] >= 12                      # the k_max a retry needs
+
+
+def test_nonfinite_reported():
+    from paper_1705_03850_amd import dem
+    s = W.plain_fcc()
+    s.v = s.v.copy(); s.v[17, 1] = np.nan
+    g = gpu(s)
+    g.prime()
+    with pytest.raises(dem.DemError) as e:
+        g.step(3)
+    assert e.value.code == dem.DEM_ERR_NONFINITE
+
+
+def test_bad_type_rejected():
+    from paper_1705_03850_amd import dem
+    s = W.plain_fcc()
+    s.type = s.type.copy(); s.type[3] = 2
+    with pytest.raises(dem.DemError) as e:
+        gpu(s)
+    assert e.value.code == dem.DEM_ERR_ARG

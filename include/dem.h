@@ -170,6 +170,17 @@ int dem_step(dem_ctx *ctx, const dem_state *s, int64_t nsteps);
  * captured HIP graph of `chunk` steps (chunk even, 2..1024; default 64). */
 int dem_set_step_options(dem_ctx *ctx, int use_graph, int32_t chunk);
 
+/* Per-kernel timing for measurement.  With enable != 0, dem_step launches
+ * its kernels one by one (no graph replay) and brackets each with a pair of
+ * HIP events on the context's stream (events are created on first use and
+ * released by dem_destroy); enabling or disabling clears the totals. */
+int dem_set_timing(dem_ctx *ctx, int enable);
+
+/* Accumulated GPU time (ms) and launch count of each timed kernel class since
+ * timing was enabled: [0] phase 0 (kick, drift), [1] forces, [2] phase 1
+ * (kick), [3] list rebuild (bin + neighbours).  Synchronises. */
+int dem_kernel_times(dem_ctx *ctx, double ms[4], int64_t launches[4]);
+
 /* Synchronise and report the sticky device flags.  info[0] = error bits
  * (1 capacity, 2 non-finite), info[1] = largest neighbour row seen (the k_max
  * a retry needs), info[2] = list builds so far, info[3] = steps so far.

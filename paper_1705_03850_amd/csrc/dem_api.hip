@@ -160,6 +160,8 @@ Layout make_layout(const Geometry &g) {
     return L;
 }
 
+constexpr int kKinds = 4;  // timed kernel classes: phase 0, forces, phase 1, list rebuild
+
 struct GraphSlot {
     hipGraphExec_t exec = nullptr;
     const void *key[10] = {nullptr};
@@ -188,6 +190,13 @@ struct dem_ctx {
     bool use_graph = false, count = true;
     int chunk = 64;
     GraphSlot graphs[2];
+    // per-kernel timing with HIP events (non-graph stepping only)
+    bool timing = false;
+    std::vector<hipEvent_t> ev;      // pairs (start, stop) recorded in this chunk
+    std::vector<int> ev_kind;        // kernel class of each pair
+    int ev_used = 0;
+    double t_ms[kKinds] = {0, 0, 0, 0};
+    int64_t t_n[kKinds] = {0, 0, 0, 0};
     std::string err;
 };
 
@@ -288,6 +297,41 @@ int do_neighbors(dem_ctx *c, const dem_state *s) {
     c->have_list = true;
     c->list_current = true;
     c->frame_identity = true;
+    return DEM_OK;
+}
+
+// Event pair around the next launch(es) of class `kind` when timing is on.
+int tic(dem_ctx *c, int kind) {
+    if (!c->timing) return DEM_OK;
+    if ((size_t)(2 * c->ev_used + 2) > c->ev.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            HIPCALL(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+        c->ev_kind.resize(c->ev.size() / 2);
+    }
+    c->ev_kind[c->ev_used] = kind;
+    HIPCALL(c, hipEventRecord(c->ev[2 * c->ev_used], c->stream));
+    return DEM_OK;
+}
+
+int toc(dem_ctx *c) {
+    if (!c->timing) return DEM_OK;
+    HIPCALL(c, hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream));
+    ++c->ev_used;
+    return DEM_OK;
+}
+
+// After a synchronisation: fold the recorded pairs into the totals.
+int collect_times(dem_ctx *c) {
+    for (int k = 0; k < c->ev_used; ++k) {
+        float ms = 0.0f;
+        HIPCALL(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+        c->t_ms[c->ev_kind[k]] += ms;
+        c->t_n[c->ev_kind[k]] += 1;
+    }
+    c->ev_used = 0;
     return DEM_OK;
 }
 
@@ -463,7 +507,7 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
         const int64_t m = std::min<int64_t>(c->chunk, nsteps - done);
         HIPCALL(c, launch_ctrl(c->d_flags, 0, c->step_counter, c->stream));
         KArgs a = kargs(c, s);
-        if (c->use_graph && m == c->chunk) {
+        if (c->use_graph && !c->timing && m == c->chunk) {
             GraphSlot &gs = c->graphs[c->cur];
             const void *key[10] = {s->x, s->v, s->w, s->f, s->t, s->r, s->type, s->id, c->lists[c->cur].nbr, nullptr};
             if (!gs.exec || memcmp(gs.key, key, sizeof key) || gs.chunk != c->chunk || gs.count != (c->count ? 1 : 0)) {
@@ -472,21 +516,31 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
             HIPCALL(c, hipGraphLaunch(gs.exec, c->stream));
         } else {
             for (int64_t k = 0; k < m; ++k) {
+                if ((rc = tic(c, 0))) return rc;
                 HIPCALL(c, launch_phase(a, 0, (int)k, 1, c->stream));
+                if ((rc = toc(c)) || (rc = tic(c, 1))) return rc;
                 HIPCALL(c, launch_forces(a, 1, (int)k, 1, c->count ? 1 : 0, c->stream));
+                if ((rc = toc(c)) || (rc = tic(c, 2))) return rc;
                 HIPCALL(c, launch_phase(a, 1, (int)k, 1, c->stream));
+                if ((rc = toc(c))) return rc;
             }
         }
         if ((rc = read_flags(c, h))) return rc;
+        if ((rc = collect_times(c))) return rc;
         if ((rc = flag_error(c, h))) return rc;
         if (h.abort_at != INT64_MAX) {
             // step abort_at has drifted; rebuild, then finish it
             const int64_t k = h.abort_at - c->step_counter;
             c->binned = false;
+            if ((rc = tic(c, 3))) return rc;
             if ((rc = do_bin(c, s)) || (rc = do_neighbors(c, s))) return rc;
+            if ((rc = toc(c))) return rc;
             KArgs b = kargs(c, s);
+            if ((rc = tic(c, 1))) return rc;
             HIPCALL(c, launch_forces(b, 1, 0, 0, c->count ? 1 : 0, c->stream));
+            if ((rc = toc(c)) || (rc = tic(c, 2))) return rc;
             HIPCALL(c, launch_phase(b, 1, 0, 0, c->stream));
+            if ((rc = toc(c))) return rc;
             HIPCALL(c, launch_ctrl(c->d_flags, 3, 1, c->stream));
             done += k + 1;
             c->step_counter += k + 1;
@@ -496,9 +550,27 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
         }
     }
     if ((rc = read_flags(c, h))) return rc;
+    if ((rc = collect_times(c))) return rc;
     c->binned = false;
     c->forces_valid = true;
     return flag_error(c, h);
+}
+
+int dem_set_timing(dem_ctx *c, int enable) {
+    if (!c) return DEM_ERR_ARG;
+    c->timing = enable != 0;
+    for (int k = 0; k < kKinds; ++k) { c->t_ms[k] = 0.0; c->t_n[k] = 0; }
+    c->ev_used = 0;
+    return DEM_OK;
+}
+
+int dem_kernel_times(dem_ctx *c, double ms[4], int64_t launches[4]) {
+    if (!c || !ms || !launches) return DEM_ERR_ARG;
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    int rc = collect_times(c);
+    if (rc) return rc;
+    for (int k = 0; k < kKinds; ++k) { ms[k] = c->t_ms[k]; launches[k] = c->t_n[k]; }
+    return DEM_OK;
 }
 
 int dem_check(dem_ctx *c, int64_t info[4]) {
@@ -711,6 +783,7 @@ const char *dem_last_error(const dem_ctx *c) { return c ? c->err.c_str() : g_ini
 
 int dem_destroy(dem_ctx *c) {
     if (!c) return DEM_ERR_ARG;
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (GraphSlot &g : c->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     delete c;

@@ -47,7 +47,7 @@ class State(ctypes.Structure):
 _lib = None
 _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_batch_init", "dem_reset", "dem_bin",
             "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_set_step_options", "dem_check",
-            "dem_stats", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
+            "dem_stats", "dem_set_timing", "dem_kernel_times", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
             "dem_last_error", "dem_destroy"]
 
 
@@ -73,6 +73,8 @@ def load(path: str = LIB_PATH):
     L.dem_set_step_options.argtypes = [vp, ctypes.c_int, i32]
     L.dem_check.argtypes = [vp, P(i64)]
     L.dem_stats.argtypes = [vp, P(i64)]
+    L.dem_set_timing.argtypes = [vp, ctypes.c_int]
+    L.dem_kernel_times.argtypes = [vp, P(ctypes.c_double), P(i64)]
     ip, dp = P(i32), P(ctypes.c_double)
     L.dem_export_neighbors.argtypes = [vp, P(State), ip, ip, i64, P(i64)]
     L.dem_export_contacts.argtypes = [vp, P(State), ip, ip, dp, i64, P(i64)]
@@ -250,6 +252,16 @@ class DemSystem:
         """Bin, build the list and evaluate the initial forces (history untouched)."""
         self.build_list()
         self.forces(False)
+
+    def set_timing(self, enable: bool):
+        self._rc(self.L.dem_set_timing(self.ctx, int(enable)))
+
+    def kernel_times(self):
+        """{class: (total ms, launches)} for phase0, forces, phase1, rebuild."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        self._rc(self.L.dem_kernel_times(self.ctx, ms, n))
+        return {k: (ms[q], n[q]) for q, k in enumerate(("phase0", "forces", "phase1", "rebuild"))}
 
     def check(self):
         info = (ctypes.c_int64 * 4)()

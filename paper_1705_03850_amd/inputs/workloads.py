@@ -204,8 +204,46 @@ def bed(n: int, r: np.ndarray, Lx: float, Ly: float, rng: np.random.Generator, o
     return pos, stuck
 
 
-def settled_bed(seed: int = 2, n: int = 1_000_000, footprint: float = 80e-3) -> System:
-    """N spheres, r ~ U[0.8, 1.2] mm, on a periodic square footprint, settled by deposition."""
+def _cache_path(name: str) -> str | None:
+    d = os.environ.get("DEM_INPUT_CACHE", "/tmp/dem_input_cache")
+    try:
+        os.makedirs(d, exist_ok=True)
+    except OSError:
+        return None
+    src = open(os.path.join(_HERE, "deposit.c"), "rb").read() + open(os.path.abspath(__file__), "rb").read()
+    import hashlib
+    tag = hashlib.sha256(src).hexdigest()[:16]
+    return os.path.join(d, f"{name}_{tag}.npz")
+
+
+def settled_bed(seed: int = 2, n: int = 1_000_000, footprint: float = 80e-3, cache: bool = True) -> System:
+    """N spheres, r ~ U[0.8, 1.2] mm, on a periodic square footprint, settled by deposition.
+
+    Deposition of 1e6 spheres takes ~20 s, so the result is kept in a cache
+    file keyed by the arguments and a hash of the generator sources."""
+    path = _cache_path(f"bed_{seed}_{n}_{footprint!r}") if cache else None
+    if path and os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            pos, r, ids, stuck = z["x"], z["r"], z["id"], int(z["stuck"])
+        return _bed_system(pos, r, ids, footprint, n, stuck)
+    pos, r, ids, stuck = _settled_bed_arrays(seed, n, footprint)
+    if path:
+        tmp = path + f".{os.getpid()}.tmp.npz"
+        np.savez(tmp, x=pos, r=r, id=ids, stuck=stuck)
+        os.replace(tmp, path)
+    return _bed_system(pos, r, ids, footprint, n, stuck)
+
+
+def _bed_system(pos, r, ids, footprint, n, stuck):
+    rmax = 1.2e-3
+    top = float(pos[:, 2].max()) + 4.0 * rmax
+    return System(x=pos, v=np.zeros((n, 3)), w=np.zeros((n, 3)), r=r, type=np.zeros(n, np.int32), id=ids,
+                  materials=[MAT_A], lo=(0.0, 0.0, 0.0), hi=(footprint, footprint, top), periodic=(1, 1, 0),
+                  wall_z0=1, g=(0.0, 0.0, -G0), dt=1e-6, skin=0.1 * rmax, steps=10_000,
+                  name=f"settled_bed_{n}", meta={"deposit_stuck": stuck})
+
+
+def _settled_bed_arrays(seed, n, footprint):
     rng = np.random.default_rng(seed)
     r = rng.uniform(0.8e-3, 1.2e-3, n)
     pos, stuck = bed(n, r, footprint, footprint, rng)
@@ -215,12 +253,7 @@ def settled_bed(seed: int = 2, n: int = 1_000_000, footprint: float = 80e-3) -> 
     perm = rng.permutation(n)
     pos = pos[perm]; r = r[perm]
     ids = perm.astype(np.int32)
-    rmax = 1.2e-3
-    top = float(pos[:, 2].max()) + 4.0 * rmax
-    return System(x=pos, v=np.zeros((n, 3)), w=np.zeros((n, 3)), r=r, type=np.zeros(n, np.int32), id=ids,
-                  materials=[MAT_A], lo=(0.0, 0.0, 0.0), hi=(footprint, footprint, top), periodic=(1, 1, 0),
-                  wall_z0=1, g=(0.0, 0.0, -G0), dt=1e-6, skin=0.1 * rmax, steps=10_000,
-                  name=f"settled_bed_{n}", meta={"deposit_stuck": stuck})
+    return pos, r, ids, stuck
 
 
 # ----------------------------------------------------------------------------

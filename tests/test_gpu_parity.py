@@ -116,7 +116,7 @@ def test_forces_first_evaluation_bed():
     print("bitwise-equal force fraction", exact)
 
 
-@pytest.mark.parametrize("k", [10, 50, 100])
+@pytest.mark.parametrize("k", [50, 100, 300])
 def test_resumed_step_parity(k):
     """From oracle-dumped states (positions, velocities, forces, history) one more
     step on both sides: forces, contact set and history mapping."""
@@ -138,7 +138,7 @@ def test_resumed_step_parity(k):
     ca, cb, cx = g.export_contacts()
     lo, hi, xi = o.history()
     ea, eb, ex = directed(lo, hi, xi)
-    assert len(ca) > 100
+    assert len(ca) > 100                      # the state has contacts (the lattice starts gapped)
     assert np.array_equal(ca, ea) and np.array_equal(cb, eb)
     scale = np.maximum(np.abs(ex).max(), 1e-300)
     assert np.max(np.abs(cx - ex)) <= 1e-12 * scale

@@ -29,17 +29,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s and contact-pairs/s (FP64) vs HBM roofline; batched & adjoint vs plain"
-PMC_FILE = os.path.join(ROOT, "profiles", "forces_settled_bed_1e6_traffic.txt")
+PMC_FILE = os.path.join(ROOT, "profiles", "step_settled_bed_1e6_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1705_03850_amd", "csrc", f) for f in ("dem_kernels.hip", "dem_core.h")]
 
-# Algorithmic bytes (FP64 = 8 B, int32 = 4 B) of each kernel.
-#   forces : per particle x, v, w (72) + r (8) + type (4) read, f, t (48) written = 132 B;
-#            per listed slot its neighbour index (4 B); per directed contact its
-#            tangential history read and written (48 B); per wall contact 48 B.
-#   phase 0: per particle read x, v, w, f, t, disp (144) + 1/m, 1/I (16), write x, v, w, disp (96) = 256 B
-#   phase 1: per particle read v, w, f, t (96) + 1/m, 1/I (16), write v, w (48) = 160 B
-FORCE_PER_PARTICLE, FORCE_PER_SLOT, FORCE_PER_CONTACT, FORCE_PER_WALL = 132, 4, 48, 48
-PHASE0_PER_PARTICLE, PHASE1_PER_PARTICLE = 256, 160
+# Algorithmic bytes (FP64 = 8 B, int32 = 4 B) of the fused step kernel k_step: every array element it
+# must touch, counted once (neighbour re-reads are the cache's business):
+#   per particle: packed position+radius, velocity+mass, spin+type read and written (96 + 96),
+#                 (1/m, 1/I) read (16), displacement read and written (24 + 24),
+#                 row length (4) and history mask (8) read                       = 268 B
+#   per listed slot: its neighbour index (4 B)
+#   per directed contact: its tangential history read and written (48 B)
+#   per wall contact: the wall history read and written (48 B)
+STEP_PER_PARTICLE, STEP_PER_SLOT, STEP_PER_CONTACT, STEP_PER_WALL = 268, 4, 48, 48
 
 
 def log(msg):
@@ -96,6 +97,8 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--max-blocks", type=int, default=0, help="grid cap of the fused step kernel (0 = resident capacity)")
+    ap.add_argument("--lanes", type=int, default=4, help="threads per particle in the force pass (4, 8, 16)")
     ap.add_argument("--timing-steps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -125,6 +128,7 @@ def main():
     log(f"bed ready in {time.perf_counter() - t0:.1f} s (height {bed.x[:, 2].max() * 1e3:.0f} mm)")
 
     g = dem.DemSystem(bed, k_max=32, block=args.block, use_graph=not args.no_graph, chunk=args.chunk)
+    g.set_launch(args.lanes, args.max_blocks)
     g.prime()
     torch.cuda.synchronize()
 
@@ -176,26 +180,21 @@ def main():
     slots = float(g.stats()["slots"])
     contacts_step = (t_s1["contacts"] - t_s0["contacts"]) / tsteps
     walls_step = (t_s1["wall_contacts"] - t_s0["wall_contacts"]) / tsteps
-    bytes_forces = (n * FORCE_PER_PARTICLE + slots * FORCE_PER_SLOT + contacts_step * FORCE_PER_CONTACT
-                    + walls_step * FORCE_PER_WALL)
+    bytes_step = (n * STEP_PER_PARTICLE + slots * STEP_PER_SLOT + contacts_step * STEP_PER_CONTACT
+                  + walls_step * STEP_PER_WALL)
     kernels = {}
-    for name, per_launch_bytes in (("forces", bytes_forces), ("phase0", n * PHASE0_PER_PARTICLE),
-                                   ("phase1", n * PHASE1_PER_PARTICLE)):
+    for name in ("pack", "step", "last", "rebuild"):
         ms, cnt = kt[name]
         if cnt:
-            avg = ms / cnt * 1e-3
-            kernels[name] = {"avg_us": avg * 1e6, "launches": cnt, "alg_bytes": per_launch_bytes,
-                             "GBps": per_launch_bytes / avg / 1e9}
-    if kt["rebuild"][1]:
-        kernels["rebuild"] = {"avg_us": kt["rebuild"][0] / kt["rebuild"][1] * 1e3, "launches": kt["rebuild"][1]}
-    dom = max(("forces", "phase0", "phase1"), key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
-    achieved = kernels[dom]["GBps"]
-    traffic = read_traffic() if dom == "forces" else None
-    roofline = {"bound": "hbm", "kernel": f"k_forces" if dom == "forces" else f"k_{dom}",
+            kernels[name] = {"avg_us": ms / cnt * 1e3, "launches": cnt}
+    kernels["step"]["alg_bytes"] = bytes_step
+    kernels["step"]["GBps"] = bytes_step / (kernels["step"]["avg_us"] * 1e-6) / 1e9
+    achieved = kernels["step"]["GBps"]
+    traffic = read_traffic()
+    roofline = {"bound": "hbm", "kernel": "k_step (fused forces + kick + kick-drift)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "alg_bytes_per_launch": round(kernels[dom]["alg_bytes"]),
-                "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
+                "alg_bytes_per_launch": round(bytes_step), "avg_launch_us": round(kernels["step"]["avg_us"], 2)}
 
     cpu = None
     if not args.no_cpu_baseline:

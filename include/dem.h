@@ -89,7 +89,7 @@ typedef struct dem_config {
     double r_max;                      /* largest particle radius in this system (m)    */
     int64_t n;                         /* particle count, >= 0                          */
     int32_t k_max;                     /* neighbour slots per particle, 1..63           */
-    int32_t block;                     /* threads per block: 64, 128, 256; 0 = 128      */
+    int32_t block;                     /* threads per block: 64, 128, 256; 0 = 256      */
 } dem_config;
 
 /* Caller-owned device arrays of the particles (see Conventions). */
@@ -158,7 +158,11 @@ int dem_integrate(dem_ctx *ctx, const dem_state *s, int phase);
 
 /* nsteps velocity-Verlet steps: phase 0, rebuild (bin + list) when some
  * particle moved more than skin/2 since the last build, forces with history
- * update, phase 1.  The forces in s->f, s->t must belong to the current state
+ * update, phase 1.  The step loop runs on a packed copy of the particles in
+ * the workspace, with one fused kernel per step (forces, kick, and the next
+ * step's kick and drift); the caller's arrays are read at the start and
+ * written at the end.  Results are bit-identical to calling dem_integrate(0),
+ * dem_bin/dem_neighbors when needed, dem_forces(1) and dem_integrate(1).  The forces in s->f, s->t must belong to the current state
  * (call dem_forces(ctx, s, 0) once after dem_reset, or provide them); the
  * library cannot check this.  The rebuild decision is
  * taken on the device; the host learns of it at a synchronisation every few
@@ -176,10 +180,19 @@ int dem_set_step_options(dem_ctx *ctx, int use_graph, int32_t chunk);
  * released by dem_destroy); enabling or disabling clears the totals. */
 int dem_set_timing(dem_ctx *ctx, int enable);
 
-/* Accumulated GPU time (ms) and launch count of each timed kernel class since
- * timing was enabled: [0] phase 0 (kick, drift), [1] forces, [2] phase 1
- * (kick), [3] list rebuild (bin + neighbours).  Synchronises. */
+/* Accumulated GPU time (ms) and launch count of each timed kernel class of
+ * dem_step since timing was enabled: [0] the first kick-drift of a call
+ * (with packing of the caller arrays), [1] the fused step (forces, kick,
+ * next kick-drift), [2] the last step of a call (forces, kick, write-back),
+ * [3] list rebuild (unpack, bin, neighbours, repack).  Synchronises. */
 int dem_kernel_times(dem_ctx *ctx, double ms[4], int64_t launches[4]);
+
+/* Launch shape of the force pass: `lanes` threads per particle (4, 8 or 16,
+ * default 4; a particle's row is split over them) and at most max_blocks
+ * workgroups, each walking several tiles of particles (0 = as many as stay
+ * resident on the device).  The schedule changes, the results do not: the
+ * pair terms of a row are always added in neighbour-id order. */
+int dem_set_launch(dem_ctx *ctx, int32_t lanes, int32_t max_blocks);
 
 /* Synchronise and report the sticky device flags.  info[0] = error bits
  * (1 capacity, 2 non-finite), info[1] = largest neighbour row seen (the k_max

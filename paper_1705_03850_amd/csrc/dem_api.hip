@@ -23,6 +23,7 @@ struct Layout {
     size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame;
     size_t nbr[2], cnt[2], xi[2], mask[2], ids[2];
     size_t cell_of, rank, order, cell_count, cell_start, scan_partial, shadow_d, shadow_i;
+    size_t pos[2], vel[2], spin[2], im;
     size_t total;
 };
 
@@ -40,7 +41,7 @@ double cutoff_of(const dem_config &c) { return 2.0 * c.r_max + c.skin; }
 int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::string &err) {
     if (nsys < 1 || !cfgs) { err = "need at least one system"; return DEM_ERR_ARG; }
     g = Geometry();
-    g.block = cfgs[0].block == 0 ? 128 : cfgs[0].block;
+    g.block = cfgs[0].block == 0 ? 256 : cfgs[0].block;
     if (g.block != 64 && g.block != 128 && g.block != 256) { err = "block must be 64, 128 or 256"; return DEM_ERR_ARG; }
     for (int s = 0; s < nsys; ++s) {
         const dem_config &c = cfgs[s];
@@ -60,7 +61,7 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         if (!(c.r_max > 0.0)) { err = "r_max must be > 0"; return DEM_ERR_ARG; }
         if (c.n < 0) { err = "n must be >= 0"; return DEM_ERR_ARG; }
         if (c.k_max < 1 || c.k_max > kMaxSlots) { err = "k_max must be in 1..63"; return DEM_ERR_ARG; }
-        if ((c.block == 0 ? 128 : c.block) != g.block) { err = "all systems of a batch need the same block size"; return DEM_ERR_ARG; }
+        if ((c.block == 0 ? 256 : c.block) != g.block) { err = "all systems of a batch need the same block size"; return DEM_ERR_ARG; }
         const double cut = cutoff_of(c);
         double h = c.cell > 0.0 ? c.cell : cut;
         if (h < cut) { err = "cell must be >= 2 r_max + skin"; return DEM_ERR_ARG; }
@@ -109,10 +110,14 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
                 double e = (a.e + b.e) / 2.0;
                 double mu = (a.mu + b.mu) / 2.0;
                 double le = std::log(e);
+                const double Es = 1.0 / inv_E, Gs = 1.0 / inv_G;
+                const double beta = le / std::sqrt(le * le + M_PI * M_PI);
                 PairCoef k;
-                k.Es = 1.0 / inv_E;
-                k.Gs = 1.0 / inv_G;
-                k.beta = le / std::sqrt(le * le + M_PI * M_PI);
+                memset(&k, 0, sizeof k);
+                k.kn0 = 4.0 / 3.0 * Es;
+                k.kt0 = 8.0 * Gs;
+                k.gn0 = -beta * std::sqrt(20.0 / 3.0 * Es);
+                k.gt0 = -beta * std::sqrt(80.0 / 3.0 * Gs);
                 k.mu = mu;
                 g.coef.push_back(k);
             }
@@ -144,7 +149,7 @@ Layout make_layout(const Geometry &g) {
     for (int b = 0; b < 2; ++b) {
         L.nbr[b] = take(K * n * 4);
         L.cnt[b] = take(n * 4);
-        L.xi[b] = take(3 * K * n * 8);
+        L.xi[b] = take(K * n * sizeof(D4));
         L.mask[b] = take(n * 8);
         L.ids[b] = take(n * 4);
     }
@@ -156,6 +161,12 @@ Layout make_layout(const Geometry &g) {
     L.scan_partial = take(((C + 1023) / 1024 + 1) * 4);
     L.shadow_d = take(25 * n * 8);
     L.shadow_i = take(3 * n * 4);
+    for (int b = 0; b < 2; ++b) {
+        L.pos[b] = take(n * sizeof(D4));
+        L.vel[b] = take(n * sizeof(D4));
+        L.spin[b] = take(n * sizeof(D4));
+    }
+    L.im = take(n * sizeof(D2));
     L.total = o;
     return L;
 }
@@ -189,6 +200,9 @@ struct dem_ctx {
     // options
     bool use_graph = false, count = true;
     int chunk = 64;
+    int64_t grid_cap = 0;   // 0: resident capacity, set at init
+    int lanes = 4;
+    int cus = 256;
     GraphSlot graphs[2];
     // per-kernel timing with HIP events (non-graph stepping only)
     bool timing = false;
@@ -236,6 +250,10 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.nsys = (int32_t)c->geo.sys.size();
     a.kmax = c->geo.kmax;
     a.block = c->geo.block;
+    // default: as many workgroups as stay resident (3 waves per SIMD), each
+    // walking several tiles; the dispatch of every extra workgroup costs time
+    a.grid_cap = (int32_t)(c->grid_cap > 0 ? c->grid_cap : (int64_t)c->cus * 12 * 64 / c->geo.block);
+    a.lanes = c->lanes;
     a.n = c->geo.n;
     a.ncell = c->geo.ncell;
     a.flags = c->d_flags;
@@ -249,6 +267,12 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.scan_partial = (int32_t *)(w + L.scan_partial);
     a.shadow_d = (double *)(w + L.shadow_d);
     a.shadow_i = (int32_t *)(w + L.shadow_i);
+    for (int b = 0; b < 2; ++b) {
+        a.pos[b] = (D4 *)(w + L.pos[b]);
+        a.vel[b] = (D4 *)(w + L.vel[b]);
+        a.spin[b] = (D4 *)(w + L.spin[b]);
+    }
+    a.im = (D2 *)(w + L.im);
     return a;
 }
 
@@ -335,24 +359,22 @@ int collect_times(dem_ctx *c) {
     return DEM_OK;
 }
 
+// One graph of `chunk` fused steps starting from packed buffer 0 (k = 0..chunk-1).
 int capture_graph(dem_ctx *c, const dem_state *s, GraphSlot &gs) {
     if (gs.exec) { (void)hipGraphExecDestroy(gs.exec); gs.exec = nullptr; }
     KArgs a = kargs(c, s);
     hipGraph_t graph = nullptr;
     HIPCALL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < c->chunk && e == hipSuccess; ++k) {
-        e = launch_phase(a, 0, k, 1, c->stream);
-        if (e == hipSuccess) e = launch_forces(a, 1, k, 1, c->count ? 1 : 0, c->stream);
-        if (e == hipSuccess) e = launch_phase(a, 1, k, 1, c->stream);
-    }
+    for (int k = 0; k < c->chunk && e == hipSuccess; ++k)
+        e = launch_step(a, k & 1, 1, k, 1, c->count ? 1 : 0, c->stream);
     hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch during graph capture");
     if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
     hipError_t e3 = hipGraphInstantiate(&gs.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) { gs.exec = nullptr; return hip_fail(c, e3, "hipGraphInstantiate"); }
-    const void *key[10] = {s->x, s->v, s->w, s->f, s->t, s->r, s->type, s->id, c->lists[c->cur].nbr, nullptr};
+    const void *key[10] = {c->lists[c->cur].nbr, nullptr};
     memcpy(gs.key, key, sizeof key);
     gs.chunk = c->chunk;
     gs.count = c->count ? 1 : 0;
@@ -400,7 +422,7 @@ int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *wo
     for (int b = 0; b < 2; ++b) {
         c->lists[b].nbr = (int32_t *)(c->ws + lay.nbr[b]);
         c->lists[b].cnt = (int32_t *)(c->ws + lay.cnt[b]);
-        c->lists[b].xi = (double *)(c->ws + lay.xi[b]);
+        c->lists[b].xi = (D4 *)(c->ws + lay.xi[b]);
         c->lists[b].mask = (uint64_t *)(c->ws + lay.mask[b]);
         c->lists[b].ids = (int32_t *)(c->ws + lay.ids[b]);
     }
@@ -412,6 +434,12 @@ int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *wo
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_rho, g.rho.data(), g.rho.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_ctrl(c->d_flags, 2, 0, c->stream);
+    if (e == hipSuccess) {
+        int dev = 0, cus = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess && cus > 0) c->cus = cus;
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         g_init_error = std::string("HIP error during init: ") + hipGetErrorString(e);
@@ -464,7 +492,8 @@ int dem_forces(dem_ctx *c, const dem_state *s, int update_history) {
     if (rc) return rc;
     if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_forces needs a neighbour list for the current order");
     KArgs a = kargs(c, s);
-    HIPCALL(c, launch_forces(a, update_history ? 1 : 0, 0, 0, 0, c->stream));
+    HIPCALL(c, launch_pack(a, 0, 0, 0, 0, c->stream));
+    HIPCALL(c, launch_step(a, 0, 0, 0, update_history ? 1 : 0, 0, c->stream));
     c->forces_valid = true;
     return DEM_OK;
 }
@@ -491,6 +520,17 @@ int dem_set_step_options(dem_ctx *c, int use_graph, int32_t chunk) {
     return DEM_OK;
 }
 
+int dem_set_launch(dem_ctx *c, int32_t lanes, int32_t max_blocks) {
+    if (!c) return DEM_ERR_ARG;
+    if (max_blocks < 0) return fail(c, DEM_ERR_ARG, "max_blocks must be >= 0");
+    if (lanes != 4 && lanes != 8 && lanes != 16) return fail(c, DEM_ERR_ARG, "lanes must be 4, 8 or 16");
+    if (lanes > c->geo.block) return fail(c, DEM_ERR_ARG, "lanes must not exceed the block size");
+    c->grid_cap = max_blocks;
+    c->lanes = lanes;
+    for (GraphSlot &g : c->graphs) g.chunk = 0;  // re-capture with the new grid
+    return DEM_OK;
+}
+
 int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
     int rc = check_state(c, s);
     if (rc) return rc;
@@ -501,56 +541,66 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
         // binned but no list yet: build it (f and t were permuted with the particles)
         if ((rc = do_bin(c, s)) || (rc = do_neighbors(c, s))) return rc;
     }
-    int64_t done = 0;
+    // Steps are numbered 1..nsteps.  The state of step q after its drift lives
+    // in packed buffer (q-1)&1; the fused kernel of step q computes its forces
+    // and kicks, then drifts into q+1.  Groups of launches run between
+    // synchronisations; a group that needs a rebuild stops at the step whose
+    // drift asked for it.
+    const int64_t base = c->step_counter;
+    const int cnt = c->count ? 1 : 0;
+    int64_t q = 1, q0 = 1;
     Flags h;
-    while (done < nsteps) {
-        const int64_t m = std::min<int64_t>(c->chunk, nsteps - done);
-        HIPCALL(c, launch_ctrl(c->d_flags, 0, c->step_counter, c->stream));
+    HIPCALL(c, launch_ctrl(c->d_flags, 0, base + 1, c->stream));
+    {
         KArgs a = kargs(c, s);
-        if (c->use_graph && !c->timing && m == c->chunk) {
+        if ((rc = tic(c, 0))) return rc;
+        HIPCALL(c, launch_pack(a, 0, 1, 0, 1, c->stream));
+        if ((rc = toc(c))) return rc;
+    }
+    while (q <= nsteps) {
+        KArgs a = kargs(c, s);
+        if (c->use_graph && !c->timing && q == q0 && ((q - 1) & 1) == 0 && q + c->chunk - 1 <= nsteps - 1) {
             GraphSlot &gs = c->graphs[c->cur];
-            const void *key[10] = {s->x, s->v, s->w, s->f, s->t, s->r, s->type, s->id, c->lists[c->cur].nbr, nullptr};
-            if (!gs.exec || memcmp(gs.key, key, sizeof key) || gs.chunk != c->chunk || gs.count != (c->count ? 1 : 0)) {
+            const void *key[10] = {c->lists[c->cur].nbr, nullptr};
+            if (!gs.exec || memcmp(gs.key, key, sizeof key) || gs.chunk != c->chunk || gs.count != cnt)
                 if ((rc = capture_graph(c, s, gs))) return rc;
-            }
             HIPCALL(c, hipGraphLaunch(gs.exec, c->stream));
+            q += c->chunk;
         } else {
-            for (int64_t k = 0; k < m; ++k) {
-                if ((rc = tic(c, 0))) return rc;
-                HIPCALL(c, launch_phase(a, 0, (int)k, 1, c->stream));
-                if ((rc = toc(c)) || (rc = tic(c, 1))) return rc;
-                HIPCALL(c, launch_forces(a, 1, (int)k, 1, c->count ? 1 : 0, c->stream));
-                if ((rc = toc(c)) || (rc = tic(c, 2))) return rc;
-                HIPCALL(c, launch_phase(a, 1, (int)k, 1, c->stream));
+            while (q <= nsteps && q - q0 < c->chunk) {
+                const int last = q == nsteps;
+                if ((rc = tic(c, last ? 2 : 1))) return rc;
+                HIPCALL(c, launch_step(a, (int)((q - 1) & 1), last ? 2 : 1, (int)(q - q0), 1, cnt, c->stream));
                 if ((rc = toc(c))) return rc;
+                ++q;
             }
         }
         if ((rc = read_flags(c, h))) return rc;
         if ((rc = collect_times(c))) return rc;
         if ((rc = flag_error(c, h))) return rc;
         if (h.abort_at != INT64_MAX) {
-            // step abort_at has drifted; rebuild, then finish it
-            const int64_t k = h.abort_at - c->step_counter;
-            c->binned = false;
+            // the drift into step q_a asked for a new list: rebuild on the caller's
+            // arrays and repack into the same buffer
+            const int64_t qa = h.abort_at - base;
+            const int buf = (int)((qa - 1) & 1);
             if ((rc = tic(c, 3))) return rc;
+            HIPCALL(c, launch_unpack(a, buf, c->stream));
+            c->binned = false;
             if ((rc = do_bin(c, s)) || (rc = do_neighbors(c, s))) return rc;
-            if ((rc = toc(c))) return rc;
             KArgs b = kargs(c, s);
-            if ((rc = tic(c, 1))) return rc;
-            HIPCALL(c, launch_forces(b, 1, 0, 0, c->count ? 1 : 0, c->stream));
-            if ((rc = toc(c)) || (rc = tic(c, 2))) return rc;
-            HIPCALL(c, launch_phase(b, 1, 0, 0, c->stream));
+            HIPCALL(c, launch_pack(b, buf, 0, 0, 0, c->stream));
             if ((rc = toc(c))) return rc;
-            HIPCALL(c, launch_ctrl(c->d_flags, 3, 1, c->stream));
-            done += k + 1;
-            c->step_counter += k + 1;
-        } else {
-            done += m;
-            c->step_counter += m;
+            q = qa;
+        }
+        if (q <= nsteps) {
+            HIPCALL(c, launch_ctrl(c->d_flags, 0, base + q, c->stream));
+            q0 = q;
         }
     }
+    HIPCALL(c, launch_ctrl(c->d_flags, 3, nsteps, c->stream));
     if ((rc = read_flags(c, h))) return rc;
     if ((rc = collect_times(c))) return rc;
+    c->step_counter += nsteps;
     c->binned = false;
     c->forces_valid = true;
     return flag_error(c, h);
@@ -629,9 +679,9 @@ int fetch_list(dem_ctx *c, const dem_state *s, HostList &H, bool with_xi, bool w
     HIPCALL(c, hipMemcpy(H.ids.data(), L.ids, n * 4, hipMemcpyDeviceToHost));
     HIPCALL(c, hipMemcpy(H.mask.data(), L.mask, n * 8, hipMemcpyDeviceToHost));
     if (with_xi) {
-        H.xi.resize(3 * K * n);
+        H.xi.resize(4 * K * n);
         H.xiw.resize(3 * n);
-        HIPCALL(c, hipMemcpy(H.xi.data(), L.xi, 3 * K * n * 8, hipMemcpyDeviceToHost));
+        HIPCALL(c, hipMemcpy(H.xi.data(), L.xi, 4 * K * n * 8, hipMemcpyDeviceToHost));
         HIPCALL(c, hipMemcpy(H.xiw.data(), c->ws + c->lay.xiw, 3 * n * 8, hipMemcpyDeviceToHost));
     }
     if (with_pos) {
@@ -661,7 +711,7 @@ int dem_export_neighbors(dem_ctx *c, const dem_state *s, int32_t *id_i, int32_t 
     const int64_t n = c->geo.n;
     std::vector<std::pair<int32_t, int32_t>> out;
     for (int64_t i = 0; i < n; ++i)
-        for (int q = 0; q < H.cnt[i]; ++q) out.push_back({H.ids[i], H.ids[H.nbr[(int64_t)q * n + i]]});
+        for (int q = 0; q < H.cnt[i]; ++q) out.push_back({H.ids[i], H.ids[H.nbr[i * c->geo.kmax + q]]});
     std::sort(out.begin(), out.end());
     *count = (int64_t)out.size();
     for (int64_t k = 0; k < *count && k < cap; ++k) {
@@ -687,16 +737,16 @@ int dem_export_contacts(dem_ctx *c, const dem_state *s, int32_t *id_i, int32_t *
     for (int64_t i = 0; i < n; ++i) {
         const SysDesc &sd = c->geo.sys[sys_index(c->geo, i)];
         for (int q = 0; q < H.cnt[i]; ++q) {
-            const int64_t j = H.nbr[(int64_t)q * n + i];
+            const int64_t j = H.nbr[i * K + q];
             double dx = min_image(H.x[i] - H.x[j], sd.L[0], sd.hL[0], sd.periodic[0]);
             double dy = min_image(H.x[n + i] - H.x[n + j], sd.L[1], sd.hL[1], sd.periodic[1]);
             double dz = min_image(H.x[2 * n + i] - H.x[2 * n + j], sd.L[2], sd.hL[2], sd.periodic[2]);
             double d2 = dx * dx + dy * dy + dz * dz;
             double rs = H.r[i] + H.r[j];
             if (!(d2 < rs * rs)) continue;
-            const int64_t slot = (int64_t)q * n + i, plane = K * n;
+            const int64_t rec = 4 * (i * K + q);
             Rec r{H.ids[i], H.ids[j], 0.0, 0.0, 0.0};
-            if ((H.mask[i] >> q) & 1ull) { r.x = H.xi[slot]; r.y = H.xi[plane + slot]; r.z = H.xi[2 * plane + slot]; }
+            if ((H.mask[i] >> q) & 1ull) { r.x = H.xi[rec]; r.y = H.xi[rec + 1]; r.z = H.xi[rec + 2]; }
             out.push_back(r);
         }
     }
@@ -747,7 +797,7 @@ int dem_import_history(dem_ctx *c, const dem_state *s, int64_t npairs, const int
     if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_import_history needs a neighbour list");
     HostList H;
     if ((rc = fetch_list(c, s, H, true, false))) return rc;
-    const int64_t n = c->geo.n, K = c->geo.kmax, plane = K * n;
+    const int64_t n = c->geo.n, K = c->geo.kmax;
     std::unordered_map<uint64_t, int64_t> pairs;
     pairs.reserve((size_t)npairs * 2);
     for (int64_t k = 0; k < npairs; ++k)
@@ -757,12 +807,12 @@ int dem_import_history(dem_ctx *c, const dem_state *s, int64_t npairs, const int
     for (int64_t i = 0; i < n; ++i) {
         uint64_t m = 0;
         for (int q = 0; q < H.cnt[i]; ++q) {
-            const int64_t slot = (int64_t)q * n + i;
-            const int32_t a = H.ids[i], b = H.ids[H.nbr[slot]];
+            const int32_t a = H.ids[i], b = H.ids[H.nbr[i * K + q]];
             auto it = pairs.find(((uint64_t)(uint32_t)a << 32) | (uint32_t)b);
             double v[3] = {0.0, 0.0, 0.0};
             if (it != pairs.end()) for (int d = 0; d < 3; ++d) v[d] = xi[3 * it->second + d];
-            for (int d = 0; d < 3; ++d) H.xi[d * plane + slot] = v[d];
+            for (int d = 0; d < 3; ++d) H.xi[4 * (i * K + q) + d] = v[d];
+            H.xi[4 * (i * K + q) + 3] = 0.0;
             if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) m |= 1ull << q;
         }
         auto w = walls.find(H.ids[i]);
@@ -773,7 +823,7 @@ int dem_import_history(dem_ctx *c, const dem_state *s, int64_t npairs, const int
         H.mask[i] = m;
     }
     const List &L = c->lists[c->cur];
-    HIPCALL(c, hipMemcpy(L.xi, H.xi.data(), 3 * K * n * 8, hipMemcpyHostToDevice));
+    HIPCALL(c, hipMemcpy(L.xi, H.xi.data(), 4 * K * n * 8, hipMemcpyHostToDevice));
     HIPCALL(c, hipMemcpy(L.mask, H.mask.data(), n * 8, hipMemcpyHostToDevice));
     HIPCALL(c, hipMemcpy(c->ws + c->lay.xiw, H.xiw.data(), 3 * n * 8, hipMemcpyHostToDevice));
     return DEM_OK;

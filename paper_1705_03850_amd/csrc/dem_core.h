@@ -16,9 +16,15 @@ constexpr uint64_t kWallBit = 1ull << 63;
 // Sticky error bits of the device flag block.
 enum : int { kErrCapacity = 1, kErrNonFinite = 2, kErrCellOverflow = 4, kErrBadInput = 8 };
 
-// Effective pair coefficients of Eq. (6): E*, G*, beta(e), mu of a type pair.
+// Coefficients of Eq. (6) for a type pair, folded so that a contact needs
+// three square roots and two divisions:
+//   k_n = kn0 sqrt(R delta),        kn0 = (4/3) E*
+//   k_t = kt0 sqrt(R delta),        kt0 = 8 G*
+//   g_n = gn0 sqrt(m* sqrt(R delta)), gn0 = -beta sqrt((20/3) E*)   [= -beta sqrt(5 m* k_n)]
+//   g_t = gt0 sqrt(m* sqrt(R delta)), gt0 = -beta sqrt((80/3) G*)   [= -beta sqrt((10/3) m* k_t)]
 struct PairCoef {
-    double Es, Gs, beta, mu;
+    double kn0, kt0, gn0, gt0, mu;
+    double pad[3];
 };
 
 // One system of a batch.  Cells of system s occupy [c0, c0 + nc0*nc1*nc2).
@@ -52,22 +58,33 @@ struct Flags {
 };
 
 // Neighbour list (ELL, slot-major: slot k of particle i at k*n + i).
+// Packed working state of the step loop (one 32-byte record per particle and
+// field group, so that a neighbour's position and radius arrive in one
+// request): pos = (x, y, z, r), vel = (vx, vy, vz, m), spin = (wx, wy, wz, type).
+struct alignas(32) D4 {
+    double x, y, z, w;
+};
+struct alignas(16) D2 {
+    double a, b;
+};
+
 struct List {
-    int32_t *nbr;    // [kmax][n] neighbour index (in the particle order of the build)
+    int32_t *nbr;    // [n][kmax] neighbour index (in the particle order of the build)
     int32_t *cnt;    // [n] row length
-    double *xi;      // [3][kmax][n] tangential history of each slot
+    D4 *xi;          // [n][kmax] tangential history of each slot (x, y, z, unused): one
+                     // 32-byte record, so a contact reads and writes one line
     uint64_t *mask;  // [n] bit k: slot k holds non-zero history; bit 63: wall history non-zero
     int32_t *ids;    // [n] particle ids in the order of the build
 };
 
 // ---------------------------------------------------------------- helpers
 
+// Nearest periodic image of a coordinate difference (branch-free selects;
+// the same result as subtracting L above L/2 and adding it below -L/2).
 __host__ __device__ inline double min_image(double d, double L, double hL, int periodic) {
-    if (periodic) {
-        if (d > hL) d -= L;
-        else if (d < -hL) d += L;
-    }
-    return d;
+    const double dm = d - L, dp = d + L;
+    const double r = d > hL ? dm : (d < -hL ? dp : d);
+    return periodic ? r : d;
 }
 
 __host__ __device__ inline int cell_coord(double x, const SysDesc &s, int a) {
@@ -79,13 +96,13 @@ __host__ __device__ inline int cell_coord(double x, const SysDesc &s, int a) {
     return c;
 }
 
-// Contact of particle a with b (b_is_wall: flat wall z = 0, normal +z).
-// Inputs are a's and b's state; xi is the slot's history (updated in place
-// when update != 0).  Returns false (and touches nothing) when not in
-// contact.  Outputs: force on a, tangential force and normal for the torque.
-// The arithmetic order is fixed so that a pair evaluated from either side
-// gives exactly opposite results (no contraction into fused multiply-adds
-// anywhere in this library's force path).
+// Contact of particle a with b (wall: flat wall z = 0, normal +z).  Inputs
+// are a's and b's state; xi is the slot's history (updated in place when
+// update != 0).  Returns false (and touches nothing) when not in contact.
+// Outputs: force on a, tangential force and normal (for the torque), f_n.
+// Every expression is either symmetric in a and b or flips sign exactly with
+// the roles swapped, and nothing is contracted into fused multiply-adds, so a
+// pair evaluated from either side gives exactly opposite forces and history.
 struct ContactIn {
     double dx, dy, dz;   // x_a - x_b (minimum image); wall: (0, 0, z_a)
     double ra, rb;       // radii (wall: rb unused)
@@ -111,27 +128,35 @@ __host__ __device__ inline bool contact_force(const ContactIn &c, bool wall, con
     }
     double delta = rs - dist;
     if (!(delta > 0.0)) return false;
+    double R, M;
     if (!wall) {
-        nx = c.dx / dist; ny = c.dy / dist; nz = c.dz / dist;
+        const double inv_d = 1.0 / dist;
+        nx = c.dx * inv_d; ny = c.dy * inv_d; nz = c.dz * inv_d;
+        // R = r_a r_b / (r_a + r_b) and m* = m_a m_b / (m_a + m_b) with one division
+        const double sm = c.ma + c.mb;
+        const double inv = 1.0 / (rs * sm);
+        R = c.ra * c.rb * sm * inv;
+        M = c.ma * c.mb * rs * inv;
     } else {
         nx = 0.0; ny = 0.0; nz = 1.0;
+        R = c.ra;
+        M = c.ma;
     }
-    double R = wall ? c.ra : c.ra * c.rb / (c.ra + c.rb);
-    double M = wall ? c.ma : c.ma * c.mb / (c.ma + c.mb);
-    double sq = sqrt(R * delta);
-    double kn = 4.0 / 3.0 * k.Es * sq;
-    double kt = 8.0 * k.Gs * sq;
-    double gn = -k.beta * sqrt(5.0 * M * kn);
-    double gt = -k.beta * sqrt(10.0 / 3.0 * M * kt);
-    double vn = c.vrx * nx + c.vry * ny + c.vrz * nz;
-    double cx = c.wsy * nz - c.wsz * ny;
-    double cy = c.wsz * nx - c.wsx * nz;
-    double cz = c.wsx * ny - c.wsy * nx;
-    double vtx = c.vrx - vn * nx - cx;
-    double vty = c.vry - vn * ny - cy;
-    double vtz = c.vrz - vn * nz - cz;
-    double fn = kn * delta - gn * vn;
-    double xn = xix * nx + xiy * ny + xiz * nz;
+    const double sq = sqrt(R * delta);
+    const double kn = k.kn0 * sq;
+    const double kt = k.kt0 * sq;
+    const double sg = sqrt(M * sq);
+    const double gn = k.gn0 * sg;
+    const double gt = k.gt0 * sg;
+    const double vn = c.vrx * nx + c.vry * ny + c.vrz * nz;
+    const double cx = c.wsy * nz - c.wsz * ny;
+    const double cy = c.wsz * nx - c.wsx * nz;
+    const double cz = c.wsx * ny - c.wsy * nx;
+    const double vtx = c.vrx - vn * nx - cx;
+    const double vty = c.vry - vn * ny - cy;
+    const double vtz = c.vrz - vn * nz - cz;
+    const double fn = kn * delta - gn * vn;
+    const double xn = xix * nx + xiy * ny + xiz * nz;
     double zx = xix - xn * nx, zy = xiy - xn * ny, zz = xiz - xn * nz;
     if (update) {
         zx = zx + vtx * dt;
@@ -141,14 +166,15 @@ __host__ __device__ inline bool contact_force(const ContactIn &c, bool wall, con
     double tx = -kt * zx - gt * vtx;
     double ty = -kt * zy - gt * vty;
     double tz = -kt * zz - gt * vtz;
-    double ft2 = tx * tx + ty * ty + tz * tz;
-    double cap = k.mu * fabs(fn);
+    const double ft2 = tx * tx + ty * ty + tz * tz;
+    const double cap = k.mu * fabs(fn);
     if (ft2 > cap * cap) {
-        double scale = cap / sqrt(ft2);
+        const double scale = cap / sqrt(ft2);
         tx = scale * tx; ty = scale * ty; tz = scale * tz;
-        zx = -(tx + gt * vtx) / kt;
-        zy = -(ty + gt * vty) / kt;
-        zz = -(tz + gt * vtz) / kt;
+        const double inv_kt = 1.0 / kt;
+        zx = -(tx + gt * vtx) * inv_kt;
+        zy = -(ty + gt * vty) * inv_kt;
+        zz = -(tz + gt * vtz) * inv_kt;
     }
     if (update) { xix = zx; xiy = zy; xiz = zz; }
     fx = fn * nx + tx;

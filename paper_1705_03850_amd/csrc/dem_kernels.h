@@ -20,7 +20,8 @@ struct KArgs {
     int32_t nsys;
     int32_t kmax;
     int32_t block;
-    int32_t pad;
+    int32_t grid_cap;      // blocks of the fused step kernel (0 = one per tile)
+    int32_t lanes;         // lanes per particle in the force pass: 4, 8 or 16
     int64_t n;             // particles, all systems
     int64_t ncell;         // cells, all systems
     Flags *flags;
@@ -29,6 +30,9 @@ struct KArgs {
     int32_t *cell_of, *rank, *cell_count, *cell_start, *scan_partial, *order;
     double *shadow_d;      // [25][n]
     int32_t *shadow_i;     // [3][n]
+    // packed step state, two buffers used alternately
+    D4 *pos[2], *vel[2], *spin[2];
+    D2 *im;                // (1/m, 1/I)
 };
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
@@ -37,8 +41,14 @@ hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_ctrl(Flags *f, int op, int64_t value, hipStream_t st);
 hipError_t launch_init_mass(const KArgs &a, hipStream_t st);
 hipError_t launch_phase(const KArgs &a, int phase, int k, int gate, hipStream_t st);
-hipError_t launch_forces(const KArgs &a, int update, int k, int gate, int count, hipStream_t st);
 hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st);
 hipError_t launch_neighbors(const KArgs &a, int have_old, hipStream_t st);
+// mode 0: pack only; 1: pack and do phase 0 of step `k` (gated)
+hipError_t launch_pack(const KArgs &a, int dst, int mode, int k, int gate, hipStream_t st);
+hipError_t launch_unpack(const KArgs &a, int src, hipStream_t st);
+// force pass over packed buffer src: mode 0 forces only (to f, t); mode 1 fused
+// step (forces, kick, next kick + drift into buffer src^1); mode 2 last step
+// (forces, kick, f, t, x, v, w to the caller's arrays).
+hipError_t launch_step(const KArgs &a, int src, int mode, int k, int update, int count, hipStream_t st);
 
 }  // namespace dem

@@ -171,114 +171,6 @@ __global__ void k_phase1(KArgs a, int k, int gate) {
     }
 }
 
-// ------------------------------------------------------------------ forces
-
-// One thread per particle: gravity, then every slot of its row (ascending
-// neighbour id), then the wall.  Pair terms are evaluated from this
-// particle's side only; the partner evaluates the mirrored contact in its own
-// row, which gives the exact negative (see contact_force).  With update the
-// slot history is advanced and stored; slots that are out of contact simply
-// lose their mask bit (their history reads as zero from then on).
-template <bool BATCH, bool COUNT>
-__global__ void __launch_bounds__(256) k_forces(KArgs a, int update, int k, int gate) {
-    if (gate) {
-        int64_t step = a.flags->step_base + k;
-        if (a.flags->abort_at <= step) return;
-    }
-    const int64_t n = a.n;
-    const List L = a.cur;
-    unsigned ncont = 0, nwall = 0;
-    FOR_EACH_PARTICLE(n, i) {
-        const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
-        const PairCoef *coef = a.coef + s.coef0;
-        const double xi = a.x[i], yi = a.x[n + i], zi = a.x[2 * n + i];
-        const double vxi = a.v[i], vyi = a.v[n + i], vzi = a.v[2 * n + i];
-        const double wxi = a.w[i], wyi = a.w[n + i], wzi = a.w[2 * n + i];
-        const double ri = a.r[i], mi = a.m[i];
-        const int ti = a.type[i];
-        double Fx = mi * s.g[0], Fy = mi * s.g[1], Fz = mi * s.g[2];
-        double Tx = 0.0, Ty = 0.0, Tz = 0.0;
-        const int cnt = L.cnt[i];
-        const uint64_t mask = L.mask[i];
-        uint64_t nmask = 0;
-        for (int q = 0; q < cnt; ++q) {
-            const int32_t j = L.nbr[(int64_t)q * n + i];
-            ContactIn c;
-            c.dx = min_image(xi - a.x[j], s.L[0], s.hL[0], s.periodic[0]);
-            c.dy = min_image(yi - a.x[n + j], s.L[1], s.hL[1], s.periodic[1]);
-            c.dz = min_image(zi - a.x[2 * n + j], s.L[2], s.hL[2], s.periodic[2]);
-            c.ra = ri;
-            c.rb = a.r[j];
-            const double d2 = c.dx * c.dx + c.dy * c.dy + c.dz * c.dz;
-            const double rs = c.ra + c.rb;
-            if (!(d2 < rs * rs)) continue;
-            c.ma = mi;
-            c.mb = a.m[j];
-            c.vrx = vxi - a.v[j]; c.vry = vyi - a.v[n + j]; c.vrz = vzi - a.v[2 * n + j];
-            c.wsx = ri * wxi + c.rb * a.w[j];
-            c.wsy = ri * wyi + c.rb * a.w[n + j];
-            c.wsz = ri * wzi + c.rb * a.w[2 * n + j];
-            const PairCoef pc = coef[ti * s.ntypes + a.type[j]];
-            double hx = 0.0, hy = 0.0, hz = 0.0;
-            const int64_t slot = (int64_t)q * n + i;
-            const int64_t plane = (int64_t)a.kmax * n;
-            if ((mask >> q) & 1ull) {
-                hx = L.xi[slot]; hy = L.xi[plane + slot]; hz = L.xi[2 * plane + slot];
-            }
-            double fx, fy, fz, tx, ty, tz, nx, ny, nz, fn;
-            if (!contact_force(c, false, pc, s.dt, update != 0, hx, hy, hz, fx, fy, fz, tx, ty, tz, nx, ny, nz, fn))
-                continue;
-            if (COUNT) ++ncont;
-            Fx = Fx + fx; Fy = Fy + fy; Fz = Fz + fz;
-            Tx = Tx - ri * (ny * tz - nz * ty);
-            Ty = Ty - ri * (nz * tx - nx * tz);
-            Tz = Tz - ri * (nx * ty - ny * tx);
-            if (update) {
-                L.xi[slot] = hx; L.xi[plane + slot] = hy; L.xi[2 * plane + slot] = hz;
-                nmask |= 1ull << q;
-            }
-        }
-        if (s.wall && zi < ri) {
-            ContactIn c;
-            c.dx = 0.0; c.dy = 0.0; c.dz = zi;
-            c.ra = ri; c.rb = 0.0; c.ma = mi; c.mb = 0.0;
-            c.vrx = vxi; c.vry = vyi; c.vrz = vzi;
-            c.wsx = ri * wxi; c.wsy = ri * wyi; c.wsz = ri * wzi;
-            const PairCoef pc = coef[ti * s.ntypes + ti];
-            double hx = 0.0, hy = 0.0, hz = 0.0;
-            if (mask & kWallBit) { hx = a.xiw[i]; hy = a.xiw[n + i]; hz = a.xiw[2 * n + i]; }
-            double fx, fy, fz, tx, ty, tz, nx, ny, nz, fn;
-            if (contact_force(c, true, pc, s.dt, update != 0, hx, hy, hz, fx, fy, fz, tx, ty, tz, nx, ny, nz, fn)) {
-                if (COUNT) ++nwall;
-                Fx = Fx + fx; Fy = Fy + fy; Fz = Fz + fz;
-                Tx = Tx - ri * (ny * tz - nz * ty);
-                Ty = Ty - ri * (nz * tx - nx * tz);
-                Tz = Tz - ri * (nx * ty - ny * tx);
-                if (update) {
-                    a.xiw[i] = hx; a.xiw[n + i] = hy; a.xiw[2 * n + i] = hz;
-                    nmask |= kWallBit;
-                }
-            }
-        }
-        a.f[i] = Fx; a.f[n + i] = Fy; a.f[2 * n + i] = Fz;
-        a.t[i] = Tx; a.t[n + i] = Ty; a.t[2 * n + i] = Tz;
-        if (update && nmask != mask) L.mask[i] = nmask;
-    }
-    if (COUNT) {
-        // statistics only (contact-pair rate); the force sums above use no atomics
-        __shared__ unsigned long long sc[2];
-        if (threadIdx.x == 0) { sc[0] = 0; sc[1] = 0; }
-        __syncthreads();
-        if (ncont) atomicAdd(&sc[0], (unsigned long long)ncont);
-        if (nwall) atomicAdd(&sc[1], (unsigned long long)nwall);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (sc[0]) atomicAdd(&a.flags->contacts, sc[0]);
-            if (sc[1]) atomicAdd(&a.flags->wall_contacts, sc[1]);
-        }
-    }
-}
-
 // ------------------------------------------------------------------ binning
 
 template <bool BATCH>
@@ -453,7 +345,6 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a, int have_old) {
     int32_t *ridx = rid + kmax;
     int maxrow = 0;
     const List L = a.cur, O = a.old;
-    const int64_t plane = (int64_t)kmax * n;
     FOR_EACH_PARTICLE(n, i) {
         const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
         const double xi = a.x[i], yi = a.x[n + i], zi = a.x[2 * n + i], ri = a.r[i];
@@ -508,17 +399,14 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a, int have_old) {
             int p = 0;
             for (int q = 0; q < cnt; ++q) {
                 const int32_t idq = rid[q];
-                while (p < ocnt && O.ids[O.nbr[(int64_t)p * n + o]] < idq) ++p;
-                if (p < ocnt && O.ids[O.nbr[(int64_t)p * n + o]] == idq && ((omask >> p) & 1ull)) {
-                    const int64_t os = (int64_t)p * n + o, ns = (int64_t)q * n + i;
-                    L.xi[ns] = O.xi[os];
-                    L.xi[plane + ns] = O.xi[plane + os];
-                    L.xi[2 * plane + ns] = O.xi[2 * plane + os];
+                while (p < ocnt && O.ids[O.nbr[o * kmax + p]] < idq) ++p;
+                if (p < ocnt && O.ids[O.nbr[o * kmax + p]] == idq && ((omask >> p) & 1ull)) {
+                    L.xi[i * kmax + q] = O.xi[o * kmax + p];
                     nmask |= 1ull << q;
                 }
             }
         }
-        for (int q = 0; q < cnt; ++q) L.nbr[(int64_t)q * n + i] = ridx[q];
+        for (int q = 0; q < cnt; ++q) L.nbr[i * kmax + q] = ridx[q];
         L.cnt[i] = cnt;
         L.mask[i] = nmask;
         L.ids[i] = a.id[i];
@@ -528,13 +416,264 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a, int have_old) {
     if (maxrow) atomicMax(&a.flags->max_row, maxrow);
 }
 
+// ------------------------------------------------------------- fused step
+
+// Caller arrays (structure of arrays) -> packed buffer `dst`.  mode 1 also
+// does phase 0 of velocity Verlet for the step step_base + k (gated like the
+// fused step: it asks for a rebuild when the displacement exceeds skin/2).
+template <bool BATCH>
+__global__ void k_pack(KArgs a, int dst, int mode, int k, int gate) {
+    int64_t step = 0;
+    if (gate) {
+        step = a.flags->step_base + k;
+        if (a.flags->abort_at < step) return;
+    }
+    const int64_t n = a.n;
+    bool need = false, bad = false;
+    D4 *P = a.pos[dst], *V = a.vel[dst], *S = a.spin[dst];
+    FOR_EACH_PARTICLE(n, i) {
+        const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
+        const double im = a.inv_m[i], iI = a.inv_I[i];
+        double x[3], v[3], w[3];
+        for (int c = 0; c < 3; ++c) {
+            x[c] = a.x[c * n + i];
+            v[c] = a.v[c * n + i];
+            w[c] = a.w[c * n + i];
+        }
+        if (mode == 1) {
+            double dsq = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                v[c] = v[c] + s.hdt * (a.f[c * n + i] * im);
+                w[c] = w[c] + s.hdt * (a.t[c * n + i] * iI);
+                x[c] = wrap_axis(x[c] + s.dt * v[c], s, c);
+                const double d = a.disp[c * n + i] + s.dt * v[c];
+                a.disp[c * n + i] = d;
+                dsq += d * d;
+            }
+            if (!(dsq <= s.disp_thr2)) need = true;
+            if (!isfinite(x[0] + x[1] + x[2] + v[0] + v[1] + v[2])) bad = true;
+        }
+        P[i] = D4{x[0], x[1], x[2], a.r[i]};
+        V[i] = D4{v[0], v[1], v[2], a.m[i]};
+        S[i] = D4{w[0], w[1], w[2], (double)a.type[i]};
+        a.im[i] = D2{im, iI};
+    }
+    if (bad) atomicOr(&a.flags->err, kErrNonFinite);
+    if (need && gate) a.flags->abort_at = step;
+}
+
+// Packed buffer `src` -> caller arrays x, v, w.
+__global__ void k_unpack(KArgs a, int src) {
+    const int64_t n = a.n;
+    const D4 *P = a.pos[src], *V = a.vel[src], *S = a.spin[src];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const D4 p = P[i], v = V[i], w = S[i];
+        a.x[i] = p.x; a.x[n + i] = p.y; a.x[2 * n + i] = p.z;
+        a.v[i] = v.x; a.v[n + i] = v.y; a.v[2 * n + i] = v.z;
+        a.w[i] = w.x; a.w[n + i] = w.y; a.w[2 * n + i] = w.z;
+    }
+}
+
+// Force pass over the packed state in buffer src, one group of G lanes per
+// particle (lane g of the group takes slots g, g+G, ... of the row), so a
+// whole row's loads are in flight at once.  The pair terms (contact_force,
+// Eq. (3)-(6)) are computed in parallel and then added in ascending slot
+// order -- the row is sorted by neighbour id -- by every lane of the group,
+// reading each term from its lane: per particle the sum is gravity, then the
+// contacts in ascending neighbour id, then the wall, exactly the sequential
+// order, whatever the list composition, the lanes or the block size.
+//   MODE 0: forces only, written to f and t (history advanced when update);
+//   MODE 1: fused step -- forces, kick 1/2, then the next step's kick 1/2,
+//           drift, wrap and rebuild check, written to buffer src^1 (gated:
+//           does nothing once an earlier step asked for a rebuild);
+//   MODE 2: last step of a call -- forces, kick 1/2, and f, t, x, v, w
+//           written to the caller's arrays (gated).
+template <bool BATCH, bool COUNT, int MODE, int G>
+__global__ void __launch_bounds__(256) k_step(KArgs a, int src, int k, int update) {
+    int64_t step = 0;
+    if (MODE != 0) {
+        step = a.flags->step_base + k;
+        if (a.flags->abort_at <= step) return;
+        update = 1;
+    }
+    const int64_t n = a.n;
+    const List L = a.cur;
+    const D4 *__restrict__ P = a.pos[src];
+    const D4 *__restrict__ V = a.vel[src];
+    const D4 *__restrict__ S = a.spin[src];
+    const int64_t kmax = a.kmax;
+    const int g = threadIdx.x % G;
+    const int ppb = blockDim.x / G;                        // particles per tile
+    const int gbase = (threadIdx.x % warpSize) / G * G;    // first lane of the group in the wave
+    const uint64_t gmask = (1ull << G) - 1;
+    unsigned ncont = 0, nwall = 0;
+    bool need = false, bad = false;
+    const int64_t ntiles = (n + ppb - 1) / ppb;
+    const int per = gridDim.x / kXcd;
+    const int64_t chunk = (ntiles + kXcd - 1) / kXcd;
+    const int64_t t0 = (blockIdx.x % kXcd) * chunk;
+    const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
+    for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {
+        const int64_t i = t * ppb + threadIdx.x / G;
+        if (i >= n) continue;
+        const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
+        const PairCoef *coef = a.coef + s.coef0;
+        const D4 pi = P[i];
+        const D4 vi = V[i];
+        const D4 si = S[i];
+        const double ri = pi.w, mi = vi.w;
+        const int ti = (int)si.w;
+        double Fx = mi * s.g[0], Fy = mi * s.g[1], Fz = mi * s.g[2];
+        double Tx = 0.0, Ty = 0.0, Tz = 0.0;
+        const int cnt = L.cnt[i];
+        const uint64_t mask = L.mask[i];
+        uint64_t nmask = 0;
+        for (int c0 = 0; c0 < cnt; c0 += G) {
+            const int q = c0 + g;
+            const bool valid = q < cnt;
+            const int64_t slot = i * kmax + q;
+            const int32_t j = valid ? L.nbr[slot] : (int32_t)i;
+            const D4 pj = P[j];
+            ContactIn c;
+            c.dx = min_image(pi.x - pj.x, s.L[0], s.hL[0], s.periodic[0]);
+            c.dy = min_image(pi.y - pj.y, s.L[1], s.hL[1], s.periodic[1]);
+            c.dz = min_image(pi.z - pj.z, s.L[2], s.hL[2], s.periodic[2]);
+            c.ra = ri;
+            c.rb = pj.w;
+            const double rs = c.ra + c.rb;
+            double fx = 0.0, fy = 0.0, fz = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
+            bool hit = false, stored = false;
+            if (valid && c.dx * c.dx + c.dy * c.dy + c.dz * c.dz < rs * rs) {
+                const D4 vj = V[j];
+                const D4 sj = S[j];
+                double hx = 0.0, hy = 0.0, hz = 0.0;
+                if ((mask >> q) & 1ull) {
+                    const D4 h = L.xi[slot];
+                    hx = h.x; hy = h.y; hz = h.z;
+                }
+                c.ma = mi; c.mb = vj.w;
+                c.vrx = vi.x - vj.x; c.vry = vi.y - vj.y; c.vrz = vi.z - vj.z;
+                c.wsx = ri * si.x + pj.w * sj.x;
+                c.wsy = ri * si.y + pj.w * sj.y;
+                c.wsz = ri * si.z + pj.w * sj.z;
+                const PairCoef pc = coef[ti * s.ntypes + (int)sj.w];
+                double ftx, fty, ftz, nx, ny, nz, fn;
+                if (contact_force(c, false, pc, s.dt, update != 0, hx, hy, hz, fx, fy, fz, ftx, fty, ftz, nx, ny,
+                                  nz, fn)) {
+                    if (COUNT) ++ncont;
+                    hit = true;
+                    tx = -(ri * (ny * ftz - nz * fty));
+                    ty = -(ri * (nz * ftx - nx * ftz));
+                    tz = -(ri * (nx * fty - ny * ftx));
+                    if (update) {
+                        L.xi[slot] = D4{hx, hy, hz, 0.0};
+                        stored = true;
+                    }
+                }
+            }
+            // add this chunk's contacts in ascending slot order
+            uint64_t b = (__ballot(hit) >> gbase) & gmask;
+            while (b) {
+                const int src_lane = gbase + __builtin_ctzll(b);
+                b &= b - 1;
+                Fx = Fx + __shfl(fx, src_lane);
+                Fy = Fy + __shfl(fy, src_lane);
+                Fz = Fz + __shfl(fz, src_lane);
+                Tx = Tx + __shfl(tx, src_lane);
+                Ty = Ty + __shfl(ty, src_lane);
+                Tz = Tz + __shfl(tz, src_lane);
+            }
+            nmask |= ((__ballot(stored) >> gbase) & gmask) << c0;
+        }
+        // the wall (every lane of the group computes it; lane 0 stores)
+        if (s.wall && pi.z < ri) {
+            ContactIn c;
+            c.dx = 0.0; c.dy = 0.0; c.dz = pi.z;
+            c.ra = ri; c.rb = 0.0; c.ma = mi; c.mb = 0.0;
+            c.vrx = vi.x; c.vry = vi.y; c.vrz = vi.z;
+            c.wsx = ri * si.x; c.wsy = ri * si.y; c.wsz = ri * si.z;
+            const PairCoef pc = coef[ti * s.ntypes + ti];
+            double hx = 0.0, hy = 0.0, hz = 0.0;
+            if (mask & kWallBit) { hx = a.xiw[i]; hy = a.xiw[n + i]; hz = a.xiw[2 * n + i]; }
+            double fx, fy, fz, ftx, fty, ftz, nx, ny, nz, fn;
+            if (contact_force(c, true, pc, s.dt, update != 0, hx, hy, hz, fx, fy, fz, ftx, fty, ftz, nx, ny, nz,
+                              fn)) {
+                if (COUNT && g == 0) ++nwall;
+                Fx = Fx + fx; Fy = Fy + fy; Fz = Fz + fz;
+                Tx = Tx + -(ri * (ny * ftz - nz * fty));
+                Ty = Ty + -(ri * (nz * ftx - nx * ftz));
+                Tz = Tz + -(ri * (nx * fty - ny * ftx));
+                if (update) {
+                    if (g == 0) { a.xiw[i] = hx; a.xiw[n + i] = hy; a.xiw[2 * n + i] = hz; }
+                    nmask |= kWallBit;
+                }
+            }
+        }
+        if (g != 0) continue;
+        if (update && nmask != mask) L.mask[i] = nmask;
+        if (MODE == 0) {
+            a.f[i] = Fx; a.f[n + i] = Fy; a.f[2 * n + i] = Fz;
+            a.t[i] = Tx; a.t[n + i] = Ty; a.t[2 * n + i] = Tz;
+            continue;
+        }
+        // kick 1/2 with the new forces
+        const D2 im = a.im[i];
+        double vx = vi.x + s.hdt * (Fx * im.a), vy = vi.y + s.hdt * (Fy * im.a), vz = vi.z + s.hdt * (Fz * im.a);
+        double wx = si.x + s.hdt * (Tx * im.b), wy = si.y + s.hdt * (Ty * im.b), wz = si.z + s.hdt * (Tz * im.b);
+        if (MODE == 2) {
+            a.f[i] = Fx; a.f[n + i] = Fy; a.f[2 * n + i] = Fz;
+            a.t[i] = Tx; a.t[n + i] = Ty; a.t[2 * n + i] = Tz;
+            a.x[i] = pi.x; a.x[n + i] = pi.y; a.x[2 * n + i] = pi.z;
+            a.v[i] = vx; a.v[n + i] = vy; a.v[2 * n + i] = vz;
+            a.w[i] = wx; a.w[n + i] = wy; a.w[2 * n + i] = wz;
+        } else {
+            // next step: kick 1/2, drift, wrap, displacement since the last build
+            vx = vx + s.hdt * (Fx * im.a); vy = vy + s.hdt * (Fy * im.a); vz = vz + s.hdt * (Fz * im.a);
+            wx = wx + s.hdt * (Tx * im.b); wy = wy + s.hdt * (Ty * im.b); wz = wz + s.hdt * (Tz * im.b);
+            const double x = wrap_axis(pi.x + s.dt * vx, s, 0);
+            const double y = wrap_axis(pi.y + s.dt * vy, s, 1);
+            const double z = wrap_axis(pi.z + s.dt * vz, s, 2);
+            const double ddx = a.disp[i] + s.dt * vx;
+            const double ddy = a.disp[n + i] + s.dt * vy;
+            const double ddz = a.disp[2 * n + i] + s.dt * vz;
+            a.disp[i] = ddx; a.disp[n + i] = ddy; a.disp[2 * n + i] = ddz;
+            double dsq = 0.0;
+            dsq += ddx * ddx;
+            dsq += ddy * ddy;
+            dsq += ddz * ddz;
+            if (!(dsq <= s.disp_thr2)) need = true;
+            if (!isfinite(x + y + z + vx + vy + vz)) bad = true;
+            a.pos[src ^ 1][i] = D4{x, y, z, ri};
+            a.vel[src ^ 1][i] = D4{vx, vy, vz, mi};
+            a.spin[src ^ 1][i] = D4{wx, wy, wz, si.w};
+        }
+    }
+    if (bad) atomicOr(&a.flags->err, kErrNonFinite);
+    if (MODE == 1 && need) a.flags->abort_at = step + 1;
+    if (COUNT) {
+        // statistics only (contact-pair rate); the force sums above use no atomics
+        __shared__ unsigned long long sc[2];
+        if (threadIdx.x == 0) { sc[0] = 0; sc[1] = 0; }
+        __syncthreads();
+        if (ncont) atomicAdd(&sc[0], (unsigned long long)ncont);
+        if (nwall) atomicAdd(&sc[1], (unsigned long long)nwall);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (sc[0]) atomicAdd(&a.flags->contacts, sc[0]);
+            if (sc[1]) atomicAdd(&a.flags->wall_contacts, sc[1]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
-static int grid_for(int64_t n, int block) {
+// Blocks for a particle kernel: one per tile (rounded up to a multiple of the
+// XCD count) unless `cap` (> 0) limits the grid, in which case blocks walk
+// several tiles of their XCD's chunk.
+static int grid_for(int64_t n, int block, int64_t cap = 0) {
     int64_t tiles = (n + block - 1) / block;
     int64_t g = (tiles + kXcd - 1) / kXcd * kXcd;
-    const int64_t cap = 256 * kXcd;  // persistent: at most 8 waves of tiles per XCD slot
-    if (g > cap) g = cap;
+    if (cap > 0 && g > cap) g = (cap + kXcd - 1) / kXcd * kXcd;
     if (g < kXcd) g = kXcd;
     return (int)g;
 }
@@ -588,19 +727,6 @@ hipError_t launch_phase(const KArgs &a, int phase, int k, int gate, hipStream_t 
     CHECK_LAUNCH();
 }
 
-hipError_t launch_forces(const KArgs &a, int update, int k, int gate, int count, hipStream_t st) {
-    if (a.n <= 0) return hipSuccess;
-    const int g = grid_for(a.n, a.block);
-    if (a.nsys > 1) {
-        if (count) k_forces<true, true><<<g, a.block, 0, st>>>(a, update, k, gate);
-        else k_forces<true, false><<<g, a.block, 0, st>>>(a, update, k, gate);
-    } else {
-        if (count) k_forces<false, true><<<g, a.block, 0, st>>>(a, update, k, gate);
-        else k_forces<false, false><<<g, a.block, 0, st>>>(a, update, k, gate);
-    }
-    CHECK_LAUNCH();
-}
-
 hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
     hipError_t e;
@@ -632,6 +758,49 @@ hipError_t launch_neighbors(const KArgs &a, int have_old, hipStream_t st) {
     if (a.nsys > 1) k_neighbors<true><<<g, block, lds, st>>>(a, have_old);
     else k_neighbors<false><<<g, block, lds, st>>>(a, have_old);
     CHECK_LAUNCH();
+}
+
+hipError_t launch_pack(const KArgs &a, int dst, int mode, int k, int gate, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    const int g = grid_for(a.n, a.block);
+    if (a.nsys > 1) k_pack<true><<<g, a.block, 0, st>>>(a, dst, mode, k, gate);
+    else k_pack<false><<<g, a.block, 0, st>>>(a, dst, mode, k, gate);
+    CHECK_LAUNCH();
+}
+
+hipError_t launch_unpack(const KArgs &a, int src, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    k_unpack<<<flat_grid(a.n, 256), 256, 0, st>>>(a, src);
+    CHECK_LAUNCH();
+}
+
+template <int G>
+static hipError_t launch_step_g(const KArgs &a, int src, int mode, int k, int update, int count, hipStream_t st) {
+    const int ppb = a.block / G;
+    const int g = grid_for((a.n + ppb - 1) / ppb * a.block, a.block, a.grid_cap);
+    const int B = a.block;
+#define STEP_LAUNCH(BT, CT, MD) k_step<BT, CT, MD, G><<<g, B, 0, st>>>(a, src, k, update)
+#define STEP_MODES(BT, CT)                                  \
+    if (mode == 0) STEP_LAUNCH(BT, CT, 0);                  \
+    else if (mode == 1) STEP_LAUNCH(BT, CT, 1);             \
+    else STEP_LAUNCH(BT, CT, 2)
+    if (a.nsys > 1) {
+        if (count) { STEP_MODES(true, true); } else { STEP_MODES(true, false); }
+    } else {
+        if (count) { STEP_MODES(false, true); } else { STEP_MODES(false, false); }
+    }
+#undef STEP_MODES
+#undef STEP_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const KArgs &a, int src, int mode, int k, int update, int count, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    switch (a.lanes) {
+    case 4: return launch_step_g<4>(a, src, mode, k, update, count, st);
+    case 16: return launch_step_g<16>(a, src, mode, k, update, count, st);
+    default: return launch_step_g<8>(a, src, mode, k, update, count, st);
+    }
 }
 
 }  // namespace dem

@@ -46,7 +46,7 @@ class State(ctypes.Structure):
 
 _lib = None
 _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_batch_init", "dem_reset", "dem_bin",
-            "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_set_step_options", "dem_check",
+            "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_set_step_options", "dem_set_launch", "dem_check",
             "dem_stats", "dem_set_timing", "dem_kernel_times", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
             "dem_last_error", "dem_destroy"]
 
@@ -71,6 +71,7 @@ def load(path: str = LIB_PATH):
     L.dem_integrate.argtypes = [vp, P(State), ctypes.c_int]
     L.dem_step.argtypes = [vp, P(State), i64]
     L.dem_set_step_options.argtypes = [vp, ctypes.c_int, i32]
+    L.dem_set_launch.argtypes = [vp, i32, i32]
     L.dem_check.argtypes = [vp, P(i64)]
     L.dem_stats.argtypes = [vp, P(i64)]
     L.dem_set_timing.argtypes = [vp, ctypes.c_int]
@@ -139,7 +140,7 @@ class DemSystem:
     """
 
     def __init__(self, systems, k_max: int = 32, block: int = 0, cell=0.0, skin=None, device: str = "cuda",
-                 use_graph: bool = False, chunk: int = 64):
+                 use_graph: bool = False, chunk: int = 64, lanes: int = 4, max_blocks: int = 0):
         import torch
 
         self.torch = torch
@@ -180,6 +181,7 @@ class DemSystem:
         self.load_state()
         self._state = State(*[_ptr(t) for t in (self.x, self.v, self.w, self.f, self.t, self.r, self.type, self.id)])
         self._rc(self.L.dem_set_step_options(self.ctx, int(use_graph), int(chunk)))
+        self._rc(self.L.dem_set_launch(self.ctx, int(lanes), int(max_blocks)))
         self.reset()
 
     # ------------------------------------------------------------ helpers
@@ -248,6 +250,9 @@ class DemSystem:
     def set_step_options(self, use_graph: bool, chunk: int = 64):
         self._rc(self.L.dem_set_step_options(self.ctx, int(use_graph), int(chunk)))
 
+    def set_launch(self, lanes: int = 4, max_blocks: int = 0):
+        self._rc(self.L.dem_set_launch(self.ctx, int(lanes), int(max_blocks)))
+
     def prime(self):
         """Bin, build the list and evaluate the initial forces (history untouched)."""
         self.build_list()
@@ -257,11 +262,11 @@ class DemSystem:
         self._rc(self.L.dem_set_timing(self.ctx, int(enable)))
 
     def kernel_times(self):
-        """{class: (total ms, launches)} for phase0, forces, phase1, rebuild."""
+        """{class: (total ms, launches)}: first kick-drift (pack), fused step, last step, rebuild."""
         ms = (ctypes.c_double * 4)()
         n = (ctypes.c_int64 * 4)()
         self._rc(self.L.dem_kernel_times(self.ctx, ms, n))
-        return {k: (ms[q], n[q]) for q, k in enumerate(("phase0", "forces", "phase1", "rebuild"))}
+        return {k: (ms[q], n[q]) for q, k in enumerate(("pack", "step", "last", "rebuild"))}
 
     def check(self):
         info = (ctypes.c_int64 * 4)()

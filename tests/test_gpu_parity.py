@@ -231,7 +231,8 @@ def test_launch_options_do_not_change_results():
     s = W.plain_fcc()
     ref = None
     for kw in (dict(), dict(block=64), dict(block=256, cell=5e-3), dict(skin=30e-6),
-               dict(use_graph=True, chunk=16)):
+               dict(use_graph=True, chunk=16), dict(max_blocks=64), dict(block=64, max_blocks=8),
+               dict(block=128, max_blocks=100000)):
         g = gpu(s, **kw)
         g.prime()
         g.step(150)
@@ -240,6 +241,22 @@ def test_launch_options_do_not_change_results():
             ref = h
         for k in ("x", "v", "w", "f", "t"):
             assert np.array_equal(h[k], ref[k]), (kw, k)
+
+
+@pytest.mark.parametrize("lanes", [8, 16])
+def test_lanes_do_not_change_results(lanes):
+    """Another split of a row over lanes changes only who computes which pair
+    term; the terms are added in the same (id) order, so results are equal."""
+    s = W.plain_fcc()
+    out = []
+    for kw in (dict(), dict(lanes=lanes), dict(lanes=lanes, block=64, skin=20e-6)):
+        g = gpu(s, **kw)
+        g.prime()
+        g.step(100)
+        out.append(g.host())
+    for o in out[1:]:
+        for k in ("x", "v", "w", "f", "t"):
+            assert np.array_equal(o[k], out[0][k]), k
 
 
 def test_batch_equals_separate_systems():

@@ -89,6 +89,95 @@ def cpu_baseline(system, steps):
                       f"1 thread, {dt:.1f} s"}
 
 
+def timed_steps(g, steps, warm):
+    import torch
+
+    g.step(warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def batch_suite(args):
+    """Batched against plain on the same GPU (one JSON line).
+
+    64 systems (N log-uniform in [5e3, 2e5], alpha in {1, 2, 4, 8}, dt = alpha 1e-6 s):
+      batched    -- all systems in one context: one launch per step for all of them, graph replay;
+      sequential -- the same systems, each in its own context, stepped one after another;
+      equal N    -- one plain bed with the same total particle count.
+    Two-level chute (2e5 spheres alpha = 4 + 5e5 spheres alpha = 1): one 2-system batch against the two
+    systems one after another.  Launch shape, skin and cell come from the autotuner."""
+    import torch
+
+    from paper_1705_03850_amd import autotune, dem
+    from paper_1705_03850_amd.inputs import workloads as W
+
+    steps = args.steps if args.steps != 10000 else 2000
+    log("generating 64 batch systems")
+    systems = W.batch_systems()
+    ntot = sum(s.n for s in systems)
+    log(f"{len(systems)} systems, {ntot} particles; autotuning")
+    if args.no_autotune:
+        choice = {"skin_factor": 0.1, "cell_factor": 1.0, "block": 256, "lanes": 4}
+    else:
+        choice = autotune.autotune(systems, steps=128, long_steps=1024, log=log)
+    kw = autotune.apply(systems, choice)
+    g = dem.DemSystem(systems, use_graph=True, chunk=args.chunk, **kw)
+    g.prime()
+    t_batch = timed_steps(g, steps, 64)
+    builds_batch = g.stats()["builds"]
+    del g
+    torch.cuda.empty_cache()
+    log("sequential plain contexts")
+    t_seq = 0.0
+    for k, s in enumerate(systems):
+        gk = dem.DemSystem(s, use_graph=True, chunk=args.chunk, skin=kw["skin"][k], cell=kw["cell"][k],
+                           block=kw["block"], lanes=kw["lanes"])
+        gk.prime()
+        t_seq += timed_steps(gk, steps, 64)
+        del gk
+    torch.cuda.empty_cache()
+    log("equal-N plain system")
+    big = W.tiled_bed(ntot)
+    gb = dem.DemSystem(big, use_graph=True, chunk=args.chunk, block=kw["block"], lanes=kw["lanes"])
+    gb.prime()
+    t_big = timed_steps(gb, steps, 64)
+    del gb
+    torch.cuda.empty_cache()
+    log("two-level chute")
+    two = W.chute_two_level()
+    n2 = sum(s.n for s in two)
+    g2 = dem.DemSystem(two, use_graph=True, chunk=args.chunk)
+    g2.prime()
+    steps2 = 5000 if args.steps == 10000 else args.steps
+    t_two = timed_steps(g2, steps2, 64)
+    builds_two = g2.stats()["builds"]
+    del g2
+    t_two_seq = 0.0
+    for s in two:
+        gk = dem.DemSystem(s, use_graph=True, chunk=args.chunk)
+        gk.prime()
+        t_two_seq += timed_steps(gk, steps2, 64)
+        del gk
+    out = {
+        "suite": "batch", "unit": "particle-steps/s", "dtype": "f64", "data": "synthetic",
+        "batch64": {"systems": len(systems), "particles": ntot, "steps": steps,
+                    "batched": ntot * steps / t_batch, "sequential_plain": ntot * steps / t_seq,
+                    "equal_n_plain": big.n * steps / t_big, "equal_n_particles": big.n,
+                    "batched_vs_sequential": t_seq / t_batch,
+                    "batched_vs_equal_n": (ntot / t_batch) / (big.n / t_big),
+                    "list_builds_batched": builds_batch, "autotune": {k: choice[k] for k in
+                                                                       ("lanes", "block", "skin_factor", "cell_factor")}},
+        "two_level_chute": {"particles": n2, "steps": steps2, "batched": n2 * steps2 / t_two,
+                            "sequential_plain": n2 * steps2 / t_two_seq, "batched_vs_sequential": t_two_seq / t_two,
+                            "list_builds_batched": builds_two},
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +192,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--suite", choices=("plain", "batch"), default="plain",
+                    help="plain: the 1e6-sphere bed (default); batch: 64-system and two-level batches vs plain")
+    ap.add_argument("--no-autotune", action="store_true", help="batch suite: default launch shape and skin")
     ap.add_argument("--profile-pass", action="store_true",
                     help="a few non-graph steps plus a 256 MiB device copy (counter calibration), no JSON")
     args = ap.parse_args()
@@ -121,6 +213,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
+    if args.suite == "batch":
+        batch_suite(args)
+        return
     footprint = 80e-3 * (args.n / 1e6) ** 0.5
     log(f"generating the settled bed of {args.n} spheres")
     t0 = time.perf_counter()

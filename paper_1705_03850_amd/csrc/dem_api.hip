@@ -23,7 +23,7 @@ struct Layout {
     size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame;
     size_t nbr[2], cnt[2], xi[2], mask[2], ids[2];
     size_t cell_of, rank, order, cell_count, cell_start, scan_partial, shadow_d, shadow_i;
-    size_t pos[2], vel[2], spin[2], im;
+    size_t pos[2], vel[2], spin[2], im, sel, lcur;
     size_t total;
 };
 
@@ -167,6 +167,8 @@ Layout make_layout(const Geometry &g) {
         L.spin[b] = take(n * sizeof(D4));
     }
     L.im = take(n * sizeof(D2));
+    L.sel = take(g.sys.size() * 4);
+    L.lcur = take(g.sys.size() * 4);
     L.total = o;
     return L;
 }
@@ -192,7 +194,6 @@ struct dem_ctx {
     double *d_rho = nullptr;
     Flags *d_flags = nullptr;
     List lists[2];
-    int cur = 0;
     // host-side state machine
     bool masses = false, have_list = false, list_current = false, binned = false, frame_identity = true;
     bool forces_valid = false;
@@ -203,7 +204,9 @@ struct dem_ctx {
     int64_t grid_cap = 0;   // 0: resident capacity, set at init
     int lanes = 4;
     int cus = 256;
-    GraphSlot graphs[2];
+    GraphSlot graphs[8];          // replay graphs of 2^(k+3) fused steps
+    double gap_avg = 1e9;         // running estimate of steps between rebuilds
+    int64_t since_rebuild = 0;
     // per-kernel timing with HIP events (non-graph stepping only)
     bool timing = false;
     std::vector<hipEvent_t> ev;      // pairs (start, stop) recorded in this chunk
@@ -257,8 +260,8 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.n = c->geo.n;
     a.ncell = c->geo.ncell;
     a.flags = c->d_flags;
-    a.cur = c->lists[c->cur];
-    a.old = c->lists[1 - c->cur];
+    a.lst[0] = c->lists[0];
+    a.lst[1] = c->lists[1];
     a.cell_of = (int32_t *)(w + L.cell_of);
     a.rank = (int32_t *)(w + L.rank);
     a.order = (int32_t *)(w + L.order);
@@ -273,6 +276,8 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
         a.spin[b] = (D4 *)(w + L.spin[b]);
     }
     a.im = (D2 *)(w + L.im);
+    a.sel = (int32_t *)(w + L.sel);
+    a.lcur = (int32_t *)(w + L.lcur);
     return a;
 }
 
@@ -302,8 +307,10 @@ int flag_error(dem_ctx *c, const Flags &h) {
     return DEM_OK;
 }
 
-int do_bin(dem_ctx *c, const dem_state *s) {
+// all: rebuild every system; otherwise only those whose step flagged them
+int do_bin(dem_ctx *c, const dem_state *s, bool all) {
     KArgs a = kargs(c, s);
+    if (all || !c->have_list) HIPCALL(c, launch_fill_i32(a.sel, (int64_t)c->geo.sys.size(), 1, c->stream));
     HIPCALL(c, launch_bin(a, c->frame_identity ? 1 : 0, c->stream));
     c->binned = true;
     c->frame_identity = false;
@@ -311,12 +318,14 @@ int do_bin(dem_ctx *c, const dem_state *s) {
     return DEM_OK;
 }
 
-int do_neighbors(dem_ctx *c, const dem_state *s) {
+int do_neighbors(dem_ctx *c, const dem_state *s, bool clear_sel = true) {
     if (!c->binned) return fail(c, DEM_ERR_STATE, "dem_neighbors needs dem_bin on the current positions");
     int have_old = c->have_list ? 1 : 0;
-    c->cur = 1 - c->cur;  // build into the other buffer; the previous list becomes `old`
     KArgs a = kargs(c, s);
+    // each selected system builds into its other buffer, then switches to it
     HIPCALL(c, launch_neighbors(a, have_old, c->stream));
+    HIPCALL(c, launch_flip(a, c->stream));
+    if (clear_sel) HIPCALL(c, launch_fill_i32(a.sel, (int64_t)c->geo.sys.size(), 0, c->stream));
     HIPCALL(c, launch_ctrl(c->d_flags, 4, 1, c->stream));
     c->have_list = true;
     c->list_current = true;
@@ -359,14 +368,14 @@ int collect_times(dem_ctx *c) {
     return DEM_OK;
 }
 
-// One graph of `chunk` fused steps starting from packed buffer 0 (k = 0..chunk-1).
-int capture_graph(dem_ctx *c, const dem_state *s, GraphSlot &gs) {
+// One graph of `len` fused steps starting from packed buffer 0 (k = 0..len-1).
+int capture_graph(dem_ctx *c, const dem_state *s, GraphSlot &gs, int len) {
     if (gs.exec) { (void)hipGraphExecDestroy(gs.exec); gs.exec = nullptr; }
     KArgs a = kargs(c, s);
     hipGraph_t graph = nullptr;
     HIPCALL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < c->chunk && e == hipSuccess; ++k)
+    for (int k = 0; k < len && e == hipSuccess; ++k)
         e = launch_step(a, k & 1, 1, k, 1, c->count ? 1 : 0, c->stream);
     hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch during graph capture");
@@ -374,9 +383,9 @@ int capture_graph(dem_ctx *c, const dem_state *s, GraphSlot &gs) {
     hipError_t e3 = hipGraphInstantiate(&gs.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) { gs.exec = nullptr; return hip_fail(c, e3, "hipGraphInstantiate"); }
-    const void *key[10] = {c->lists[c->cur].nbr, nullptr};
+    const void *key[10] = {c->ws, nullptr};
     memcpy(gs.key, key, sizeof key);
-    gs.chunk = c->chunk;
+    gs.chunk = len;
     gs.count = c->count ? 1 : 0;
     return DEM_OK;
 }
@@ -461,6 +470,8 @@ int dem_reset(dem_ctx *c, const dem_state *s) {
     HIPCALL(c, launch_init_mass(a, c->stream));
     HIPCALL(c, launch_fill_f64(a.disp, 3 * c->geo.n, 0.0, c->stream));
     HIPCALL(c, launch_fill_f64(a.xiw, 3 * c->geo.n, 0.0, c->stream));
+    HIPCALL(c, launch_fill_i32(a.sel, (int64_t)c->geo.sys.size(), 0, c->stream));
+    HIPCALL(c, launch_fill_i32(a.lcur, (int64_t)c->geo.sys.size(), 0, c->stream));
     Flags h;
     if ((rc = read_flags(c, h))) return rc;
     if ((rc = flag_error(c, h))) return rc;
@@ -477,7 +488,7 @@ int dem_bin(dem_ctx *c, const dem_state *s) {
     int rc = check_state(c, s);
     if (rc) return rc;
     if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first");
-    return do_bin(c, s);
+    return do_bin(c, s, true);
 }
 
 int dem_neighbors(dem_ctx *c, const dem_state *s) {
@@ -527,7 +538,7 @@ int dem_set_launch(dem_ctx *c, int32_t lanes, int32_t max_blocks) {
     if (lanes > c->geo.block) return fail(c, DEM_ERR_ARG, "lanes must not exceed the block size");
     c->grid_cap = max_blocks;
     c->lanes = lanes;
-    for (GraphSlot &g : c->graphs) g.chunk = 0;  // re-capture with the new grid
+    for (GraphSlot &g : c->graphs) g.chunk = 0;  // re-capture with the new grid/lanes
     return DEM_OK;
 }
 
@@ -539,7 +550,7 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
     if (nsteps == 0 || c->geo.n == 0) return DEM_OK;
     if (!c->list_current) {
         // binned but no list yet: build it (f and t were permuted with the particles)
-        if ((rc = do_bin(c, s)) || (rc = do_neighbors(c, s))) return rc;
+        if ((rc = do_bin(c, s, true)) || (rc = do_neighbors(c, s))) return rc;
     }
     // Steps are numbered 1..nsteps.  The state of step q after its drift lives
     // in packed buffer (q-1)&1; the fused kernel of step q computes its forces
@@ -559,15 +570,26 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
     }
     while (q <= nsteps) {
         KArgs a = kargs(c, s);
-        if (c->use_graph && !c->timing && q == q0 && ((q - 1) & 1) == 0 && q + c->chunk - 1 <= nsteps - 1) {
-            GraphSlot &gs = c->graphs[c->cur];
-            const void *key[10] = {c->lists[c->cur].nbr, nullptr};
-            if (!gs.exec || memcmp(gs.key, key, sizeof key) || gs.chunk != c->chunk || gs.count != cnt)
-                if ((rc = capture_graph(c, s, gs))) return rc;
+        // group length: the full chunk, or shorter while rebuilds come often (a
+        // rebuild stops the group; the rest of it would run as empty launches)
+        int len = c->chunk;
+        if (c->gap_avg < 2.0 * c->chunk) {
+            len = 8;
+            while (2 * len <= c->chunk && 2 * len <= c->gap_avg / 2) len *= 2;
+            if (len > c->chunk) len = c->chunk;
+        }
+        int slot = 0;
+        while ((8 << slot) < len && slot < 7) ++slot;
+        if (c->use_graph && !c->timing && (8 << slot) == len && q == q0 && ((q - 1) & 1) == 0 &&
+            q + len - 1 <= nsteps - 1) {
+            GraphSlot &gs = c->graphs[slot];
+            const void *key[10] = {c->ws, nullptr};
+            if (!gs.exec || memcmp(gs.key, key, sizeof key) || gs.chunk != len || gs.count != cnt)
+                if ((rc = capture_graph(c, s, gs, len))) return rc;
             HIPCALL(c, hipGraphLaunch(gs.exec, c->stream));
-            q += c->chunk;
+            q += len;
         } else {
-            while (q <= nsteps && q - q0 < c->chunk) {
+            while (q <= nsteps && q - q0 < len) {
                 const int last = q == nsteps;
                 if ((rc = tic(c, last ? 2 : 1))) return rc;
                 HIPCALL(c, launch_step(a, (int)((q - 1) & 1), last ? 2 : 1, (int)(q - q0), 1, cnt, c->stream));
@@ -583,14 +605,22 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
             // arrays and repack into the same buffer
             const int64_t qa = h.abort_at - base;
             const int buf = (int)((qa - 1) & 1);
+            // only the systems that asked for it are unpacked, rebuilt and repacked
             if ((rc = tic(c, 3))) return rc;
-            HIPCALL(c, launch_unpack(a, buf, c->stream));
+            HIPCALL(c, launch_unpack(a, buf, 1, c->stream));
             c->binned = false;
-            if ((rc = do_bin(c, s)) || (rc = do_neighbors(c, s))) return rc;
+            if ((rc = do_bin(c, s, false)) || (rc = do_neighbors(c, s, false))) return rc;
             KArgs b = kargs(c, s);
-            HIPCALL(c, launch_pack(b, buf, 0, 0, 0, c->stream));
+            HIPCALL(c, launch_pack(b, buf, 2, 0, 0, c->stream));
+            HIPCALL(c, launch_fill_i32(b.sel, (int64_t)c->geo.sys.size(), 0, c->stream));
             if ((rc = toc(c))) return rc;
+            const double gap = (double)(c->since_rebuild + (qa - q0));
+            c->gap_avg = 0.5 * (c->gap_avg < 1e8 ? c->gap_avg : gap) + 0.5 * gap;
+            c->since_rebuild = 0;
             q = qa;
+        } else {
+            c->since_rebuild += q - q0;
+            if ((double)c->since_rebuild > c->gap_avg) c->gap_avg = (double)c->since_rebuild;
         }
         if (q <= nsteps) {
             HIPCALL(c, launch_ctrl(c->d_flags, 0, base + q, c->stream));
@@ -648,9 +678,14 @@ int dem_stats(dem_ctx *c, int64_t out[5]) {
     out[3] = (int64_t)h.wall_contacts;
     int64_t slots = 0;
     if (c->have_list && c->geo.n > 0) {
-        std::vector<int32_t> cnt(c->geo.n);
-        HIPCALL(c, hipMemcpy(cnt.data(), c->lists[c->cur].cnt, c->geo.n * 4, hipMemcpyDeviceToHost));
-        for (int32_t q : cnt) slots += q;
+        std::vector<int32_t> cnt[2], cur(c->geo.sys.size());
+        for (int b = 0; b < 2; ++b) {
+            cnt[b].resize(c->geo.n);
+            HIPCALL(c, hipMemcpy(cnt[b].data(), c->lists[b].cnt, c->geo.n * 4, hipMemcpyDeviceToHost));
+        }
+        HIPCALL(c, hipMemcpy(cur.data(), c->ws + c->lay.lcur, cur.size() * 4, hipMemcpyDeviceToHost));
+        for (size_t sy = 0; sy < c->geo.sys.size(); ++sy)
+            for (int64_t i = c->geo.sys[sy].p0; i < c->geo.sys[sy].p1; ++i) slots += cnt[cur[sy] & 1][i];
     }
     out[4] = slots;
     return DEM_OK;
@@ -661,27 +696,52 @@ int dem_stats(dem_ctx *c, int64_t out[5]) {
 namespace {
 
 struct HostList {
+    std::vector<uint8_t> which;
     std::vector<int32_t> nbr, cnt, ids, id_now;
     std::vector<uint64_t> mask;
     std::vector<double> xi, x, r, xiw;
 };
 
+// Host copy of every system's current list (rows taken from the buffer each
+// system currently uses).  `which` records that buffer per particle.
 int fetch_list(dem_ctx *c, const dem_state *s, HostList &H, bool with_xi, bool with_pos) {
     const int64_t n = c->geo.n, K = c->geo.kmax;
-    const List &L = c->lists[c->cur];
     HIPCALL(c, hipStreamSynchronize(c->stream));
+    std::vector<int32_t> cur(c->geo.sys.size());
+    HIPCALL(c, hipMemcpy(cur.data(), c->ws + c->lay.lcur, cur.size() * 4, hipMemcpyDeviceToHost));
+    H.which.assign(n, 0);
+    for (size_t sy = 0; sy < c->geo.sys.size(); ++sy)
+        for (int64_t i = c->geo.sys[sy].p0; i < c->geo.sys[sy].p1; ++i) H.which[i] = (uint8_t)(cur[sy] & 1);
     H.nbr.resize(K * n);
     H.cnt.resize(n);
     H.ids.resize(n);
     H.mask.resize(n);
-    HIPCALL(c, hipMemcpy(H.nbr.data(), L.nbr, K * n * 4, hipMemcpyDeviceToHost));
-    HIPCALL(c, hipMemcpy(H.cnt.data(), L.cnt, n * 4, hipMemcpyDeviceToHost));
-    HIPCALL(c, hipMemcpy(H.ids.data(), L.ids, n * 4, hipMemcpyDeviceToHost));
-    HIPCALL(c, hipMemcpy(H.mask.data(), L.mask, n * 8, hipMemcpyDeviceToHost));
+    if (with_xi) H.xi.resize(4 * K * n);
+    for (int b = 0; b < 2; ++b) {
+        const List &L = c->lists[b];
+        std::vector<int32_t> nbr(K * n), cnt(n), ids(n);
+        std::vector<uint64_t> mask(n);
+        std::vector<double> xi;
+        HIPCALL(c, hipMemcpy(nbr.data(), L.nbr, K * n * 4, hipMemcpyDeviceToHost));
+        HIPCALL(c, hipMemcpy(cnt.data(), L.cnt, n * 4, hipMemcpyDeviceToHost));
+        HIPCALL(c, hipMemcpy(ids.data(), L.ids, n * 4, hipMemcpyDeviceToHost));
+        HIPCALL(c, hipMemcpy(mask.data(), L.mask, n * 8, hipMemcpyDeviceToHost));
+        if (with_xi) {
+            xi.resize(4 * K * n);
+            HIPCALL(c, hipMemcpy(xi.data(), L.xi, 4 * K * n * 8, hipMemcpyDeviceToHost));
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (H.which[i] != b) continue;
+            H.cnt[i] = cnt[i];
+            H.ids[i] = ids[i];
+            H.mask[i] = mask[i];
+            for (int64_t q = 0; q < K; ++q) H.nbr[i * K + q] = nbr[i * K + q];
+            if (with_xi)
+                for (int64_t q = 0; q < 4 * K; ++q) H.xi[4 * K * i + q] = xi[4 * K * i + q];
+        }
+    }
     if (with_xi) {
-        H.xi.resize(4 * K * n);
         H.xiw.resize(3 * n);
-        HIPCALL(c, hipMemcpy(H.xi.data(), L.xi, 4 * K * n * 8, hipMemcpyDeviceToHost));
         HIPCALL(c, hipMemcpy(H.xiw.data(), c->ws + c->lay.xiw, 3 * n * 8, hipMemcpyDeviceToHost));
     }
     if (with_pos) {
@@ -822,9 +882,21 @@ int dem_import_history(dem_ctx *c, const dem_state *s, int64_t npairs, const int
         if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) m |= kWallBit;
         H.mask[i] = m;
     }
-    const List &L = c->lists[c->cur];
-    HIPCALL(c, hipMemcpy(L.xi, H.xi.data(), 4 * K * n * 8, hipMemcpyHostToDevice));
-    HIPCALL(c, hipMemcpy(L.mask, H.mask.data(), n * 8, hipMemcpyHostToDevice));
+    for (int b = 0; b < 2; ++b) {
+        // rows of the particles whose system uses buffer b
+        const List &L = c->lists[b];
+        std::vector<double> xi(4 * K * n);
+        std::vector<uint64_t> mask(n);
+        HIPCALL(c, hipMemcpy(xi.data(), L.xi, 4 * K * n * 8, hipMemcpyDeviceToHost));
+        HIPCALL(c, hipMemcpy(mask.data(), L.mask, n * 8, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) {
+            if (H.which[i] != b) continue;
+            mask[i] = H.mask[i];
+            for (int64_t q = 0; q < 4 * K; ++q) xi[4 * K * i + q] = H.xi[4 * K * i + q];
+        }
+        HIPCALL(c, hipMemcpy(L.xi, xi.data(), 4 * K * n * 8, hipMemcpyHostToDevice));
+        HIPCALL(c, hipMemcpy(L.mask, mask.data(), n * 8, hipMemcpyHostToDevice));
+    }
     HIPCALL(c, hipMemcpy(c->ws + c->lay.xiw, H.xiw.data(), 3 * n * 8, hipMemcpyHostToDevice));
     return DEM_OK;
 }

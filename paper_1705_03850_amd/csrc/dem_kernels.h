@@ -25,7 +25,8 @@ struct KArgs {
     int64_t n;             // particles, all systems
     int64_t ncell;         // cells, all systems
     Flags *flags;
-    List cur, old;         // current list and the one before it
+    List lst[2];           // two list buffers; system s uses lst[lcur[s]], builds into the other
+    int32_t *lcur;         // [nsys] current list buffer of each system
     // binning scratch
     int32_t *cell_of, *rank, *cell_count, *cell_start, *scan_partial, *order;
     double *shadow_d;      // [25][n]
@@ -33,6 +34,7 @@ struct KArgs {
     // packed step state, two buffers used alternately
     D4 *pos[2], *vel[2], *spin[2];
     D2 *im;                // (1/m, 1/I)
+    int32_t *sel;          // [nsys] 1 = system needs (or gets) a new list
 };
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
@@ -43,9 +45,13 @@ hipError_t launch_init_mass(const KArgs &a, hipStream_t st);
 hipError_t launch_phase(const KArgs &a, int phase, int k, int gate, hipStream_t st);
 hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st);
 hipError_t launch_neighbors(const KArgs &a, int have_old, hipStream_t st);
-// mode 0: pack only; 1: pack and do phase 0 of step `k` (gated)
+// after a build: the selected systems switch to their new list buffer
+hipError_t launch_flip(const KArgs &a, hipStream_t st);
+// mode 0: pack only; 1: pack and do phase 0 of step `k` (gated); 2: pack the
+// particles of the systems selected for a rebuild only
 hipError_t launch_pack(const KArgs &a, int dst, int mode, int k, int gate, hipStream_t st);
-hipError_t launch_unpack(const KArgs &a, int src, hipStream_t st);
+// selected != 0: only particles of systems selected for a rebuild
+hipError_t launch_unpack(const KArgs &a, int src, int selected, hipStream_t st);
 // force pass over packed buffer src: mode 0 forces only (to f, t); mode 1 fused
 // step (forces, kick, next kick + drift into buffer src^1); mode 2 last step
 // (forces, kick, f, t, x, v, w to the caller's arrays).

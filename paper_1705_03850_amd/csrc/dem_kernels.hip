@@ -49,6 +49,32 @@ __device__ inline int sys_of(const KArgs &a, int64_t i) {
     return lo;
 }
 
+__device__ inline int sys_of_any(const KArgs &a, int64_t i) {
+    int lo = 0, hi = a.nsys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (i < a.sys[mid].p1) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ inline List list_of(const KArgs &a, int sy, int which) {
+    // which 0: the system's current list, 1: its other buffer
+    const int b = a.lcur[sy] ^ which;
+    return b ? a.lst[1] : a.lst[0];
+}
+
+__device__ inline int sys_of_cell(const KArgs &a, int64_t c) {
+    int lo = 0, hi = a.nsys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a.sys[mid].c0 <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ inline double wrap_axis(double x, const SysDesc &s, int ax) {
     if (!s.periodic[ax]) return x;
     if (x >= s.hi[ax]) x -= s.L[ax];
@@ -250,9 +276,12 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const int32_t *in, in
     }
 }
 
+// Particles of the systems selected for a rebuild go to their cell's range;
+// the others keep their place (their list is kept, not rebuilt).
 template <bool BATCH>
 __global__ void k_bin_place(KArgs a) {
     FOR_EACH_PARTICLE(a.n, i) {
+        if (!a.sel[sys_of<BATCH>(a, i)]) continue;
         int32_t c = a.cell_of[i];
         a.order[a.cell_start[c] + a.rank[i]] = (int32_t)i;
     }
@@ -262,6 +291,7 @@ __global__ void k_bin_place(KArgs a) {
 __global__ void k_cell_sort(KArgs a) {
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.ncell;
          c += (int64_t)gridDim.x * blockDim.x) {
+        if (!a.sel[sys_of_cell(a, c)]) continue;
         int32_t b = a.cell_start[c], e = a.cell_start[c + 1];
         if (e - b > kCellSortMax) {
             atomicOr(&a.flags->err, kErrCellOverflow);
@@ -284,6 +314,7 @@ __global__ void k_cell_sort(KArgs a) {
 __global__ void k_gather(KArgs a, int frame_identity) {
     const int64_t n = a.n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!a.sel[sys_of_any(a, i)]) continue;  // not rebuilt: stays in place
         const int64_t src = a.order[i];
         double *sd = a.shadow_d;
         for (int c = 0; c < 3; ++c) {
@@ -309,6 +340,7 @@ __global__ void k_gather(KArgs a, int frame_identity) {
 __global__ void k_scatter_back(KArgs a) {
     const int64_t n = a.n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!a.sel[sys_of_any(a, i)]) continue;
         const double *sd = a.shadow_d;
         for (int c = 0; c < 3; ++c) {
             a.x[c * n + i] = sd[(0 + c) * n + i];
@@ -344,9 +376,11 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a, int have_old) {
     int32_t *rid = lds + threadIdx.x * 2 * kmax;
     int32_t *ridx = rid + kmax;
     int maxrow = 0;
-    const List L = a.cur, O = a.old;
     FOR_EACH_PARTICLE(n, i) {
-        const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
+        const int sy = sys_of<BATCH>(a, i);
+        const SysDesc &s = a.sys[sy];
+        if (!a.sel[sy]) continue;  // system keeps its list
+        const List O = list_of(a, sy, 0), L = list_of(a, sy, 1);
         const double xi = a.x[i], yi = a.x[n + i], zi = a.x[2 * n + i], ri = a.r[i];
         const int ccx = cell_coord(xi, s, 0), ccy = cell_coord(yi, s, 1), ccz = cell_coord(zi, s, 2);
         int count = 0;
@@ -416,6 +450,12 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a, int have_old) {
     if (maxrow) atomicMax(&a.flags->max_row, maxrow);
 }
 
+// After a build: the selected systems switch to the buffer just written.
+__global__ void k_flip(KArgs a) {
+    for (int sy = threadIdx.x; sy < a.nsys; sy += blockDim.x)
+        if (a.sel[sy]) a.lcur[sy] ^= 1;
+}
+
 // ------------------------------------------------------------- fused step
 
 // Caller arrays (structure of arrays) -> packed buffer `dst`.  mode 1 also
@@ -432,7 +472,9 @@ __global__ void k_pack(KArgs a, int dst, int mode, int k, int gate) {
     bool need = false, bad = false;
     D4 *P = a.pos[dst], *V = a.vel[dst], *S = a.spin[dst];
     FOR_EACH_PARTICLE(n, i) {
-        const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
+        const int sy = sys_of<BATCH>(a, i);
+        if (mode == 2 && !a.sel[sy]) continue;
+        const SysDesc &s = a.sys[sy];
         const double im = a.inv_m[i], iI = a.inv_I[i];
         double x[3], v[3], w[3];
         for (int c = 0; c < 3; ++c) {
@@ -450,23 +492,28 @@ __global__ void k_pack(KArgs a, int dst, int mode, int k, int gate) {
                 a.disp[c * n + i] = d;
                 dsq += d * d;
             }
-            if (!(dsq <= s.disp_thr2)) need = true;
+            if (!(dsq <= s.disp_thr2)) {
+                need = true;
+                a.sel[sys_of<BATCH>(a, i)] = 1;
+            }
             if (!isfinite(x[0] + x[1] + x[2] + v[0] + v[1] + v[2])) bad = true;
         }
         P[i] = D4{x[0], x[1], x[2], a.r[i]};
         V[i] = D4{v[0], v[1], v[2], a.m[i]};
-        S[i] = D4{w[0], w[1], w[2], (double)a.type[i]};
+        S[i] = D4{w[0], w[1], w[2], (double)(sy * 16 + a.type[i])};  // system and type in one exact code
         a.im[i] = D2{im, iI};
     }
     if (bad) atomicOr(&a.flags->err, kErrNonFinite);
     if (need && gate) a.flags->abort_at = step;
 }
 
-// Packed buffer `src` -> caller arrays x, v, w.
-__global__ void k_unpack(KArgs a, int src) {
+// Packed buffer `src` -> caller arrays x, v, w (with selected: only the
+// systems selected for a rebuild).
+__global__ void k_unpack(KArgs a, int src, int selected) {
     const int64_t n = a.n;
     const D4 *P = a.pos[src], *V = a.vel[src], *S = a.spin[src];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (selected && !a.sel[sys_of_any(a, i)]) continue;
         const D4 p = P[i], v = V[i], w = S[i];
         a.x[i] = p.x; a.x[n + i] = p.y; a.x[2 * n + i] = p.z;
         a.v[i] = v.x; a.v[n + i] = v.y; a.v[2 * n + i] = v.z;
@@ -488,41 +535,23 @@ __global__ void k_unpack(KArgs a, int src) {
 //           does nothing once an earlier step asked for a rebuild);
 //   MODE 2: last step of a call -- forces, kick 1/2, and f, t, x, v, w
 //           written to the caller's arrays (gated).
+// One particle of the force pass (see k_step): every lane of its group calls
+// this with the same i; sy is the particle's system (wave-uniform).
 template <bool BATCH, bool COUNT, int MODE, int G>
-__global__ void __launch_bounds__(256) k_step(KArgs a, int src, int k, int update) {
-    int64_t step = 0;
-    if (MODE != 0) {
-        step = a.flags->step_base + k;
-        if (a.flags->abort_at <= step) return;
-        update = 1;
-    }
+__device__ __forceinline__ void step_particle(const KArgs &a, int src, int update, int64_t i, int sy, const D4 &pi,
+                                              const D4 &vi, const D4 &si, int code, int g, int gbase,
+                                              uint64_t gmask, unsigned &ncont, unsigned &nwall, bool &need,
+                                              bool &bad) {
     const int64_t n = a.n;
-    const List L = a.cur;
     const D4 *__restrict__ P = a.pos[src];
     const D4 *__restrict__ V = a.vel[src];
     const D4 *__restrict__ S = a.spin[src];
     const int64_t kmax = a.kmax;
-    const int g = threadIdx.x % G;
-    const int ppb = blockDim.x / G;                        // particles per tile
-    const int gbase = (threadIdx.x % warpSize) / G * G;    // first lane of the group in the wave
-    const uint64_t gmask = (1ull << G) - 1;
-    unsigned ncont = 0, nwall = 0;
-    bool need = false, bad = false;
-    const int64_t ntiles = (n + ppb - 1) / ppb;
-    const int per = gridDim.x / kXcd;
-    const int64_t chunk = (ntiles + kXcd - 1) / kXcd;
-    const int64_t t0 = (blockIdx.x % kXcd) * chunk;
-    const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
-    for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {
-        const int64_t i = t * ppb + threadIdx.x / G;
-        if (i >= n) continue;
-        const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
+        const int ti = code & 15;
+        const SysDesc &s = a.sys[sy];
+        const List L = list_of(a, sy, 0);
         const PairCoef *coef = a.coef + s.coef0;
-        const D4 pi = P[i];
-        const D4 vi = V[i];
-        const D4 si = S[i];
         const double ri = pi.w, mi = vi.w;
-        const int ti = (int)si.w;
         double Fx = mi * s.g[0], Fy = mi * s.g[1], Fz = mi * s.g[2];
         double Tx = 0.0, Ty = 0.0, Tz = 0.0;
         const int cnt = L.cnt[i];
@@ -556,7 +585,7 @@ __global__ void __launch_bounds__(256) k_step(KArgs a, int src, int k, int updat
                 c.wsx = ri * si.x + pj.w * sj.x;
                 c.wsy = ri * si.y + pj.w * sj.y;
                 c.wsz = ri * si.z + pj.w * sj.z;
-                const PairCoef pc = coef[ti * s.ntypes + (int)sj.w];
+                const PairCoef pc = coef[ti * s.ntypes + ((int)sj.w & 15)];
                 double ftx, fty, ftz, nx, ny, nz, fn;
                 if (contact_force(c, false, pc, s.dt, update != 0, hx, hy, hz, fx, fy, fz, ftx, fty, ftz, nx, ny,
                                   nz, fn)) {
@@ -609,12 +638,12 @@ __global__ void __launch_bounds__(256) k_step(KArgs a, int src, int k, int updat
                 }
             }
         }
-        if (g != 0) continue;
+        if (g != 0) return;
         if (update && nmask != mask) L.mask[i] = nmask;
         if (MODE == 0) {
             a.f[i] = Fx; a.f[n + i] = Fy; a.f[2 * n + i] = Fz;
             a.t[i] = Tx; a.t[n + i] = Ty; a.t[2 * n + i] = Tz;
-            continue;
+            return;
         }
         // kick 1/2 with the new forces
         const D2 im = a.im[i];
@@ -641,12 +670,54 @@ __global__ void __launch_bounds__(256) k_step(KArgs a, int src, int k, int updat
             dsq += ddx * ddx;
             dsq += ddy * ddy;
             dsq += ddz * ddz;
-            if (!(dsq <= s.disp_thr2)) need = true;
+            if (!(dsq <= s.disp_thr2)) {
+                need = true;
+                a.sel[sy] = 1;
+            }
             if (!isfinite(x + y + z + vx + vy + vz)) bad = true;
             a.pos[src ^ 1][i] = D4{x, y, z, ri};
             a.vel[src ^ 1][i] = D4{vx, vy, vz, mi};
             a.spin[src ^ 1][i] = D4{wx, wy, wz, si.w};
         }
+}
+
+template <bool BATCH, bool COUNT, int MODE, int G>
+__global__ void __launch_bounds__(256) k_step(KArgs a, int src, int k, int update) {
+    int64_t step = 0;
+    if (MODE != 0) {
+        step = a.flags->step_base + k;
+        if (a.flags->abort_at <= step) return;
+        update = 1;
+    }
+    const int64_t n = a.n;
+    const D4 *__restrict__ P = a.pos[src];
+    const D4 *__restrict__ V = a.vel[src];
+    const D4 *__restrict__ S = a.spin[src];
+    const int g = threadIdx.x % G;
+    const int ppb = blockDim.x / G;                        // particles per tile
+    const int gbase = (threadIdx.x % warpSize) / G * G;    // first lane of the group in the wave
+    const uint64_t gmask = (1ull << G) - 1;
+    unsigned ncont = 0, nwall = 0;
+    bool need = false, bad = false;
+    const int64_t ntiles = (n + ppb - 1) / ppb;
+    const int per = gridDim.x / kXcd;
+    const int64_t chunk = (ntiles + kXcd - 1) / kXcd;
+    const int64_t t0 = (blockIdx.x % kXcd) * chunk;
+    const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
+    for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {
+        const int64_t i = t * ppb + threadIdx.x / G;
+        if (!BATCH) {
+            if (i >= n) continue;
+            const D4 pi = P[i], vi = V[i], si = S[i];
+            step_particle<BATCH, COUNT, MODE, G>(a, src, update, i, 0, pi, vi, si, (int)si.w, g, gbase, gmask, ncont,
+                                                 nwall, need, bad);
+            continue;
+        }
+        if (i >= n) continue;
+        const D4 pi = P[i], vi = V[i], si = S[i];
+        const int code = (int)si.w;
+        step_particle<BATCH, COUNT, MODE, G>(a, src, update, i, code >> 4, pi, vi, si, code, g, gbase, gmask, ncont,
+                                             nwall, need, bad);
     }
     if (bad) atomicOr(&a.flags->err, kErrNonFinite);
     if (MODE == 1 && need) a.flags->abort_at = step + 1;
@@ -749,6 +820,11 @@ hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st) {
     CHECK_LAUNCH();
 }
 
+hipError_t launch_flip(const KArgs &a, hipStream_t st) {
+    k_flip<<<1, 64, 0, st>>>(a);
+    CHECK_LAUNCH();
+}
+
 hipError_t launch_neighbors(const KArgs &a, int have_old, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
     // two LDS rows of kmax ints per thread; keep the workgroup at <= 32 KB
@@ -768,9 +844,9 @@ hipError_t launch_pack(const KArgs &a, int dst, int mode, int k, int gate, hipSt
     CHECK_LAUNCH();
 }
 
-hipError_t launch_unpack(const KArgs &a, int src, hipStream_t st) {
+hipError_t launch_unpack(const KArgs &a, int src, int selected, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    k_unpack<<<flat_grid(a.n, 256), 256, 0, st>>>(a, src);
+    k_unpack<<<flat_grid(a.n, 256), 256, 0, st>>>(a, src, selected);
     CHECK_LAUNCH();
 }
 

@@ -265,6 +265,25 @@ def chute_gravity(angle_deg: float = 30.0):
     return (G0 * math.sin(a), 0.0, -G0 * math.cos(a))
 
 
+def tiled_bed(n_total: int, seed: int = 6) -> System:
+    """A settled bed of about n_total spheres made of a periodic bed of
+    n_total/4 spheres repeated 2 x 2 in x and y (exact, since the tile is
+    periodic); used as one plain system of the same size as a batch."""
+    n = max(1, int(round(n_total / 4)))
+    fp = 80e-3 * math.sqrt(n / 1e6)
+    tile = settled_bed(seed=seed, n=n, footprint=fp)
+    xs, rs, ids = [], [], []
+    for k, (ox, oy) in enumerate(((0, 0), (1, 0), (0, 1), (1, 1))):
+        xs.append(tile.x + np.array([ox * fp, oy * fp, 0.0]))
+        rs.append(tile.r)
+        ids.append(tile.id.astype(np.int64) + k * n)
+    x = np.concatenate(xs); r = np.concatenate(rs); idv = np.concatenate(ids).astype(np.int32)
+    m = x.shape[0]
+    return System(x=x, v=np.zeros((m, 3)), w=np.zeros((m, 3)), r=r, type=np.zeros(m, np.int32), id=idv,
+                  materials=[MAT_A], lo=(0.0, 0.0, 0.0), hi=(2 * fp, 2 * fp, tile.hi[2]), periodic=(1, 1, 0),
+                  wall_z0=1, g=(0.0, 0.0, -G0), dt=1e-6, skin=tile.skin, steps=2000, name=f"tiled_bed_{m}")
+
+
 def _system_from_bed(pos, r, types, materials, Lx, Ly, g, dt, skin, steps, name, alpha, v=None, rng=None):
     n = r.shape[0]
     rmax = float(r.max())
@@ -275,54 +294,107 @@ def _system_from_bed(pos, r, types, materials, Lx, Ly, g, dt, skin, steps, name,
 
 
 def chute_two_level(seed: int = 3, n_fine: int = 500_000, n_coarse: int = 200_000):
-    """Two systems of one batch: coarse (alpha = 4, r = 4 mm, 1000 x 400 mm) and
-    fine (r = 1 mm, 200 x 100 mm), both on a periodic 30 degree chute.
+    """Two systems of one batch on a periodic 30 degree chute (Sec. 2.3: a fine
+    region embedded in a coarse-grain domain):
 
-    The fine particles within 10 mm of the fine block's top face form the
-    coupling shell; their indices are returned in ``meta['shell']`` (the shell
-    receives an external-force array that stays zero until the coupling
-    controllers exist).
+    * coarse: n_coarse spheres of r = 4 mm (alpha = 4), 1000 x 400 mm footprint;
+    * fine:   n_fine spheres of r = 1 mm, 200 x 100 mm footprint.
+
+    Footprints scale with sqrt(n) for smaller test sizes.  The fine particles
+    within 10 mm of the fine bed's top face form the coupling shell; their
+    indices are in ``meta['shell']`` (the shell receives an external-force array
+    that stays zero until the coupling controllers exist).  Both use dt = 1e-6 s.
     """
-    rng = np.random.default_rng(seed)
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(2)
     g = chute_gravity(30.0)
-    rc = np.full(n_coarse, 4e-3)
     Lc = (1000e-3 * math.sqrt(n_coarse / 200_000), 400e-3 * math.sqrt(n_coarse / 200_000))
-    pc, _ = bed(n_coarse, rc, Lc[0], Lc[1], rng, strain_bottom=0.01)
+    Lf = (200e-3 * math.sqrt(n_fine / 500_000), 100e-3 * math.sqrt(n_fine / 500_000))
+    jobs = [(n_coarse, (4.0, 0.0), Lc[0], Lc[1], 0.01, kids[0]), (n_fine, (1.0, 0.0), Lf[0], Lf[1], 0.01, kids[1])]
+    (pc, rc, _), (pf, rf, _) = _cached_beds(f"chute{seed}", jobs)
     coarse = _system_from_bed(pc, rc, np.zeros(n_coarse, np.int32), [MAT_A], Lc[0], Lc[1], g, 1e-6,
                               0.1 * 4e-3, 5000, "chute_coarse", 4.0)
-    rf = np.full(n_fine, 1e-3)
-    Lf = (200e-3 * math.sqrt(n_fine / 500_000), 100e-3 * math.sqrt(n_fine / 500_000))
-    pf, _ = bed(n_fine, rf, Lf[0], Lf[1], rng, strain_bottom=0.01)
     fine = _system_from_bed(pf, rf, np.zeros(n_fine, np.int32), [MAT_A], Lf[0], Lf[1], g, 1e-6, 0.1e-3, 5000,
                             "chute_fine", 1.0)
     fine.meta["shell"] = np.nonzero(pf[:, 2] > pf[:, 2].max() - 10e-3)[0].astype(np.int64)
     return [coarse, fine]
 
 
+def _deposit_job(args):
+    """Worker: one bed from its own seed (used to build batches in parallel)."""
+    n, r_args, Lx, Ly, strain, child = args
+    rng = np.random.default_rng(child)
+    alpha, p = r_args
+    r = alpha * 1e-3 * rng.uniform(1.0 - p, 1.0 + p, n)
+    pos, stuck = bed(n, r, Lx, Ly, rng, strain_bottom=strain)
+    return pos, r, stuck
+
+
+def _cached_beds(tag: str, jobs, workers: int | None = None):
+    """Run deposition jobs (in worker processes), caching each result on disk."""
+    out = [None] * len(jobs)
+    todo = []
+    paths = []
+    for k, job in enumerate(jobs):
+        path = _cache_path(f"{tag}_{k}_{job[0]}_{job[1]!r}_{job[2]!r}_{job[3]!r}_{job[4]!r}_{job[5].entropy}_{job[5].spawn_key}")
+        paths.append(path)
+        if path and os.path.exists(path):
+            with np.load(path, allow_pickle=False) as z:
+                out[k] = (z["x"], z["r"], int(z["stuck"]))
+        else:
+            todo.append(k)
+    if todo:
+        nw = workers or min(16, os.cpu_count() or 1, len(todo))
+        if nw > 1:
+            import concurrent.futures as cf
+            import multiprocessing as mp
+            with cf.ProcessPoolExecutor(max_workers=nw, mp_context=mp.get_context("fork")) as ex:
+                res = list(ex.map(_deposit_job, [jobs[k] for k in todo]))
+        else:
+            res = [_deposit_job(jobs[k]) for k in todo]
+        for k, rr in zip(todo, res):
+            out[k] = rr
+            if paths[k]:
+                tmp = paths[k] + f".{os.getpid()}.tmp.npz"
+                np.savez(tmp, x=rr[0], r=rr[1], stuck=rr[2])
+                os.replace(tmp, paths[k])
+    return out
+
+
 def batch_systems(seed: int = 4, count: int = 64, n_lo: int = 5_000, n_hi: int = 200_000,
-                  dt_scaled: bool = True):
+                  dt_scaled: bool = True, scale: float = 1.0):
     """``count`` independent beds: N log-uniform in [n_lo, n_hi], alpha in {1,2,4,8},
     r = alpha U[1-p, 1+p] mm with p ~ U(0, 0.2), footprint aspect U(1, 4), bed
-    depth about 20 alpha mm; dt = alpha * 1e-6 s when ``dt_scaled``."""
-    rng = np.random.default_rng(seed)
-    systems = []
+    depth about 20 alpha mm; dt = alpha * 1e-6 s when ``dt_scaled`` (Sec. 3: the
+    time step may grow with the particle size).  ``scale`` multiplies every N
+    (for small test batches).  The per-system draws come from ``seed``; each bed
+    is deposited from its own child seed, so beds can be built in parallel."""
+    ss = np.random.SeedSequence(seed)
+    rng = np.random.default_rng(ss)
+    children = ss.spawn(count)
+    params = []
     for s in range(count):
-        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        n = max(8, int(round(scale * math.exp(rng.uniform(math.log(n_lo), math.log(n_hi))))))
         alpha = float(rng.choice([1, 2, 4, 8]))
         p = rng.uniform(0.0, 0.2)
-        r = alpha * 1e-3 * rng.uniform(1.0 - p, 1.0 + p, n)
         aspect = rng.uniform(1.0, 4.0)
         depth = 20e-3 * alpha
-        area = float(np.sum(4.0 / 3.0 * math.pi * r ** 3)) / (0.58 * depth)
+        mean_r3 = (alpha * 1e-3) ** 3 * (1.0 + p * p)          # E[r^3] for r = alpha U[1-p, 1+p]
+        area = n * 4.0 / 3.0 * math.pi * mean_r3 / (0.58 * depth)
         Lx = math.sqrt(area * aspect)
         Ly = area / Lx
-        rmax = float(r.max())
+        rmax = alpha * 1e-3 * (1.0 + p)
         cut = 2.0 * rmax * 1.1
         Lx = max(Lx, 3.0 * cut); Ly = max(Ly, 3.0 * cut)
-        pos, _ = bed(n, r, Lx, Ly, rng, strain_bottom=0.005)
+        params.append((n, alpha, p, Lx, Ly))
+    jobs = [(n, (alpha, p), Lx, Ly, 0.005, children[k]) for k, (n, alpha, p, Lx, Ly) in enumerate(params)]
+    beds = _cached_beds(f"batch{seed}", jobs)
+    systems = []
+    for k, ((n, alpha, p, Lx, Ly), (pos, r, _)) in enumerate(zip(params, beds)):
         dt = alpha * 1e-6 if dt_scaled else 1e-6
+        rmax = float(r.max())
         systems.append(_system_from_bed(pos, r, np.zeros(n, np.int32), [MAT_A], Lx, Ly, (0.0, 0.0, -G0), dt,
-                                        0.1 * rmax, 2000, f"batch_{s}", alpha))
+                                        0.1 * rmax, 2000, f"batch_{k}", alpha))
     return systems
 
 

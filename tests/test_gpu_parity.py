@@ -261,14 +261,17 @@ def test_lanes_do_not_change_results(lanes):
 
 def test_batch_equals_separate_systems():
     """Two systems of different coarse-grain factor in one context evolve exactly
-    as each alone (Sec. 2.3 levels as a batch)."""
+    as each alone (Sec. 2.3 levels as a batch).  The first system's small skin
+    makes it ask for a new list every few steps; only that system is rebuilt."""
     a = W.plain_fcc()
+    a.skin = 3e-6
     b = W.plain_fcc(seed=9)
     b.x = b.x * 2.0; b.r = b.r * 2.0; b.hi = tuple(2 * q for q in b.hi); b.skin *= 2; b.dt *= 2
     bg = gpu([a, b])
     bg.prime()
     bg.step(120)
     hb = bg.host()
+    assert bg.stats()["builds"] > 5
     for k, s in enumerate((a, b)):
         g = gpu(s)
         g.prime()
@@ -277,6 +280,37 @@ def test_batch_equals_separate_systems():
         sl = slice(int(bg.offsets[k]), int(bg.offsets[k + 1]))
         for key in ("x", "v", "w", "f", "t"):
             assert np.array_equal(hb[key][sl], h[key]), (k, key)
+
+
+def test_batch_of_64_systems():
+    """The 64-system workload at 5 % size (polydisperse, alpha in {1, 2, 4, 8},
+    dt = alpha 1e-6 s): batched with graph replay equals systems run alone, and a
+    system of the batch matches the oracle after 40 steps."""
+    systems = W.batch_systems(scale=0.05)
+    bg = gpu(systems, use_graph=True, chunk=16)
+    bg.prime()
+    bg.step(40)
+    hb = bg.host()
+    for k in (0, 7, 33, 63):
+        s = systems[k]
+        g = gpu(s)
+        g.prime()
+        g.step(40)
+        h = g.host()
+        sl = slice(int(bg.offsets[k]), int(bg.offsets[k + 1]))
+        for key in ("x", "v", "w", "f", "t"):
+            assert np.array_equal(hb[key][sl], h[key]), (k, key)
+    k = 7
+    s = systems[k]
+    o = O.Oracle(s)
+    o.forces(False)
+    o.step(40)
+    X = by_id(s, o.state()["x"])
+    sl = slice(int(bg.offsets[k]), int(bg.offsets[k + 1]))
+    d = hb["x"][sl] - X
+    d[:, 0] -= s.hi[0] * np.round(d[:, 0] / s.hi[0])
+    d[:, 1] -= s.hi[1] * np.round(d[:, 1] / s.hi[1])
+    assert np.max(np.abs(d)) <= 1e-9 * max(s.hi)
 
 
 def test_capacity_error_reported():

@@ -591,6 +591,23 @@ void orc_tan_free(void *h) { delete (SimT *)h; }
 void orc_tan_forces(void *h, int update_history) { forces(*(SimT *)h, update_history != 0); }
 void orc_tan_step(void *h, int nsteps) { step(*(SimT *)h, nsteps); }
 
+/* Value and tangent of one per-particle vector: which = 0..4 for x, v, w, f, t;
+ * val[n*3], tan[n*3*6] (direction fastest).  Either pointer may be null. */
+void orc_tan_get_ext(void *h, int which, double *val, double *tan) {
+    SimT *s = (SimT *)h;
+    for (size_t i = 0; i < s->p.size(); ++i) {
+        const Particle<Dual> &q = s->p[i];
+        const V3<Dual> *vec[5] = {&q.x, &q.v, &q.w, &q.f, &q.t};
+        const V3<Dual> &u = *vec[which < 0 || which > 4 ? 0 : which];
+        const Dual *c3[3] = {&u.x, &u.y, &u.z};
+        for (int c = 0; c < 3; ++c) {
+            if (val) val[3 * i + c] = c3[c]->v;
+            if (tan)
+                for (int k = 0; k < NDIR; ++k) tan[(3 * i + c) * NDIR + k] = c3[c]->d[k];
+        }
+    }
+}
+
 /* Values and tangents of x and v: val[n*3], tan[n*3*6] (direction fastest). */
 void orc_tan_get(void *h, double *xv, double *xt, double *vv, double *vt) {
     SimT *s = (SimT *)h;

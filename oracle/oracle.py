@@ -73,6 +73,7 @@ def lib():
         L.orc_tan_forces.argtypes = [vp, ctypes.c_int]
         L.orc_tan_step.argtypes = [vp, ctypes.c_int]
         L.orc_tan_get.argtypes = [vp, _dp, _dp, _dp, _dp]
+        L.orc_tan_get_ext.argtypes = [vp, ctypes.c_int, _dp, _dp]
         _lib = L
     return _lib
 
@@ -197,3 +198,10 @@ class Oracle:
         xt = np.empty((self.n, 3, 6)); vt = np.empty((self.n, 3, 6))
         self.L.orc_tan_get(self.h, _d(xv), _d(xt), _d(vv), _d(vt))
         return xv, xt, vv, vt
+
+    def tan_vector(self, name: str):
+        """Value (n,3) and tangent (n,3,6) of one of x, v, w, f, t."""
+        which = ("x", "v", "w", "f", "t").index(name)
+        val = np.empty((self.n, 3)); tan = np.empty((self.n, 3, 6))
+        self.L.orc_tan_get_ext(self.h, which, _d(val), _d(tan))
+        return val, tan

@@ -178,6 +178,82 @@ def batch_suite(args):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_suite(args):
+    """Adjoint against plain on the chute calibration workload (one JSON line).
+
+    50,000 spheres, two types 50/50 (r ~ U[0.9, 1.1] mm), 30-degree periodic
+    chute, 200 steps, checkpoints every 20 steps.  Loss: mean squared difference
+    of the 20-bin mass-flux profile from the oracle's profile at a perturbed
+    parameter set (tests/golden/chute_flux_target.json).
+      plain    -- dem_step over the 200 steps (graph replay), after one force evaluation;
+      adjoint  -- DemRollout forward (windows + checkpoints) and loss.backward()
+                  (recompute of every window + reverse sweep + parameter gradient).
+    Reports (forward + backward) / plain, the parts, and the device memory."""
+    import numpy as np
+    import torch
+
+    from paper_1705_03850_amd import dem
+    from paper_1705_03850_amd import rollout as R
+    from paper_1705_03850_amd.inputs import workloads as W
+
+    with open(os.path.join(ROOT, "tests", "golden", "chute_flux_target.json")) as fh:
+        tgt = json.load(fh)
+    steps, window, reps = tgt["steps"], args.window, 3
+    log("generating the 50,000-sphere chute")
+    s = W.chute_adjoint()
+    H0, Lx, Ly = s.meta["H0"], s.hi[0] - s.lo[0], s.hi[1] - s.lo[1]
+    target = torch.tensor(tgt["target_flux"], dtype=torch.float64, device="cuda")
+    t_plain = []
+    g = dem.DemSystem(s, use_graph=True, chunk=20)
+    for _ in range(reps + 1):
+        g.load_state()
+        g.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.prime()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t_plain.append(time.perf_counter() - t0)
+    plain_builds = g.stats()["builds"]
+    del g
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    g = dem.DemSystem(s)
+    adj = g.adjoint(steps, window=window)
+    t_fwd, t_bwd = [], []
+    for _ in range(reps + 1):
+        g.load_state()
+        g.reset()
+        theta = R.theta_of(s.materials).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, v, w = R.rollout(theta, adj)
+        flux = R.mass_flux_profile(x, v, R.masses(g), H0, Lx, Ly)
+        loss = ((flux - target) ** 2).mean()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t_bwd.append(time.perf_counter() - t1)
+        t_fwd.append(t1 - t0)
+    info = adj.info()
+    tp, tf, tb = (float(np.median(t[1:])) for t in (t_plain, t_fwd, t_bwd))
+    out = {
+        "suite": "adjoint", "workload": "chute_adjoint(seed=5, n=50000), 200 steps, flux loss in 20 bins",
+        "n": s.n, "steps": steps, "window": window, "dtype": "f64", "data": "synthetic",
+        "plain_forward_s": tp, "adjoint_forward_s": tf, "backward_s": tb,
+        "adjoint_vs_plain": (tf + tb) / tp, "backward_vs_plain": tb / tp,
+        "plain_particle_steps_per_s": s.n * steps / tp,
+        "windows": info["windows"], "rebuilds": info["rebuilds"], "plain_list_builds": plain_builds,
+        "adjoint_workspace_bytes": info["bytes"], "context_workspace_bytes": g.ws_bytes,
+        "peak_torch_bytes": torch.cuda.max_memory_allocated(),
+        "loss": float(loss.detach().cpu()), "grad": {"E": theta.grad[0].tolist(), "e": theta.grad[1].tolist(),
+                                                     "mu": theta.grad[2].tolist()},
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,7 +268,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--suite", choices=("plain", "batch"), default="plain",
+    ap.add_argument("--window", type=int, default=20, help="adjoint suite: steps per checkpoint window")
+    ap.add_argument("--suite", choices=("plain", "batch", "adjoint"), default="plain",
                     help="plain: the 1e6-sphere bed (default); batch: 64-system and two-level batches vs plain")
     ap.add_argument("--no-autotune", action="store_true", help="batch suite: default launch shape and skin")
     ap.add_argument("--profile-pass", action="store_true",
@@ -213,6 +290,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
+    if args.suite == "adjoint":
+        adjoint_suite(args)
+        return
     if args.suite == "batch":
         batch_suite(args)
         return

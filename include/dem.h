@@ -225,6 +225,72 @@ int dem_export_wall(dem_ctx *ctx, const dem_state *s, int32_t *id, double *xi, i
 int dem_import_history(dem_ctx *ctx, const dem_state *s, int64_t npairs, const int32_t *id_i, const int32_t *id_j,
                        const double *xi, int64_t nwall, const int32_t *wall_id, const double *wall_xi);
 
+/* ---------------------------------------------------------------------------
+ * Material parameters and gradients with respect to them.
+ *
+ * The per-type E, e and mu enter the contact law through Eq. (6) (stiffnesses
+ * from E* and G*, damping from beta(e)) and Eq. (5) (the Coulomb cap).  The
+ * adjoint calls below give dL/dE, dL/de and dL/dmu of a scalar L of the
+ * final state of a rollout (reverse mode, hand-written for the kernels).
+ * ------------------------------------------------------------------------- */
+
+/* Replace the materials of system `sys` (ntypes entries, as in its
+ * configuration); the folded coefficients are recomputed and uploaded.  rho
+ * must be unchanged (masses are fixed at dem_reset): DEM_ERR_ARG otherwise,
+ * or for invalid values.  Synchronises. */
+int dem_set_materials(dem_ctx *ctx, int32_t sys, const dem_material *mat, int32_t ntypes);
+
+typedef struct dem_adjoint dem_adjoint;   /* opaque: rollout checkpoints and adjoint state */
+
+/* Device bytes of the adjoint workspace of a rollout of nsteps steps with
+ * checkpoints every `window` steps (1..4096) on a context of one system
+ * (DEM_ERR_ARG for a batch).  max_windows bounds the number of windows: a
+ * list rebuild ends a window early, so a rollout can need more than
+ * ceil(nsteps / window); 0 selects 2 ceil(nsteps / window) + 1.  Memory:
+ * (max_windows + window) x (128 + 32 k_max) bytes per particle, plus
+ * (max_windows + 1) x (28 + 4 k_max) bytes per particle for the lists. */
+int dem_adjoint_workspace_size(dem_ctx *ctx, int64_t nsteps, int32_t window, int32_t max_windows, size_t *bytes);
+
+/* Bind an adjoint to a context and a caller-owned device workspace (256-byte
+ * aligned, at least the size above, untouched until dem_adjoint_destroy). */
+int dem_adjoint_init(dem_ctx *ctx, int64_t nsteps, int32_t window, int32_t max_windows, void *workspace,
+                     size_t bytes, dem_adjoint **out);
+
+/* The rollout: the force evaluation of the current state without history
+ * update (as dem_forces(ctx, s, 0)), then nsteps steps bit-identical to
+ * dem_step, run in windows of at most `window` steps with a checkpoint of the
+ * packed state and the history at the start of each.  A list rebuild happens
+ * only between windows (a rebuild request ends the window), so the contact
+ * topology is fixed inside every window.  On return s holds the final state
+ * (permuted by the rebuilds, as after dem_step).  DEM_ERR_CAPACITY when more
+ * than max_windows windows are needed.  Synchronises once per window. */
+int dem_rollout_forward(dem_adjoint *adj, const dem_state *s);
+
+/* Reverse mode of the last dem_rollout_forward (no other stepping in
+ * between: DEM_ERR_STATE).  Inputs: gx, gv, gw = dL/dx, dL/dv, dL/dw of the
+ * final state, device [3][n] in the final order.  Outputs: ax0, av0, aw0 =
+ * dL/d(initial x, v, w), device [3][n] in the order of the first list build,
+ * whose ids go to ids0 (device [n], may be NULL); grad = host [3][ntypes]:
+ * dL/dE_t, then dL/de_t, then dL/dmu_t.  Each window is recomputed from its
+ * checkpoint and reversed step by step; sums over particles are taken in a
+ * fixed order, so results are reproducible.  Synchronises. */
+int dem_rollout_backward(dem_adjoint *adj, const dem_state *s, const double *gx, const double *gv, const double *gw,
+                         double *ax0, double *av0, double *aw0, int32_t *ids0, double *grad);
+
+/* Reverse mode of one force evaluation without history update (dem_forces(ctx,
+ * s, 0)) at the current state and list: fb, tb = dL/df, dL/dt (device [3][n])
+ * -> xb, vb, wb = dL/dx, dL/dv, dL/dw (device [3][n]) and grad (host
+ * [3][ntypes], as above).  Uses the adjoint workspace.  Synchronises. */
+int dem_forces_vjp(dem_adjoint *adj, const dem_state *s, const double *fb, const double *tb, double *xb, double *vb,
+                   double *wb, double *grad);
+
+/* out[0] windows of the last forward, out[1] list rebuilds in it, out[2]
+ * workspace bytes, out[3] max_windows. */
+int dem_adjoint_info(dem_adjoint *adj, int64_t out[4]);
+
+/* Release the adjoint (host memory only). */
+int dem_adjoint_destroy(dem_adjoint *adj);
+
 const char *dem_last_error(const dem_ctx *ctx);
 
 /* Release the context (host memory only; the workspace stays the caller's). */

@@ -587,6 +587,23 @@ void *orc_tan_new(const orc_config *cfg, int n, const double *x, const double *v
     }
     return s;
 }
+/* Re-seed tangent direction k (0..5) along the initial state: x += eps dx,
+ * v += eps dv, w += eps dw ((n,3) arrays in input order; null = zero), with
+ * no parameter moving in that direction. */
+void orc_tan_seed_state(void *h, int k, const double *dx, const double *dv, const double *dw) {
+    SimT *s = (SimT *)h;
+    if (k < 0 || k >= NDIR) return;
+    for (int t = 0; t < 4; ++t) { s->E[t].d[k] = 0.0; s->e[t].d[k] = 0.0; s->mu[t].d[k] = 0.0; }
+    for (size_t i = 0; i < s->p.size(); ++i) {
+        Particle<Dual> &q = s->p[i];
+        V3<Dual> *vec[3] = {&q.x, &q.v, &q.w};
+        const double *src[3] = {dx, dv, dw};
+        for (int a = 0; a < 3; ++a) {
+            Dual *c3[3] = {&vec[a]->x, &vec[a]->y, &vec[a]->z};
+            for (int c = 0; c < 3; ++c) c3[c]->d[k] = src[a] ? src[a][3 * i + c] : 0.0;
+        }
+    }
+}
 void orc_tan_free(void *h) { delete (SimT *)h; }
 void orc_tan_forces(void *h, int update_history) { forces(*(SimT *)h, update_history != 0); }
 void orc_tan_step(void *h, int nsteps) { step(*(SimT *)h, nsteps); }

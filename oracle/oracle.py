@@ -74,6 +74,7 @@ def lib():
         L.orc_tan_step.argtypes = [vp, ctypes.c_int]
         L.orc_tan_get.argtypes = [vp, _dp, _dp, _dp, _dp]
         L.orc_tan_get_ext.argtypes = [vp, ctypes.c_int, _dp, _dp]
+        L.orc_tan_seed_state.argtypes = [vp, ctypes.c_int, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -198,6 +199,12 @@ class Oracle:
         xt = np.empty((self.n, 3, 6)); vt = np.empty((self.n, 3, 6))
         self.L.orc_tan_get(self.h, _d(xv), _d(xt), _d(vv), _d(vt))
         return xv, xt, vv, vt
+
+    def tan_seed_state(self, k: int, dx=None, dv=None, dw=None):
+        """Make tangent direction k the derivative along an initial-state
+        perturbation (dx, dv, dw: (n,3) in input order) instead of a parameter."""
+        a = [None if q is None else np.ascontiguousarray(q, dtype=np.float64) for q in (dx, dv, dw)]
+        self.L.orc_tan_seed_state(self.h, int(k), *[_d(q) for q in a])
 
     def tan_vector(self, name: str):
         """Value (n,3) and tangent (n,3,6) of one of x, v, w, f, t."""

@@ -9,33 +9,39 @@
 #include <vector>
 
 #include "../../include/dem.h"
-#include "dem_kernels.h"
+#include "dem_ctx.h"
 
 using namespace dem;
 
-namespace {
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame;
-    size_t nbr[2], cnt[2], xi[2], mask[2], ids[2];
-    size_t cell_of, rank, order, cell_count, cell_start, scan_partial, shadow_d, shadow_i;
-    size_t pos[2], vel[2], spin[2], im, sel, lcur;
-    size_t total;
-};
-
-struct Geometry {
-    std::vector<SysDesc> sys;
-    std::vector<PairCoef> coef;
-    std::vector<double> rho;
-    int64_t n = 0, ncell = 0;
-    int32_t kmax = 0, block = 128;
-};
+namespace dem {
+namespace host {
 
 double cutoff_of(const dem_config &c) { return 2.0 * c.r_max + c.skin; }
+
+bool material_ok(const dem_material &m) {
+    return m.E > 0.0 && m.nu > -1.0 && m.nu < 0.5 && m.rho > 0.0 && m.e > 0.0 && m.e <= 1.0 && m.mu >= 0.0 &&
+           std::isfinite(m.E) && std::isfinite(m.mu) && std::isfinite(m.rho);
+}
+
+// Eq. (6) with the effective properties of the two materials: harmonic E* and
+// G*, arithmetic means of e and mu, folded into the per-contact factors.
+PairCoef pair_coef(const dem_material &a, const dem_material &b) {
+    double inv_E = (1.0 - a.nu * a.nu) / a.E + (1.0 - b.nu * b.nu) / b.E;
+    double inv_G = 2.0 * (2.0 - a.nu) * (1.0 + a.nu) / a.E + 2.0 * (2.0 - b.nu) * (1.0 + b.nu) / b.E;
+    double e = (a.e + b.e) / 2.0;
+    double mu = (a.mu + b.mu) / 2.0;
+    double le = std::log(e);
+    const double Es = 1.0 / inv_E, Gs = 1.0 / inv_G;
+    const double beta = le / std::sqrt(le * le + M_PI * M_PI);
+    PairCoef k;
+    memset(&k, 0, sizeof k);
+    k.kn0 = 4.0 / 3.0 * Es;
+    k.kt0 = 8.0 * Gs;
+    k.gn0 = -beta * std::sqrt(20.0 / 3.0 * Es);
+    k.gt0 = -beta * std::sqrt(80.0 / 3.0 * Gs);
+    k.mu = mu;
+    return k;
+}
 
 // Validates the configurations and derives the device descriptors.
 int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::string &err) {
@@ -49,8 +55,7 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         if (c.ntypes < 1 || c.ntypes > DEM_MAX_TYPES) { err = "ntypes out of range"; return DEM_ERR_ARG; }
         for (int t = 0; t < c.ntypes; ++t) {
             const dem_material &m = c.mat[t];
-            if (!(m.E > 0.0) || !(m.nu > -1.0 && m.nu < 0.5) || !(m.rho > 0.0) || !(m.e > 0.0 && m.e <= 1.0) ||
-                !(m.mu >= 0.0) || !std::isfinite(m.E) || !std::isfinite(m.mu)) {
+            if (!material_ok(m)) {
                 snprintf(buf, sizeof buf, "system %d type %d: need E > 0, -1 < nu < 0.5, rho > 0, 0 < e <= 1, mu >= 0", s, t);
                 err = buf;
                 return DEM_ERR_ARG;
@@ -103,25 +108,9 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         d.coef0 = (int32_t)g.coef.size();
         d.type0 = (int32_t)g.rho.size();
         for (int ti = 0; ti < c.ntypes; ++ti)
-            for (int tj = 0; tj < c.ntypes; ++tj) {
-                const dem_material &a = c.mat[ti], &b = c.mat[tj];
-                double inv_E = (1.0 - a.nu * a.nu) / a.E + (1.0 - b.nu * b.nu) / b.E;
-                double inv_G = 2.0 * (2.0 - a.nu) * (1.0 + a.nu) / a.E + 2.0 * (2.0 - b.nu) * (1.0 + b.nu) / b.E;
-                double e = (a.e + b.e) / 2.0;
-                double mu = (a.mu + b.mu) / 2.0;
-                double le = std::log(e);
-                const double Es = 1.0 / inv_E, Gs = 1.0 / inv_G;
-                const double beta = le / std::sqrt(le * le + M_PI * M_PI);
-                PairCoef k;
-                memset(&k, 0, sizeof k);
-                k.kn0 = 4.0 / 3.0 * Es;
-                k.kt0 = 8.0 * Gs;
-                k.gn0 = -beta * std::sqrt(20.0 / 3.0 * Es);
-                k.gt0 = -beta * std::sqrt(80.0 / 3.0 * Gs);
-                k.mu = mu;
-                g.coef.push_back(k);
-            }
+            for (int tj = 0; tj < c.ntypes; ++tj) g.coef.push_back(pair_coef(c.mat[ti], c.mat[tj]));
         for (int t = 0; t < c.ntypes; ++t) g.rho.push_back(c.mat[t].rho);
+        for (int t = 0; t < c.ntypes; ++t) g.mat.push_back(c.mat[t]);
         g.sys.push_back(d);
         g.n += c.n;
         g.ncell += cells;
@@ -173,52 +162,6 @@ Layout make_layout(const Geometry &g) {
     return L;
 }
 
-constexpr int kKinds = 4;  // timed kernel classes: phase 0, forces, phase 1, list rebuild
-
-struct GraphSlot {
-    hipGraphExec_t exec = nullptr;
-    const void *key[10] = {nullptr};
-    int chunk = 0;
-    int count = 0;
-};
-
-}  // namespace
-
-struct dem_ctx {
-    Geometry geo;
-    Layout lay;
-    char *ws = nullptr;
-    hipStream_t stream = nullptr;
-    SysDesc *d_sys = nullptr;
-    PairCoef *d_coef = nullptr;
-    double *d_rho = nullptr;
-    Flags *d_flags = nullptr;
-    List lists[2];
-    // host-side state machine
-    bool masses = false, have_list = false, list_current = false, binned = false, frame_identity = true;
-    bool forces_valid = false;
-    int64_t step_counter = 0;
-    // options
-    bool use_graph = false, count = true;
-    int chunk = 64;
-    int64_t grid_cap = 0;   // 0: resident capacity, set at init
-    int lanes = 4;
-    int cus = 256;
-    GraphSlot graphs[8];          // replay graphs of 2^(k+3) fused steps
-    double gap_avg = 1e9;         // running estimate of steps between rebuilds
-    int64_t since_rebuild = 0;
-    // per-kernel timing with HIP events (non-graph stepping only)
-    bool timing = false;
-    std::vector<hipEvent_t> ev;      // pairs (start, stop) recorded in this chunk
-    std::vector<int> ev_kind;        // kernel class of each pair
-    int ev_used = 0;
-    double t_ms[kKinds] = {0, 0, 0, 0};
-    int64_t t_n[kKinds] = {0, 0, 0, 0};
-    std::string err;
-};
-
-namespace {
-
 int fail(dem_ctx *c, int code, const std::string &msg) {
     if (c) c->err = msg;
     return code;
@@ -228,11 +171,6 @@ int hip_fail(dem_ctx *c, hipError_t e, const char *what) {
     return fail(c, DEM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIPCALL(c, expr)                                            \
-    do {                                                            \
-        hipError_t _e = (expr);                                     \
-        if (_e != hipSuccess) return hip_fail((c), _e, #expr);      \
-    } while (0)
 
 KArgs kargs(dem_ctx *c, const dem_state *s) {
     KArgs a;
@@ -318,7 +256,7 @@ int do_bin(dem_ctx *c, const dem_state *s, bool all) {
     return DEM_OK;
 }
 
-int do_neighbors(dem_ctx *c, const dem_state *s, bool clear_sel = true) {
+int do_neighbors(dem_ctx *c, const dem_state *s, bool clear_sel) {
     if (!c->binned) return fail(c, DEM_ERR_STATE, "dem_neighbors needs dem_bin on the current positions");
     int have_old = c->have_list ? 1 : 0;
     KArgs a = kargs(c, s);
@@ -330,6 +268,14 @@ int do_neighbors(dem_ctx *c, const dem_state *s, bool clear_sel = true) {
     c->have_list = true;
     c->list_current = true;
     c->frame_identity = true;
+    return DEM_OK;
+}
+
+int live_list(dem_ctx *c, int sy, List &out) {
+    int32_t cur = 0;
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    HIPCALL(c, hipMemcpy(&cur, c->ws + c->lay.lcur + 4 * (size_t)sy, 4, hipMemcpyDeviceToHost));
+    out = c->lists[cur & 1];
     return DEM_OK;
 }
 
@@ -390,7 +336,10 @@ int capture_graph(dem_ctx *c, const dem_state *s, GraphSlot &gs, int len) {
     return DEM_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace dem
+
+using namespace dem::host;
 
 extern "C" {
 

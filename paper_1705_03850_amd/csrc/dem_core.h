@@ -96,6 +96,15 @@ __host__ __device__ inline int cell_coord(double x, const SysDesc &s, int a) {
     return c;
 }
 
+// Periodic wrap of a drifted coordinate into [lo, hi).
+__host__ __device__ inline double wrap_axis(double x, const SysDesc &s, int ax) {
+    if (!s.periodic[ax]) return x;
+    if (x >= s.hi[ax]) x -= s.L[ax];
+    if (x < s.lo[ax]) x += s.L[ax];
+    if (x >= s.hi[ax]) x = s.lo[ax];
+    return x;
+}
+
 // Contact of particle a with b (wall: flat wall z = 0, normal +z).  Inputs
 // are a's and b's state; xi is the slot's history (updated in place when
 // update != 0).  Returns false (and touches nothing) when not in contact.
@@ -182,6 +191,195 @@ __host__ __device__ inline bool contact_force(const ContactIn &c, bool wall, con
     fz = fn * nz + tz;
     ftx = tx; fty = ty; ftz = tz;
     fn_out = fn;
+    return true;
+}
+
+// Reverse mode of contact_force at the same inputs, for gradients of a
+// trajectory with respect to the contact law.  Seeds: fb is the adjoint of the
+// force on a, gb of g = n x F_t (both torques are -r g), zb of the updated
+// history (used when update != 0).  Results: the adjoints of d = x_a - x_b
+// (wall: of z_a in dbz), of v_a - v_b, of r_a w_a + r_b w_b, of the history
+// before the update, and of the five folded coefficients.  Every branch
+// (contact, Coulomb) is decided by the same expressions as in contact_force.
+// With a's and b's roles swapped and the seeds mirrored (fb and zb negated,
+// gb unchanged) every result flips sign exactly or stays the same, as the
+// forward arithmetic does.  Returns false (and writes nothing) when not in
+// contact.
+struct ContactAdj {
+    double dbx, dby, dbz;    // separation
+    double vbx, vby, vbz;    // relative velocity
+    double wbx, wby, wbz;    // r_a w_a + r_b w_b
+    double xbx, xby, xbz;    // history before the update
+    double kn0, kt0, gn0, gt0, mu;
+};
+
+__host__ __device__ inline bool contact_vjp(const ContactIn &c, bool wall, const PairCoef &k, double dt, bool update,
+                                            double xix, double xiy, double xiz, double fbx, double fby, double fbz,
+                                            double gbx, double gby, double gbz, double zbx, double zby, double zbz,
+                                            ContactAdj &o) {
+    // ---- forward values (the expressions of contact_force)
+    double rs, dist;
+    if (!wall) {
+        double d2 = c.dx * c.dx + c.dy * c.dy + c.dz * c.dz;
+        rs = c.ra + c.rb;
+        if (!(d2 < rs * rs)) return false;
+        dist = sqrt(d2);
+    } else {
+        rs = c.ra;
+        if (!(c.dz < c.ra)) return false;
+        dist = c.dz;
+    }
+    const double delta = rs - dist;
+    if (!(delta > 0.0)) return false;
+    double nx, ny, nz, R, M, inv_d = 0.0;
+    if (!wall) {
+        inv_d = 1.0 / dist;
+        nx = c.dx * inv_d; ny = c.dy * inv_d; nz = c.dz * inv_d;
+        const double sm = c.ma + c.mb;
+        const double inv = 1.0 / (rs * sm);
+        R = c.ra * c.rb * sm * inv;
+        M = c.ma * c.mb * rs * inv;
+    } else {
+        nx = 0.0; ny = 0.0; nz = 1.0;
+        R = c.ra;
+        M = c.ma;
+    }
+    const double sq = sqrt(R * delta);
+    const double kn = k.kn0 * sq;
+    const double kt = k.kt0 * sq;
+    const double sg = sqrt(M * sq);
+    const double gn = k.gn0 * sg;
+    const double gt = k.gt0 * sg;
+    const double vn = c.vrx * nx + c.vry * ny + c.vrz * nz;
+    const double cx = c.wsy * nz - c.wsz * ny;
+    const double cy = c.wsz * nx - c.wsx * nz;
+    const double cz = c.wsx * ny - c.wsy * nx;
+    const double vtx = c.vrx - vn * nx - cx;
+    const double vty = c.vry - vn * ny - cy;
+    const double vtz = c.vrz - vn * nz - cz;
+    const double fn = kn * delta - gn * vn;
+    const double xn = xix * nx + xiy * ny + xiz * nz;
+    double zx = xix - xn * nx, zy = xiy - xn * ny, zz = xiz - xn * nz;
+    if (update) {
+        zx = zx + vtx * dt;
+        zy = zy + vty * dt;
+        zz = zz + vtz * dt;
+    }
+    const double tx = -kt * zx - gt * vtx;
+    const double ty = -kt * zy - gt * vty;
+    const double tz = -kt * zz - gt * vtz;
+    const double ft2 = tx * tx + ty * ty + tz * tz;
+    const double cap = k.mu * fabs(fn);
+    const bool slip = ft2 > cap * cap;
+    double tpx = tx, tpy = ty, tpz = tz;   // total tangential force
+    double s = 1.0, q = 0.0, inv_kt = 0.0, zpx = zx, zpy = zy, zpz = zz;
+    if (slip) {
+        q = sqrt(ft2);
+        s = cap / q;
+        tpx = s * tx; tpy = s * ty; tpz = s * tz;
+        inv_kt = 1.0 / kt;
+        zpx = -(tpx + gt * vtx) * inv_kt;
+        zpy = -(tpy + gt * vty) * inv_kt;
+        zpz = -(tpz + gt * vtz) * inv_kt;
+    }
+    if (!update) { zbx = 0.0; zby = 0.0; zbz = 0.0; }
+    // ---- reverse sweep
+    // f = f_n n + t',  g = n x t'
+    double tbx = fbx + (gby * nz - gbz * ny);
+    double tby = fby + (gbz * nx - gbx * nz);
+    double tbz = fbz + (gbx * ny - gby * nx);
+    double nbx = fn * fbx + (tpy * gbz - tpz * gby);
+    double nby = fn * fby + (tpz * gbx - tpx * gbz);
+    double nbz = fn * fbz + (tpx * gby - tpy * gbx);
+    double fnb = fbx * nx + fby * ny + fbz * nz;
+    double ktb = 0.0, gtb = 0.0, mub = 0.0, vtbx = 0.0, vtby = 0.0, vtbz = 0.0;
+    double zqx, zqy, zqz;   // adjoint of the trial history z
+    if (slip) {
+        // z' = -(t' + g_t v_t) / k_t
+        tbx = tbx + -inv_kt * zbx;
+        tby = tby + -inv_kt * zby;
+        tbz = tbz + -inv_kt * zbz;
+        gtb = -inv_kt * (zbx * vtx + zby * vty + zbz * vtz);
+        const double gk = gt * inv_kt;
+        vtbx = -gk * zbx; vtby = -gk * zby; vtbz = -gk * zbz;
+        ktb = -inv_kt * (zbx * zpx + zby * zpy + zbz * zpz);
+        // t' = (cap / |t|) t
+        const double tt = tx * tbx + ty * tby + tz * tbz;
+        const double rr = tt / ft2;
+        tbx = s * (tbx - tx * rr);
+        tby = s * (tby - ty * rr);
+        tbz = s * (tbz - tz * rr);
+        const double capb = tt / q;
+        mub = fabs(fn) * capb;
+        fnb = fnb + (fn < 0.0 ? -k.mu * capb : k.mu * capb);
+        zqx = 0.0; zqy = 0.0; zqz = 0.0;
+    } else {
+        zqx = zbx; zqy = zby; zqz = zbz;
+    }
+    // t = -k_t z - g_t v_t
+    zqx = zqx + -kt * tbx;
+    zqy = zqy + -kt * tby;
+    zqz = zqz + -kt * tbz;
+    ktb = ktb + -(zx * tbx + zy * tby + zz * tbz);
+    gtb = gtb + -(vtx * tbx + vty * tby + vtz * tbz);
+    vtbx = vtbx + -gt * tbx;
+    vtby = vtby + -gt * tby;
+    vtbz = vtbz + -gt * tbz;
+    // z = (xi - (xi.n) n) + v_t dt
+    if (update) {
+        vtbx = vtbx + dt * zqx;
+        vtby = vtby + dt * zqy;
+        vtbz = vtbz + dt * zqz;
+    }
+    const double xnb = -(nx * zqx + ny * zqy + nz * zqz);
+    nbx = nbx + -xn * zqx + xnb * xix;
+    nby = nby + -xn * zqy + xnb * xiy;
+    nbz = nbz + -xn * zqz + xnb * xiz;
+    o.xbx = zqx + xnb * nx;
+    o.xby = zqy + xnb * ny;
+    o.xbz = zqz + xnb * nz;
+    // f_n = k_n delta - g_n v_n
+    const double knb = delta * fnb;
+    double deltab = kn * fnb;
+    const double gnb = -vn * fnb;
+    double vnb = -gn * fnb;
+    // v_t = v_r - v_n n - w_s x n
+    vnb = vnb + -(nx * vtbx + ny * vtby + nz * vtbz);
+    nbx = nbx + -vn * vtbx;
+    nby = nby + -vn * vtby;
+    nbz = nbz + -vn * vtbz;
+    const double cbx = -vtbx, cby = -vtby, cbz = -vtbz;
+    o.wbx = ny * cbz - nz * cby;
+    o.wby = nz * cbx - nx * cbz;
+    o.wbz = nx * cby - ny * cbx;
+    nbx = nbx + (cby * c.wsz - cbz * c.wsy);
+    nby = nby + (cbz * c.wsx - cbx * c.wsz);
+    nbz = nbz + (cbx * c.wsy - cby * c.wsx);
+    // v_n = v_r . n
+    o.vbx = vtbx + vnb * nx;
+    o.vby = vtby + vnb * ny;
+    o.vbz = vtbz + vnb * nz;
+    nbx = nbx + vnb * c.vrx;
+    nby = nby + vnb * c.vry;
+    nbz = nbz + vnb * c.vrz;
+    // g = g0 sqrt(m* sqrt(R delta)),  k = k0 sqrt(R delta)
+    o.gn0 = sg * gnb;
+    o.gt0 = sg * gtb;
+    o.kn0 = sq * knb;
+    o.kt0 = sq * ktb;
+    o.mu = mub;
+    const double sgb = k.gn0 * gnb + k.gt0 * gtb;
+    const double sqb = k.kn0 * knb + k.kt0 * ktb + sgb * (0.5 * M / sg);
+    deltab = deltab + sqb * (0.5 * R / sq);
+    if (wall) {
+        o.dbx = 0.0; o.dby = 0.0; o.dbz = -deltab;
+    } else {
+        // delta = r_a + r_b - |d|,  n = d / |d|
+        const double nn = nx * nbx + ny * nby + nz * nbz;
+        o.dbx = (nbx - nx * nn) * inv_d - deltab * nx;
+        o.dby = (nby - ny * nn) * inv_d - deltab * ny;
+        o.dbz = (nbz - nz * nn) * inv_d - deltab * nz;
+    }
     return true;
 }
 

@@ -75,14 +75,6 @@ __device__ inline int sys_of_cell(const KArgs &a, int64_t c) {
     return lo;
 }
 
-__device__ inline double wrap_axis(double x, const SysDesc &s, int ax) {
-    if (!s.periodic[ax]) return x;
-    if (x >= s.hi[ax]) x -= s.L[ax];
-    if (x < s.lo[ax]) x += s.L[ax];
-    if (x >= s.hi[ax]) x = s.lo[ax];
-    return x;
-}
-
 // ------------------------------------------------------------------ utilities
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {

@@ -48,7 +48,8 @@ _lib = None
 _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_batch_init", "dem_reset", "dem_bin",
             "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_set_step_options", "dem_set_launch", "dem_check",
             "dem_stats", "dem_set_timing", "dem_kernel_times", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
-            "dem_last_error", "dem_destroy"]
+            "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
+            "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_adjoint_info", "dem_adjoint_destroy"]
 
 
 def load(path: str = LIB_PATH):
@@ -61,6 +62,7 @@ def load(path: str = LIB_PATH):
     L = ctypes.CDLL(path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     P = ctypes.POINTER
+    ip, dp = P(i32), P(ctypes.c_double)
     L.dem_workspace_size.argtypes = [P(Config), P(ctypes.c_size_t)]
     L.dem_batch_workspace_size.argtypes = [i32, P(Config), P(ctypes.c_size_t)]
     L.dem_init.argtypes = [P(vp), P(Config), vp, ctypes.c_size_t, vp]
@@ -76,7 +78,6 @@ def load(path: str = LIB_PATH):
     L.dem_stats.argtypes = [vp, P(i64)]
     L.dem_set_timing.argtypes = [vp, ctypes.c_int]
     L.dem_kernel_times.argtypes = [vp, P(ctypes.c_double), P(i64)]
-    ip, dp = P(i32), P(ctypes.c_double)
     L.dem_export_neighbors.argtypes = [vp, P(State), ip, ip, i64, P(i64)]
     L.dem_export_contacts.argtypes = [vp, P(State), ip, ip, dp, i64, P(i64)]
     L.dem_export_wall.argtypes = [vp, P(State), ip, dp, i64, P(i64)]
@@ -84,6 +85,14 @@ def load(path: str = LIB_PATH):
     L.dem_last_error.argtypes = [vp]
     L.dem_last_error.restype = ctypes.c_char_p
     L.dem_destroy.argtypes = [vp]
+    L.dem_set_materials.argtypes = [vp, i32, P(Material), i32]
+    L.dem_adjoint_workspace_size.argtypes = [vp, i64, i32, i32, P(ctypes.c_size_t)]
+    L.dem_adjoint_init.argtypes = [vp, i64, i32, i32, vp, ctypes.c_size_t, P(vp)]
+    L.dem_rollout_forward.argtypes = [vp, P(State)]
+    L.dem_rollout_backward.argtypes = [vp, P(State), vp, vp, vp, vp, vp, vp, vp, dp]
+    L.dem_forces_vjp.argtypes = [vp, P(State), vp, vp, vp, vp, vp, dp]
+    L.dem_adjoint_info.argtypes = [vp, P(i64)]
+    L.dem_adjoint_destroy.argtypes = [vp]
     for name in _SYMBOLS:
         if name != "dem_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -312,6 +321,16 @@ class DemSystem:
         self._rc(self.L.dem_export_wall(self.ctx, self._state, _i32p(a), _dp(xi), cnt.value, ctypes.byref(cnt)))
         return a, xi
 
+    def set_materials(self, materials, sys: int = 0):
+        """New per-type materials of system `sys` (objects with E, nu, rho, e, mu)."""
+        arr = (Material * len(materials))()
+        for t, m in enumerate(materials):
+            arr[t].E, arr[t].nu, arr[t].rho, arr[t].e, arr[t].mu = m.E, m.nu, m.rho, m.e, m.mu
+        self._rc(self.L.dem_set_materials(self.ctx, int(sys), arr, len(materials)))
+
+    def adjoint(self, nsteps: int, window: int = 20, max_windows: int = 0) -> "Adjoint":
+        return Adjoint(self, nsteps, window, max_windows)
+
     def import_history(self, id_i, id_j, xi, wall_id=None, wall_xi=None):
         id_i = np.ascontiguousarray(id_i, np.int32); id_j = np.ascontiguousarray(id_j, np.int32)
         xi = np.ascontiguousarray(xi, np.float64).reshape(-1, 3)
@@ -319,3 +338,79 @@ class DemSystem:
         wall_xi = np.zeros((0, 3)) if wall_xi is None else np.ascontiguousarray(wall_xi, np.float64).reshape(-1, 3)
         self._rc(self.L.dem_import_history(self.ctx, self._state, len(id_i), _i32p(id_i), _i32p(id_j), _dp(xi),
                                            len(wall_id), _i32p(wall_id), _dp(wall_xi)))
+
+
+class Adjoint:
+    """Reverse mode of a rollout on a DemSystem of one system (dem_rollout_*).
+
+    ``forward()`` runs ``nsteps`` steps from the system's current state with
+    checkpoints every ``window`` steps; ``backward(gx, gv, gw)`` takes the
+    adjoints of the final x, v, w ((3, n) device tensors in the system's
+    current order) and returns the gradients with respect to the per-type
+    E, e and mu and to the initial x, v, w (rows in id order)."""
+
+    def __init__(self, dsys: DemSystem, nsteps: int, window: int = 20, max_windows: int = 0):
+        torch = dsys.torch
+        self.dsys = dsys
+        self.L = dsys.L
+        self.nsteps = int(nsteps)
+        self.window = int(window)
+        self.ntypes = len(dsys.systems[0].materials)
+        nb = ctypes.c_size_t()
+        dsys._rc(self.L.dem_adjoint_workspace_size(dsys.ctx, self.nsteps, self.window, int(max_windows),
+                                                   ctypes.byref(nb)))
+        self.bytes = nb.value
+        self.workspace = torch.empty(self.bytes + 256, dtype=torch.uint8, device=dsys.device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.h = ctypes.c_void_p()
+        dsys._rc(self.L.dem_adjoint_init(dsys.ctx, self.nsteps, self.window, int(max_windows), ctypes.c_void_p(ptr),
+                                         ctypes.c_size_t(self.bytes), ctypes.byref(self.h)))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.L.dem_adjoint_destroy(h)
+            self.h = None
+
+    def forward(self):
+        self.dsys._rc(self.L.dem_rollout_forward(self.h, self.dsys.state))
+
+    def _by_id(self, ids, *arrays):
+        order = np.argsort(ids, kind="stable")
+        return [a.cpu().numpy().T[order].copy() for a in arrays]
+
+    def backward(self, gx=None, gv=None, gw=None) -> dict:
+        torch = self.dsys.torch
+        d = self.dsys
+        z = lambda g: torch.zeros((3, d.n), dtype=torch.float64, device=d.device) if g is None else \
+            g.to(torch.float64).contiguous()  # noqa: E731
+        gx, gv, gw = z(gx), z(gv), z(gw)
+        ax, av, aw = (torch.empty((3, d.n), dtype=torch.float64, device=d.device) for _ in range(3))
+        ids0 = torch.empty(d.n, dtype=torch.int32, device=d.device)
+        grad = (ctypes.c_double * (3 * self.ntypes))()
+        torch.cuda.current_stream(d.device).synchronize()
+        d._rc(self.L.dem_rollout_backward(self.h, d.state, _ptr(gx), _ptr(gv), _ptr(gw), _ptr(ax), _ptr(av),
+                                          _ptr(aw), _ptr(ids0), grad))
+        g = np.array(grad[:]).reshape(3, self.ntypes)
+        ids = ids0.cpu().numpy()
+        x0, v0, w0 = self._by_id(ids, ax, av, aw)
+        return dict(E=g[0], e=g[1], mu=g[2], x0=x0, v0=v0, w0=w0, ids=np.sort(ids))
+
+    def forces_vjp(self, fb, tb) -> dict:
+        """Reverse mode of one force evaluation (no history update) at the current
+        state: dL/df, dL/dt ((3, n) device, current order) -> dL/dx, dL/dv, dL/dw
+        (current order) and the material gradients."""
+        torch = self.dsys.torch
+        d = self.dsys
+        fb = fb.to(torch.float64).contiguous(); tb = tb.to(torch.float64).contiguous()
+        xb, vb, wb = (torch.empty((3, d.n), dtype=torch.float64, device=d.device) for _ in range(3))
+        grad = (ctypes.c_double * (3 * self.ntypes))()
+        torch.cuda.current_stream(d.device).synchronize()
+        d._rc(self.L.dem_forces_vjp(self.h, d.state, _ptr(fb), _ptr(tb), _ptr(xb), _ptr(vb), _ptr(wb), grad))
+        g = np.array(grad[:]).reshape(3, self.ntypes)
+        return dict(E=g[0], e=g[1], mu=g[2], x=xb, v=vb, w=wb)
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * 4)()
+        self.dsys._rc(self.L.dem_adjoint_info(self.h, out))
+        return dict(windows=out[0], rebuilds=out[1], bytes=out[2], max_windows=out[3])

@@ -218,3 +218,64 @@ def test_tangent_matches_central_difference():
             vals.append(np.sum(a * xf) * scale_x + np.sum(b * vf) * scale_v)
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - tan[k]) <= 1e-5 * max(abs(tan[k]), 1e-3 * np.abs(tan).max()), (name, fd, tan[k])
+
+
+def test_state_tangent_free_flight():
+    """A state-seeded tangent direction in free flight: velocity Verlet under
+    constant gravity gives x(T) = x0 + v0 T + g T^2 / 2 exactly, so
+    dx(T)/dx0 = 1 and dx(T)/dv0 = T, and dv(T)/dv0 = 1."""
+    s = sphere_on_wall(5e-3, v=(0.1, 0.0, 0.0))
+    o = O.Oracle(s, tangent=True)
+    o.tan_seed_state(0, dx=np.array([[1.0, 0.0, 0.0]]))
+    o.tan_seed_state(1, dv=np.array([[0.0, 0.0, 1.0]]))
+    o.tan_seed_state(2, dw=np.array([[0.0, 1.0, 0.0]]))
+    o.tan_forces(False)
+    o.tan_step(100)
+    _, xt = o.tan_vector("x")
+    _, vt = o.tan_vector("v")
+    _, wt = o.tan_vector("w")
+    T = 100 * s.dt
+    assert xt[0, 0, 0] == 1.0 and xt[0, 1, 0] == 0.0 and xt[0, 2, 0] == 0.0
+    assert abs(xt[0, 2, 1] - T) < 1e-15 and vt[0, 2, 1] == 1.0
+    assert wt[0, 1, 2] == 1.0 and xt[0, 0, 2] == 0.0
+    # the remaining directions are still the parameters (no contact: zero)
+    assert np.all(xt[..., 3:] == 0.0)
+
+
+def test_state_tangent_matches_central_difference():
+    """State-seeded tangents of a linear functional after 40 steps of the
+    two-type chute against central differences of the plain oracle."""
+    s = small_chute()
+    nsteps = 40
+    rng = np.random.default_rng(21)
+    a = rng.normal(size=(s.n, 3))
+    b = rng.normal(size=(s.n, 3))
+    dirs = {"x": rng.normal(size=(s.n, 3)), "v": rng.normal(size=(s.n, 3)), "w": rng.normal(size=(s.n, 3))}
+    o = O.Oracle(s, tangent=True)
+    o.tan_seed_state(0, dx=dirs["x"])
+    o.tan_seed_state(1, dv=dirs["v"])
+    o.tan_seed_state(2, dw=dirs["w"])
+    o.tan_forces(False)
+    o.tan_step(nsteps)
+    _, xt = o.tan_vector("x")
+    _, vt = o.tan_vector("v")
+    tan = np.einsum("ic,ick->k", a, xt) * 1e3 + np.einsum("ic,ick->k", b, vt)
+
+    def L(**kw):
+        q = s.copy()
+        for k, val in kw.items():
+            setattr(q, k, val)
+        oo = O.Oracle(q)
+        oo.forces(False)
+        oo.step(nsteps)
+        st = oo.state()
+        return np.sum(a * st["x"]) * 1e3 + np.sum(b * st["v"])
+
+    # differences that move positions by ~4e-12 m: larger steps straddle contact
+    # onsets (damping ~ delta^(1/4) has an infinite slope there) and Coulomb
+    # switches, and the difference quotient converges to the tangent only below
+    # ~1e-11 m (2.4e-2, 3.9e-4, 3.8e-6 at 1e-9, 1e-10, 1e-11 m)
+    for k, (name, h) in enumerate((("x", 5e-12), ("v", 1e-7), ("w", 1e-4))):
+        base = getattr(s, name)
+        fd = (L(**{name: base + h * dirs[name]}) - L(**{name: base - h * dirs[name]})) / (2 * h)
+        assert abs(fd - tan[k]) <= 1e-5 * abs(tan[k]), (name, fd, tan[k])

@@ -284,6 +284,11 @@ int dem_rollout_backward(dem_adjoint *adj, const dem_state *s, const double *gx,
 int dem_forces_vjp(dem_adjoint *adj, const dem_state *s, const double *fb, const double *tb, double *xb, double *vb,
                    double *wb, double *grad);
 
+/* Threads per particle in the recompute and reverse kernels: 4 (default) or
+ * 8.  Sums over a particle's row are taken per lane and then over the lanes
+ * in order, so results are reproducible for a given choice. */
+int dem_adjoint_set_lanes(dem_adjoint *adj, int32_t lanes);
+
 /* out[0] windows of the last forward, out[1] list rebuilds in it, out[2]
  * workspace bytes, out[3] max_windows. */
 int dem_adjoint_info(dem_adjoint *adj, int64_t out[4]);

@@ -41,6 +41,7 @@ struct AArgs {
     D4 *muw;                 // [n] wall history adjoint
     double *gp;              // [5 ntypes][n] coefficient adjoint partials of each particle
     double seed_scale;       // factor on the seeds read from rin
+    int32_t lanes;           // threads per particle in the recompute and reverse passes (4 or 8)
     double *ox, *ov, *ow;    // priming evaluation: adjoints of the initial x, v, w ([3][n])
 };
 
@@ -60,7 +61,9 @@ hipError_t launch_adj_reverse(const AArgs &a, int prime, hipStream_t st);
 // order (frame: new index -> previous index), slot adjoints matched by id.
 hipError_t launch_adj_carry(const AArgs &a, const int32_t *frame, const int32_t *nids, const int32_t *onbr,
                             const int32_t *ocnt, const int32_t *oids, D4 *mu_old, D4 *muw_old, hipStream_t st);
-// acc[(ti ntypes + tj) 5 + c] += sum over particles of type ti of gp[(tj 5 + c)][i], fixed order.
-hipError_t launch_adj_reduce(const AArgs &a, double *acc, hipStream_t st);
+// acc[(ti ntypes + tj) 5 + c] += sum over particles of type ti of gp[(tj 5 + c)][i], in a
+// fixed order; part is scratch of adj_reduce_scratch_bytes(ntypes).
+hipError_t launch_adj_reduce(const AArgs &a, double *part, double *acc, hipStream_t st);
+size_t adj_reduce_scratch_bytes(int ntypes);
 
 }  // namespace dem

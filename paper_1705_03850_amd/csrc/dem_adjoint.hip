@@ -1,7 +1,7 @@
 // dem_adjoint.hip -- kernels of the reverse-mode rollout (gradients of a
 // trajectory with respect to the contact-law parameters of Eq. (3)-(6)).
 //
-// One group of kAG lanes per particle, like the force pass of the step.  The
+// One group of G lanes per particle (4 or 8), like the force pass of the step.  The
 // recompute kernel repeats the step's arithmetic in the step's order (slots
 // summed in ascending neighbour id, then the wall), so it reproduces the
 // forward trajectory bit for bit.  The reverse kernel evaluates, for every
@@ -18,19 +18,25 @@ namespace dem {
 
 namespace {
 
-constexpr int kAG = 4;          // lanes per particle
 constexpr int kABlock = 256;
+// Waves per SIMD the reverse kernel is compiled for: 2 caps it at 256
+// registers (a few spill to scratch), which ran the chute backward 11 % faster
+// than one wave with no spills.
+#ifndef DEM_ADJ_WAVES
+#define DEM_ADJ_WAVES 2
+#endif
 
+// Sum over the G lanes of a group, in lane order.
+template <int G>
 __device__ inline double group_sum(double v, int gbase) {
     double s = __shfl(v, gbase);
-    s = s + __shfl(v, gbase + 1);
-    s = s + __shfl(v, gbase + 2);
-    s = s + __shfl(v, gbase + 3);
+#pragma unroll
+    for (int l = 1; l < G; ++l) s = s + __shfl(v, gbase + l);
     return s;
 }
 
-int adj_grid(int64_t n) {
-    int64_t g = (n * kAG + kABlock - 1) / kABlock;
+int adj_grid(int64_t n, int lanes) {
+    int64_t g = (n * lanes + kABlock - 1) / kABlock;
     if (g < 1) g = 1;
     if (g > (1 << 20)) g = 1 << 20;
     return (int)g;
@@ -67,16 +73,17 @@ __global__ void k_adj_expand(AArgs a, const D4 *xi, const uint64_t *mask, const 
 
 // ------------------------------------------------------------ recompute
 
+template <int G>
 __global__ void __launch_bounds__(kABlock) k_adj_forward(AArgs a) {
     const int64_t n = a.n;
     const int64_t kmax = a.kmax;
     const SysDesc &s = *a.sys;
-    const int g = threadIdx.x % kAG;
-    const int gbase = (threadIdx.x % warpSize) / kAG * kAG;
-    const uint64_t gmask = (1ull << kAG) - 1;
-    const int64_t ppb = blockDim.x / kAG;
+    const int g = threadIdx.x % G;
+    const int gbase = (threadIdx.x % warpSize) / G * G;
+    const uint64_t gmask = (1ull << G) - 1;
+    const int64_t ppb = blockDim.x / G;
     for (int64_t i0 = (int64_t)blockIdx.x * ppb; i0 < n; i0 += (int64_t)gridDim.x * ppb) {
-        const int64_t i = i0 + threadIdx.x / kAG;
+        const int64_t i = i0 + threadIdx.x / G;
         if (i >= n) continue;
         const D4 pi = a.pos[i], vi = a.vel[i], si = a.spin[i];
         const int ti = (int)si.w & 15;
@@ -84,7 +91,7 @@ __global__ void __launch_bounds__(kABlock) k_adj_forward(AArgs a) {
         double Fx = mi * s.g[0], Fy = mi * s.g[1], Fz = mi * s.g[2];
         double Tx = 0.0, Ty = 0.0, Tz = 0.0;
         const int cnt = a.cnt[i];
-        for (int c0 = 0; c0 < cnt; c0 += kAG) {
+        for (int c0 = 0; c0 < cnt; c0 += G) {
             const int q = c0 + g;
             const bool valid = q < cnt;
             const int64_t slot = i * kmax + q;
@@ -201,18 +208,18 @@ __global__ void k_adj_seed_forces(AArgs a, const double *fb, const double *tb) {
 
 // ------------------------------------------------------------ reverse
 
-template <int NT, bool PRIME>
-__global__ void __launch_bounds__(kABlock) k_adj_reverse(AArgs a) {
+template <int NT, bool PRIME, int G>
+__global__ void __launch_bounds__(kABlock, DEM_ADJ_WAVES) k_adj_reverse(AArgs a) {
     const int64_t n = a.n;
     const int64_t kmax = a.kmax;
     const SysDesc &s = *a.sys;
-    const int g = threadIdx.x % kAG;
-    const int gbase = (threadIdx.x % warpSize) / kAG * kAG;
-    const int64_t ppb = blockDim.x / kAG;
+    const int g = threadIdx.x % G;
+    const int gbase = (threadIdx.x % warpSize) / G * G;
+    const int64_t ppb = blockDim.x / G;
     const double sc = a.seed_scale;
     const bool update = !PRIME;
     for (int64_t i0 = (int64_t)blockIdx.x * ppb; i0 < n; i0 += (int64_t)gridDim.x * ppb) {
-        const int64_t i = i0 + threadIdx.x / kAG;
+        const int64_t i = i0 + threadIdx.x / G;
         if (i >= n) continue;
         const D4 pi = a.pos[i], vi = a.vel[i], si = a.spin[i];
         const int ti = (int)si.w & 15;
@@ -227,7 +234,7 @@ __global__ void __launch_bounds__(kABlock) k_adj_reverse(AArgs a) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) acc[t][k] = 0.0;
         const int cnt = a.cnt[i];
-        for (int q = g; q < cnt; q += kAG) {
+        for (int q = g; q < cnt; q += G) {
             const int64_t slot = i * kmax + q;
             const int32_t j = a.nbr[slot];
             const D4 pj = a.pos[j];
@@ -309,13 +316,13 @@ __global__ void __launch_bounds__(kABlock) k_adj_reverse(AArgs a) {
             a.muw[i] = mw_before;
         }
         // lanes in a fixed order
-        jx0 = group_sum(jx0, gbase); jx1 = group_sum(jx1, gbase); jx2 = group_sum(jx2, gbase);
-        ju0 = group_sum(ju0, gbase); ju1 = group_sum(ju1, gbase); ju2 = group_sum(ju2, gbase);
-        jw0 = group_sum(jw0, gbase); jw1 = group_sum(jw1, gbase); jw2 = group_sum(jw2, gbase);
+        jx0 = group_sum<G>(jx0, gbase); jx1 = group_sum<G>(jx1, gbase); jx2 = group_sum<G>(jx2, gbase);
+        ju0 = group_sum<G>(ju0, gbase); ju1 = group_sum<G>(ju1, gbase); ju2 = group_sum<G>(ju2, gbase);
+        jw0 = group_sum<G>(jw0, gbase); jw1 = group_sum<G>(jw1, gbase); jw2 = group_sum<G>(jw2, gbase);
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int k = 0; k < 5; ++k) acc[t][k] = group_sum(acc[t][k], gbase);
+            for (int k = 0; k < 5; ++k) acc[t][k] = group_sum<G>(acc[t][k], gbase);
         if (g != 0) continue;
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -370,21 +377,28 @@ __global__ void k_adj_carry(AArgs a, const int32_t *frame, const int32_t *nids, 
 
 // ------------------------------------------------------------ reduction
 
-__global__ void __launch_bounds__(kABlock) k_adj_reduce(AArgs a, double *acc) {
+// Stage 1: block b of column col sums particles [b*chunk, (b+1)*chunk) by
+// type (fixed per-thread strides, then a fixed tree) into part[col][b][type];
+// stage 2: one thread per (col, type) adds the blocks in order.
+constexpr int kRedBlocks = 64;
+
+__global__ void __launch_bounds__(kABlock) k_adj_reduce1(AArgs a, double *part) {
     __shared__ double red[kMaxTypes][kABlock];
-    const int col = blockIdx.x;          // tj * 5 + c
-    const int nt = a.ntypes;
+    const int col = blockIdx.y;          // tj * 5 + c
     const int64_t n = a.n;
-    double part[kMaxTypes] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    double p[kMaxTypes] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         const int ti = (int)a.spin[i].w & 15;
         const double v = a.gp[(int64_t)col * n + i];
 #pragma unroll
         for (int t = 0; t < kMaxTypes; ++t)
-            if (t == ti) part[t] += v;
+            if (t == ti) p[t] += v;
     }
 #pragma unroll
-    for (int t = 0; t < kMaxTypes; ++t) red[t][threadIdx.x] = part[t];
+    for (int t = 0; t < kMaxTypes; ++t) red[t][threadIdx.x] = p[t];
     __syncthreads();
     for (int w = kABlock / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
@@ -392,10 +406,18 @@ __global__ void __launch_bounds__(kABlock) k_adj_reduce(AArgs a, double *acc) {
             for (int t = 0; t < kMaxTypes; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const int tj = col / 5, c = col % 5;
-        for (int t = 0; t < nt; ++t) acc[(t * nt + tj) * 5 + c] += red[t][0];
-    }
+    if (threadIdx.x < kMaxTypes) part[((int64_t)col * kRedBlocks + blockIdx.x) * kMaxTypes + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_adj_reduce2(AArgs a, const double *part, double *acc) {
+    const int nt = a.ntypes;
+    const int k = threadIdx.x;           // col * nt + ti
+    if (k >= 5 * nt * nt) return;
+    const int col = k / nt, ti = k % nt;
+    double s = 0.0;
+    for (int b = 0; b < kRedBlocks; ++b) s += part[((int64_t)col * kRedBlocks + b) * kMaxTypes + ti];
+    const int tj = col / 5, c = col % 5;
+    acc[(ti * nt + tj) * 5 + c] += s;
 }
 
 // ------------------------------------------------------------ launchers
@@ -411,7 +433,8 @@ hipError_t launch_adj_expand(const AArgs &a, const D4 *xi, const uint64_t *mask,
 
 hipError_t launch_adj_forward(const AArgs &a, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    k_adj_forward<<<adj_grid(a.n), kABlock, 0, st>>>(a);
+    if (a.lanes == 8) k_adj_forward<8><<<adj_grid(a.n, 8), kABlock, 0, st>>>(a);
+    else k_adj_forward<4><<<adj_grid(a.n, 4), kABlock, 0, st>>>(a);
     CHECK_LAUNCH();
 }
 
@@ -427,10 +450,16 @@ hipError_t launch_adj_seed_forces(const AArgs &a, const double *fb, const double
     CHECK_LAUNCH();
 }
 
+template <int NT, int G>
+static void reverse_ntg(const AArgs &a, int prime, hipStream_t st) {
+    if (prime) k_adj_reverse<NT, true, G><<<adj_grid(a.n, G), kABlock, 0, st>>>(a);
+    else k_adj_reverse<NT, false, G><<<adj_grid(a.n, G), kABlock, 0, st>>>(a);
+}
+
 template <int NT>
 static void reverse_nt(const AArgs &a, int prime, hipStream_t st) {
-    if (prime) k_adj_reverse<NT, true><<<adj_grid(a.n), kABlock, 0, st>>>(a);
-    else k_adj_reverse<NT, false><<<adj_grid(a.n), kABlock, 0, st>>>(a);
+    if (a.lanes == 8) reverse_ntg<NT, 8>(a, prime, st);
+    else reverse_ntg<NT, 4>(a, prime, st);
 }
 
 hipError_t launch_adj_reverse(const AArgs &a, int prime, hipStream_t st) {
@@ -451,9 +480,14 @@ hipError_t launch_adj_carry(const AArgs &a, const int32_t *frame, const int32_t 
     CHECK_LAUNCH();
 }
 
-hipError_t launch_adj_reduce(const AArgs &a, double *acc, hipStream_t st) {
+size_t adj_reduce_scratch_bytes(int ntypes) { return (size_t)5 * ntypes * kRedBlocks * kMaxTypes * sizeof(double); }
+
+hipError_t launch_adj_reduce(const AArgs &a, double *part, double *acc, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    k_adj_reduce<<<5 * a.ntypes, kABlock, 0, st>>>(a, acc);
+    k_adj_reduce1<<<dim3(kRedBlocks, 5 * a.ntypes), kABlock, 0, st>>>(a, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_adj_reduce2<<<1, 128, 0, st>>>(a, part, acc);
     CHECK_LAUNCH();
 }
 

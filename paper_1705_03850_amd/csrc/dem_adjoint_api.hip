@@ -47,7 +47,8 @@ struct dem_adjoint {
     std::vector<Ckpt> ck;         // slot 0: state before the rollout; 1..: window starts
     std::vector<Topo> topo;
     std::vector<StepBuf> traj;    // inputs of a window's evaluations 2..len
-    size_t rec[2] = {0, 0}, mu[2] = {0, 0}, muw[2] = {0, 0}, gp = 0, acc = 0;
+    size_t rec[2] = {0, 0}, mu[2] = {0, 0}, muw[2] = {0, 0}, gp = 0, acc = 0, part = 0;
+    int32_t lanes = 4;
     int nck = 0, ntopo = 0;
     int64_t step_end = -1;        // the context's step counter after the last forward
     int64_t rebuilds = 0;
@@ -59,7 +60,7 @@ struct AdjLayout {
     std::vector<Ckpt> ck;
     std::vector<Topo> topo;
     std::vector<StepBuf> traj;
-    size_t rec[2], mu[2], muw[2], gp, acc, total;
+    size_t rec[2], mu[2], muw[2], gp, acc, part, total;
 };
 
 AdjLayout adj_layout(int64_t n, int64_t K, int32_t window, int32_t max_windows, int nt) {
@@ -90,6 +91,7 @@ AdjLayout adj_layout(int64_t n, int64_t K, int32_t window, int32_t max_windows, 
     }
     L.gp = take(N * 5 * (size_t)nt * 8);
     L.acc = take(5 * (size_t)nt * (size_t)nt * 8);
+    L.part = take(adj_reduce_scratch_bytes(nt));
     L.total = o;
     return L;
 }
@@ -125,6 +127,7 @@ AArgs base_args(dem_adjoint *A) {
     a.sys = c->d_sys;
     a.coef = c->d_coef + c->geo.sys[0].coef0;
     a.seed_scale = 1.0;
+    a.lanes = A->lanes;
     return a;
 }
 
@@ -277,6 +280,7 @@ int dem_adjoint_init(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_win
     for (int k = 0; k < 2; ++k) { A->rec[k] = L.rec[k]; A->mu[k] = L.mu[k]; A->muw[k] = L.muw[k]; }
     A->gp = L.gp;
     A->acc = L.acc;
+    A->part = L.part;
     *out = A;
     return DEM_OK;
 }
@@ -414,7 +418,7 @@ int dem_rollout_backward(dem_adjoint *A, const dem_state *s, const double *gx, c
             cur ^= 1;
         }
         in_of(0, a);
-        HIPCALL(c, launch_adj_reduce(a, at<double>(A, A->acc), st));
+        HIPCALL(c, launch_adj_reduce(a, at<double>(A, A->part), at<double>(A, A->acc), st));
         if ((rc = fill_zero(A, A->gp, (size_t)5 * nt * n))) return rc;
         if (C.rebuilt) {
             const Topo &O = A->topo[A->ck[w - 1].topo];
@@ -445,7 +449,7 @@ int dem_rollout_backward(dem_adjoint *A, const dem_state *s, const double *gx, c
         a.seed_scale = 0.5;
         a.ox = ax0; a.ov = av0; a.ow = aw0;
         HIPCALL(c, launch_adj_reverse(a, 1, st));
-        HIPCALL(c, launch_adj_reduce(a, at<double>(A, A->acc), st));
+        HIPCALL(c, launch_adj_reduce(a, at<double>(A, A->part), at<double>(A, A->acc), st));
         if (ids0) HIPCALL(c, hipMemcpyAsync(ids0, A->ws + T.ids, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
     }
     return finish_grad(A, grad);
@@ -488,8 +492,15 @@ int dem_forces_vjp(dem_adjoint *A, const dem_state *s, const double *fb, const d
     a.seed_scale = 1.0;
     a.ox = xb; a.ov = vb; a.ow = wb;
     HIPCALL(c, launch_adj_reverse(a, 1, st));
-    HIPCALL(c, launch_adj_reduce(a, at<double>(A, A->acc), st));
+    HIPCALL(c, launch_adj_reduce(a, at<double>(A, A->part), at<double>(A, A->acc), st));
     return finish_grad(A, grad);
+}
+
+int dem_adjoint_set_lanes(dem_adjoint *A, int32_t lanes) {
+    if (!A) return DEM_ERR_ARG;
+    if (lanes != 4 && lanes != 8) return fail(A->ctx, DEM_ERR_ARG, "lanes must be 4 or 8");
+    A->lanes = lanes;
+    return DEM_OK;
 }
 
 int dem_adjoint_info(dem_adjoint *A, int64_t out[4]) {

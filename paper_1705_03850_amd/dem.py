@@ -49,7 +49,8 @@ _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_b
             "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_set_step_options", "dem_set_launch", "dem_check",
             "dem_stats", "dem_set_timing", "dem_kernel_times", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
             "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
-            "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_adjoint_info", "dem_adjoint_destroy"]
+            "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
+            "dem_adjoint_destroy"]
 
 
 def load(path: str = LIB_PATH):
@@ -91,6 +92,7 @@ def load(path: str = LIB_PATH):
     L.dem_rollout_forward.argtypes = [vp, P(State)]
     L.dem_rollout_backward.argtypes = [vp, P(State), vp, vp, vp, vp, vp, vp, vp, dp]
     L.dem_forces_vjp.argtypes = [vp, P(State), vp, vp, vp, vp, vp, dp]
+    L.dem_adjoint_set_lanes.argtypes = [vp, i32]
     L.dem_adjoint_info.argtypes = [vp, P(i64)]
     L.dem_adjoint_destroy.argtypes = [vp]
     for name in _SYMBOLS:
@@ -347,7 +349,8 @@ class Adjoint:
     checkpoints every ``window`` steps; ``backward(gx, gv, gw)`` takes the
     adjoints of the final x, v, w ((3, n) device tensors in the system's
     current order) and returns the gradients with respect to the per-type
-    E, e and mu and to the initial x, v, w (rows in id order)."""
+    E, e and mu (host) and to the initial x, v, w (device, in the order of
+    ``ids0``; ``initial_by_id`` gives host rows in id order)."""
 
     def __init__(self, dsys: DemSystem, nsteps: int, window: int = 20, max_windows: int = 0):
         torch = dsys.torch
@@ -375,9 +378,12 @@ class Adjoint:
     def forward(self):
         self.dsys._rc(self.L.dem_rollout_forward(self.h, self.dsys.state))
 
-    def _by_id(self, ids, *arrays):
+    @staticmethod
+    def initial_by_id(r: dict) -> dict:
+        """Host copies of the initial-state adjoints of backward(), rows in id order."""
+        ids = r["ids0"].cpu().numpy()
         order = np.argsort(ids, kind="stable")
-        return [a.cpu().numpy().T[order].copy() for a in arrays]
+        return {k: r[k].cpu().numpy().T[order].copy() for k in ("x0", "v0", "w0")}
 
     def backward(self, gx=None, gv=None, gw=None) -> dict:
         torch = self.dsys.torch
@@ -392,9 +398,8 @@ class Adjoint:
         d._rc(self.L.dem_rollout_backward(self.h, d.state, _ptr(gx), _ptr(gv), _ptr(gw), _ptr(ax), _ptr(av),
                                           _ptr(aw), _ptr(ids0), grad))
         g = np.array(grad[:]).reshape(3, self.ntypes)
-        ids = ids0.cpu().numpy()
-        x0, v0, w0 = self._by_id(ids, ax, av, aw)
-        return dict(E=g[0], e=g[1], mu=g[2], x0=x0, v0=v0, w0=w0, ids=np.sort(ids))
+        # initial-state adjoints stay on the device, (3, n) in the order of ids0
+        return dict(E=g[0], e=g[1], mu=g[2], x0=ax, v0=av, w0=aw, ids0=ids0)
 
     def forces_vjp(self, fb, tb) -> dict:
         """Reverse mode of one force evaluation (no history update) at the current
@@ -409,6 +414,9 @@ class Adjoint:
         d._rc(self.L.dem_forces_vjp(self.h, d.state, _ptr(fb), _ptr(tb), _ptr(xb), _ptr(vb), _ptr(wb), grad))
         g = np.array(grad[:]).reshape(3, self.ntypes)
         return dict(E=g[0], e=g[1], mu=g[2], x=xb, v=vb, w=wb)
+
+    def set_lanes(self, lanes: int):
+        self.dsys._rc(self.L.dem_adjoint_set_lanes(self.h, int(lanes)))
 
     def info(self) -> dict:
         out = (ctypes.c_int64 * 4)()

@@ -75,6 +75,7 @@ def gpu_rollout_grad(s, nsteps, a, b, c, window=20, skin=None, max_windows=0):
     adj = g.adjoint(nsteps, window=window, max_windows=max_windows)
     adj.forward()
     r = adj.backward(device_by_id(g, a), device_by_id(g, b), device_by_id(g, c))
+    r.update(adj.initial_by_id(r))
     vec = np.array([r[p][t] for p, t in DIRS])
     return vec, r, adj.info(), g
 

@@ -191,9 +191,11 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.nsys = (int32_t)c->geo.sys.size();
     a.kmax = c->geo.kmax;
     a.block = c->geo.block;
-    // default: as many workgroups as stay resident (3 waves per SIMD), each
-    // walking several tiles; the dispatch of every extra workgroup costs time
-    a.grid_cap = (int32_t)(c->grid_cap > 0 ? c->grid_cap : (int64_t)c->cus * 12 * 64 / c->geo.block);
+    // default: as many workgroups as stay resident (the step kernel's
+    // occupancy: 4 waves per SIMD, 3 for a batch), each walking several tiles;
+    // the dispatch of every extra workgroup costs time
+    const int64_t waves_per_cu = c->geo.sys.size() > 1 ? 12 : 16;
+    a.grid_cap = (int32_t)(c->grid_cap > 0 ? c->grid_cap : (int64_t)c->cus * waves_per_cu * 64 / c->geo.block);
     a.lanes = c->lanes;
     a.n = c->geo.n;
     a.ncell = c->geo.ncell;

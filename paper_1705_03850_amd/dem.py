@@ -60,6 +60,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build() or paper_1705_03850_amd/build.py")
+    try:
+        # the library must bind to the HIP runtime that PyTorch loads (it ships its own):
+        # load PyTorch first so that the runtime is already resolved
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     P = ctypes.POINTER

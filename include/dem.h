@@ -175,9 +175,11 @@ int dem_step(dem_ctx *ctx, const dem_state *s, int64_t nsteps);
 int dem_set_step_options(dem_ctx *ctx, int use_graph, int32_t chunk);
 
 /* Per-kernel timing for measurement.  With enable != 0, dem_step launches
- * its kernels one by one (no graph replay) and brackets each with a pair of
- * HIP events on the context's stream (events are created on first use and
- * released by dem_destroy); enabling or disabling clears the totals. */
+ * its kernels one by one (no graph replay) and brackets them with pairs of
+ * HIP events on the context's stream: one pair around each run of fused
+ * steps between synchronisations, one around each other launch (events are
+ * created on first use and released by dem_destroy); enabling or disabling
+ * clears the totals. */
 int dem_set_timing(dem_ctx *ctx, int enable);
 
 /* Accumulated GPU time (ms) and launch count of each timed kernel class of

@@ -191,11 +191,10 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.nsys = (int32_t)c->geo.sys.size();
     a.kmax = c->geo.kmax;
     a.block = c->geo.block;
-    // default: as many workgroups as stay resident (the step kernel's
-    // occupancy: 4 waves per SIMD, 3 for a batch), each walking several tiles;
-    // the dispatch of every extra workgroup costs time
-    const int64_t waves_per_cu = c->geo.sys.size() > 1 ? 12 : 16;
-    a.grid_cap = (int32_t)(c->grid_cap > 0 ? c->grid_cap : (int64_t)c->cus * waves_per_cu * 64 / c->geo.block);
+    // default: as many workgroups as stay resident (the step kernel runs 4
+    // waves per SIMD, 16 per CU), each walking several tiles; the dispatch of
+    // every extra workgroup costs time
+    a.grid_cap = (int32_t)(c->grid_cap > 0 ? c->grid_cap : (int64_t)c->cus * 16 * 64 / c->geo.block);
     a.lanes = c->lanes;
     a.n = c->geo.n;
     a.ncell = c->geo.ncell;
@@ -291,15 +290,18 @@ int tic(dem_ctx *c, int kind) {
             c->ev.push_back(e);
         }
         c->ev_kind.resize(c->ev.size() / 2);
+        c->ev_count.resize(c->ev.size() / 2);
     }
     c->ev_kind[c->ev_used] = kind;
     HIPCALL(c, hipEventRecord(c->ev[2 * c->ev_used], c->stream));
     return DEM_OK;
 }
 
-int toc(dem_ctx *c) {
+// Closes the pair opened by tic; `launches` kernels of its class ran in between.
+int toc(dem_ctx *c, int launches = 1) {
     if (!c->timing) return DEM_OK;
     HIPCALL(c, hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream));
+    c->ev_count[c->ev_used] = launches;
     ++c->ev_used;
     return DEM_OK;
 }
@@ -310,7 +312,7 @@ int collect_times(dem_ctx *c) {
         float ms = 0.0f;
         HIPCALL(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
         c->t_ms[c->ev_kind[k]] += ms;
-        c->t_n[c->ev_kind[k]] += 1;
+        c->t_n[c->ev_kind[k]] += c->ev_count[k];
     }
     c->ev_used = 0;
     return DEM_OK;
@@ -531,6 +533,7 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
         }
         int slot = 0;
         while ((8 << slot) < len && slot < 7) ++slot;
+        int pair1 = -1, pair2 = -1;   // timed event pairs of this group (fused steps, last step)
         if (c->use_graph && !c->timing && (8 << slot) == len && q == q0 && ((q - 1) & 1) == 0 &&
             q + len - 1 <= nsteps - 1) {
             GraphSlot &gs = c->graphs[slot];
@@ -540,15 +543,42 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
             HIPCALL(c, hipGraphLaunch(gs.exec, c->stream));
             q += len;
         } else {
+            // with timing on, one pair of events brackets each run of fused
+            // steps (the last step of a call gets a pair of its own), so the
+            // events add no gaps between the kernels they time
+            int open = 0;
             while (q <= nsteps && q - q0 < len) {
                 const int last = q == nsteps;
-                if ((rc = tic(c, last ? 2 : 1))) return rc;
+                if (last && open) {
+                    if ((rc = toc(c, open))) return rc;
+                    open = 0;
+                }
+                if (last) {
+                    pair2 = c->ev_used;
+                    if ((rc = tic(c, 2))) return rc;
+                } else if (!open) {
+                    pair1 = c->ev_used;
+                    if ((rc = tic(c, 1))) return rc;
+                }
                 HIPCALL(c, launch_step(a, (int)((q - 1) & 1), last ? 2 : 1, (int)(q - q0), 1, cnt, c->stream));
-                if ((rc = toc(c))) return rc;
+                if (last) {
+                    if ((rc = toc(c))) return rc;
+                } else {
+                    ++open;
+                }
                 ++q;
             }
+            if (open && (rc = toc(c, open))) return rc;
         }
         if ((rc = read_flags(c, h))) return rc;
+        if (c->timing && h.abort_at != INT64_MAX) {
+            // launches at or after the rebuild request did no work: count only
+            // the fused steps that ran (their near-empty launches stay inside
+            // the timed interval, a few microseconds each)
+            const int64_t ran = h.abort_at - base - q0;
+            if (pair1 >= 0 && c->ev_count[pair1] > ran) c->ev_count[pair1] = (int)(ran > 0 ? ran : 0);
+            if (pair2 >= 0 && h.abort_at - base <= nsteps) c->ev_count[pair2] = 0;
+        }
         if ((rc = collect_times(c))) return rc;
         if ((rc = flag_error(c, h))) return rc;
         if (h.abort_at != INT64_MAX) {

@@ -72,6 +72,7 @@ struct dem_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev;      // pairs (start, stop) recorded in this chunk
     std::vector<int> ev_kind;        // kernel class of each pair
+    std::vector<int> ev_count;       // launches between the two events of each pair
     int ev_used = 0;
     double t_ms[dem::host::kKinds] = {0, 0, 0, 0};
     int64_t t_n[dem::host::kKinds] = {0, 0, 0, 0};

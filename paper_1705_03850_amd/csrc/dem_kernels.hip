@@ -529,9 +529,6 @@ __global__ void k_unpack(KArgs a, int src, int selected) {
 //           written to the caller's arrays (gated).
 // One particle of the force pass (see k_step): every lane of its group calls
 // this with the same i; sy is the particle's system (wave-uniform).
-template <bool BATCH>
-constexpr int kStepWaves = BATCH ? 3 : 4;
-
 template <bool BATCH, bool COUNT, int MODE, int G>
 __device__ __forceinline__ void step_particle(const KArgs &a, int src, int update, int64_t i, int sy, const D4 &pi,
                                               const D4 &vi, const D4 &si, int code, int g, int gbase,
@@ -677,11 +674,12 @@ __device__ __forceinline__ void step_particle(const KArgs &a, int src, int updat
 }
 
 template <bool BATCH, bool COUNT, int MODE, int G>
-// Compiled for kStepWaves<BATCH> waves per SIMD: the kernel waits on gathers,
-// and a fourth wave (128 registers, no spills) ran the 1e6-sphere bed 15 %
-// faster than three; at five or more the spills cost twice that.  The batch
-// form needs a few more registers and keeps three.
-__global__ void __launch_bounds__(256, kStepWaves<BATCH>) k_step(KArgs a, int src, int k, int update) {
+// Compiled for four waves per SIMD (at most 128 registers): the kernel waits
+// on gathers, and the fourth wave ran the 1e6-sphere bed 15 % and the
+// 64-system batch 14 % faster than three (the batch form spills a few bytes
+// and still gains); at five or more waves the spills cost more than the
+// extra wave brings.
+__global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int update) {
     int64_t step = 0;
     if (MODE != 0) {
         step = a.flags->step_base + k;

@@ -265,7 +265,7 @@ def main():
     ap.add_argument("--max-blocks", type=int, default=0, help="grid cap of the fused step kernel (0 = resident capacity)")
     ap.add_argument("--lanes", type=int, default=4, help="threads per particle in the force pass (4, 8, 16)")
     ap.add_argument("--timing-steps", type=int, default=300)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--window", type=int, default=20, help="adjoint suite: steps per checkpoint window")

@@ -404,8 +404,10 @@ class Adjoint:
         d._rc(self.L.dem_rollout_backward(self.h, d.state, _ptr(gx), _ptr(gv), _ptr(gw), _ptr(ax), _ptr(av),
                                           _ptr(aw), _ptr(ids0), grad))
         g = np.array(grad[:]).reshape(3, self.ntypes)
-        # initial-state adjoints stay on the device, (3, n) in the order of ids0
-        return dict(E=g[0], e=g[1], mu=g[2], x0=ax, v0=av, w0=aw, ids0=ids0)
+        # initial-state adjoints stay on the device, (3, n) in the order of ids0;
+        # the last result is also kept on the object (for callers of DemRollout)
+        self.last = dict(E=g[0], e=g[1], mu=g[2], x0=ax, v0=av, w0=aw, ids0=ids0)
+        return self.last
 
     def forces_vjp(self, fb, tb) -> dict:
         """Reverse mode of one force evaluation (no history update) at the current

@@ -248,15 +248,20 @@ typedef struct dem_adjoint dem_adjoint;   /* opaque: rollout checkpoints and adj
  * checkpoints every `window` steps (1..4096) on a context of one system
  * (DEM_ERR_ARG for a batch).  max_windows bounds the number of windows: a
  * list rebuild ends a window early, so a rollout can need more than
- * ceil(nsteps / window); 0 selects 2 ceil(nsteps / window) + 1.  Memory:
- * (max_windows + window) x (128 + 32 k_max) bytes per particle, plus
- * (max_windows + 1) x (28 + 4 k_max) bytes per particle for the lists. */
-int dem_adjoint_workspace_size(dem_ctx *ctx, int64_t nsteps, int32_t window, int32_t max_windows, size_t *bytes);
+ * ceil(nsteps / window); 0 selects 2 ceil(nsteps / window) + 1.
+ * keep = 0: checkpoints at window starts, each window recomputed by the
+ * backward; memory (max_windows + window) x (128 + 32 k_max) bytes per
+ * particle.  keep = 1: the inputs of every step are stored by the forward and
+ * nothing is recomputed; memory (nsteps + 2) x (128 + 32 k_max) bytes per
+ * particle.  Both: plus (max_windows + 1) x (28 + 4 k_max) bytes per particle
+ * for the lists. */
+int dem_adjoint_workspace_size(dem_ctx *ctx, int64_t nsteps, int32_t window, int32_t max_windows, int32_t keep,
+                               size_t *bytes);
 
 /* Bind an adjoint to a context and a caller-owned device workspace (256-byte
  * aligned, at least the size above, untouched until dem_adjoint_destroy). */
-int dem_adjoint_init(dem_ctx *ctx, int64_t nsteps, int32_t window, int32_t max_windows, void *workspace,
-                     size_t bytes, dem_adjoint **out);
+int dem_adjoint_init(dem_ctx *ctx, int64_t nsteps, int32_t window, int32_t max_windows, int32_t keep,
+                     void *workspace, size_t bytes, dem_adjoint **out);
 
 /* The rollout: the force evaluation of the current state without history
  * update (as dem_forces(ctx, s, 0)), then nsteps steps bit-identical to
@@ -265,7 +270,10 @@ int dem_adjoint_init(dem_ctx *ctx, int64_t nsteps, int32_t window, int32_t max_w
  * only between windows (a rebuild request ends the window), so the contact
  * topology is fixed inside every window.  On return s holds the final state
  * (permuted by the rebuilds, as after dem_step).  DEM_ERR_CAPACITY when more
- * than max_windows windows are needed.  Synchronises once per window. */
+ * than max_windows windows are needed.  Synchronises once per window.  With
+ * keep the steps are run by the evaluation kernel of the reverse pass, same
+ * arithmetic and order, storing every step's inputs; the contact counters of
+ * dem_stats are then not advanced. */
 int dem_rollout_forward(dem_adjoint *adj, const dem_state *s);
 
 /* Reverse mode of the last dem_rollout_forward (no other stepping in
@@ -275,7 +283,8 @@ int dem_rollout_forward(dem_adjoint *adj, const dem_state *s);
  * whose ids go to ids0 (device [n], may be NULL); grad = host [3][ntypes]:
  * dL/dE_t, then dL/de_t, then dL/dmu_t.  Each window is recomputed from its
  * checkpoint and reversed step by step; sums over particles are taken in a
- * fixed order, so results are reproducible.  Synchronises. */
+ * fixed order, so results are reproducible (and equal with and without keep).
+ * Synchronises. */
 int dem_rollout_backward(dem_adjoint *adj, const dem_state *s, const double *gx, const double *gv, const double *gw,
                          double *ax0, double *av0, double *aw0, int32_t *ids0, double *grad);
 
@@ -286,7 +295,7 @@ int dem_rollout_backward(dem_adjoint *adj, const dem_state *s, const double *gx,
 int dem_forces_vjp(dem_adjoint *adj, const dem_state *s, const double *fb, const double *tb, double *xb, double *vb,
                    double *wb, double *grad);
 
-/* Threads per particle in the recompute and reverse kernels: 4 (default) or
+/* Threads per particle in the evaluation and reverse kernels: 4 (default) or
  * 8.  Sums over a particle's row are taken per lane and then over the lanes
  * in order, so results are reproducible for a given choice. */
 int dem_adjoint_set_lanes(dem_adjoint *adj, int32_t lanes);

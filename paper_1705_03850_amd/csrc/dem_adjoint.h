@@ -43,13 +43,28 @@ struct AArgs {
     double seed_scale;       // factor on the seeds read from rin
     int32_t lanes;           // threads per particle in the recompute and reverse passes (4 or 8)
     double *ox, *ov, *ow;    // priming evaluation: adjoints of the initial x, v, w ([3][n])
+    // the forward of a kept rollout (forward modes 1 and 2)
+    Flags *flags;            // gating: this evaluation is step step_base + k
+    int32_t k;
+    double *disp;            // [3][n] displacement since the last list build
+    double *x, *v, *w, *f, *t;   // caller arrays, written by the last step
 };
 
 // Live list (ELL rows with the non-zero-history mask) -> full-form history.
 hipError_t launch_adj_expand(const AArgs &a, const D4 *xi, const uint64_t *mask, const double *xiw, D4 *hout,
                              D4 *hwout, hipStream_t st);
-// One evaluation of the rollout again: pos/vel/spin, hin, hwin -> *_o, hout, hwout.
-hipError_t launch_adj_forward(const AArgs &a, hipStream_t st);
+// One evaluation: pos/vel/spin, hin, hwin -> *_o, hout, hwout, with the arithmetic
+// and summation order of the fused step.  mode 0: recompute; mode 1: a step of
+// a kept rollout (gated like the fused step; displacement, rebuild request and
+// non-finite check); mode 2: its last step (gated; forces, one half kick, and
+// x, v, w, f, t written to the caller's arrays; no drift).
+hipError_t launch_adj_forward(const AArgs &a, int mode, hipStream_t st);
+// Full-form history -> live list rows (history and mask; mask bit where the
+// stored value is not all zero bits) and wall history [3][n].
+hipError_t launch_adj_compress(const AArgs &a, const D4 *hin, const D4 *hwin, D4 *xi, uint64_t *mask, double *xiw,
+                               hipStream_t st);
+// Packed pos/vel/spin -> caller arrays x, v, w.
+hipError_t launch_adj_unpack(const AArgs &a, double *x, double *v, double *w, hipStream_t st);
 // Records of the last evaluation from the adjoints of the final x, v, w.
 hipError_t launch_adj_seed(const AArgs &a, const double *gx, const double *gv, const double *gw, hipStream_t st);
 // Records for the reverse of a single force evaluation (seeds = force and torque adjoints).

@@ -73,8 +73,14 @@ __global__ void k_adj_expand(AArgs a, const D4 *xi, const uint64_t *mask, const 
 
 // ------------------------------------------------------------ recompute
 
-template <int G>
+template <int G, int MODE>
 __global__ void __launch_bounds__(kABlock) k_adj_forward(AArgs a) {
+    int64_t step = 0;
+    if (MODE != 0) {
+        step = a.flags->step_base + a.k;
+        if (a.flags->abort_at <= step) return;
+    }
+    bool need = false, bad = false;
     const int64_t n = a.n;
     const int64_t kmax = a.kmax;
     const SysDesc &s = *a.sys;
@@ -163,14 +169,67 @@ __global__ void __launch_bounds__(kABlock) k_adj_forward(AArgs a) {
         const D2 im = a.im[i];
         double vx = vi.x + s.hdt * (Fx * im.a), vy = vi.y + s.hdt * (Fy * im.a), vz = vi.z + s.hdt * (Fz * im.a);
         double wx = si.x + s.hdt * (Tx * im.b), wy = si.y + s.hdt * (Ty * im.b), wz = si.z + s.hdt * (Tz * im.b);
+        if (MODE == 2) {
+            a.f[i] = Fx; a.f[n + i] = Fy; a.f[2 * n + i] = Fz;
+            a.t[i] = Tx; a.t[n + i] = Ty; a.t[2 * n + i] = Tz;
+            a.x[i] = pi.x; a.x[n + i] = pi.y; a.x[2 * n + i] = pi.z;
+            a.v[i] = vx; a.v[n + i] = vy; a.v[2 * n + i] = vz;
+            a.w[i] = wx; a.w[n + i] = wy; a.w[2 * n + i] = wz;
+            continue;
+        }
         vx = vx + s.hdt * (Fx * im.a); vy = vy + s.hdt * (Fy * im.a); vz = vz + s.hdt * (Fz * im.a);
         wx = wx + s.hdt * (Tx * im.b); wy = wy + s.hdt * (Ty * im.b); wz = wz + s.hdt * (Tz * im.b);
         const double x = wrap_axis(pi.x + s.dt * vx, s, 0);
         const double y = wrap_axis(pi.y + s.dt * vy, s, 1);
         const double z = wrap_axis(pi.z + s.dt * vz, s, 2);
+        if (MODE == 1) {
+            // displacement since the last build and the rebuild request, as in the fused step
+            const double ddx = a.disp[i] + s.dt * vx;
+            const double ddy = a.disp[n + i] + s.dt * vy;
+            const double ddz = a.disp[2 * n + i] + s.dt * vz;
+            a.disp[i] = ddx; a.disp[n + i] = ddy; a.disp[2 * n + i] = ddz;
+            double dsq = 0.0;
+            dsq += ddx * ddx;
+            dsq += ddy * ddy;
+            dsq += ddz * ddz;
+            if (!(dsq <= s.disp_thr2)) need = true;
+            if (!isfinite(x + y + z + vx + vy + vz)) bad = true;
+        }
         a.pos_o[i] = D4{x, y, z, ri};
         a.vel_o[i] = D4{vx, vy, vz, mi};
         a.spin_o[i] = D4{wx, wy, wz, si.w};
+    }
+    if (MODE == 1) {
+        if (bad) atomicOr(&a.flags->err, kErrNonFinite);
+        if (need) a.flags->abort_at = step + 1;
+    }
+}
+
+__global__ void k_adj_compress(AArgs a, const D4 *hin, const D4 *hwin, D4 *xi, uint64_t *mask, double *xiw) {
+    const int64_t n = a.n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int cnt = a.cnt[i];
+        uint64_t m = 0;
+        for (int q = 0; q < cnt; ++q) {
+            const int64_t slot = i * a.kmax + q;
+            const D4 h = hin[slot];
+            xi[slot] = D4{h.x, h.y, h.z, 0.0};
+            if (__double_as_longlong(h.x) | __double_as_longlong(h.y) | __double_as_longlong(h.z)) m |= 1ull << q;
+        }
+        const D4 hw = hwin[i];
+        xiw[i] = hw.x; xiw[n + i] = hw.y; xiw[2 * n + i] = hw.z;
+        if (__double_as_longlong(hw.x) | __double_as_longlong(hw.y) | __double_as_longlong(hw.z)) m |= kWallBit;
+        mask[i] = m;
+    }
+}
+
+__global__ void k_adj_unpack(AArgs a, double *x, double *v, double *w) {
+    const int64_t n = a.n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const D4 p = a.pos[i], u = a.vel[i], s = a.spin[i];
+        x[i] = p.x; x[n + i] = p.y; x[2 * n + i] = p.z;
+        v[i] = u.x; v[n + i] = u.y; v[2 * n + i] = u.z;
+        w[i] = s.x; w[n + i] = s.y; w[2 * n + i] = s.z;
     }
 }
 
@@ -431,10 +490,30 @@ hipError_t launch_adj_expand(const AArgs &a, const D4 *xi, const uint64_t *mask,
     CHECK_LAUNCH();
 }
 
-hipError_t launch_adj_forward(const AArgs &a, hipStream_t st) {
+template <int G>
+static void forward_g(const AArgs &a, int mode, hipStream_t st) {
+    if (mode == 1) k_adj_forward<G, 1><<<adj_grid(a.n, G), kABlock, 0, st>>>(a);
+    else if (mode == 2) k_adj_forward<G, 2><<<adj_grid(a.n, G), kABlock, 0, st>>>(a);
+    else k_adj_forward<G, 0><<<adj_grid(a.n, G), kABlock, 0, st>>>(a);
+}
+
+hipError_t launch_adj_forward(const AArgs &a, int mode, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    if (a.lanes == 8) k_adj_forward<8><<<adj_grid(a.n, 8), kABlock, 0, st>>>(a);
-    else k_adj_forward<4><<<adj_grid(a.n, 4), kABlock, 0, st>>>(a);
+    if (a.lanes == 8) forward_g<8>(a, mode, st);
+    else forward_g<4>(a, mode, st);
+    CHECK_LAUNCH();
+}
+
+hipError_t launch_adj_compress(const AArgs &a, const D4 *hin, const D4 *hwin, D4 *xi, uint64_t *mask, double *xiw,
+                               hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    k_adj_compress<<<flat_grid(a.n), kABlock, 0, st>>>(a, hin, hwin, xi, mask, xiw);
+    CHECK_LAUNCH();
+}
+
+hipError_t launch_adj_unpack(const AArgs &a, double *x, double *v, double *w, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    k_adj_unpack<<<flat_grid(a.n), kABlock, 0, st>>>(a, x, v, w);
     CHECK_LAUNCH();
 }
 

@@ -9,6 +9,9 @@
 // Backward: windows in reverse order; each is recomputed from its checkpoint
 // (all its evaluations' inputs kept), then reversed evaluation by evaluation,
 // and the adjoint is carried across the rebuild to the previous window.
+// Kept mode: the forward runs the evaluation kernel of the reverse pass in
+// its gated form and stores the inputs of every evaluation, so the backward
+// recomputes nothing (memory grows with the step count instead of the window).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -49,6 +52,7 @@ struct dem_adjoint {
     std::vector<StepBuf> traj;    // inputs of a window's evaluations 2..len
     size_t rec[2] = {0, 0}, mu[2] = {0, 0}, muw[2] = {0, 0}, gp = 0, acc = 0, part = 0;
     int32_t lanes = 4;
+    int32_t keep = 0;             // every evaluation's inputs stored by the forward
     int nck = 0, ntopo = 0;
     int64_t step_end = -1;        // the context's step counter after the last forward
     int64_t rebuilds = 0;
@@ -63,14 +67,15 @@ struct AdjLayout {
     size_t rec[2], mu[2], muw[2], gp, acc, part, total;
 };
 
-AdjLayout adj_layout(int64_t n, int64_t K, int32_t window, int32_t max_windows, int nt) {
+AdjLayout adj_layout(int64_t n, int64_t K, int64_t nsteps, int32_t window, int32_t max_windows, int nt, int keep) {
     AdjLayout L;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
     const size_t N = (size_t)n;
     const size_t rec = N * sizeof(D4), slots = N * (size_t)K * sizeof(D4);
     L.ck.resize((size_t)max_windows + 1);
-    for (Ckpt &c : L.ck) {
+    for (size_t k = 0; k < (keep ? 1 : L.ck.size()); ++k) {
+        Ckpt &c = L.ck[k];
         c.pos = take(rec); c.vel = take(rec); c.spin = take(rec);
         c.hist = take(slots); c.hw = take(rec);
     }
@@ -79,7 +84,8 @@ AdjLayout adj_layout(int64_t n, int64_t K, int32_t window, int32_t max_windows, 
         t.nbr = take(N * (size_t)K * 4); t.cnt = take(N * 4); t.ids = take(N * 4); t.frame = take(N * 4);
         t.im = take(N * sizeof(D2));
     }
-    L.traj.resize(window > 1 ? (size_t)window - 1 : 0);
+    // kept: slot q - 1 holds the inputs of evaluation q, slot nsteps the final history
+    L.traj.resize(keep ? (size_t)nsteps + 1 : window > 1 ? (size_t)window - 1 : 0);
     for (StepBuf &b : L.traj) {
         b.pos = take(rec); b.vel = take(rec); b.spin = take(rec);
         b.hist = take(slots); b.hw = take(rec);
@@ -151,19 +157,36 @@ int save_topology(dem_adjoint *A, const List &live, int t, bool with_frame) {
     return DEM_OK;
 }
 
-// Checkpoint slot k: packed buffer `buf` of the context and the live history.
-int save_checkpoint(dem_adjoint *A, const List &live, int k, int buf, int topo, int rebuilt, int64_t q0) {
+// Packed buffer `buf` of the context and the live history -> the state record
+// at the given offsets.
+int save_state(dem_adjoint *A, const List &live, int buf, size_t pos, size_t vel, size_t spin, size_t hist,
+               size_t hw) {
     dem_ctx *c = A->ctx;
     const size_t n = (size_t)c->geo.n;
-    Ckpt &C = A->ck[k];
     hipStream_t st = c->stream;
-    HIPCALL(c, hipMemcpyAsync(A->ws + C.pos, c->ws + c->lay.pos[buf], n * sizeof(D4), hipMemcpyDeviceToDevice, st));
-    HIPCALL(c, hipMemcpyAsync(A->ws + C.vel, c->ws + c->lay.vel[buf], n * sizeof(D4), hipMemcpyDeviceToDevice, st));
-    HIPCALL(c, hipMemcpyAsync(A->ws + C.spin, c->ws + c->lay.spin[buf], n * sizeof(D4), hipMemcpyDeviceToDevice, st));
+    HIPCALL(c, hipMemcpyAsync(A->ws + pos, c->ws + c->lay.pos[buf], n * sizeof(D4), hipMemcpyDeviceToDevice, st));
+    HIPCALL(c, hipMemcpyAsync(A->ws + vel, c->ws + c->lay.vel[buf], n * sizeof(D4), hipMemcpyDeviceToDevice, st));
+    HIPCALL(c, hipMemcpyAsync(A->ws + spin, c->ws + c->lay.spin[buf], n * sizeof(D4), hipMemcpyDeviceToDevice, st));
     AArgs a = base_args(A);
     a.cnt = live.cnt;
-    HIPCALL(c, launch_adj_expand(a, live.xi, live.mask, (const double *)(c->ws + c->lay.xiw), at<D4>(A, C.hist),
-                                 at<D4>(A, C.hw), st));
+    HIPCALL(c, launch_adj_expand(a, live.xi, live.mask, (const double *)(c->ws + c->lay.xiw), at<D4>(A, hist),
+                                 at<D4>(A, hw), st));
+    return DEM_OK;
+}
+
+// Checkpoint slot k.  Stored: packed buffer `buf` of the context and the live
+// history; kept mode (k >= 1): the record of evaluation q0's inputs, written
+// here when `buf` >= 0 and by the previous window's last evaluation otherwise.
+int save_checkpoint(dem_adjoint *A, const List &live, int k, int buf, int topo, int rebuilt, int64_t q0) {
+    Ckpt &C = A->ck[k];
+    if (A->keep && k >= 1) {
+        const StepBuf &B = A->traj[(size_t)q0 - 1];
+        C.pos = B.pos; C.vel = B.vel; C.spin = B.spin; C.hist = B.hist; C.hw = B.hw;
+    }
+    if (buf >= 0) {
+        int rc = save_state(A, live, buf, C.pos, C.vel, C.spin, C.hist, C.hw);
+        if (rc) return rc;
+    }
     C.topo = topo;
     C.rebuilt = rebuilt;
     C.q0 = q0;
@@ -177,6 +200,27 @@ int rebuild(dem_adjoint *A, const dem_state *s, int b) {
     dem_ctx *c = A->ctx;
     KArgs K = kargs(c, s);
     HIPCALL(c, launch_unpack(K, b, 0, c->stream));
+    c->binned = false;
+    int rc;
+    if ((rc = do_bin(c, s, true)) || (rc = do_neighbors(c, s))) return rc;
+    KArgs K2 = kargs(c, s);
+    HIPCALL(c, launch_pack(K2, 0, 0, 0, 0, c->stream));
+    ++A->rebuilds;
+    return DEM_OK;
+}
+
+// Kept mode: the live list takes the history of state record B (written in
+// the list's order), and, with `rebuild`, the list is rebuilt on B's state
+// as above.
+int restore_from(dem_adjoint *A, const dem_state *s, const List &live, const StepBuf &B, bool rebuild_list) {
+    dem_ctx *c = A->ctx;
+    AArgs a = base_args(A);
+    a.cnt = live.cnt;
+    a.pos = at<D4>(A, B.pos); a.vel = at<D4>(A, B.vel); a.spin = at<D4>(A, B.spin);
+    HIPCALL(c, launch_adj_compress(a, at<D4>(A, B.hist), at<D4>(A, B.hw), live.xi, live.mask,
+                                   (double *)(c->ws + c->lay.xiw), c->stream));
+    if (!rebuild_list) return DEM_OK;
+    HIPCALL(c, launch_adj_unpack(a, s->x, s->v, s->w, c->stream));
     c->binned = false;
     int rc;
     if ((rc = do_bin(c, s, true)) || (rc = do_neighbors(c, s))) return rc;
@@ -250,21 +294,22 @@ int dem_set_materials(dem_ctx *c, int32_t sys, const dem_material *mat, int32_t 
     return DEM_OK;
 }
 
-int dem_adjoint_workspace_size(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_windows, size_t *bytes) {
+int dem_adjoint_workspace_size(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_windows, int32_t keep,
+                               size_t *bytes) {
     if (!bytes) return DEM_ERR_ARG;
     int rc = adj_args(c, nsteps, window, max_windows);
     if (rc) return rc;
-    *bytes = adj_layout(c->geo.n, c->geo.kmax, window, max_windows, c->geo.sys[0].ntypes).total;
+    *bytes = adj_layout(c->geo.n, c->geo.kmax, nsteps, window, max_windows, c->geo.sys[0].ntypes, keep != 0).total;
     return DEM_OK;
 }
 
-int dem_adjoint_init(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_windows, void *workspace, size_t bytes,
-                     dem_adjoint **out) {
+int dem_adjoint_init(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_windows, int32_t keep, void *workspace,
+                     size_t bytes, dem_adjoint **out) {
     if (!out) return DEM_ERR_ARG;
     *out = nullptr;
     int rc = adj_args(c, nsteps, window, max_windows);
     if (rc) return rc;
-    AdjLayout L = adj_layout(c->geo.n, c->geo.kmax, window, max_windows, c->geo.sys[0].ntypes);
+    AdjLayout L = adj_layout(c->geo.n, c->geo.kmax, nsteps, window, max_windows, c->geo.sys[0].ntypes, keep != 0);
     if (!workspace || bytes < L.total) return fail(c, DEM_ERR_ARG, "adjoint workspace too small");
     if ((uintptr_t)workspace % kAlign) return fail(c, DEM_ERR_ARG, "adjoint workspace must be 256-byte aligned");
     dem_adjoint *A = new dem_adjoint();
@@ -272,6 +317,7 @@ int dem_adjoint_init(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_win
     A->nsteps = nsteps;
     A->window = window;
     A->max_windows = max_windows;
+    A->keep = keep != 0;
     A->ws = (char *)workspace;
     A->bytes = bytes;
     A->ck = L.ck;
@@ -328,18 +374,41 @@ int dem_rollout_forward(dem_adjoint *A, const dem_state *s) {
             if ((rc = save_topology(A, live, A->ntopo, true))) return rc;
             ++A->ntopo;
         }
-        if ((rc = save_checkpoint(A, live, A->nck, buf, A->ntopo - 1, rebuilt, q))) return rc;
+        const bool fresh = !A->keep || q == 1 || rebuilt;   // kept: else written by the last evaluation
+        if ((rc = save_checkpoint(A, live, A->nck, fresh ? buf : -1, A->ntopo - 1, rebuilt, q))) return rc;
         const int len = (int)std::min<int64_t>(A->window, S - q + 1);
         HIPCALL(c, launch_ctrl(c->d_flags, 0, base + q, c->stream));
-        for (int k = 0; k < len; ++k)
-            HIPCALL(c, launch_step(K, buf ^ (k & 1), q + k == S ? 2 : 1, k, 1, cnt, c->stream));
+        if (A->keep) {
+            const Topo &T = A->topo[A->ntopo - 1];
+            AArgs a = base_args(A);
+            a.nbr = at<int32_t>(A, T.nbr);
+            a.cnt = at<int32_t>(A, T.cnt);
+            a.im = K.im;
+            a.flags = c->d_flags;
+            a.disp = K.disp;
+            a.x = s->x; a.v = s->v; a.w = s->w; a.f = s->f; a.t = s->t;
+            for (int k = 0; k < len; ++k) {
+                const StepBuf &I = A->traj[(size_t)(q + k) - 1], &O = A->traj[(size_t)(q + k)];
+                a.pos = at<D4>(A, I.pos); a.vel = at<D4>(A, I.vel); a.spin = at<D4>(A, I.spin);
+                a.hin = at<D4>(A, I.hist); a.hwin = at<D4>(A, I.hw);
+                a.pos_o = at<D4>(A, O.pos); a.vel_o = at<D4>(A, O.vel); a.spin_o = at<D4>(A, O.spin);
+                a.hout = at<D4>(A, O.hist); a.hwout = at<D4>(A, O.hw);
+                a.k = k;
+                HIPCALL(c, launch_adj_forward(a, q + k == S ? 2 : 1, c->stream));
+            }
+        } else {
+            for (int k = 0; k < len; ++k)
+                HIPCALL(c, launch_step(K, buf ^ (k & 1), q + k == S ? 2 : 1, k, 1, cnt, c->stream));
+        }
         if ((rc = read_flags(c, h)) || (rc = flag_error(c, h))) return rc;
         Ckpt &C = A->ck[A->nck];
         if (h.abort_at != INT64_MAX) {
             const int64_t qa = h.abort_at - base;   // the first evaluation that needs the new list
             if (qa <= q || qa > q + len) return fail(c, DEM_ERR_STATE, "rebuild request outside the window");
             C.len = (int32_t)(qa - q);
-            if ((rc = rebuild(A, s, buf ^ (int)((qa - q) & 1)))) return rc;
+            if (A->keep) rc = restore_from(A, s, live, A->traj[(size_t)qa - 1], true);
+            else rc = rebuild(A, s, buf ^ (int)((qa - q) & 1));
+            if (rc) return rc;
             buf = 0;
             rebuilt = 1;
             q = qa;
@@ -351,6 +420,8 @@ int dem_rollout_forward(dem_adjoint *A, const dem_state *s) {
         }
         ++A->nck;
     }
+    // kept: the final history goes back into the live list, as the fused step leaves it
+    if (A->keep && (rc = restore_from(A, s, live, A->traj[(size_t)S], false))) return rc;
     HIPCALL(c, launch_ctrl(c->d_flags, 3, S, c->stream));
     if ((rc = read_flags(c, h))) return rc;
     c->step_counter += S;
@@ -392,7 +463,11 @@ int dem_rollout_backward(dem_adjoint *A, const dem_state *s, const double *gx, c
         a.im = at<D2>(A, T.im);
         a.gp = at<double>(A, A->gp);
         auto in_of = [&](int t, AArgs &x) {
-            if (t == 0) {
+            if (A->keep) {
+                const StepBuf &B = A->traj[(size_t)(C.q0 + t) - 1];
+                x.pos = at<D4>(A, B.pos); x.vel = at<D4>(A, B.vel); x.spin = at<D4>(A, B.spin);
+                x.hin = at<D4>(A, B.hist); x.hwin = at<D4>(A, B.hw);
+            } else if (t == 0) {
                 x.pos = at<D4>(A, C.pos); x.vel = at<D4>(A, C.vel); x.spin = at<D4>(A, C.spin);
                 x.hin = at<D4>(A, C.hist); x.hwin = at<D4>(A, C.hw);
             } else {
@@ -401,12 +476,12 @@ int dem_rollout_backward(dem_adjoint *A, const dem_state *s, const double *gx, c
                 x.hin = at<D4>(A, B.hist); x.hwin = at<D4>(A, B.hw);
             }
         };
-        for (int t = 0; t + 1 < C.len; ++t) {
+        for (int t = 0; !A->keep && t + 1 < C.len; ++t) {
             in_of(t, a);
             const StepBuf &B = A->traj[t];
             a.pos_o = at<D4>(A, B.pos); a.vel_o = at<D4>(A, B.vel); a.spin_o = at<D4>(A, B.spin);
             a.hout = at<D4>(A, B.hist); a.hwout = at<D4>(A, B.hw);
-            HIPCALL(c, launch_adj_forward(a, st));
+            HIPCALL(c, launch_adj_forward(a, 0, st));
         }
         a.mu = at<D4>(A, A->mu[m]);
         a.muw = at<D4>(A, A->muw[m]);

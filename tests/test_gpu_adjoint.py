@@ -6,7 +6,9 @@ References, none of which shares code with the library's adjoint:
     agreement to 1e-9 relative;
   * central differences (h = 1e-6 relative) of the GPU's own plain rollout
     (dem_step), which never runs the adjoint kernels: 1e-5 relative;
-  * the windowed forward against dem_step: bit for bit.
+  * the windowed forward against dem_step: bit for bit, also in kept mode
+    (every step's inputs stored, the steps run by the adjoint's own
+    evaluation kernel), which must give bit-identical gradients.
 """
 import math
 
@@ -70,9 +72,9 @@ def oracle_gradient(s, nsteps, a, b, c):
             + np.einsum("ic,ick->k", c[ids], wt))
 
 
-def gpu_rollout_grad(s, nsteps, a, b, c, window=20, skin=None, max_windows=0):
+def gpu_rollout_grad(s, nsteps, a, b, c, window=20, skin=None, max_windows=0, keep=False):
     g = dem().DemSystem(s, skin=skin)
-    adj = g.adjoint(nsteps, window=window, max_windows=max_windows)
+    adj = g.adjoint(nsteps, window=window, max_windows=max_windows, keep=keep)
     adj.forward()
     r = adj.backward(device_by_id(g, a), device_by_id(g, b), device_by_id(g, c))
     r.update(adj.initial_by_id(r))
@@ -88,9 +90,12 @@ def assert_close(got, ref, rtol, what=""):
 
 # ------------------------------------------------------------ forward
 
-def test_windowed_forward_equals_dem_step():
+@pytest.mark.parametrize("keep", [False, True])
+def test_windowed_forward_equals_dem_step(keep):
     """Windows, checkpoints and rebuilds only at window ends change nothing:
-    the final state equals dem_step's bit for bit (small skin: several rebuilds)."""
+    the final state equals dem_step's bit for bit (small skin: several
+    rebuilds), and so does the state after 25 more plain steps (the list and
+    its history are left as dem_step leaves them)."""
     s = chute(n=800)
     skin = 0.006e-3
     g1 = dem().DemSystem(s, skin=skin)
@@ -98,7 +103,7 @@ def test_windowed_forward_equals_dem_step():
     g1.step(90)
     h1 = g1.host()
     g2 = dem().DemSystem(s, skin=skin)
-    adj = g2.adjoint(90, window=7)
+    adj = g2.adjoint(90, window=7, keep=keep)
     adj.forward()
     h2 = g2.host()
     info = adj.info()
@@ -106,6 +111,11 @@ def test_windowed_forward_equals_dem_step():
     assert info["windows"] >= math.ceil(90 / 7)
     for k in ("x", "v", "w", "f", "t"):
         assert np.array_equal(h1[k], h2[k]), k
+    g1.step(25)
+    g2.step(25)
+    h1, h2 = g1.host(), g2.host()
+    for k in ("x", "v", "w", "f", "t"):
+        assert np.array_equal(h1[k], h2[k]), ("after", k)
 
 
 # ------------------------------------------------------------ one force evaluation
@@ -166,19 +176,21 @@ def test_forces_vjp_positions_match_central_differences():
 
 # ------------------------------------------------------------ rollouts
 
-@pytest.mark.parametrize("skin,window", [(None, 20), (0.006e-3, 7)])
-def test_rollout_gradient_matches_oracle_tangent(skin, window):
+@pytest.mark.parametrize("skin,window,keep", [(None, 20, False), (0.006e-3, 7, False), (0.006e-3, 7, True)])
+def test_rollout_gradient_matches_oracle_tangent(skin, window, keep):
     s = chute(n=600)
     nsteps = 60
     a, b, c = weights(s)
     ref = oracle_gradient(s, nsteps, a, b, c)
-    got, r, info, _ = gpu_rollout_grad(s, nsteps, a, b, c, window=window, skin=skin)
+    got, r, info, _ = gpu_rollout_grad(s, nsteps, a, b, c, window=window, skin=skin, keep=keep)
     if skin is not None:
         assert info["rebuilds"] >= 1, info
-    assert_close(got, ref, 1e-9, f"rollout skin={skin} window={window}")
+    assert_close(got, ref, 1e-9, f"rollout skin={skin} window={window} keep={keep}")
 
 
 def test_window_length_changes_nothing():
+    """Window lengths 1, 6 and 40 agree (1e-13; sums split differently), and
+    kept mode equals the recomputing mode at the same window bit for bit."""
     s = chute(n=600)
     a, b, c = weights(s, seed=8)
     res = [gpu_rollout_grad(s, 40, a, b, c, window=w, skin=0.006e-3) for w in (1, 6, 40)]
@@ -186,6 +198,10 @@ def test_window_length_changes_nothing():
         assert_close(got, res[0][0], 1e-13, "window")
         for k in ("x0", "v0", "w0"):
             assert np.array_equal(r[k], res[0][1][k]), k
+    got, r, info, _ = gpu_rollout_grad(s, 40, a, b, c, window=6, skin=0.006e-3, keep=True)
+    assert np.array_equal(got, res[1][0])
+    for k in ("x0", "v0", "w0"):
+        assert np.array_equal(r[k], res[1][1][k]), ("keep", k)
 
 
 def test_initial_state_adjoint_matches_oracle_tangent():

@@ -9,8 +9,9 @@ times (4 lanes per particle, 256-thread blocks, resident grid, graph replay).
   * two-level chute (2e5 + 5e5 spheres): the 2-system batch bit for bit
     equal to each system stepped alone.
   * 5e4-sphere adjoint chute: 40 steps against the oracle's dual-number
-    tangent (1e-9), with and without list rebuilds between windows; the
-    200-step flux-loss gradient independent of the window length.
+    tangent (1e-9), with and without list rebuilds between windows, and in
+    kept mode; the 200-step flux-loss gradient independent of the window
+    length, and kept mode bit for bit equal to recomputation.
 """
 import numpy as np
 import pytest
@@ -128,8 +129,8 @@ def device_by_id(g, a_by_id):
     return torch.from_numpy(np.ascontiguousarray(a_by_id[ids].T)).to(g.device)
 
 
-@pytest.mark.parametrize("skin", [None, 0.01e-3])
-def test_full_adjoint_chute_against_oracle_tangent(skin):
+@pytest.mark.parametrize("skin,keep", [(None, False), (0.01e-3, False), (0.01e-3, True)])
+def test_full_adjoint_chute_against_oracle_tangent(skin, keep):
     """All 5e4 spheres of the adjoint chute, 40 steps in windows of 8 (the small
     skin forces list rebuilds between windows): the gradient of a linear loss
     in the final x, v, w against the oracle's dual-number tangent, 1e-9."""
@@ -140,7 +141,7 @@ def test_full_adjoint_chute_against_oracle_tangent(skin):
     b = rng.normal(size=(s.n, 3))
     c = rng.normal(size=(s.n, 3)) * 1e-3
     g = dem().DemSystem(s, skin=skin)
-    adj = g.adjoint(nsteps, window=8)
+    adj = g.adjoint(nsteps, window=8, keep=keep)
     adj.forward()
     r = adj.backward(device_by_id(g, a), device_by_id(g, b), device_by_id(g, c))
     info = adj.info()
@@ -162,7 +163,8 @@ def test_full_adjoint_chute_against_oracle_tangent(skin):
 def test_full_adjoint_chute_200_steps():
     """The calibration objective at full size: 200 steps, flux loss.  Windows
     of 20 and of 50 give the same gradient (1e-12) and bit-identical
-    initial-state adjoints; central differences of the rollout (h = 1e-7
+    initial-state adjoints, kept mode at window 50 the same gradient bit for
+    bit; central differences of the rollout (h = 1e-7
     relative) agree within 5e-2 -- at this size the loss has many kinks
     (contact onsets, Coulomb switches), and differences scatter by 1e-4 to
     1e-2 whatever the step, which is why the exact check is the one above."""
@@ -173,8 +175,8 @@ def test_full_adjoint_chute_200_steps():
     target = torch.zeros(20, dtype=torch.float64, device="cuda")
     g = dem().DemSystem(s)
     res = []
-    for window in (20, 50):
-        adj = g.adjoint(nsteps, window=window)
+    for window, keep in ((20, False), (50, False), (50, True)):
+        adj = g.adjoint(nsteps, window=window, keep=keep)
         theta = R.theta_of(s.materials).requires_grad_(True)
         x, v, w = R.rollout(theta, adj, (s.x, s.v, s.w))
         loss = ((R.mass_flux_profile(x, v, R.masses(g), H0, Lx, Ly) - target) ** 2).mean()
@@ -184,6 +186,9 @@ def test_full_adjoint_chute_200_steps():
     assert np.all(np.abs(g20 - g50) <= 1e-12 * np.abs(g20).max())
     for k in ("x0", "v0", "w0"):
         assert np.array_equal(res[0][2][k], res[1][2][k]), k
+        assert np.array_equal(res[1][2][k], res[2][2][k]), ("keep", k)
+    assert np.array_equal(res[1][0], res[2][0])
+    res[2] = None
     th = R.theta_of(s.materials).numpy()
     adj = res[1][1]
 

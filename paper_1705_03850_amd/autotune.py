@@ -35,10 +35,15 @@ def _time_run(systems, steps, skin_f, cell_f, block, lanes, use_graph=True, chun
     return dt / steps, builds
 
 
-def autotune(systems, steps: int = 128, long_steps: int = 1024, out_json: str | None = None, log=print) -> dict:
+def autotune(systems, steps: int = 128, long_steps: int = 1024, out_json: str | None = None, log=print,
+             reps: int = 2, margin: float = 0.02) -> dict:
     """Coordinate search.  The launch shape (lanes, block) is timed over `steps`
     steps; skin and cell are timed over `long_steps` steps, long enough for the
-    list rebuilds they cause to show up in the time per step."""
+    list rebuilds they cause to show up in the time per step.  Every candidate
+    is timed `reps` times, the candidates interleaved, and keeps its best time;
+    a candidate replaces the current value only when it is faster by more than
+    `margin` (timing noise of a few per cent otherwise flips the choice from
+    run to run)."""
     best = {"skin_factor": 0.1, "cell_factor": 1.0, "block": 256, "lanes": 4}
     tried = []
 
@@ -60,9 +65,12 @@ def autotune(systems, steps: int = 128, long_steps: int = 1024, out_json: str | 
                                 (long_steps, "skin_factor", (0.1, 0.05, 0.2, 0.3)),
                                 (long_steps, "cell_factor", (1.0, 1.25))):
         times = {}
-        for v in values:
-            times[v] = run(nsteps, **{key: v})
-        best[key] = min(times, key=times.get)
+        for _ in range(max(1, reps)):
+            for v in values:
+                times[v] = min(times.get(v, float("inf")), run(nsteps, **{key: v}))
+        cand = min(times, key=times.get)
+        if times[cand] < times[best[key]] * (1.0 - margin):
+            best[key] = cand
     cur = min(t["ms_per_step"] for t in tried if all(t[k] == best[k] for k in best))
     result = dict(best, ms_per_step=cur, steps=steps, long_steps=long_steps, tried=tried)
     if out_json:

@@ -313,6 +313,26 @@ def test_batch_of_64_systems():
     assert np.max(np.abs(d)) <= 1e-9 * max(s.hi)
 
 
+def test_autotuned_batch_equals_default():
+    """The autotuner returns a choice from its candidate sets, and a batch run
+    with that choice (launch shape, skin, cell) equals the default run bit for
+    bit: tuning trades speed only."""
+    from paper_1705_03850_amd import autotune
+    systems = W.batch_systems(scale=0.05)[:8]
+    choice = autotune.autotune(systems, steps=8, long_steps=24, log=None)
+    assert choice["lanes"] in (4, 8) and choice["block"] in (128, 256)
+    assert choice["skin_factor"] in (0.1, 0.05, 0.2, 0.3) and choice["cell_factor"] in (1.0, 1.25)
+    assert len(choice["tried"]) >= 2 * (2 + 2)      # every launch shape timed twice
+    outs = []
+    for kw in (dict(), autotune.apply(systems, choice)):
+        g = gpu(systems, use_graph=True, chunk=16, **kw)
+        g.prime()
+        g.step(60)
+        outs.append(g.host())
+    for key in ("x", "v", "w", "f", "t"):
+        assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
 def test_capacity_error_reported():
     from paper_1705_03850_amd import dem
     s = W.plain_fcc()

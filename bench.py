@@ -41,6 +41,13 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1705_03850_amd", "csrc", f) for f in
 #   per directed contact: its tangential history read and written (48 B)
 #   per wall contact: the wall history read and written (48 B)
 STEP_PER_PARTICLE, STEP_PER_SLOT, STEP_PER_CONTACT, STEP_PER_WALL = 268, 4, 48, 48
+# ... and of the neighbour build (dem_neighbors):
+#   per particle: position+radius and id read (36), its previous row's length, mask and frame read (16),
+#                 new length, mask and id written (16), displacement cleared (24)   = 92 B
+#   per listed slot: new neighbour index written (4), previous index and its id read (8) = 12 B
+#   per directed contact carried: tangential history read and written (48 B)
+#   per cell: its start offset (4 B)
+NBR_PER_PARTICLE, NBR_PER_SLOT, NBR_PER_CONTACT, NBR_PER_CELL = 92, 12, 48, 4
 
 
 def log(msg):
@@ -268,6 +275,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=4, help="threads per particle in the force pass (4, 8, 16)")
     ap.add_argument("--timing-steps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--rebuilds", type=int, default=10, help="forced rebuilds (dem_bin + dem_neighbors) after the timing")
+    ap.add_argument("--rebuild-every", type=int, default=50, help="steps between forced rebuilds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--window", type=int, default=20, help="adjoint suite: steps per checkpoint window")
@@ -374,6 +383,40 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": round(bytes_step), "avg_launch_us": round(kernels["step"]["avg_us"], 2)}
 
+    # forced rebuilds: dem_bin and dem_neighbors every `rebuild_every` steps,
+    # each call timed with events on the library's stream
+    forced = None
+    if args.rebuilds > 0:
+        every = args.rebuild_every
+        log(f"{args.rebuilds} forced rebuilds, one every {every} steps")
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.rebuilds)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(args.rebuilds):
+            g.step(every)
+            evs[3 * r].record(g.stream)
+            g.bin()
+            evs[3 * r + 1].record(g.stream)
+            g.neighbors()
+            evs[3 * r + 2].record(g.stream)
+        torch.cuda.synchronize()
+        wall_r = time.perf_counter() - t0
+        bin_ms = sorted(evs[3 * r].elapsed_time(evs[3 * r + 1]) for r in range(args.rebuilds))
+        nbr_ms = sorted(evs[3 * r + 1].elapsed_time(evs[3 * r + 2]) for r in range(args.rebuilds))
+        nbr_med = nbr_ms[len(nbr_ms) // 2]
+        h = 2.0 * float(bed.r.max()) + float(bed.skin)         # default cell edge: the cut-off
+        ncell = 1
+        for ax in range(3):
+            ncell *= max(1, int((bed.hi[ax] - bed.lo[ax]) / (h * (1.0 + 1e-9))))
+        nbr_bytes = (n * NBR_PER_PARTICLE + slots * NBR_PER_SLOT + contacts_step * NBR_PER_CONTACT
+                     + ncell * NBR_PER_CELL)
+        forced = {"every": every, "calls": args.rebuilds,
+                  "particle_steps_per_s": n * every * args.rebuilds / wall_r,
+                  "bin_ms_median": bin_ms[len(bin_ms) // 2], "neighbors_ms_median": nbr_med,
+                  "neighbors_alg_bytes": round(nbr_bytes),
+                  "neighbors_GBps": round(nbr_bytes / (nbr_med * 1e-3) / 1e9, 1),
+                  "neighbors_frac": round(nbr_bytes / (nbr_med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline: {args.cpu_steps} steps")
@@ -403,6 +446,7 @@ def main():
         "gpu_event_ms": gpu_ms,
         "roofline": roofline,
         "kernels": kernels,
+        "forced_rebuild": forced,
         "cpu_baseline": cpu,
         "kernel_source": kernel_source_hash(),
         "device": torch.cuda.get_device_name(0),

@@ -834,18 +834,30 @@ __global__ void k_unpack(KArgs a, int src, int selected) {
 //           written to the caller's arrays (gated).
 // One particle of the force pass (see k_step): every lane of its group calls
 // this with the same i; sy is the particle's system (wave-uniform).
+// A system's descriptor copied word by word into scalar registers (the value
+// is the same for every lane).  Read through the table instead, its fields
+// are loaded again after every store the compiler cannot tell apart from it:
+// the slot loop of the fused step did that on every iteration.
+__device__ __forceinline__ SysDesc uniform_sys(const SysDesc *p) {
+    SysDesc s;
+    const uint32_t *src = (const uint32_t *)p;
+    uint32_t *dst = (uint32_t *)&s;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(SysDesc) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return s;
+}
+
 template <bool BATCH, bool COUNT, int MODE, int G>
-__device__ __forceinline__ void step_particle(const KArgs &a, int src, int update, int64_t i, int sy, const D4 &pi,
-                                              const D4 &vi, const D4 &si, int code, int g, int gbase,
-                                              uint64_t gmask, unsigned &ncont, unsigned &nwall, bool &need,
-                                              bool &bad) {
+__device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, int src, int update, int64_t i,
+                                              int sy, const D4 &pi, const D4 &vi, const D4 &si, int code, int g,
+                                              int gbase, uint64_t gmask, unsigned &ncont, unsigned &nwall,
+                                              bool &need, bool &bad) {
     const int64_t n = a.n;
     const D4 *__restrict__ P = a.pos[src];
     const D4 *__restrict__ V = a.vel[src];
     const D4 *__restrict__ S = a.spin[src];
     const int64_t kmax = a.kmax;
         const int ti = code & 15;
-        const SysDesc &s = a.sys[sy];
         const List L = list_of(a, sy, 0);
         const PairCoef *coef = a.coef + s.coef0;
         const double ri = pi.w, mi = vi.w;
@@ -1006,20 +1018,21 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
     const int64_t chunk = (ntiles + kXcd - 1) / kXcd;
     const int64_t t0 = (blockIdx.x % kXcd) * chunk;
     const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
+    const SysDesc s0 = uniform_sys(a.sys);   // the only system when !BATCH
     for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {
         const int64_t i = t * ppb + threadIdx.x / G;
         if (!BATCH) {
             if (i >= n) continue;
             const D4 pi = P[i], vi = V[i], si = S[i];
-            step_particle<BATCH, COUNT, MODE, G>(a, src, update, i, 0, pi, vi, si, (int)si.w, g, gbase, gmask, ncont,
-                                                 nwall, need, bad);
+            step_particle<BATCH, COUNT, MODE, G>(a, s0, src, update, i, 0, pi, vi, si, (int)si.w, g, gbase, gmask,
+                                                 ncont, nwall, need, bad);
             continue;
         }
         if (i >= n) continue;
         const D4 pi = P[i], vi = V[i], si = S[i];
         const int code = (int)si.w;
-        step_particle<BATCH, COUNT, MODE, G>(a, src, update, i, code >> 4, pi, vi, si, code, g, gbase, gmask, ncont,
-                                             nwall, need, bad);
+        step_particle<BATCH, COUNT, MODE, G>(a, a.sys[code >> 4], src, update, i, code >> 4, pi, vi, si, code, g,
+                                             gbase, gmask, ncont, nwall, need, bad);
     }
     if (bad) atomicOr(&a.flags->err, kErrNonFinite);
     if (MODE == 1 && need) a.flags->abort_at = step + 1;

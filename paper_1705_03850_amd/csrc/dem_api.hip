@@ -158,8 +158,24 @@ Layout make_layout(const Geometry &g) {
     L.im = take(n * sizeof(D2));
     L.sel = take(g.sys.size() * 4);
     L.lcur = take(g.sys.size() * 4);
+    L.tile0 = take((g.sys.size() + 1) * 8);
     L.total = o;
     return L;
+}
+
+// First tile of every system for the batch step at the current launch shape
+// (tiles of block / lanes particles, none shared by two systems).
+int upload_tiles(dem_ctx *c) {
+    const int64_t ppb = c->geo.block / c->lanes;
+    std::vector<int64_t> t0(c->geo.sys.size() + 1, 0);
+    for (size_t s = 0; s < c->geo.sys.size(); ++s) {
+        const int64_t ns = c->geo.sys[s].p1 - c->geo.sys[s].p0;
+        t0[s + 1] = t0[s] + (ns + ppb - 1) / ppb;
+    }
+    c->ntiles_b = t0.back();
+    HIPCALL(c, hipMemcpyAsync(c->ws + c->lay.tile0, t0.data(), t0.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    return DEM_OK;
 }
 
 int fail(dem_ctx *c, int code, const std::string &msg) {
@@ -216,6 +232,8 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     }
     a.im = (D2 *)(w + L.im);
     a.sel = (int32_t *)(w + L.sel);
+    a.tile0 = (const int64_t *)(w + L.tile0);
+    a.ntiles_b = c->ntiles_b;
     a.lcur = (int32_t *)(w + L.lcur);
     return a;
 }
@@ -396,6 +414,7 @@ int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *wo
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_rho, g.rho.data(), g.rho.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_ctrl(c->d_flags, 2, 0, c->stream);
+    if (e == hipSuccess && upload_tiles(c) != DEM_OK) e = hipErrorUnknown;
     if (e == hipSuccess) {
         int dev = 0, cus = 0;
         e = hipGetDevice(&dev);
@@ -492,7 +511,7 @@ int dem_set_launch(dem_ctx *c, int32_t lanes, int32_t max_blocks) {
     c->grid_cap = max_blocks;
     c->lanes = lanes;
     for (GraphSlot &g : c->graphs) g.chunk = 0;  // re-capture with the new grid/lanes
-    return DEM_OK;
+    return upload_tiles(c);
 }
 
 int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {

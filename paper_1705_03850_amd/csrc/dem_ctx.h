@@ -20,7 +20,7 @@ struct Layout {
     size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame;
     size_t nbr[2], cnt[2], xi[2], mask[2], ids[2];
     size_t cell_of, rank, order, cell_count, cell_start, scan_partial, shadow_d, shadow_i;
-    size_t pos[2], vel[2], spin[2], im, sel, lcur;
+    size_t pos[2], vel[2], spin[2], im, sel, lcur, tile0;
     size_t total;
 };
 
@@ -65,6 +65,7 @@ struct dem_ctx {
     int64_t grid_cap = 0;   // 0: resident capacity, set at init
     int lanes = 4;
     int cus = 256;
+    int64_t ntiles_b = 0;            // tiles of the batch step (each within one system)
     dem::host::GraphSlot graphs[8];          // replay graphs of 2^(k+3) fused steps
     double gap_avg = 1e9;         // running estimate of steps between rebuilds
     int64_t since_rebuild = 0;
@@ -94,6 +95,7 @@ KArgs kargs(dem_ctx *c, const dem_state *s);
 int check_state(dem_ctx *c, const dem_state *s);
 int read_flags(dem_ctx *c, Flags &h);
 int flag_error(dem_ctx *c, const Flags &h);
+int upload_tiles(dem_ctx *c);
 int do_bin(dem_ctx *c, const dem_state *s, bool all);
 int do_neighbors(dem_ctx *c, const dem_state *s, bool clear_sel = true);
 // The current list buffer of system sy (reads the device's choice; synchronises).

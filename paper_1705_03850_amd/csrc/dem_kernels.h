@@ -35,6 +35,10 @@ struct KArgs {
     D4 *pos[2], *vel[2], *spin[2];
     D2 *im;                // (1/m, 1/I)
     int32_t *sel;          // [nsys] 1 = system needs (or gets) a new list
+    // batch step: tiles of block / lanes particles, each within one system;
+    // system s has tiles tile0[s] .. tile0[s+1]-1
+    const int64_t *tile0;  // [nsys + 1]
+    int64_t ntiles_b;
 };
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);

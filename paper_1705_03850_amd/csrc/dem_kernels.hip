@@ -838,6 +838,13 @@ __global__ void k_unpack(KArgs a, int src, int selected) {
 // is the same for every lane).  Read through the table instead, its fields
 // are loaded again after every store the compiler cannot tell apart from it:
 // the slot loop of the fused step did that on every iteration.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ SysDesc uniform_sys(const SysDesc *p) {
     SysDesc s;
     const uint32_t *src = (const uint32_t *)p;
@@ -1013,26 +1020,35 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
     const uint64_t gmask = (1ull << G) - 1;
     unsigned ncont = 0, nwall = 0;
     bool need = false, bad = false;
-    const int64_t ntiles = (n + ppb - 1) / ppb;
+    // a batch is walked in tiles that each lie within one system, so that the
+    // block's system descriptor is uniform too; it is read again only when a
+    // block moves on to a tile of another system
+    const int64_t ntiles = BATCH ? a.ntiles_b : (n + ppb - 1) / ppb;
     const int per = gridDim.x / kXcd;
     const int64_t chunk = (ntiles + kXcd - 1) / kXcd;
     const int64_t t0 = (blockIdx.x % kXcd) * chunk;
     const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
-    const SysDesc s0 = uniform_sys(a.sys);   // the only system when !BATCH
+    SysDesc sd = uniform_sys(a.sys);   // the only system when !BATCH
+    int sy = 0;
+    int64_t tlo = 0, thi = BATCH ? 0 : ntiles;
     for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {
-        const int64_t i = t * ppb + threadIdx.x / G;
-        if (!BATCH) {
-            if (i >= n) continue;
-            const D4 pi = P[i], vi = V[i], si = S[i];
-            step_particle<BATCH, COUNT, MODE, G>(a, s0, src, update, i, 0, pi, vi, si, (int)si.w, g, gbase, gmask,
-                                                 ncont, nwall, need, bad);
-            continue;
+        if (BATCH && (t < tlo || t >= thi)) {
+            int lo = 0, hi = a.nsys - 1;   // last system whose first tile is <= t
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.tile0[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            sy = __builtin_amdgcn_readfirstlane(lo);
+            sd = uniform_sys(a.sys + sy);
+            tlo = uniform_i64(a.tile0[sy]);
+            thi = uniform_i64(a.tile0[sy + 1]);
         }
-        if (i >= n) continue;
+        const int64_t i = BATCH ? sd.p0 + (t - tlo) * ppb + threadIdx.x / G : t * ppb + threadIdx.x / G;
+        if (i >= (BATCH ? sd.p1 : n)) continue;
         const D4 pi = P[i], vi = V[i], si = S[i];
-        const int code = (int)si.w;
-        step_particle<BATCH, COUNT, MODE, G>(a, a.sys[code >> 4], src, update, i, code >> 4, pi, vi, si, code, g,
-                                             gbase, gmask, ncont, nwall, need, bad);
+        step_particle<BATCH, COUNT, MODE, G>(a, sd, src, update, i, sy, pi, vi, si, (int)si.w, g, gbase, gmask,
+                                             ncont, nwall, need, bad);
     }
     if (bad) atomicOr(&a.flags->err, kErrNonFinite);
     if (MODE == 1 && need) a.flags->abort_at = step + 1;
@@ -1178,7 +1194,8 @@ hipError_t launch_unpack(const KArgs &a, int src, int selected, hipStream_t st) 
 template <int G>
 static hipError_t launch_step_g(const KArgs &a, int src, int mode, int k, int update, int count, hipStream_t st) {
     const int ppb = a.block / G;
-    const int g = grid_for((a.n + ppb - 1) / ppb * a.block, a.block, a.grid_cap);
+    const int64_t ntiles = a.nsys > 1 ? a.ntiles_b : (a.n + ppb - 1) / ppb;
+    const int g = grid_for(ntiles * a.block, a.block, a.grid_cap);
     const int B = a.block;
 #define STEP_LAUNCH(BT, CT, MD) k_step<BT, CT, MD, G><<<g, B, 0, st>>>(a, src, k, update)
 #define STEP_MODES(BT, CT)                                  \

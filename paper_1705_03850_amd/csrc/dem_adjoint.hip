@@ -74,7 +74,7 @@ __global__ void k_adj_expand(AArgs a, const D4 *xi, const uint64_t *mask, const 
 // ------------------------------------------------------------ recompute
 
 template <int G, int MODE>
-__global__ void __launch_bounds__(kABlock) k_adj_forward(AArgs a) {
+__global__ void __launch_bounds__(kABlock, 4) k_adj_forward(AArgs a) {
     int64_t step = 0;
     if (MODE != 0) {
         step = a.flags->step_base + a.k;
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kABlock) k_adj_forward(AArgs a) {
     bool need = false, bad = false;
     const int64_t n = a.n;
     const int64_t kmax = a.kmax;
-    const SysDesc &s = *a.sys;
+    const SysDesc s = uniform_sys(a.sys);
     const int g = threadIdx.x % G;
     const int gbase = (threadIdx.x % warpSize) / G * G;
     const uint64_t gmask = (1ull << G) - 1;
@@ -271,7 +271,7 @@ template <int NT, bool PRIME, int G>
 __global__ void __launch_bounds__(kABlock, DEM_ADJ_WAVES) k_adj_reverse(AArgs a) {
     const int64_t n = a.n;
     const int64_t kmax = a.kmax;
-    const SysDesc &s = *a.sys;
+    const SysDesc s = uniform_sys(a.sys);
     const int g = threadIdx.x % G;
     const int gbase = (threadIdx.x % warpSize) / G * G;
     const int64_t ppb = blockDim.x / G;

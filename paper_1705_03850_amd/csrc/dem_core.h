@@ -96,6 +96,26 @@ __host__ __device__ inline int cell_coord(double x, const SysDesc &s, int a) {
     return c;
 }
 
+// A system's descriptor copied word by word into scalar registers (the value
+// is the same for every lane).  Read through the table instead, its fields
+// are loaded again after every store the compiler cannot tell apart from it:
+// the slot loop of the fused step did that on every iteration.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ SysDesc uniform_sys(const SysDesc *p) {
+    SysDesc s;
+    const uint32_t *src = (const uint32_t *)p;
+    uint32_t *dst = (uint32_t *)&s;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(SysDesc) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return s;
+}
+
 // Periodic wrap of a drifted coordinate into [lo, hi).
 __host__ __device__ inline double wrap_axis(double x, const SysDesc &s, int ax) {
     if (!s.periodic[ax]) return x;

@@ -834,26 +834,6 @@ __global__ void k_unpack(KArgs a, int src, int selected) {
 //           written to the caller's arrays (gated).
 // One particle of the force pass (see k_step): every lane of its group calls
 // this with the same i; sy is the particle's system (wave-uniform).
-// A system's descriptor copied word by word into scalar registers (the value
-// is the same for every lane).  Read through the table instead, its fields
-// are loaded again after every store the compiler cannot tell apart from it:
-// the slot loop of the fused step did that on every iteration.
-__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
-    const uint64_t u = (uint64_t)v;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ SysDesc uniform_sys(const SysDesc *p) {
-    SysDesc s;
-    const uint32_t *src = (const uint32_t *)p;
-    uint32_t *dst = (uint32_t *)&s;
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(SysDesc) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
-    return s;
-}
-
 template <bool BATCH, bool COUNT, int MODE, int G>
 __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, int src, int update, int64_t i,
                                               int sy, const D4 &pi, const D4 &vi, const D4 &si, int code, int g,

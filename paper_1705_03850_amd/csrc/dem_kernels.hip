@@ -834,6 +834,16 @@ __global__ void k_unpack(KArgs a, int src, int selected) {
 //           written to the caller's arrays (gated).
 // One particle of the force pass (see k_step): every lane of its group calls
 // this with the same i; sy is the particle's system (wave-uniform).
+// The block's system's pair coefficients (ntypes x ntypes): read by every
+// contact, so kept in LDS instead of three global loads per contact.
+__shared__ PairCoef step_coef[kMaxTypes * kMaxTypes];
+
+__device__ __forceinline__ void load_step_coef(const KArgs &a, const SysDesc &s) {
+    __syncthreads();   // readers of the previous table are done
+    for (int k = threadIdx.x; k < s.ntypes * s.ntypes; k += blockDim.x) step_coef[k] = a.coef[s.coef0 + k];
+    __syncthreads();
+}
+
 template <bool BATCH, bool COUNT, int MODE, int G>
 __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, int src, int update, int64_t i,
                                               int sy, const D4 &pi, const D4 &vi, const D4 &si, int code, int g,
@@ -846,7 +856,7 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
     const int64_t kmax = a.kmax;
         const int ti = code & 15;
         const List L = list_of(a, sy, 0);
-        const PairCoef *coef = a.coef + s.coef0;
+        const PairCoef *coef = step_coef;   // the system's table, in LDS
         const double ri = pi.w, mi = vi.w;
         double Fx = mi * s.g[0], Fy = mi * s.g[1], Fz = mi * s.g[2];
         double Tx = 0.0, Ty = 0.0, Tz = 0.0;
@@ -1011,7 +1021,8 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
     SysDesc sd = uniform_sys(a.sys);   // the only system when !BATCH
     int sy = 0;
     int64_t tlo = 0, thi = BATCH ? 0 : ntiles;
-    for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {
+    if (!BATCH) load_step_coef(a, sd);
+    for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {   // uniform over the block
         if (BATCH && (t < tlo || t >= thi)) {
             int lo = 0, hi = a.nsys - 1;   // last system whose first tile is <= t
             while (lo < hi) {
@@ -1023,6 +1034,7 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
             sd = uniform_sys(a.sys + sy);
             tlo = uniform_i64(a.tile0[sy]);
             thi = uniform_i64(a.tile0[sy + 1]);
+            load_step_coef(a, sd);
         }
         const int64_t i = BATCH ? sd.p0 + (t - tlo) * ppb + threadIdx.x / G : t * ppb + threadIdx.x / G;
         if (i >= (BATCH ? sd.p1 : n)) continue;

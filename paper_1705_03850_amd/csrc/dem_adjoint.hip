@@ -73,6 +73,16 @@ __global__ void k_adj_expand(AArgs a, const D4 *xi, const uint64_t *mask, const 
 
 // ------------------------------------------------------------ recompute
 
+// The system's pair coefficients, read by every contact: in LDS (the reverse
+// kernel, at its register limit, reads them from global memory: the LDS copy
+// cost it spills).
+__shared__ PairCoef adj_coef[kMaxTypes * kMaxTypes];
+
+__device__ __forceinline__ void load_adj_coef(const AArgs &a) {
+    for (int k = threadIdx.x; k < a.ntypes * a.ntypes; k += blockDim.x) adj_coef[k] = a.coef[k];
+    __syncthreads();
+}
+
 template <int G, int MODE>
 __global__ void __launch_bounds__(kABlock, 4) k_adj_forward(AArgs a) {
     int64_t step = 0;
@@ -84,6 +94,7 @@ __global__ void __launch_bounds__(kABlock, 4) k_adj_forward(AArgs a) {
     const int64_t n = a.n;
     const int64_t kmax = a.kmax;
     const SysDesc s = uniform_sys(a.sys);
+    load_adj_coef(a);
     const int g = threadIdx.x % G;
     const int gbase = (threadIdx.x % warpSize) / G * G;
     const uint64_t gmask = (1ull << G) - 1;
@@ -122,7 +133,7 @@ __global__ void __launch_bounds__(kABlock, 4) k_adj_forward(AArgs a) {
                 c.wsx = ri * si.x + pj.w * sj.x;
                 c.wsy = ri * si.y + pj.w * sj.y;
                 c.wsz = ri * si.z + pj.w * sj.z;
-                const PairCoef pc = a.coef[ti * a.ntypes + ((int)sj.w & 15)];
+                const PairCoef pc = adj_coef[ti * a.ntypes + ((int)sj.w & 15)];
                 double ftx, fty, ftz, nx, ny, nz, fn;
                 if (contact_force(c, false, pc, s.dt, true, hx, hy, hz, fx, fy, fz, ftx, fty, ftz, nx, ny, nz, fn)) {
                     hit = true;
@@ -152,7 +163,7 @@ __global__ void __launch_bounds__(kABlock, 4) k_adj_forward(AArgs a) {
             c.ra = ri; c.rb = 0.0; c.ma = mi; c.mb = 0.0;
             c.vrx = vi.x; c.vry = vi.y; c.vrz = vi.z;
             c.wsx = ri * si.x; c.wsy = ri * si.y; c.wsz = ri * si.z;
-            const PairCoef pc = a.coef[ti * a.ntypes + ti];
+            const PairCoef pc = adj_coef[ti * a.ntypes + ti];
             const D4 h = a.hwin[i];
             double hx = h.x, hy = h.y, hz = h.z;
             double fx, fy, fz, ftx, fty, ftz, nx, ny, nz, fn;

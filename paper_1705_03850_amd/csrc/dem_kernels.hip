@@ -845,9 +845,9 @@ __device__ __forceinline__ void load_step_coef(const KArgs &a, const SysDesc &s)
 }
 
 template <bool BATCH, bool COUNT, int MODE, int G>
-__device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, int src, int update, int64_t i,
-                                              int sy, const D4 &pi, const D4 &vi, const D4 &si, int code, int g,
-                                              int gbase, uint64_t gmask, unsigned &ncont, unsigned &nwall,
+__device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, const List &L, int src, int update,
+                                              int64_t i, int sy, const D4 &pi, const D4 &vi, const D4 &si, int code,
+                                              int g, int gbase, uint64_t gmask, unsigned &ncont, unsigned &nwall,
                                               bool &need, bool &bad) {
     const int64_t n = a.n;
     const D4 *__restrict__ P = a.pos[src];
@@ -855,7 +855,6 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
     const D4 *__restrict__ S = a.spin[src];
     const int64_t kmax = a.kmax;
         const int ti = code & 15;
-        const List L = list_of(a, sy, 0);
         const PairCoef *coef = step_coef;   // the system's table, in LDS
         const double ri = pi.w, mi = vi.w;
         double Fx = mi * s.g[0], Fy = mi * s.g[1], Fz = mi * s.g[2];
@@ -1021,6 +1020,8 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
     SysDesc sd = uniform_sys(a.sys);   // the only system when !BATCH
     int sy = 0;
     int64_t tlo = 0, thi = BATCH ? 0 : ntiles;
+    // the system's current list (its buffer index changes only between launches)
+    int lc = __builtin_amdgcn_readfirstlane(a.lcur[0]);
     if (!BATCH) load_step_coef(a, sd);
     for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {   // uniform over the block
         if (BATCH && (t < tlo || t >= thi)) {
@@ -1034,13 +1035,14 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
             sd = uniform_sys(a.sys + sy);
             tlo = uniform_i64(a.tile0[sy]);
             thi = uniform_i64(a.tile0[sy + 1]);
+            lc = __builtin_amdgcn_readfirstlane(a.lcur[sy]);
             load_step_coef(a, sd);
         }
         const int64_t i = BATCH ? sd.p0 + (t - tlo) * ppb + threadIdx.x / G : t * ppb + threadIdx.x / G;
         if (i >= (BATCH ? sd.p1 : n)) continue;
         const D4 pi = P[i], vi = V[i], si = S[i];
-        step_particle<BATCH, COUNT, MODE, G>(a, sd, src, update, i, sy, pi, vi, si, (int)si.w, g, gbase, gmask,
-                                             ncont, nwall, need, bad);
+        step_particle<BATCH, COUNT, MODE, G>(a, sd, (lc & 1) ? a.lst[1] : a.lst[0], src, update, i, sy, pi, vi, si,
+                                             (int)si.w, g, gbase, gmask, ncont, nwall, need, bad);
     }
     if (bad) atomicOr(&a.flags->err, kErrNonFinite);
     if (MODE == 1 && need) a.flags->abort_at = step + 1;

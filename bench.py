@@ -112,8 +112,9 @@ def batch_suite(args):
 
     64 systems (N log-uniform in [5e3, 2e5], alpha in {1, 2, 4, 8}, dt = alpha 1e-6 s):
       batched    -- all systems in one context: one launch per step for all of them, graph replay;
-      sequential -- the same systems, each in its own context, stepped one after another;
-      equal N    -- one plain bed with the same total particle count.
+      sequential -- the same systems, each in its own context with the library's default
+                    launch shape and skin (plain dem_step as a user runs it), one after another;
+      equal N    -- one plain bed with the same total particle count (defaults too).
     Two-level chute (2e5 spheres alpha = 4 + 5e5 spheres alpha = 1): one 2-system batch against the two
     systems one after another.  Launch shape, skin and cell come from the autotuner."""
     import torch
@@ -139,16 +140,15 @@ def batch_suite(args):
     torch.cuda.empty_cache()
     log("sequential plain contexts")
     t_seq = 0.0
-    for k, s in enumerate(systems):
-        gk = dem.DemSystem(s, use_graph=True, chunk=args.chunk, skin=kw["skin"][k], cell=kw["cell"][k],
-                           block=kw["block"], lanes=kw["lanes"])
+    for s in systems:
+        gk = dem.DemSystem(s, use_graph=True, chunk=args.chunk)
         gk.prime()
         t_seq += timed_steps(gk, steps, 64)
         del gk
     torch.cuda.empty_cache()
     log("equal-N plain system")
     big = W.tiled_bed(ntot)
-    gb = dem.DemSystem(big, use_graph=True, chunk=args.chunk, block=kw["block"], lanes=kw["lanes"])
+    gb = dem.DemSystem(big, use_graph=True, chunk=args.chunk)
     gb.prime()
     t_big = timed_steps(gb, steps, 64)
     del gb

@@ -193,7 +193,9 @@ int dem_kernel_times(dem_ctx *ctx, double ms[4], int64_t launches[4]);
  * default 4; a particle's row is split over them) and at most max_blocks
  * workgroups, each walking several tiles of particles (0 = as many as stay
  * resident on the device).  The schedule changes, the results do not: the
- * pair terms of a row are always added in neighbour-id order. */
+ * pair terms of a row are always added in neighbour-id order.  In a batch
+ * every tile of particles lies within one system; the per-system tile table
+ * for the new shape is uploaded here.  Synchronises. */
 int dem_set_launch(dem_ctx *ctx, int32_t lanes, int32_t max_blocks);
 
 /* Synchronise and report the sticky device flags.  info[0] = error bits

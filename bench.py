@@ -276,6 +276,7 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--rebuilds", type=int, default=10, help="forced rebuilds (dem_bin + dem_neighbors) after the timing")
+    ap.add_argument("--small-steps", type=int, default=1000, help="steps of the 2000-sphere workload timed for latency")
     ap.add_argument("--rebuild-every", type=int, default=50, help="steps between forced rebuilds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -417,6 +418,25 @@ def main():
                   "neighbors_GBps": round(nbr_bytes / (nbr_med * 1e-3) / 1e9, 1),
                   "neighbors_frac": round(nbr_bytes / (nbr_med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    # the small correctness workload: only its latency per step means anything
+    # (its state and lists fit in L2)
+    small = None
+    if args.small_steps > 0:
+        fcc = W.plain_fcc()
+        gs = dem.DemSystem(fcc, use_graph=True, chunk=64)
+        gs.prime()
+        gs.step(64)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(gs.stream)
+        gs.step(args.small_steps)
+        e1.record(gs.stream)
+        torch.cuda.synchronize()
+        small = {"workload": f"{fcc.n} spheres on a jittered FCC subset, 20x20 mm periodic, dt 1e-6 s",
+                 "steps": args.small_steps, "ms_per_step": e0.elapsed_time(e1) / args.small_steps}
+        del gs
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline: {args.cpu_steps} steps")
@@ -447,6 +467,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "forced_rebuild": forced,
+        "small_latency": small,
         "cpu_baseline": cpu,
         "kernel_source": kernel_source_hash(),
         "device": torch.cuda.get_device_name(0),

@@ -313,6 +313,30 @@ def test_batch_of_64_systems():
     assert np.max(np.abs(d)) <= 1e-9 * max(s.hi)
 
 
+@pytest.mark.parametrize("lanes,block", [(4, 256), (8, 256), (16, 256), (4, 128)])
+def test_batch_tiles_within_systems(lanes, block):
+    """The batch step walks tiles of block/lanes particles that never span two
+    systems (a system's last tile is partly empty; systems of 20 and 70
+    spheres are smaller than one or two tiles): every launch shape gives the
+    systems' own results bit for bit, with and without graph replay."""
+    from paper_1705_03850_amd.inputs import workloads as Wk
+    systems = [Wk.chute_adjoint(seed=3, n=20, Lx=14e-3, Ly=10e-3), W.plain_fcc(),
+               Wk.chute_adjoint(seed=4, n=70, Lx=14e-3, Ly=10e-3), Wk.chute_adjoint(seed=5, n=600, Lx=14e-3, Ly=10e-3)]
+    for graph in (False, True):
+        bg = gpu(systems, block=block, lanes=lanes, use_graph=graph, chunk=16)
+        bg.prime()
+        bg.step(60)
+        hb = bg.host()
+        for k, s in enumerate(systems):
+            g = gpu(s)
+            g.prime()
+            g.step(60)
+            h = g.host()
+            sl = slice(int(bg.offsets[k]), int(bg.offsets[k + 1]))
+            for key in ("x", "v", "w", "f", "t"):
+                assert np.array_equal(hb[key][sl], h[key]), (graph, k, key)
+
+
 def test_autotuned_batch_equals_default():
     """The autotuner returns a choice from its candidate sets, and a batch run
     with that choice (launch shape, skin, cell) equals the default run bit for

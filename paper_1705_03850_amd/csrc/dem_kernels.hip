@@ -832,8 +832,6 @@ __global__ void k_unpack(KArgs a, int src, int selected) {
 //           does nothing once an earlier step asked for a rebuild);
 //   MODE 2: last step of a call -- forces, kick 1/2, and f, t, x, v, w
 //           written to the caller's arrays (gated).
-// One particle of the force pass (see k_step): every lane of its group calls
-// this with the same i; sy is the particle's system (wave-uniform).
 // The block's system's pair coefficients (ntypes x ntypes): read by every
 // contact, so kept in LDS instead of three global loads per contact.
 __shared__ PairCoef step_coef[kMaxTypes * kMaxTypes];
@@ -844,6 +842,9 @@ __device__ __forceinline__ void load_step_coef(const KArgs &a, const SysDesc &s)
     __syncthreads();
 }
 
+// One particle of the force pass (see k_step): every lane of its group calls
+// this with the same i; s is the particle's system (the block's: a tile never
+// spans two systems), L its current list.
 template <bool BATCH, bool COUNT, int MODE, int G>
 __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, const List &L, int src, int update,
                                               int64_t i, int sy, const D4 &pi, const D4 &vi, const D4 &si, int code,

@@ -377,7 +377,7 @@ __global__ void k_scatter_back(KArgs a) {
 // row, also sorted by id).
 constexpr int kNbrLanes = 4;
 constexpr int kNbrTile = 64;        // particles per tile (256 threads / kNbrLanes)
-constexpr int kNbrStage = 896;      // staged candidate records per tile
+constexpr int kNbrStage = 704;      // staged candidate records per tile
 constexpr int kNbrSegCells = 40;    // cells per staged segment
 constexpr int kNbrSegs = 18;        // two x-rows of the tile x nine (dz, dy) rows
 

@@ -9,10 +9,13 @@ hot path: kick-drift, device-side rebuild check (binning + neighbour list with
 history carry when needed), forces, kick.
 
 Prints one JSON line: particle-steps/s (value), contact-pairs/s, the roofline
-of the dominant kernel (timed with HIP events inside this run) and the CPU
-oracle timed on a bounded sample of the same workload.
+of the dominant kernel (timed with HIP events inside this run), forced
+rebuilds, the small-workload latency, the 64-system and two-level batches
+against plain stepping, the kept-mode adjoint of the 200-step chute rollout
+against the plain rollout, and the CPU oracle timed on a bounded sample of the
+same workload.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-suites]
     python bench.py --profile-pass     # short run for rocprofv3 counter passes
 """
 from __future__ import annotations
@@ -50,8 +53,11 @@ STEP_PER_PARTICLE, STEP_PER_SLOT, STEP_PER_CONTACT, STEP_PER_WALL = 268, 4, 48, 
 NBR_PER_PARTICLE, NBR_PER_SLOT, NBR_PER_CONTACT, NBR_PER_CELL = 92, 12, 48, 4
 
 
+_T0 = time.perf_counter()
+
+
 def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -107,7 +113,7 @@ def timed_steps(g, steps, warm):
     return time.perf_counter() - t0
 
 
-def batch_suite(args):
+def batch_suite(args, emit=True):
     """Batched against plain on the same GPU (one JSON line).
 
     64 systems (N log-uniform in [5e3, 2e5], alpha in {1, 2, 4, 8}, dt = alpha 1e-6 s):
@@ -182,10 +188,12 @@ def batch_suite(args):
                             "list_builds_batched": builds_two},
         "device": torch.cuda.get_device_name(0),
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
-def adjoint_suite(args):
+def adjoint_suite(args, emit=True):
     """Adjoint against plain on the chute calibration workload (one JSON line).
 
     50,000 spheres, two types 50/50 (r ~ U[0.9, 1.1] mm), 30-degree periodic
@@ -260,7 +268,9 @@ def adjoint_suite(args):
                                                      "mu": theta.grad[2].tolist()},
         "device": torch.cuda.get_device_name(0),
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -277,6 +287,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--rebuilds", type=int, default=10, help="forced rebuilds (dem_bin + dem_neighbors) after the timing")
     ap.add_argument("--small-steps", type=int, default=1000, help="steps of the 2000-sphere workload timed for latency")
+    ap.add_argument("--no-suites", action="store_true", help="leave the batch and adjoint comparisons out of the line")
     ap.add_argument("--rebuild-every", type=int, default=50, help="steps between forced rebuilds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -437,6 +448,31 @@ def main():
                  "steps": args.small_steps, "ms_per_step": e0.elapsed_time(e1) / args.small_steps}
         del gs
 
+    # the metric's other two parts, compact: the 64-system batch and the
+    # two-level chute against plain stepping (library defaults, no tuner), and
+    # the kept-mode adjoint of the 200-step chute rollout against the plain rollout
+    batched = adjoint = None
+    if not args.no_suites:
+        import copy
+        del g
+        torch.cuda.empty_cache()
+        ab = copy.copy(args)
+        ab.no_autotune, ab.steps = True, 10000      # the suite's own step counts (2000 and 5000)
+        b = batch_suite(ab, emit=False)
+        batched = {"launch": "library defaults, graph replay",
+                   "batch64": {k: b["batch64"][k] for k in ("systems", "particles", "steps", "batched",
+                                                            "sequential_plain", "equal_n_plain",
+                                                            "batched_vs_sequential", "batched_vs_equal_n")},
+                   "two_level_chute": {k: b["two_level_chute"][k] for k in ("particles", "steps", "batched",
+                                                                           "sequential_plain",
+                                                                           "batched_vs_sequential")}}
+        aa = copy.copy(args)
+        aa.keep, aa.window = True, 20
+        a_ = adjoint_suite(aa, emit=False)
+        adjoint = {k: a_[k] for k in ("workload", "steps", "window", "keep", "plain_forward_s", "adjoint_forward_s",
+                                      "backward_s", "adjoint_vs_plain", "adjoint_workspace_bytes")}
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline: {args.cpu_steps} steps")
@@ -468,6 +504,8 @@ def main():
         "kernels": kernels,
         "forced_rebuild": forced,
         "small_latency": small,
+        "batched_vs_plain": batched,
+        "adjoint_vs_plain": adjoint,
         "cpu_baseline": cpu,
         "kernel_source": kernel_source_hash(),
         "device": torch.cuda.get_device_name(0),

@@ -102,6 +102,28 @@ def cpu_baseline(system, steps):
                       f"1 thread, {dt:.1f} s"}
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: a plain device-to-device copy of `nbytes`
+    (read + write counted), median of `reps` copies timed with events."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del src, dst
+    ms.sort()
+    return 2 * nbytes / (ms[len(ms) // 2] * 1e-3) / 1e9
+
+
 def timed_steps(g, steps, warm):
     import torch
 
@@ -390,10 +412,12 @@ def main():
     kernels["step"]["GBps"] = bytes_step / (kernels["step"]["avg_us"] * 1e-6) / 1e9
     achieved = kernels["step"]["GBps"]
     traffic = read_traffic()
+    copy_gbs = copy_bandwidth()
     roofline = {"bound": "hbm", "kernel": "k_step (fused forces + kick + kick-drift)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "alg_bytes_per_launch": round(bytes_step), "avg_launch_us": round(kernels["step"]["avg_us"], 2)}
+                "alg_bytes_per_launch": round(bytes_step), "avg_launch_us": round(kernels["step"]["avg_us"], 2),
+                "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     # forced rebuilds: dem_bin and dem_neighbors every `rebuild_every` steps,
     # each call timed with events on the library's stream
@@ -470,7 +494,8 @@ def main():
         aa.keep, aa.window = True, 20
         a_ = adjoint_suite(aa, emit=False)
         adjoint = {k: a_[k] for k in ("workload", "steps", "window", "keep", "plain_forward_s", "adjoint_forward_s",
-                                      "backward_s", "adjoint_vs_plain", "adjoint_workspace_bytes")}
+                                      "backward_s", "adjoint_vs_plain", "adjoint_workspace_bytes",
+                                      "context_workspace_bytes", "peak_torch_bytes")}
         torch.cuda.empty_cache()
 
     cpu = None
@@ -495,6 +520,7 @@ def main():
                                f"footprint, wall z=0, dt 1e-6 s, skin 0.1 r_max",
                    "particles": n, "parallelism": "1 GPU", "graph": not args.no_graph, "chunk": args.chunk},
         "contact_pairs_per_s": unordered_per_step * steps / seconds,
+        "listed_pairs_per_s": slots / 2.0 * steps / seconds,
         "listed_slots": slots,
         "contacts_per_step": unordered_per_step,
         "wall_contacts_per_step": wall_contacts / steps,

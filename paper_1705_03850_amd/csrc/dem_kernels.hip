@@ -357,196 +357,91 @@ __global__ void k_scatter_back(KArgs a) {
 // ------------------------------------------------------------ neighbour list
 
 // Row of particle i: all j != i with d^2 < (r_i + r_j + skin)^2 in the 27
-// surrounding cells, sorted by id.  A group of kNbrLanes lanes per particle,
-// a tile of 64 consecutive particles per block.  The three cells along x of
-// each (dz, dy) row of cells are one run of candidates.
-//
-// Staged tiles: a tile's particles lie in one or two x-rows of cells (they are
-// sorted by cell), so the candidates of all of them are nine segments of cells
-// per x-row, each segment the tile's x-extent widened by one cell on each side.
-// Those records (x, y, z, r) are read once into LDS with contiguous loads and
-// tested from there (each is a candidate of several particles of the tile).
-// Tiles that span more rows, a wide x-extent or too many records read their
-// candidates from global memory instead; both give the same rows.
-//
-// Each group deals its candidates to its lanes in turn; hits are appended to
+// surrounding cells, sorted by id.  A group of kNbrLanes lanes per particle.
+// The three cells along x of each (dz, dy) row of cells are one run of
+// candidates (two pieces where the run crosses a periodic seam in x).  The
+// bounds of all nine runs are read with no branch between the loads, so they
+// are in flight together.  Each group deals its candidates to its lanes in
+// turn, kNbrUnroll per lane loaded before any is tested; hits are appended to
 // the group's LDS buffer in candidate order (a ballot gives each its place).
 // Then the hits' ids are fetched, each lane ranks its entries by id (ids are
-// unique) and writes them to their places in the row, and the history of pairs
-// of the previous list is carried over by id (binary search of the previous
-// row, also sorted by id).
+// unique) and writes them to their places in the row, and the history of
+// pairs of the previous list is carried over by id (binary search of the
+// previous row, also sorted by id).  A group's LDS buffers are its own and
+// its lanes share a wave, so no barrier spans the block until the end.
 constexpr int kNbrLanes = 4;
-constexpr int kNbrTile = 64;        // particles per tile (256 threads / kNbrLanes)
-constexpr int kNbrStage = 704;      // staged candidate records per tile
-constexpr int kNbrSegCells = 40;    // cells per staged segment
-constexpr int kNbrSegs = 18;        // two x-rows of the tile x nine (dz, dy) rows
+#ifndef DEM_NBR_UNROLL
+#define DEM_NBR_UNROLL 2
+#endif
+#ifndef DEM_NBR_WAVES
+#define DEM_NBR_WAVES 4
+#endif
+constexpr int kNbrUnroll = DEM_NBR_UNROLL;
 
-// LDS of k_neighbors: the staging area (later reused for the hits' ids and the
-// previous rows' ids), then int32 arrays.
-__host__ __device__ inline size_t nbr_stage_bytes(int kmax) {
-    const size_t rec = (size_t)kNbrStage * sizeof(D4), ids = (size_t)2 * kNbrTile * kmax * sizeof(int32_t);
-    return rec > ids ? rec : ids;
+// LDS of k_neighbors: per group, its hits' indices, their ids and the previous
+// row's ids (kmax each).
+__host__ __device__ inline size_t nbr_lds_bytes(int kmax, int block) {
+    return (size_t)3 * (block / kNbrLanes) * kmax * sizeof(int32_t);
 }
-__host__ __device__ inline size_t nbr_lds_bytes(int kmax) {
-    return nbr_stage_bytes(kmax) +
-           sizeof(int32_t) * ((size_t)kNbrStage + (size_t)kNbrTile * kmax + (kNbrSegs + 1) + 4 * kNbrSegs +
-                              (size_t)kNbrSegs * (kNbrSegCells + 1) + (size_t)kNbrSegs * kNbrSegCells);
+
+// Orders the LDS accesses of one wave's lanes (the buffers a group shares).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Entry q of a group's hits: its rank by id gives its slot in the new row,
+// where its index is written; returns whether the previous row (ids oid,
+// sorted) holds the pair with a history, and then where (from).
+__device__ __forceinline__ bool nbr_place(const int32_t *bid, const int32_t *bidx, const int32_t *oid, int cnt,
+                                          int ocnt, uint64_t omask, int have_old, int64_t i, int64_t o, int kmax,
+                                          const List &L, int q, int64_t &slot, int64_t &from, uint64_t &bits) {
+    const int32_t idq = bid[q];
+    int rank = 0;
+    for (int k = 0; k < cnt; ++k) rank += bid[k] < idq ? 1 : 0;
+    slot = i * kmax + rank;
+    L.nbr[slot] = bidx[q];
+    if (!have_old) return false;
+    int lo = 0, hi = ocnt;   // first p with oid[p] >= idq
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (oid[mid] < idq) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < ocnt && oid[lo] == idq && ((omask >> lo) & 1ull)) {
+        from = o * kmax + lo;
+        bits |= 1ull << rank;
+        return true;
+    }
+    return false;
 }
 
 template <bool BATCH>
-__global__ void __launch_bounds__(256) k_neighbors(KArgs a, int have_old) {
-    extern __shared__ __align__(16) unsigned char nbr_lds[];
-    __shared__ int32_t tinfo[8];
+__global__ void __launch_bounds__(256, DEM_NBR_WAVES) k_neighbors(KArgs a, int have_old) {
+    extern __shared__ int32_t nbr_lds[];
+    __shared__ int32_t blockmax;
     constexpr int G = kNbrLanes;
-    constexpr int SC = kNbrSegCells;
     const int64_t n = a.n;
     const int kmax = a.kmax;
     const int g = threadIdx.x % G;
     const int grp = threadIdx.x / G;
+    const int ppb = blockDim.x / G;
     const int gbase = (threadIdx.x % warpSize) / G * G;
     const uint64_t gmask = (1ull << G) - 1;
-    const size_t sbytes = nbr_stage_bytes(kmax);
-    D4 *srec = (D4 *)nbr_lds;                                    // staged (x, y, z, r)
-    int32_t *bidall = (int32_t *)nbr_lds;                        // after the collection: hits' ids
-    int32_t *oidall = bidall + kNbrTile * kmax;                  //   and the previous rows' ids
-    int32_t *sidx = (int32_t *)(nbr_lds + sbytes);               // staged records' indices
-    int32_t *bidx = sidx + kNbrStage + grp * kmax;               // the group's hits' indices
-    int32_t *soff = sidx + kNbrStage + kNbrTile * kmax;          // [kNbrSegs + 1] first record of each segment
-    int32_t *sxs = soff + kNbrSegs + 1;                          // logical first cell of each segment
-    int32_t *sncell = sxs + kNbrSegs;                            // cells of each segment (0: none)
-    int32_t *sflag = sncell + kNbrSegs;                          // 1: minimum image in y, 2: in z
-    int32_t *scrow = sflag + kNbrSegs;                           // first cell of the segment's row
-    int32_t *spref = scrow + kNbrSegs;                           // [kNbrSegs][SC + 1] records before each cell
-    int32_t *spst = spref + kNbrSegs * (SC + 1);                 // [kNbrSegs][SC] first index of each cell
-    int32_t *bid = bidall + grp * kmax;
-    int32_t *oid = oidall + grp * kmax;
+    int32_t *bidx = nbr_lds + grp * kmax;               // the group's hits' indices
+    int32_t *bid = nbr_lds + (ppb + grp) * kmax;        //   their ids
+    int32_t *oid = nbr_lds + (2 * ppb + grp) * kmax;    //   the previous row's ids
     const D4 *Q = (const D4 *)a.shadow_d;  // (x, y, z, r) in the current order (k_nbr_pack)
-    const int ppb = kNbrTile;
+    const int32_t *cs = a.cell_start;
     const int64_t ntiles = (n + ppb - 1) / ppb;
     const int per = gridDim.x / kXcd;
     const int64_t chunk = (ntiles + kXcd - 1) / kXcd;
     const int64_t t0 = (blockIdx.x % kXcd) * chunk;
     const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
     int maxrow = 0;
-    for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {   // uniform over the block
-        const int64_t p0 = t * ppb;
-        const int64_t p1 = (p0 + ppb < n ? p0 + ppb : n) - 1;
-        // ---- can the tile be staged?  (thread 0; tinfo: staged, system, tile rows)
-        if (threadIdx.x == 0) {
-            int staged = 0;
-            const int sy0 = sys_of<BATCH>(a, p0), sy1 = sys_of<BATCH>(a, p1);
-            if (sy0 == sy1 && a.sel[sy0]) {
-                const SysDesc &s = a.sys[sy0];
-                const D4 q0 = Q[p0], q1 = Q[p1];
-                const int nx = s.nc[0], ny = s.nc[1];
-                const int cx0 = cell_coord(q0.x, s, 0), cy0 = cell_coord(q0.y, s, 1), cz0 = cell_coord(q0.z, s, 2);
-                const int cx1 = cell_coord(q1.x, s, 0), cy1 = cell_coord(q1.y, s, 1), cz1 = cell_coord(q1.z, s, 2);
-                const int64_t r0 = (int64_t)cz0 * ny + cy0, r1 = (int64_t)cz1 * ny + cy1;
-                if ((r1 == r0 || r1 == r0 + 1) && (!s.periodic[0] || nx >= 5)) {
-                    const int xb0 = r1 > r0 ? nx - 1 : cx1;
-                    if (xb0 - cx0 + 3 <= SC && (r1 == r0 || cx1 + 3 <= SC)) staged = 1;
-                    tinfo[1] = sy0;
-                    tinfo[2] = cx0; tinfo[3] = cy0; tinfo[4] = cz0;
-                    tinfo[5] = cx1; tinfo[6] = cy1; tinfo[7] = cz1;
-                }
-            }
-            tinfo[0] = staged;
-        }
-        __syncthreads();
-        bool staged = tinfo[0] != 0;
-        if (staged) {
-            // ---- segment tables: one thread per (tile row, (dz, dy))
-            if (threadIdx.x < kNbrSegs) {
-                const int sg = threadIdx.x, tr = sg / 9, k = sg % 9;
-                const SysDesc &s = a.sys[tinfo[1]];
-                const int nx = s.nc[0], ny = s.nc[1], nz = s.nc[2];
-                const bool two = (int64_t)tinfo[7] * ny + tinfo[6] != (int64_t)tinfo[4] * ny + tinfo[3];
-                const int cy_t = tr ? tinfo[6] : tinfo[3], cz_t = tr ? tinfo[7] : tinfo[4];
-                const int xa = tr ? 0 : tinfo[2];
-                const int xb = tr ? tinfo[5] : (two ? nx - 1 : tinfo[5]);
-                const int dz = k / 3 - 1, dy = k % 3 - 1;
-                int cz = cz_t + dz, cy = cy_t + dy;
-                bool ok = tr == 0 || two;
-                int flag = 0;
-                if (s.periodic[2]) {
-                    if (nz < 5 || cz < 0 || cz >= nz) flag |= 2;
-                    cz = cz < 0 ? cz + nz : (cz >= nz ? cz - nz : cz);
-                    if (nz < 3 && dz == -1) ok = false;
-                } else if (cz < 0 || cz >= nz) ok = false;
-                if (s.periodic[1]) {
-                    if (ny < 5 || cy < 0 || cy >= ny) flag |= 1;
-                    cy = cy < 0 ? cy + ny : (cy >= ny ? cy - ny : cy);
-                    if (ny < 3 && dy == -1) ok = false;
-                } else if (cy < 0 || cy >= ny) ok = false;
-                // logical cells xs .. xe (wrapped to physical cells on a periodic axis)
-                const int xs = s.periodic[0] ? xa - 1 : (xa > 0 ? xa - 1 : 0);
-                const int xe = s.periodic[0] ? xb + 1 : (xb + 1 < nx ? xb + 1 : nx - 1);
-                const int nc = ok ? xe - xs + 1 : 0;
-                sxs[sg] = xs;
-                sncell[sg] = nc;
-                sflag[sg] = flag;
-                scrow[sg] = ok ? (int32_t)(s.c0 + ((int64_t)cz * ny + cy) * nx) : 0;
-            }
-            __syncthreads();
-            // every (segment, cell): its first index and its particle count
-            for (int e = threadIdx.x; e < kNbrSegs * SC; e += blockDim.x) {
-                const int sg = e / SC, m = e - sg * SC;
-                if (m < sncell[sg]) {
-                    const int nx = a.sys[tinfo[1]].nc[0];
-                    int cx = sxs[sg] + m;
-                    cx = cx < 0 ? cx + nx : (cx >= nx ? cx - nx : cx);
-                    const int32_t cb = a.cell_start[scrow[sg] + cx], ce = a.cell_start[scrow[sg] + cx + 1];
-                    spst[sg * SC + m] = cb;
-                    spref[sg * (SC + 1) + m + 1] = ce - cb;
-                }
-            }
-            __syncthreads();
-            // counts -> records before each cell, per segment
-            if (threadIdx.x < kNbrSegs) {
-                const int sg = threadIdx.x;
-                int32_t *pr = spref + sg * (SC + 1);
-                int acc = 0;
-                pr[0] = 0;
-                for (int m = 0; m < sncell[sg]; ++m) {
-                    acc += pr[m + 1];
-                    pr[m + 1] = acc;
-                }
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                int off = 0;
-                for (int sg = 0; sg < kNbrSegs; ++sg) {
-                    soff[sg] = off;
-                    off += spref[sg * (SC + 1) + sncell[sg]];
-                }
-                soff[kNbrSegs] = off;
-                tinfo[0] = off <= kNbrStage ? 1 : 0;
-            }
-            __syncthreads();
-            staged = tinfo[0] != 0;
-            if (staged) {
-                // ---- the records, read once
-                const int U = soff[kNbrSegs];
-                for (int u = threadIdx.x; u < U; u += blockDim.x) {
-                    int sg = 0;
-                    for (int q = 1; q < kNbrSegs; ++q) sg = u >= soff[q] ? q : sg;
-                    const int w = u - soff[sg];
-                    const int32_t *pr = spref + sg * (SC + 1);
-                    int lo = 0, hi = sncell[sg] - 1;   // last cell m with pr[m] <= w
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (pr[mid] <= w) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    const int32_t j = spst[sg * SC + lo] + (w - pr[lo]);
-                    srec[u] = Q[j];
-                    sidx[u] = j;
-                }
-            }
-            __syncthreads();
-        }
-        // ---- collection, one group per particle
-        const int64_t i = p0 + grp;
+    for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {
+        const int64_t i = t * ppb + grp;
         int sy = 0;
         bool active = i < n;
         if (active) {
@@ -554,174 +449,150 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a, int have_old) {
             active = a.sel[sy] != 0;   // else the system keeps its list
         }
         int count = 0;
+        int64_t o = 0;
         if (active) {
+            if (have_old) o = a.frame[i];   // needed after the collection; loaded early
             const SysDesc &s = a.sys[sy];
             const D4 qi = Q[i];
             const int nx = s.nc[0], ny = s.nc[1], nz = s.nc[2];
+            const int px = s.periodic[0], py = s.periodic[1], pz = s.periodic[2];
             const int ccx = cell_coord(qi.x, s, 0), ccy = cell_coord(qi.y, s, 1), ccz = cell_coord(qi.z, s, 2);
             // Within one row of cells that does not wrap, |d| < 2 cell widths; on an
             // axis of five or more cells that is under half the box, where the
             // minimum image is d itself, so it is only taken where a row can wrap.
-            const bool mix = s.periodic[0] && (nx < 5 || ccx == 0 || ccx == nx - 1);
-            // the nine runs of candidates: start, length (two pieces across a periodic
-            // seam when read from global memory), minimum-image flags
+            const bool mix = px && (nx < 5 || ccx == 0 || ccx == nx - 1);
+            // cells x0 .. x1 of each row, and on a periodic axis of three or more
+            // cells at its seam, the cell c2 across it (else c2 = x0, no second piece)
+            const bool wrapx = px && nx >= 3;
+            const bool seam = wrapx && (ccx == 0 || ccx == nx - 1);
+            const int x0 = wrapx ? (ccx == 0 ? 0 : ccx - 1) : (ccx > 0 ? ccx - 1 : 0);
+            const int x1 = wrapx ? (ccx == nx - 1 ? nx - 1 : ccx + 1) : (ccx + 1 < nx ? ccx + 1 : nx - 1);
+            const int c2 = seam ? (ccx == 0 ? nx - 1 : 0) : x0;
+            // the nine runs: first index and length of each piece, minimum-image flags
             int32_t rb1[9], rl1[9], rb2[9], pre[10];
-            uint32_t my = 0, mz = 0;
+            uint32_t my = 0, mz = 0, okm = 0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int dz = k / 3 - 1, dy = k % 3 - 1;
+                int cz = ccz + dz, cy = ccy + dy;
+                bool ok = true;
+                if (pz) {
+                    if (nz < 5 || cz < 0 || cz >= nz) mz |= 1u << k;
+                    cz = cz < 0 ? cz + nz : (cz >= nz ? cz - nz : cz);
+                    if (nz < 3 && dz == -1) ok = false;
+                } else if (cz < 0 || cz >= nz) ok = false;
+                if (py) {
+                    if (ny < 5 || cy < 0 || cy >= ny) my |= 1u << k;
+                    cy = cy < 0 ? cy + ny : (cy >= ny ? cy - ny : cy);
+                    if (ny < 3 && dy == -1) ok = false;
+                } else if (cy < 0 || cy >= ny) ok = false;
+                if (ok) okm |= 1u << k;
+                const int64_t crow = s.c0 + (ok ? ((int64_t)cz * ny + cy) * nx : 0);   // a valid row either way
+                rb1[k] = cs[crow + x0];
+                rl1[k] = cs[crow + x1 + 1];   // end, made a length below
+                rb2[k] = cs[crow + c2];
+                pre[k] = cs[crow + c2 + 1];   // end of the second piece, likewise
+            }
             int total = 0;
-            if (staged) {
-                const int tr = (int64_t)ccz * ny + ccy == (int64_t)tinfo[4] * ny + tinfo[3] ? 0 : 1;
-                const int xlo = s.periodic[0] ? ccx - 1 : (ccx > 0 ? ccx - 1 : 0);
-                const int xhi = s.periodic[0] ? ccx + 1 : (ccx + 1 < nx ? ccx + 1 : nx - 1);
 #pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const int sg = tr * 9 + k;
-                    int32_t b1 = 0, l1 = 0;
-                    if (sncell[sg] > 0) {
-                        const int32_t *pr = spref + sg * (SC + 1);
-                        const int m0 = xlo - sxs[sg], m1 = xhi - sxs[sg];
-                        b1 = soff[sg] + pr[m0];
-                        l1 = pr[m1 + 1] - pr[m0];
-                        const int f = sflag[sg];
-                        if (f & 1) my |= 1u << k;
-                        if (f & 2) mz |= 1u << k;
-                    }
-                    rb1[k] = b1; rl1[k] = l1; rb2[k] = 0;
-                    pre[k] = total;
-                    total += l1;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const int dz = k / 3 - 1, dy = k % 3 - 1;
-                    int cz = ccz + dz, cy = ccy + dy;
-                    bool ok = true;
-                    if (s.periodic[2]) {
-                        if (nz < 5 || cz < 0 || cz >= nz) mz |= 1u << k;
-                        cz = cz < 0 ? cz + nz : (cz >= nz ? cz - nz : cz);
-                        if (nz < 3 && dz == -1) ok = false;
-                    } else if (cz < 0 || cz >= nz) ok = false;
-                    if (s.periodic[1]) {
-                        if (ny < 5 || cy < 0 || cy >= ny) my |= 1u << k;
-                        cy = cy < 0 ? cy + ny : (cy >= ny ? cy - ny : cy);
-                        if (ny < 3 && dy == -1) ok = false;
-                    } else if (cy < 0 || cy >= ny) ok = false;
-                    int32_t b1 = 0, l1 = 0, b2 = 0, l2 = 0;
-                    if (ok) {
-                        const int64_t crow = s.c0 + ((int64_t)cz * ny + cy) * nx;
-                        if (!s.periodic[0] || nx < 3) {
-                            // cells max(ccx-1, 0) .. min(ccx+1, nx-1); with a periodic axis of
-                            // two cells that is both cells, each once
-                            const int x0 = ccx > 0 ? ccx - 1 : 0;
-                            const int x1 = ccx + 1 < nx ? ccx + 1 : nx - 1;
-                            b1 = a.cell_start[crow + x0];
-                            l1 = a.cell_start[crow + x1 + 1] - b1;
-                        } else if (ccx >= 1 && ccx + 1 < nx) {
-                            b1 = a.cell_start[crow + ccx - 1];
-                            l1 = a.cell_start[crow + ccx + 2] - b1;
-                        } else if (ccx == 0) {
-                            // cells 0, 1 and nx-1
-                            b1 = a.cell_start[crow];
-                            l1 = a.cell_start[crow + 2] - b1;
-                            b2 = a.cell_start[crow + nx - 1];
-                            l2 = a.cell_start[crow + nx] - b2;
-                        } else {
-                            // cells nx-2, nx-1 and 0
-                            b1 = a.cell_start[crow + nx - 2];
-                            l1 = a.cell_start[crow + nx] - b1;
-                            b2 = a.cell_start[crow];
-                            l2 = a.cell_start[crow + 1] - b2;
-                        }
-                    }
-                    rb1[k] = b1; rl1[k] = l1; rb2[k] = b2;
-                    pre[k] = total;
-                    total += l1 + l2;
-                }
+            for (int k = 0; k < 9; ++k) {
+                const bool ok = (okm >> k) & 1u;
+                const int32_t l1 = ok ? rl1[k] - rb1[k] : 0;
+                const int32_t l2 = ok && seam ? pre[k] - rb2[k] : 0;
+                rl1[k] = l1;
+                pre[k] = total;
+                total += l1 + l2;
             }
             pre[9] = total;
             // the system's constants in registers: the loop stores to LDS, and the
             // compiler would otherwise read them again from the table every round
             const double Lx = s.L[0], Ly = s.L[1], Lz = s.L[2];
             const double hx = s.hL[0], hy = s.hL[1], hz = s.hL[2], skin = s.skin;
-            const int px = s.periodic[0], py = s.periodic[1], pz = s.periodic[2];
-            // one loop per source of the records (LDS or global), so that each
-            // compiles to its own load instructions
-#define DEM_NBR_COLLECT(LOAD)                                                                  \
-    for (int v0 = 0; v0 < total; v0 += G) { /* same trip count for the group */                \
-        const int v = v0 + g;                                                                  \
-        bool hit = false;                                                                      \
-        int32_t j = 0;                                                                         \
-        if (v < total) {                                                                       \
-            int32_t b1 = rb1[0], l1 = rl1[0], b2 = rb2[0], p0k = 0, k = 0;                     \
-            _Pragma("unroll") for (int m = 1; m < 9; ++m) if (v >= pre[m]) {                   \
-                b1 = rb1[m]; l1 = rl1[m]; b2 = rb2[m]; p0k = pre[m]; k = m;                     \
-            }                                                                                  \
-            const int u = v - p0k;                                                             \
-            const int32_t at = u < l1 ? b1 + u : b2 + (u - l1);                                \
-            D4 qj;                                                                             \
-            LOAD;                                                                              \
-            if (j != i) {                                                                      \
-                double ddx = qi.x - qj.x, ddy = qi.y - qj.y, ddz = qi.z - qj.z;                \
-                if (mix) ddx = min_image(ddx, Lx, hx, px);                                     \
-                if ((my >> k) & 1u) ddy = min_image(ddy, Ly, hy, py);                          \
-                if ((mz >> k) & 1u) ddz = min_image(ddz, Lz, hz, pz);                          \
-                const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;                           \
-                const double cut = qi.w + qj.w + skin;                                         \
-                hit = d2 < cut * cut;                                                          \
-            }                                                                                  \
-        }                                                                                      \
-        const uint64_t bal = (__ballot(hit) >> gbase) & gmask;                                 \
-        if (hit) {                                                                             \
-            const int pos = count + __popcll(bal & ((1ull << g) - 1));                         \
-            if (pos < kmax) bidx[pos] = j;                                                     \
-        }                                                                                      \
-        count += __popcll(bal);                                                                \
-    }
-            if (staged) {
-                DEM_NBR_COLLECT(qj = srec[at]; j = sidx[at])
-            } else {
-                DEM_NBR_COLLECT(qj = Q[at]; j = at)
+            for (int v0 = 0; v0 < total; v0 += G * kNbrUnroll) {   // same trip count for the group
+                D4 qj[kNbrUnroll];
+                int32_t jj[kNbrUnroll], kk[kNbrUnroll];
+#pragma unroll
+                for (int e = 0; e < kNbrUnroll; ++e) {
+                    const int v = v0 + e * G + g;
+                    int32_t b1 = rb1[0], l1 = rl1[0], b2 = rb2[0], p0k = 0, k = 0;
+#pragma unroll
+                    for (int m = 1; m < 9; ++m)
+                        if (v >= pre[m]) { b1 = rb1[m]; l1 = rl1[m]; b2 = rb2[m]; p0k = pre[m]; k = m; }
+                    const int u = v - p0k;
+                    // past the end: the particle itself, which is no hit
+                    jj[e] = v < total ? (u < l1 ? b1 + u : b2 + (u - l1)) : (int32_t)i;
+                    kk[e] = k;
+                    qj[e] = Q[jj[e]];
+                }
+#pragma unroll
+                for (int e = 0; e < kNbrUnroll; ++e) {
+                    const int32_t j = jj[e];
+                    bool hit = false;
+                    if (j != i) {
+                        double ddx = qi.x - qj[e].x, ddy = qi.y - qj[e].y, ddz = qi.z - qj[e].z;
+                        if (mix) ddx = min_image(ddx, Lx, hx, px);
+                        if ((my >> kk[e]) & 1u) ddy = min_image(ddy, Ly, hy, py);
+                        if ((mz >> kk[e]) & 1u) ddz = min_image(ddz, Lz, hz, pz);
+                        const double d2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                        const double cut = qi.w + qj[e].w + skin;
+                        hit = d2 < cut * cut;
+                    }
+                    const uint64_t bal = (__ballot(hit) >> gbase) & gmask;
+                    if (hit) {
+                        const int pos = count + __popcll(bal & ((1ull << g) - 1));
+                        if (pos < kmax) bidx[pos] = j;
+                    }
+                    count += __popcll(bal);
+                }
             }
-#undef DEM_NBR_COLLECT
         }
-        __syncthreads();   // the staging area becomes the id buffers
+        wave_sync();
         // ---- the hits' ids and the previous row's ids, all loads in flight at once
         const int cnt = count < kmax ? count : kmax;
         int ocnt = 0;
-        int64_t o = 0;
         uint64_t omask = 0;
+        // (each lane takes two entries per round, both loads issued before either
+        // is used: a row of up to 2 G entries is one round trip)
         if (active) {
-            for (int q = g; q < cnt; q += G) bid[q] = a.id[bidx[q]];
+            for (int q0 = g; q0 < cnt; q0 += 2 * G) {
+                const int q1 = q0 + G;
+                const int32_t j0 = bidx[q0], j1 = q1 < cnt ? bidx[q1] : j0;
+                const int32_t id0 = a.id[j0], id1 = a.id[j1];
+                bid[q0] = id0;
+                if (q1 < cnt) bid[q1] = id1;
+            }
             if (have_old) {
                 const List O = list_of(a, sy, 0);
-                o = a.frame[i];
                 ocnt = O.cnt[o];
                 omask = O.mask[o];
-                for (int p = g; p < ocnt; p += G) oid[p] = O.ids[O.nbr[o * kmax + p]];
+                const int32_t *orow = O.nbr + o * kmax;
+                for (int p0 = g; p0 < ocnt; p0 += 2 * G) {
+                    const int p1 = p0 + G;
+                    const int32_t j0 = orow[p0], j1 = orow[p1 < ocnt ? p1 : p0];
+                    const int32_t id0 = O.ids[j0], id1 = O.ids[j1];
+                    oid[p0] = id0;
+                    if (p1 < ocnt) oid[p1] = id1;
+                }
             }
         }
-        __syncthreads();
+        wave_sync();
         // ---- ranks, the row, and the history carried over
         if (active) {
             const List O = list_of(a, sy, 0), L = list_of(a, sy, 1);
             uint64_t bits = 0;
-            for (int q = g; q < cnt; q += G) {
-                const int32_t idq = bid[q];
-                int rank = 0;
-                for (int k = 0; k < cnt; ++k) rank += bid[k] < idq ? 1 : 0;
-                const int64_t slot = i * kmax + rank;
-                L.nbr[slot] = bidx[q];
-                if (have_old) {
-                    int lo = 0, hi = ocnt;   // first p with oid[p] >= idq
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (oid[mid] < idq) lo = mid + 1;
-                        else hi = mid;
-                    }
-                    if (lo < ocnt && oid[lo] == idq && ((omask >> lo) & 1ull)) {
-                        L.xi[slot] = O.xi[o * kmax + lo];
-                        bits |= 1ull << rank;
-                    }
-                }
+            for (int q0 = g; q0 < cnt; q0 += 2 * G) {
+                const int q1 = q0 + G;
+                int64_t s0, s1 = 0, f0, f1 = 0;
+                const bool c0 = nbr_place(bid, bidx, oid, cnt, ocnt, omask, have_old, i, o, kmax, L, q0, s0, f0, bits);
+                const bool c1 = q1 < cnt && nbr_place(bid, bidx, oid, cnt, ocnt, omask, have_old, i, o, kmax, L, q1, s1,
+                                                      f1, bits);
+                // both loads unconditional (slot 0 where nothing is carried), so that
+                // they are issued together
+                const D4 *p0 = O.xi + (c0 ? f0 : 0), *p1 = O.xi + (c1 ? f1 : 0);
+                const double x0 = p0->x, y0 = p0->y, z0 = p0->z, w0 = p0->w;
+                const double x1 = p1->x, y1 = p1->y, z1 = p1->z, w1 = p1->w;
+                if (c0) L.xi[s0] = D4{x0, y0, z0, w0};
+                if (c1) L.xi[s1] = D4{x1, y1, z1, w1};
             }
             for (int off = 1; off < G; off <<= 1) bits |= __shfl_xor(bits, off);
             if (g == 0) {
@@ -732,18 +603,18 @@ __global__ void __launch_bounds__(256) k_neighbors(KArgs a, int have_old) {
                 a.disp[i] = 0.0; a.disp[n + i] = 0.0; a.disp[2 * n + i] = 0.0;
             }
         }
-        __syncthreads();   // the buffers are reused by the next tile
+        wave_sync();   // the group's buffers are reused by the next tile
     }
     // the longest row: reduced over the block first, then one atomic per block
     // (one per particle, all on one address, serialised and cost about as much
     // as the whole build)
-    if (threadIdx.x == 0) tinfo[0] = 0;
+    if (threadIdx.x == 0) blockmax = 0;
     __syncthreads();
-    if (maxrow) atomicMax(&tinfo[0], maxrow);
+    if (maxrow) atomicMax(&blockmax, maxrow);
     __syncthreads();
-    if (threadIdx.x == 0 && tinfo[0]) {
-        if (tinfo[0] > kmax) atomicOr(&a.flags->err, kErrCapacity);
-        atomicMax(&a.flags->max_row, tinfo[0]);
+    if (threadIdx.x == 0 && blockmax) {
+        if (blockmax > kmax) atomicOr(&a.flags->err, kErrCapacity);
+        atomicMax(&a.flags->max_row, blockmax);
     }
 }
 
@@ -1163,9 +1034,9 @@ __global__ void k_nbr_pack(KArgs a) {
 hipError_t launch_neighbors(const KArgs &a, int have_old, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
     k_nbr_pack<<<flat_grid(a.n, 256), 256, 0, st>>>(a);
-    // staging area, tables and per-particle hit buffers (46 KB per block at kmax = 32)
-    const int block = kNbrTile * kNbrLanes;
-    const size_t lds = nbr_lds_bytes(a.kmax);
+    // per-group hit, id and previous-id buffers (24 KB per block at kmax = 32)
+    const int block = 256;
+    const size_t lds = nbr_lds_bytes(a.kmax, block);
     const int g = grid_for(a.n * kNbrLanes, block);
     if (a.nsys > 1) k_neighbors<true><<<g, block, lds, st>>>(a, have_old);
     else k_neighbors<false><<<g, block, lds, st>>>(a, have_old);

@@ -68,9 +68,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per force launch from the committed counter summary, or None
-    when the kernel sources changed since the counters were taken."""
+def read_traffic(key="hbm_bytes_per_launch"):
+    """HBM bytes per launch from the committed counter summary (force kernel by
+    default; "nbr_hbm_bytes_per_launch" for the neighbour build), or None when
+    the kernel sources changed since the counters were taken."""
     if not os.path.exists(PMC_FILE):
         return None
     vals = {}
@@ -82,7 +83,7 @@ def read_traffic():
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -319,7 +320,8 @@ def main():
                     help="plain: the 1e6-sphere bed (default); batch: 64-system and two-level batches vs plain")
     ap.add_argument("--no-autotune", action="store_true", help="batch suite: default launch shape and skin")
     ap.add_argument("--profile-pass", action="store_true",
-                    help="a few non-graph steps plus a 256 MiB device copy (counter calibration), no JSON")
+                    help="a few non-graph steps, three list rebuilds and a 256 MiB device copy (counter "
+                         "calibration), no JSON")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -356,6 +358,9 @@ def main():
     if args.profile_pass:
         g.set_step_options(False, args.chunk)
         g.step(args.timing_steps)
+        for _ in range(3):                   # neighbour builds with history carry
+            g.bin()
+            g.neighbors()
         torch.cuda.synchronize()
         nbytes = 256 << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -363,7 +368,7 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        log(f"profile pass done: {args.timing_steps} steps, 3 copies of {nbytes} bytes")
+        log(f"profile pass done: {args.timing_steps} steps, 3 rebuilds, 3 copies of {nbytes} bytes")
         return
 
     log(f"warmup {args.warmup} steps")
@@ -451,7 +456,8 @@ def main():
                   "bin_ms_median": bin_ms[len(bin_ms) // 2], "neighbors_ms_median": nbr_med,
                   "neighbors_alg_bytes": round(nbr_bytes),
                   "neighbors_GBps": round(nbr_bytes / (nbr_med * 1e-3) / 1e9, 1),
-                  "neighbors_frac": round(nbr_bytes / (nbr_med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                  "neighbors_frac": round(nbr_bytes / (nbr_med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "neighbors_traffic": read_traffic("nbr_hbm_bytes_per_launch")}
 
     # the small correctness workload: only its latency per step means anything
     # (its state and lists fit in L2)

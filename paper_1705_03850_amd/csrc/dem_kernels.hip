@@ -359,9 +359,10 @@ __global__ void k_scatter_back(KArgs a) {
 // Row of particle i: all j != i with d^2 < (r_i + r_j + skin)^2 in the 27
 // surrounding cells, sorted by id.  A group of kNbrLanes lanes per particle.
 // The three cells along x of each (dz, dy) row of cells are one run of
-// candidates (two pieces where the run crosses a periodic seam in x).  The
-// bounds of all nine runs are read with no branch between the loads, so they
-// are in flight together.  Each group deals its candidates to its lanes in
+// candidates (two pieces where the run crosses a periodic seam in x).  Each
+// lane reads the bounds of three of the nine runs into the group's LDS table,
+// with no branch between the loads, so that they are in flight together.
+// Each group deals its candidates to its lanes in
 // turn, kNbrUnroll per lane loaded before any is tested; hits are appended to
 // the group's LDS buffer in candidate order (a ballot gives each its place).
 // Then the hits' ids are fetched, each lane ranks its entries by id (ids are
@@ -370,18 +371,27 @@ __global__ void k_scatter_back(KArgs a) {
 // previous row, also sorted by id).  A group's LDS buffers are its own and
 // its lanes share a wave, so no barrier spans the block until the end.
 //
-// Measured on the 1e6-sphere bed (ms per build): 4 lanes per particle 0.48,
+// Measured on the 1e6-sphere bed (ms per build), with the run bounds held in
+// registers (117 of them, four waves per SIMD): 4 lanes per particle 0.48,
 // against 0.51 for 2, 0.61 for 8, 0.80 for 1 and 0.90 for 16; two candidates
-// per lane in flight against one 0.52 and four (which spill) 0.52; one
-// candidate at five waves per SIMD 0.51.
+// per lane in flight against one 0.52 and four (which spill) 0.52.  With the
+// run table in LDS the kernel needs 95 registers and runs five waves per
+// SIMD: 0.41 (six waves spill: 0.42).
 constexpr int kNbrLanes = 4;
 constexpr int kNbrBlock = 256;
+static_assert(3 * kNbrLanes >= 9, "each lane reads the bounds of at most three of the nine runs");
 constexpr int kNbrUnroll = 2;
 
-// LDS of k_neighbors: per group, its hits' indices, their ids and the previous
-// row's ids (kmax each).
+// LDS of k_neighbors, per group: its hits' indices (kmax words), then their ids and the previous
+// row's ids (kmax each), over which the table of the nine runs (3 words each)
+// lies during the collection; an odd number of words, so that the groups of a
+// wave start in different banks.
+__host__ __device__ inline int nbr_group_words(int kmax) {
+    const int w = kmax + (2 * kmax > 27 ? 2 * kmax : 27);
+    return w | 1;
+}
 __host__ __device__ inline size_t nbr_lds_bytes(int kmax, int block) {
-    return (size_t)3 * (block / kNbrLanes) * kmax * sizeof(int32_t);
+    return (size_t)nbr_group_words(kmax) * (block / kNbrLanes) * sizeof(int32_t);
 }
 
 // Orders the LDS accesses of one wave's lanes (the buffers a group shares).
@@ -418,7 +428,7 @@ __device__ __forceinline__ bool nbr_place(const int32_t *bid, const int32_t *bid
 }
 
 template <bool BATCH>
-__global__ void __launch_bounds__(kNbrBlock, 4) k_neighbors(KArgs a, int have_old) {
+__global__ void __launch_bounds__(kNbrBlock, 5) k_neighbors(KArgs a, int have_old) {
     extern __shared__ int32_t nbr_lds[];
     __shared__ int32_t blockmax;
     constexpr int G = kNbrLanes;
@@ -429,9 +439,10 @@ __global__ void __launch_bounds__(kNbrBlock, 4) k_neighbors(KArgs a, int have_ol
     const int ppb = blockDim.x / G;
     const int gbase = (threadIdx.x % warpSize) / G * G;
     const uint64_t gmask = (1ull << G) - 1;
-    int32_t *bidx = nbr_lds + grp * kmax;               // the group's hits' indices
-    int32_t *bid = nbr_lds + (ppb + grp) * kmax;        //   their ids
-    int32_t *oid = nbr_lds + (2 * ppb + grp) * kmax;    //   the previous row's ids
+    int32_t *bidx = nbr_lds + grp * nbr_group_words(kmax);   // the group's hits' indices
+    int32_t *bid = bidx + kmax;                               //   their ids
+    int32_t *oid = bid + kmax;                                //   the previous row's ids
+    int32_t *runs = bid;                                      //   the nine runs, while collecting
     const D4 *Q = (const D4 *)a.shadow_d;  // (x, y, z, r) in the current order (k_nbr_pack)
     const int32_t *cs = a.cell_start;
     const int64_t ntiles = (n + ppb - 1) / ppb;
@@ -470,40 +481,50 @@ __global__ void __launch_bounds__(kNbrBlock, 4) k_neighbors(KArgs a, int have_ol
             const int x0 = wrapx ? (ccx == 0 ? 0 : ccx - 1) : (ccx > 0 ? ccx - 1 : 0);
             const int x1 = wrapx ? (ccx == nx - 1 ? nx - 1 : ccx + 1) : (ccx + 1 < nx ? ccx + 1 : nx - 1);
             const int c2 = seam ? (ccx == 0 ? nx - 1 : 0) : x0;
-            // the nine runs: first index and length of each piece, minimum-image flags
-            int32_t rb1[9], rl1[9], rb2[9], pre[10];
-            uint32_t my = 0, mz = 0, okm = 0;
+            // minimum-image flags of the nine runs (every lane), then the runs'
+            // bounds, each lane reading those of runs g, g + G, g + 2 G into the
+            // group's LDS table (first index of each piece, length of the first)
+            uint32_t my = 0, mz = 0;
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
+                const int dz = k / 3 - 1, dy = k % 3 - 1;
+                const int cz = ccz + dz, cy = ccy + dy;
+                if (pz && (nz < 5 || cz < 0 || cz >= nz)) mz |= 1u << k;
+                if (py && (ny < 5 || cy < 0 || cy >= ny)) my |= 1u << k;
+            }
+            int32_t lt[3] = {0, 0, 0};   // whole length of this lane's runs g, g + G, g + 2 G
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int k = g + r * G;
+                if (k >= 9) break;
                 const int dz = k / 3 - 1, dy = k % 3 - 1;
                 int cz = ccz + dz, cy = ccy + dy;
                 bool ok = true;
                 if (pz) {
-                    if (nz < 5 || cz < 0 || cz >= nz) mz |= 1u << k;
                     cz = cz < 0 ? cz + nz : (cz >= nz ? cz - nz : cz);
                     if (nz < 3 && dz == -1) ok = false;
                 } else if (cz < 0 || cz >= nz) ok = false;
                 if (py) {
-                    if (ny < 5 || cy < 0 || cy >= ny) my |= 1u << k;
                     cy = cy < 0 ? cy + ny : (cy >= ny ? cy - ny : cy);
                     if (ny < 3 && dy == -1) ok = false;
                 } else if (cy < 0 || cy >= ny) ok = false;
-                if (ok) okm |= 1u << k;
                 const int64_t crow = s.c0 + (ok ? ((int64_t)cz * ny + cy) * nx : 0);   // a valid row either way
-                rb1[k] = cs[crow + x0];
-                rl1[k] = cs[crow + x1 + 1];   // end, made a length below
-                rb2[k] = cs[crow + c2];
-                pre[k] = cs[crow + c2 + 1];   // end of the second piece, likewise
+                const int32_t b1 = cs[crow + x0], e1 = cs[crow + x1 + 1];
+                const int32_t b2 = cs[crow + c2], e2 = cs[crow + c2 + 1];
+                const int32_t l1 = ok ? e1 - b1 : 0, l2 = ok && seam ? e2 - b2 : 0;
+                runs[3 * k] = b1;
+                runs[3 * k + 1] = b2;
+                runs[3 * k + 2] = l1;
+                lt[r] = l1 + l2;
             }
+            wave_sync();
+            // the runs' lengths from the lanes that read them, and their prefix
+            int32_t pre[10];
             int total = 0;
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                const bool ok = (okm >> k) & 1u;
-                const int32_t l1 = ok ? rl1[k] - rb1[k] : 0;
-                const int32_t l2 = ok && seam ? pre[k] - rb2[k] : 0;
-                rl1[k] = l1;
                 pre[k] = total;
-                total += l1 + l2;
+                total += __shfl(lt[k / G], gbase + k % G);
             }
             pre[9] = total;
             // the system's constants in registers: the loop stores to LDS, and the
@@ -516,10 +537,11 @@ __global__ void __launch_bounds__(kNbrBlock, 4) k_neighbors(KArgs a, int have_ol
 #pragma unroll
                 for (int e = 0; e < kNbrUnroll; ++e) {
                     const int v = v0 + e * G + g;
-                    int32_t b1 = rb1[0], l1 = rl1[0], b2 = rb2[0], p0k = 0, k = 0;
+                    int32_t p0k = 0, k = 0;
 #pragma unroll
                     for (int m = 1; m < 9; ++m)
-                        if (v >= pre[m]) { b1 = rb1[m]; l1 = rl1[m]; b2 = rb2[m]; p0k = pre[m]; k = m; }
+                        if (v >= pre[m]) { p0k = pre[m]; k = m; }
+                    const int32_t b1 = runs[3 * k], b2 = runs[3 * k + 1], l1 = runs[3 * k + 2];
                     const int u = v - p0k;
                     // past the end: the particle itself, which is no hit
                     jj[e] = v < total ? (u < l1 ? b1 + u : b2 + (u - l1)) : (int32_t)i;

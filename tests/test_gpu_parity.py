@@ -105,6 +105,31 @@ def test_neighbor_list_bitexact_bed():
     assert np.array_equal(a, ea) and np.array_equal(b, eb)
 
 
+@pytest.mark.parametrize("ncx,ncy,pz", [(2, 3, 0), (3, 3, 0), (4, 2, 0), (5, 3, 1), (7, 4, 1)])
+def test_neighbor_list_bitexact_small_periodic_boxes(ncx, ncy, pz):
+    """Boxes of two to seven cells per periodic axis: the x-runs of three cells
+    (one piece, or two across the seam), the minimum image on short axes and
+    the duplicate-free runs of two-cell axes, against brute force."""
+    from paper_1705_03850_amd.inputs.workloads import MAT_A, System
+    rng = np.random.default_rng(100 + 10 * ncx + ncy)
+    edge = 2.6e-3                         # just above the cut-off 2 r_max + skin = 2.52 mm
+    L = (ncx * edge, ncy * edge, (3 if pz else 4) * edge)
+    n = int(0.2e9 * L[0] * L[1] * L[2])   # about ten neighbours per particle
+    x = rng.uniform(0.0, 1.0, size=(n, 3)) * np.array(L)
+    s = System(x=x, v=np.zeros((n, 3)), w=np.zeros((n, 3)), r=rng.uniform(0.8e-3, 1.2e-3, n),
+               type=np.zeros(n, np.int32), id=rng.permutation(n).astype(np.int32), materials=[MAT_A],
+               lo=(0.0, 0.0, 0.0), hi=L, periodic=(1, 1, pz), wall_z0=0, g=(0.0, 0.0, 0.0), dt=1e-6,
+               skin=0.12e-3, steps=0, name=f"gas_{ncx}x{ncy}")
+    g = gpu(s)
+    g.build_list()
+    a, b = g.export_neighbors()
+    o = O.Oracle(s)
+    lo, hi = o.pairs(s.skin, brute=True)
+    ea, eb = directed(lo, hi)
+    assert len(a) > 4 * n
+    assert np.array_equal(a, ea) and np.array_equal(b, eb)
+
+
 def test_forces_first_evaluation_bed():
     """Settled bed: contacts from the start, zero history; one force evaluation."""
     s = W.settled_bed(seed=8, n=20000, footprint=80e-3 * np.sqrt(0.02))

@@ -260,6 +260,8 @@ def adjoint_suite(args, emit=True):
     torch.cuda.reset_peak_memory_stats()
     g = dem.DemSystem(s)
     adj = g.adjoint(steps, window=window, keep=args.keep)
+    if args.adj_lanes:
+        adj.set_lanes(args.adj_lanes)
     t_fwd, t_bwd = [], []
     for _ in range(reps + 1):
         g.load_state()
@@ -280,7 +282,8 @@ def adjoint_suite(args, emit=True):
     tp, tf, tb = (float(np.median(t[1:])) for t in (t_plain, t_fwd, t_bwd))
     out = {
         "suite": "adjoint", "workload": "chute_adjoint(seed=5, n=50000), 200 steps, flux loss in 20 bins",
-        "n": s.n, "steps": steps, "window": window, "keep": bool(args.keep), "dtype": "f64", "data": "synthetic",
+        "n": s.n, "steps": steps, "window": window, "keep": bool(args.keep), "lanes": args.adj_lanes or "default",
+        "dtype": "f64", "data": "synthetic",
         "plain_forward_s": tp, "adjoint_forward_s": tf, "backward_s": tb,
         "adjoint_vs_plain": (tf + tb) / tp, "backward_vs_plain": tb / tp,
         "plain_particle_steps_per_s": s.n * steps / tp,
@@ -316,6 +319,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--window", type=int, default=20, help="adjoint suite: steps per checkpoint window")
     ap.add_argument("--keep", action="store_true", help="adjoint suite: store every step's inputs (no recompute)")
+    ap.add_argument("--adj-lanes", type=int, default=0, help="adjoint suite: threads per particle (0: library default)")
     ap.add_argument("--suite", choices=("plain", "batch", "adjoint"), default="plain",
                     help="plain: the 1e6-sphere bed (default); batch: 64-system and two-level batches vs plain")
     ap.add_argument("--no-autotune", action="store_true", help="batch suite: default launch shape and skin")

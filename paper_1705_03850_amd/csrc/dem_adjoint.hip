@@ -22,9 +22,7 @@ constexpr int kABlock = 256;
 // Waves per SIMD the reverse kernel is compiled for: 2 caps it at 256
 // registers (a few spill to scratch), which ran the chute backward 11 % faster
 // than one wave with no spills.
-#ifndef DEM_ADJ_WAVES
-#define DEM_ADJ_WAVES 2
-#endif
+constexpr int kAdjReverseWaves = 2;
 
 // Sum over the G lanes of a group, in lane order.
 template <int G>
@@ -279,7 +277,7 @@ __global__ void k_adj_seed_forces(AArgs a, const double *fb, const double *tb) {
 // ------------------------------------------------------------ reverse
 
 template <int NT, bool PRIME, int G>
-__global__ void __launch_bounds__(kABlock, DEM_ADJ_WAVES) k_adj_reverse(AArgs a) {
+__global__ void __launch_bounds__(kABlock, kAdjReverseWaves) k_adj_reverse(AArgs a) {
     const int64_t n = a.n;
     const int64_t kmax = a.kmax;
     const SysDesc s = uniform_sys(a.sys);

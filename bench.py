@@ -308,7 +308,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--max-blocks", type=int, default=0, help="grid cap of the fused step kernel (0 = resident capacity)")
-    ap.add_argument("--lanes", type=int, default=4, help="threads per particle in the force pass (4, 8, 16)")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="threads per particle in the force pass (4, 8, 16; 0: the library default)")
     ap.add_argument("--timing-steps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--rebuilds", type=int, default=10, help="forced rebuilds (dem_bin + dem_neighbors) after the timing")

@@ -189,8 +189,9 @@ int dem_set_timing(dem_ctx *ctx, int enable);
  * [3] list rebuild (unpack, bin, neighbours, repack).  Synchronises. */
 int dem_kernel_times(dem_ctx *ctx, double ms[4], int64_t launches[4]);
 
-/* Launch shape of the force pass: `lanes` threads per particle (4, 8 or 16,
- * default 4; a particle's row is split over them) and at most max_blocks
+/* Launch shape of the force pass: `lanes` threads per particle (4, 8 or 16; a
+ * particle's row is split over them; 0 = the default, also set at init: the
+ * most of 4, 8 and 16 with n * lanes <= 65536, else 4) and at most max_blocks
  * workgroups, each walking several tiles of particles (0 = as many as stay
  * resident on the device).  The schedule changes, the results do not: the
  * pair terms of a row are always added in neighbour-id order.  In a batch

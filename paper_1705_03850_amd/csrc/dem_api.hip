@@ -379,6 +379,19 @@ int dem_workspace_size(const dem_config *cfg, size_t *bytes) { return dem_batch_
 
 static std::string g_init_error;
 
+// Default lanes per particle: the most of 4, 8 and 16 that keep the force pass
+// within 65,536 threads (one wave per SIMD of the device), else 4.  Small
+// systems cannot fill the device, and more lanes shorten each particle's chain
+// of dependent loads: 2,000 spheres step in 9.0 us with 16 lanes against 13.5
+// with 4, 5,154 in 11.9 us with 8 against 14.0; from about 17,000 particles 4
+// lanes are fastest.
+static int32_t default_lanes(int64_t n, int32_t block) {
+    int32_t lanes = 4;
+    for (int32_t l = 16; l > 4; l /= 2)
+        if (l <= block && n * l <= 65536) { lanes = l; break; }
+    return lanes;
+}
+
 int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *workspace, size_t ws_bytes,
                    void *stream) {
     if (!out) return DEM_ERR_ARG;
@@ -399,6 +412,7 @@ int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *wo
     c->d_coef = (PairCoef *)(c->ws + lay.coef);
     c->d_rho = (double *)(c->ws + lay.rho);
     c->d_flags = (Flags *)(c->ws + lay.flags);
+    c->lanes = default_lanes(g.n, g.block);
     for (int b = 0; b < 2; ++b) {
         c->lists[b].nbr = (int32_t *)(c->ws + lay.nbr[b]);
         c->lists[b].cnt = (int32_t *)(c->ws + lay.cnt[b]);
@@ -506,7 +520,8 @@ int dem_set_step_options(dem_ctx *c, int use_graph, int32_t chunk) {
 int dem_set_launch(dem_ctx *c, int32_t lanes, int32_t max_blocks) {
     if (!c) return DEM_ERR_ARG;
     if (max_blocks < 0) return fail(c, DEM_ERR_ARG, "max_blocks must be >= 0");
-    if (lanes != 4 && lanes != 8 && lanes != 16) return fail(c, DEM_ERR_ARG, "lanes must be 4, 8 or 16");
+    if (lanes == 0) lanes = default_lanes(c->geo.n, c->geo.block);
+    if (lanes != 4 && lanes != 8 && lanes != 16) return fail(c, DEM_ERR_ARG, "lanes must be 0, 4, 8 or 16");
     if (lanes > c->geo.block) return fail(c, DEM_ERR_ARG, "lanes must not exceed the block size");
     c->grid_cap = max_blocks;
     c->lanes = lanes;

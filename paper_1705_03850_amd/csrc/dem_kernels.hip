@@ -362,9 +362,9 @@ __global__ void k_scatter_back(KArgs a) {
 // candidates (two pieces where the run crosses a periodic seam in x).  Each
 // lane reads the bounds of three of the nine runs into the group's LDS table,
 // with no branch between the loads, so that they are in flight together.
-// Each group deals its candidates to its lanes in
-// turn, kNbrUnroll per lane loaded before any is tested; hits are appended to
-// the group's LDS buffer in candidate order (a ballot gives each its place).
+// Each group deals its candidates to its lanes in turn, kNbrUnroll per lane
+// loaded before any is tested; hits are appended to the group's LDS buffer in
+// candidate order (a ballot gives each its place).
 // Then the hits' ids are fetched, each lane ranks its entries by id (ids are
 // unique) and writes them to their places in the row, and the history of
 // pairs of the previous list is carried over by id (binary search of the
@@ -382,10 +382,10 @@ constexpr int kNbrBlock = 256;
 static_assert(3 * kNbrLanes >= 9, "each lane reads the bounds of at most three of the nine runs");
 constexpr int kNbrUnroll = 2;
 
-// LDS of k_neighbors, per group: its hits' indices (kmax words), then their ids and the previous
-// row's ids (kmax each), over which the table of the nine runs (3 words each)
-// lies during the collection; an odd number of words, so that the groups of a
-// wave start in different banks.
+// LDS of k_neighbors, per group: its hits' indices (kmax words), then their
+// ids and the previous row's ids (kmax each), over which the table of the nine
+// runs (3 words each) lies during the collection; an odd number of words, so
+// that the groups of a wave start in different banks.
 __host__ __device__ inline int nbr_group_words(int kmax) {
     const int w = kmax + (2 * kmax > 27 ? 2 * kmax : 27);
     return w | 1;

@@ -157,7 +157,7 @@ class DemSystem:
     """
 
     def __init__(self, systems, k_max: int = 32, block: int = 0, cell=0.0, skin=None, device: str = "cuda",
-                 use_graph: bool = False, chunk: int = 64, lanes: int = 4, max_blocks: int = 0):
+                 use_graph: bool = False, chunk: int = 64, lanes: int = 0, max_blocks: int = 0):
         import torch
 
         self.torch = torch
@@ -267,7 +267,7 @@ class DemSystem:
     def set_step_options(self, use_graph: bool, chunk: int = 64):
         self._rc(self.L.dem_set_step_options(self.ctx, int(use_graph), int(chunk)))
 
-    def set_launch(self, lanes: int = 4, max_blocks: int = 0):
+    def set_launch(self, lanes: int = 0, max_blocks: int = 0):
         self._rc(self.L.dem_set_launch(self.ctx, int(lanes), int(max_blocks)))
 
     def prime(self):

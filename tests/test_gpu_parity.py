@@ -203,6 +203,48 @@ def test_hundred_steps_positions(skin):
     assert np.max(np.abs(cx - ex)) <= 1e-9 * max(np.abs(ex).max(), 1e-300)
 
 
+def test_empty_system_is_a_no_op():
+    """No particles: every call succeeds and changes nothing."""
+    from paper_1705_03850_amd.inputs.workloads import MAT_A, System
+    z = np.zeros((0, 3))
+    s = System(x=z, v=z, w=z, r=np.zeros(0), type=np.zeros(0, np.int32), id=np.zeros(0, np.int32), materials=[MAT_A],
+               lo=(0.0, 0.0, 0.0), hi=(10e-3, 10e-3, 10e-3), periodic=(1, 1, 0), wall_z0=1, g=(0.0, 0.0, -9.81),
+               dt=1e-6, skin=0.1e-3, steps=0, name="empty")
+    g = gpu(s)
+    g.prime()
+    g.step(10)
+    h = g.host()
+    assert h["x"].shape == (0, 3)
+    st = g.stats()
+    assert st["contacts"] == 0 and st["slots"] == 0
+
+
+@pytest.mark.parametrize("case", ["one_on_wall", "two_head_on"])
+def test_one_and_two_particles_against_oracle(case):
+    """Degenerate sizes: a single sphere dropped onto the wall (no pairs, the
+    wall only) and two spheres meeting head-on (one pair, no wall), 600 steps
+    through the contact, against the oracle."""
+    from systems import sphere_on_wall, two_spheres
+    s = sphere_on_wall(1.0e-3 + 2e-6, v=(0.05, 0.0, -0.3)) if case == "one_on_wall" else two_spheres(1.0)
+    g = gpu(s)
+    g.prime()
+    g.step(600)
+    o = O.Oracle(s)
+    o.forces(False)
+    o.step(600)
+    h = g.host()
+    st = o.state()
+    X, V = by_id(s, st["x"]), by_id(s, st["v"])
+    assert np.max(np.abs(h["x"] - X)) <= 1e-9 * 40e-3
+    assert np.max(np.abs(h["v"] - V)) <= 1e-9 * np.abs(V).max()
+    # the contact happened and is over: the spheres move apart, the single
+    # sphere has bounced off the wall
+    if case == "two_head_on":
+        assert V[0, 0] < 0.0 < V[1, 0]
+    else:
+        assert V[0, 2] > 0.0
+
+
 def test_history_antisymmetric_bitwise():
     s = W.plain_fcc()
     g = gpu(s)

@@ -82,9 +82,12 @@ def compare_forces(g, system, o, tol=1e-12):
 
 # --------------------------------------------------------------------------
 
-def test_neighbor_list_bitexact_plain():
+@pytest.mark.parametrize("k_max", [16, 32, 63])
+def test_neighbor_list_bitexact_plain(k_max):
+    """Row capacities from just above the FCC rows (12) to the largest
+    allowed (63, the most LDS per group)."""
     s = W.plain_fcc()
-    g = gpu(s)
+    g = gpu(s, k_max=k_max)
     g.build_list()
     a, b = g.export_neighbors()
     o = O.Oracle(s)

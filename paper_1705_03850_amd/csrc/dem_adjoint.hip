@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kABlock, 4) k_adj_forward(AArgs a) {
             const int q = c0 + g;
             const bool valid = q < cnt;
             const int64_t slot = i * kmax + q;
-            const int32_t j = valid ? a.nbr[slot] : (int32_t)i;
+            const int32_t j = valid ? a.nbr[q * n + i] : (int32_t)i;
             const D4 pj = a.pos[j];
             ContactIn c;
             c.dx = min_image(pi.x - pj.x, s.L[0], s.hL[0], s.periodic[0]);
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(kABlock, kAdjReverseWaves) k_adj_reverse(AArgs
         const int cnt = a.cnt[i];
         for (int q = g; q < cnt; q += G) {
             const int64_t slot = i * kmax + q;
-            const int32_t j = a.nbr[slot];
+            const int32_t j = a.nbr[q * n + i];
             const D4 pj = a.pos[j];
             ContactIn c;
             c.dx = min_image(pi.x - pj.x, s.L[0], s.hL[0], s.periodic[0]);
@@ -434,10 +434,10 @@ __global__ void k_adj_carry(AArgs a, const int32_t *frame, const int32_t *nids, 
         const int cn = a.cnt[i], co = ocnt[o];
         int q = 0;
         for (int p = 0; p < co; ++p) {
-            const int32_t idp = oids[onbr[o * kmax + p]];
-            while (q < cn && nids[a.nbr[i * kmax + q]] < idp) ++q;
+            const int32_t idp = oids[onbr[p * n + o]];
+            while (q < cn && nids[a.nbr[q * n + i]] < idp) ++q;
             D4 m = {0.0, 0.0, 0.0, 0.0};
-            if (q < cn && nids[a.nbr[i * kmax + q]] == idp) m = a.mu[i * kmax + q];
+            if (q < cn && nids[a.nbr[q * n + i]] == idp) m = a.mu[i * kmax + q];
             mu_old[o * kmax + p] = m;
         }
     }

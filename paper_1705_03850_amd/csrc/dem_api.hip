@@ -750,7 +750,7 @@ int fetch_list(dem_ctx *c, const dem_state *s, HostList &H, bool with_xi, bool w
             H.cnt[i] = cnt[i];
             H.ids[i] = ids[i];
             H.mask[i] = mask[i];
-            for (int64_t q = 0; q < K; ++q) H.nbr[i * K + q] = nbr[i * K + q];
+            for (int64_t q = 0; q < K; ++q) H.nbr[i * K + q] = nbr[q * n + i];   // device: slot major
             if (with_xi)
                 for (int64_t q = 0; q < 4 * K; ++q) H.xi[4 * K * i + q] = xi[4 * K * i + q];
         }

@@ -69,7 +69,9 @@ struct alignas(16) D2 {
 };
 
 struct List {
-    int32_t *nbr;    // [n][kmax] neighbour index (in the particle order of the build)
+    int32_t *nbr;    // [kmax][n] neighbour index (in the particle order of the build), slot
+                     // major: slot q of particle i at q n + i, so that the slot-q reads of
+                     // consecutive particles share lines
     int32_t *cnt;    // [n] row length
     D4 *xi;          // [n][kmax] tangential history of each slot (x, y, z, unused): one
                      // 32-byte record, so a contact reads and writes one line

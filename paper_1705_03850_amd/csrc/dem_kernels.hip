@@ -405,13 +405,14 @@ __device__ __forceinline__ void wave_sync() {
 // where its index is written; returns whether the previous row (ids oid,
 // sorted) holds the pair with a history, and then where (from).
 __device__ __forceinline__ bool nbr_place(const int32_t *bid, const int32_t *bidx, const int32_t *oid, int cnt,
-                                          int ocnt, uint64_t omask, int have_old, int64_t i, int64_t o, int kmax,
-                                          const List &L, int q, int64_t &slot, int64_t &from, uint64_t &bits) {
+                                          int ocnt, uint64_t omask, int have_old, int64_t n, int64_t i, int64_t o,
+                                          int kmax, const List &L, int q, int64_t &slot, int64_t &from,
+                                          uint64_t &bits) {
     const int32_t idq = bid[q];
     int rank = 0;
     for (int k = 0; k < cnt; ++k) rank += bid[k] < idq ? 1 : 0;
     slot = i * kmax + rank;
-    L.nbr[slot] = bidx[q];
+    L.nbr[rank * n + i] = bidx[q];
     if (!have_old) return false;
     int lo = 0, hi = ocnt;   // first p with oid[p] >= idq
     while (lo < hi) {
@@ -589,10 +590,10 @@ __global__ void __launch_bounds__(kNbrBlock, 5) k_neighbors(KArgs a, int have_ol
                 const List O = list_of(a, sy, 0);
                 ocnt = O.cnt[o];
                 omask = O.mask[o];
-                const int32_t *orow = O.nbr + o * kmax;
+                const int32_t *orow = O.nbr + o;   // entry p at orow[p n]
                 for (int p0 = g; p0 < ocnt; p0 += 2 * G) {
                     const int p1 = p0 + G;
-                    const int32_t j0 = orow[p0], j1 = orow[p1 < ocnt ? p1 : p0];
+                    const int32_t j0 = orow[p0 * n], j1 = orow[(p1 < ocnt ? p1 : p0) * n];
                     const int32_t id0 = O.ids[j0], id1 = O.ids[j1];
                     oid[p0] = id0;
                     if (p1 < ocnt) oid[p1] = id1;
@@ -607,9 +608,10 @@ __global__ void __launch_bounds__(kNbrBlock, 5) k_neighbors(KArgs a, int have_ol
             for (int q0 = g; q0 < cnt; q0 += 2 * G) {
                 const int q1 = q0 + G;
                 int64_t s0, s1 = 0, f0, f1 = 0;
-                const bool c0 = nbr_place(bid, bidx, oid, cnt, ocnt, omask, have_old, i, o, kmax, L, q0, s0, f0, bits);
-                const bool c1 = q1 < cnt && nbr_place(bid, bidx, oid, cnt, ocnt, omask, have_old, i, o, kmax, L, q1, s1,
-                                                      f1, bits);
+                const bool c0 = nbr_place(bid, bidx, oid, cnt, ocnt, omask, have_old, n, i, o, kmax, L, q0, s0, f0,
+                                          bits);
+                const bool c1 = q1 < cnt && nbr_place(bid, bidx, oid, cnt, ocnt, omask, have_old, n, i, o, kmax, L, q1,
+                                                      s1, f1, bits);
                 // both loads unconditional (slot 0 where nothing is carried), so that
                 // they are issued together
                 const D4 *p0 = O.xi + (c0 ? f0 : 0), *p1 = O.xi + (c1 ? f1 : 0);
@@ -762,7 +764,7 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
             const int q = c0 + g;
             const bool valid = q < cnt;
             const int64_t slot = i * kmax + q;
-            const int32_t j = valid ? L.nbr[slot] : (int32_t)i;
+            const int32_t j = valid ? L.nbr[q * n + i] : (int32_t)i;
             const D4 pj = P[j];
             ContactIn c;
             c.dx = min_image(pi.x - pj.x, s.L[0], s.hL[0], s.periodic[0]);

@@ -162,13 +162,25 @@ int dem_integrate(dem_ctx *ctx, const dem_state *s, int phase);
  * the workspace, with one fused kernel per step (forces, kick, and the next
  * step's kick and drift); the caller's arrays are read at the start and
  * written at the end.  Results are bit-identical to calling dem_integrate(0),
- * dem_bin/dem_neighbors when needed, dem_forces(1) and dem_integrate(1).  The forces in s->f, s->t must belong to the current state
- * (call dem_forces(ctx, s, 0) once after dem_reset, or provide them); the
- * library cannot check this.  The rebuild decision is
- * taken on the device; the host learns of it at a synchronisation every few
- * dozen steps, so this call synchronises the stream.  Returns the sticky
- * device errors (DEM_ERR_CAPACITY, DEM_ERR_NONFINITE). */
+ * dem_bin/dem_neighbors when needed, dem_forces(1) and dem_integrate(1).
+ * The first half kick of velocity Verlet uses s->f and s->t, so they must be
+ * the forces of the current state: the context tracks this and returns
+ * DEM_ERR_STATE (stepping nothing) unless, since the last dem_reset,
+ * dem_set_materials or dem_integrate(ctx, s, 0), the forces were evaluated
+ * (dem_forces, a previous dem_step or dem_rollout_forward) or declared with
+ * dem_declare_forces.  dem_bin and dem_neighbors keep them valid (they permute
+ * f and t with the particles).  The rebuild decision is taken on the device;
+ * the host learns of it at a synchronisation every few dozen steps, so this
+ * call synchronises the stream.  Returns the sticky device errors
+ * (DEM_ERR_CAPACITY, DEM_ERR_NONFINITE). */
 int dem_step(dem_ctx *ctx, const dem_state *s, int64_t nsteps);
+
+/* The caller states that s->f and s->t hold the force and torque of the
+ * current positions and velocities (restored from a checkpoint, computed
+ * elsewhere), so that dem_step may take its first half kick from them
+ * (velocity Verlet, Eq. (1)-(2)).  Host only; nothing is checked on the
+ * device. */
+int dem_declare_forces(dem_ctx *ctx);
 
 /* Step-loop options: use_graph != 0 replays the per-step kernels as one
  * captured HIP graph of `chunk` steps (chunk even, 2..1024; default 64). */

@@ -291,6 +291,7 @@ int dem_set_materials(dem_ctx *c, int32_t sys, const dem_material *mat, int32_t 
     HIPCALL(c, hipMemcpyAsync(c->d_coef + sd.coef0, c->geo.coef.data() + sd.coef0,
                               (size_t)ntypes * ntypes * sizeof(PairCoef), hipMemcpyHostToDevice, c->stream));
     HIPCALL(c, hipStreamSynchronize(c->stream));
+    c->forces_valid = false;   // the stored forces belong to the old materials
     return DEM_OK;
 }
 

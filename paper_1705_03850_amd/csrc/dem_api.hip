@@ -509,6 +509,12 @@ int dem_integrate(dem_ctx *c, const dem_state *s, int phase) {
     return DEM_OK;
 }
 
+int dem_declare_forces(dem_ctx *c) {
+    if (!c) return DEM_ERR_ARG;
+    c->forces_valid = true;
+    return DEM_OK;
+}
+
 int dem_set_step_options(dem_ctx *c, int use_graph, int32_t chunk) {
     if (!c) return DEM_ERR_ARG;
     if (chunk < 2 || chunk > 1024 || (chunk & 1)) return fail(c, DEM_ERR_ARG, "chunk must be even, 2..1024");
@@ -534,6 +540,9 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
     if (rc) return rc;
     if (nsteps < 0) return fail(c, DEM_ERR_ARG, "nsteps < 0");
     if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first");
+    if (!c->forces_valid)
+        return fail(c, DEM_ERR_STATE,
+                    "dem_step needs the forces of the current state: call dem_forces(ctx, s, 0) or dem_declare_forces");
     if (nsteps == 0 || c->geo.n == 0) return DEM_OK;
     if (!c->list_current) {
         // binned but no list yet: build it (f and t were permuted with the particles)

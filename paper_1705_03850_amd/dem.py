@@ -46,7 +46,7 @@ class State(ctypes.Structure):
 
 _lib = None
 _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_batch_init", "dem_reset", "dem_bin",
-            "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_set_step_options", "dem_set_launch", "dem_check",
+            "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_declare_forces", "dem_set_step_options", "dem_set_launch", "dem_check",
             "dem_stats", "dem_set_timing", "dem_kernel_times", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
             "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
             "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
     L.dem_forces.argtypes = [vp, P(State), ctypes.c_int]
     L.dem_integrate.argtypes = [vp, P(State), ctypes.c_int]
     L.dem_step.argtypes = [vp, P(State), i64]
+    L.dem_declare_forces.argtypes = [vp]
     L.dem_set_step_options.argtypes = [vp, ctypes.c_int, i32]
     L.dem_set_launch.argtypes = [vp, i32, i32]
     L.dem_check.argtypes = [vp, P(i64)]
@@ -263,6 +264,11 @@ class DemSystem:
 
     def step(self, nsteps: int):
         self._rc(self.L.dem_step(self.ctx, self._state, int(nsteps)))
+
+    def declare_forces(self):
+        """State that f and t hold the forces of the current state (e.g. loaded
+        with load_state), so that step() may start from them."""
+        self._rc(self.L.dem_declare_forces(self.ctx))
 
     def set_step_options(self, use_graph: bool, chunk: int = 64):
         self._rc(self.L.dem_set_step_options(self.ctx, int(use_graph), int(chunk)))

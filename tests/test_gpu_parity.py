@@ -64,6 +64,7 @@ def load_oracle_state(g, system, o):
     a, b, x = directed(lo, hi, xi)
     wid, wxi = o.wall_history()
     g.import_history(a, b, x, wid, wxi)
+    g.declare_forces()          # f, t are the oracle's forces of this state
 
 
 def compare_forces(g, system, o, tol=1e-12):
@@ -460,3 +461,34 @@ def test_bad_type_rejected():
     with pytest.raises(dem.DemError) as e:
         gpu(s)
     assert e.value.code == dem.DEM_ERR_ARG
+
+
+def test_step_refuses_stale_forces():
+    """dem_step takes its first half kick from f and t: after dem_reset (or a
+    drift, or new materials) it returns DEM_ERR_STATE and steps nothing until
+    the forces are evaluated or declared; then it runs as usual."""
+    from paper_1705_03850_amd import dem
+    s = W.plain_fcc()
+    g = gpu(s)
+    g.build_list()
+    x0 = g.x.clone()
+    with pytest.raises(dem.DemError) as e:
+        g.step(5)
+    assert e.value.code == dem.DEM_ERR_STATE
+    assert torch.equal(g.x, x0)                          # nothing stepped
+    g.forces(False)
+    g.step(5)
+    g.integrate(0)                                       # a drift: the forces are stale again
+    with pytest.raises(dem.DemError) as e:
+        g.step(1)
+    assert e.value.code == dem.DEM_ERR_STATE
+    g.build_list()
+    g.forces(True)
+    g.integrate(1)
+    g.step(1)                                            # forces of the last evaluation, kept by the kick
+    g.set_materials(s.materials)
+    with pytest.raises(dem.DemError) as e:
+        g.step(1)
+    assert e.value.code == dem.DEM_ERR_STATE
+    g.declare_forces()
+    g.step(1)

@@ -120,7 +120,7 @@ template <class S> struct Particle {
     V3<S> x, v, w, f, t;
 };
 
-template <class S> struct PairRecord { int lo, hi; double fn_mag, f_mag, ft_mag, fncap; };
+template <class S> struct PairRecord { int lo, hi; double fn_mag, f_mag, ft_mag, fncap, ft_normal; };
 
 template <class S> struct Sim {
     Config cfg;
@@ -249,6 +249,8 @@ bool contact(const Sim<S> &s, const Particle<S> &a, const Particle<S> *b, V3<S> 
         rec->f_mag = std::sqrt(fx * fx + fy * fy + fz * fz);
         rec->ft_mag = std::sqrt(val(ft.x) * val(ft.x) + val(ft.y) * val(ft.y) + val(ft.z) * val(ft.z));
         rec->fncap = val(cap);
+        /* normal component of the tangential force (zero for a force in the tangent plane) */
+        rec->ft_normal = std::fabs(val(ft.x) * val(n.x) + val(ft.y) * val(n.y) + val(ft.z) * val(n.z));
     }
     return true;
 }
@@ -352,7 +354,7 @@ template <class S> void forces(Sim<S> &s, bool update) {
         auto it = s.hist.find(key);
         V3<S> xi = it == s.hist.end() ? V3<S>{0.0, 0.0, 0.0} : it->second;
         V3<S> f, ft, n;
-        PairRecord<S> rec{a.id, b.id, 0, 0, 0, 0};
+        PairRecord<S> rec{a.id, b.id, 0, 0, 0, 0, 0};
         if (!contact(s, a, &b, xi, update, f, ft, n, &rec)) continue;
         s.records.push_back(rec);
         if (update) next[key] = xi;
@@ -369,7 +371,7 @@ template <class S> void forces(Sim<S> &s, bool update) {
             auto it = s.whist.find(a.id);
             V3<S> xi = it == s.whist.end() ? V3<S>{0.0, 0.0, 0.0} : it->second;
             V3<S> f, ft, n;
-            PairRecord<S> rec{a.id, -1, 0, 0, 0, 0};
+            PairRecord<S> rec{a.id, -1, 0, 0, 0, 0, 0};
             if (!contact(s, a, (const Particle<S> *)nullptr, xi, update, f, ft, n, &rec)) continue;
             s.records.push_back(rec);
             if (update) wnext[a.id] = xi;
@@ -559,14 +561,16 @@ long orc_pairs(void *h, double extra, int brute, int *lo, int *hi, long cap) {
 }
 
 /* Per-contact records of the last force evaluation: ids (hi = -1 for the
- * wall) and magnitudes |f_n| (scalar normal force), |F_ij|, |F_t| and the
- * Coulomb cap mu |f_n|. */
-long orc_records(void *h, int *lo, int *hi, double *fn, double *fmag, double *ftmag, double *cap, long capn) {
+ * wall) and magnitudes |f_n| (scalar normal force), |F_ij|, |F_t|, the
+ * Coulomb cap mu |f_n| and |F_t . n| (ftn may be null). */
+long orc_records(void *h, int *lo, int *hi, double *fn, double *fmag, double *ftmag, double *cap, double *ftn,
+                 long capn) {
     SimD *s = (SimD *)h;
     long k = 0;
     for (auto &r : s->records) {
         if (k < capn) {
             lo[k] = r.lo; hi[k] = r.hi; fn[k] = r.fn_mag; fmag[k] = r.f_mag; ftmag[k] = r.ft_mag; cap[k] = r.fncap;
+            if (ftn) ftn[k] = r.ft_normal;
         }
         ++k;
     }

@@ -29,23 +29,30 @@ class OrcConfig(ctypes.Structure):
                 ("periodic", ctypes.c_int * 3), ("wall_z0", ctypes.c_int)]
 
 
+def compile_to(src: str, out: str) -> str:
+    """g++ with the oracle's flags (no FMA contraction, no -march)."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", src, "-o", tmp])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with plain g++ (no FMA contraction, no -march)."""
+    """Compile the oracle (only when the source is newer than the library)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", _SRC,
-                               "-o", tmp])
-        os.replace(tmp, _LIB)
+        compile_to(_SRC, _LIB)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        L = ctypes.CDLL(build())
+def lib(path: str | None = None):
+    """The oracle library (default: the one built from dem_oracle.cpp).  Tests
+    of the pins themselves may load a modified copy compiled elsewhere."""
+    key = path or _LIB
+    if key not in _libs:
+        L = ctypes.CDLL(build() if path is None else path)
         vp = ctypes.c_void_p
         L.orc_new.restype = vp
         L.orc_new.argtypes = [ctypes.POINTER(OrcConfig), ctypes.c_int, _dp, _dp, _dp, _dp, _ip, _ip]
@@ -69,14 +76,14 @@ def lib():
         L.orc_pairs.restype = ctypes.c_long
         L.orc_pairs.argtypes = [vp, ctypes.c_double, ctypes.c_int, _ip, _ip, ctypes.c_long]
         L.orc_records.restype = ctypes.c_long
-        L.orc_records.argtypes = [vp, _ip, _ip, _dp, _dp, _dp, _dp, ctypes.c_long]
+        L.orc_records.argtypes = [vp, _ip, _ip, _dp, _dp, _dp, _dp, _dp, ctypes.c_long]
         L.orc_tan_forces.argtypes = [vp, ctypes.c_int]
         L.orc_tan_step.argtypes = [vp, ctypes.c_int]
         L.orc_tan_get.argtypes = [vp, _dp, _dp, _dp, _dp]
         L.orc_tan_get_ext.argtypes = [vp, ctypes.c_int, _dp, _dp]
         L.orc_tan_seed_state.argtypes = [vp, ctypes.c_int, _dp, _dp, _dp]
-        _lib = L
-    return _lib
+        _libs[key] = L
+    return _libs[key]
 
 
 def _d(a):
@@ -105,8 +112,8 @@ def make_config(system) -> OrcConfig:
 class Oracle:
     """One simulated system in the oracle; arrays are (n, 3) in input order."""
 
-    def __init__(self, system, tangent: bool = False):
-        self.L = lib()
+    def __init__(self, system, tangent: bool = False, lib_path: str | None = None):
+        self.L = lib(lib_path)
         self.n = system.n
         self.tangent = tangent
         self.cfg = make_config(system)
@@ -180,11 +187,13 @@ class Oracle:
         return lo, hi
 
     def records(self):
-        k = self.L.orc_records(self.h, None, None, None, None, None, None, 0)
+        """Contacts of the last force evaluation: ids (hi = -1: wall), |f_n|, |F_ij|,
+        |F_t|, the Coulomb cap mu |f_n| and the normal part |F_t . n|."""
+        k = self.L.orc_records(self.h, None, None, None, None, None, None, None, 0)
         lo = np.empty(k, np.int32); hi = np.empty(k, np.int32)
-        fn, fm, ftm, cap = (np.empty(k) for _ in range(4))
-        self.L.orc_records(self.h, _i(lo), _i(hi), _d(fn), _d(fm), _d(ftm), _d(cap), k)
-        return dict(lo=lo, hi=hi, fn=fn, fmag=fm, ftmag=ftm, cap=cap)
+        fn, fm, ftm, cap, ftn = (np.empty(k) for _ in range(5))
+        self.L.orc_records(self.h, _i(lo), _i(hi), _d(fn), _d(fm), _d(ftm), _d(cap), _d(ftn), k)
+        return dict(lo=lo, hi=hi, fn=fn, fmag=fm, ftmag=ftm, cap=cap, ftn=ftn)
 
     # ---- forward-mode handle
     def tan_forces(self, update_history: bool = False):

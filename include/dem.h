@@ -122,6 +122,23 @@ int dem_init(dem_ctx **ctx, const dem_config *cfg, void *workspace, size_t ws_by
 int dem_batch_init(dem_ctx **ctx, int32_t nsys, const dem_config *cfgs, void *workspace, size_t ws_bytes,
                    void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): dem_init of one
+ * system with the workspace placed in the library's static device array of
+ * 64 MiB (67,108,864 bytes) instead of a caller buffer.  Each device holds
+ * its own array from the library's load to the end of the process; this call
+ * takes its address for the current device, clears the part the system needs
+ * (the array keeps the previous context's contents) and calls no allocating
+ * routine for device memory (the context itself is host memory, as with
+ * dem_init).  Only one context per device may use the array at a time:
+ * DEM_ERR_STATE while another lives (dem_destroy releases it, after
+ * synchronising its stream).  Work of two such contexts on one device must
+ * not overlap in time; it would race on the array.  DEM_ERR_CAPACITY (before
+ * any device work) when dem_workspace_size(cfg) exceeds the array, e.g. beyond
+ * about 20,000 particles at k_max = 32; other errors as dem_init.  The
+ * context is used and destroyed like any other. */
+int dem_init_noalloc(dem_ctx **ctx, const dem_config *cfg, void *stream);
+
 /* Start from the particles in *s: computes masses m = (4/3) pi rho r^3 and
  * inertias I = (2/5) m r^2 (solid spheres, Eq. (1)-(2)), clears the tangential
  * history of all pairs and of the wall, and marks the neighbour list invalid.

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -447,6 +448,74 @@ int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *wo
 
 int dem_init(dem_ctx **ctx, const dem_config *cfg, void *workspace, size_t ws_bytes, void *stream) {
     return dem_batch_init(ctx, 1, cfg, workspace, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- static workspace (no allocation)
+//
+// dem_init_noalloc places a context's workspace in this array instead of a
+// caller buffer.  Each device holds its own copy for the life of the process;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device (the array's name is a host-side stand-in).  One
+// context per device may use it at a time.
+static constexpr size_t kStaticWsBytes = (size_t)64 << 20;
+
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices];          // device address of `scratch` on each device
+const dem_ctx *g_static_owner[kMaxDevices];  // the context that uses it, if any
+
+}  // namespace
+
+extern "C" {
+
+int dem_init_noalloc(dem_ctx **out, const dem_config *cfg, void *stream) {
+    if (!out) return DEM_ERR_ARG;
+    *out = nullptr;
+    Geometry g;
+    std::string err;
+    int rc = build_geometry(1, cfg, g, err);
+    if (rc) { g_init_error = err; return rc; }
+    const size_t need = make_layout(g).total;
+    if (need > kStaticWsBytes) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "this system needs %zu bytes of workspace; the static workspace holds %zu (use dem_init)",
+                 need, kStaticWsBytes);
+        g_init_error = buf;
+        return DEM_ERR_CAPACITY;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { g_init_error = std::string("hipGetDevice: ") + hipGetErrorString(e); return DEM_ERR_HIP; }
+    if (dev < 0 || dev >= kMaxDevices) { g_init_error = "device index out of range"; return DEM_ERR_ARG; }
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_init_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return DEM_ERR_HIP;
+        }
+        g_static_ptr[dev] = p;
+    }
+    if (g_static_owner[dev]) {
+        g_init_error = "the static workspace of this device is used by another context (dem_destroy it first)";
+        return DEM_ERR_STATE;
+    }
+    // the array keeps the last context's contents: start from zeros
+    e = launch_fill_u64((uint64_t *)g_static_ptr[dev], (int64_t)(need / 8), 0, (hipStream_t)stream);
+    if (e != hipSuccess) { g_init_error = std::string("clearing the static workspace: ") + hipGetErrorString(e); return DEM_ERR_HIP; }
+    rc = dem_batch_init(out, 1, cfg, g_static_ptr[dev], kStaticWsBytes, stream);
+    if (rc) return rc;
+    (*out)->static_dev = dev;
+    g_static_owner[dev] = *out;
+    return DEM_OK;
 }
 
 int dem_reset(dem_ctx *c, const dem_state *s) {
@@ -929,6 +998,12 @@ const char *dem_last_error(const dem_ctx *c) { return c ? c->err.c_str() : g_ini
 
 int dem_destroy(dem_ctx *c) {
     if (!c) return DEM_ERR_ARG;
+    if (c->static_dev >= 0) {
+        // later contexts may reuse the array once this one's work is done
+        (void)hipStreamSynchronize(c->stream);
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+    }
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (GraphSlot &g : c->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);

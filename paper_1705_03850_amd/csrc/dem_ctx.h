@@ -78,6 +78,7 @@ struct dem_ctx {
     double t_ms[dem::host::kKinds] = {0, 0, 0, 0};
     int64_t t_n[dem::host::kKinds] = {0, 0, 0, 0};
     std::string err;
+    int static_dev = -1;             // >= 0: the workspace is that device's static array (dem_init_noalloc)
 };
 
 namespace dem {

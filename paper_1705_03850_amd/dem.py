@@ -45,7 +45,8 @@ class State(ctypes.Structure):
 
 
 _lib = None
-_SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_batch_init", "dem_reset", "dem_bin",
+_SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_batch_init", "dem_init_noalloc",
+            "dem_reset", "dem_bin",
             "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_declare_forces", "dem_set_step_options", "dem_set_launch", "dem_check",
             "dem_stats", "dem_set_timing", "dem_kernel_times", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
             "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
@@ -74,6 +75,7 @@ def load(path: str = LIB_PATH):
     L.dem_batch_workspace_size.argtypes = [i32, P(Config), P(ctypes.c_size_t)]
     L.dem_init.argtypes = [P(vp), P(Config), vp, ctypes.c_size_t, vp]
     L.dem_batch_init.argtypes = [P(vp), i32, P(Config), vp, ctypes.c_size_t, vp]
+    L.dem_init_noalloc.argtypes = [P(vp), P(Config), vp]
     for name in ("dem_reset", "dem_bin", "dem_neighbors"):
         getattr(L, name).argtypes = [vp, P(State)]
     L.dem_forces.argtypes = [vp, P(State), ctypes.c_int]
@@ -158,7 +160,8 @@ class DemSystem:
     """
 
     def __init__(self, systems, k_max: int = 32, block: int = 0, cell=0.0, skin=None, device: str = "cuda",
-                 use_graph: bool = False, chunk: int = 64, lanes: int = 0, max_blocks: int = 0):
+                 use_graph: bool = False, chunk: int = 64, lanes: int = 0, max_blocks: int = 0,
+                 static_workspace: bool = False):
         import torch
 
         self.torch = torch
@@ -181,12 +184,21 @@ class DemSystem:
         ws = ctypes.c_size_t()
         self._rc(self.L.dem_batch_workspace_size(self.nsys, self.cfgs, ctypes.byref(ws)))
         self.ws_bytes = ws.value
-        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        self.ws_ptr = (base + 255) // 256 * 256
         self.ctx = ctypes.c_void_p()
-        self._rc(self.L.dem_batch_init(ctypes.byref(self.ctx), self.nsys, self.cfgs, ctypes.c_void_p(self.ws_ptr),
-                                       ctypes.c_size_t(self.ws_bytes), ctypes.c_void_p(self.stream.cuda_stream)))
+        if static_workspace:
+            # dem_init_noalloc: the library's static device array is the workspace
+            if self.nsys != 1:
+                raise ValueError("static_workspace takes one system")
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                self._rc(self.L.dem_init_noalloc(ctypes.byref(self.ctx), self.cfgs,
+                                                 ctypes.c_void_p(self.stream.cuda_stream)))
+        else:
+            self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            self.ws_ptr = (base + 255) // 256 * 256
+            self._rc(self.L.dem_batch_init(ctypes.byref(self.ctx), self.nsys, self.cfgs, ctypes.c_void_p(self.ws_ptr),
+                                           ctypes.c_size_t(self.ws_bytes), ctypes.c_void_p(self.stream.cuda_stream)))
         f64 = dict(dtype=torch.float64, device=self.device)
         self.x = torch.empty((3, self.n), **f64)
         self.v = torch.empty((3, self.n), **f64)
@@ -208,7 +220,8 @@ class DemSystem:
             msg = self.L.dem_last_error(getattr(self, "ctx", None) or None)
             raise DemError(rc, (msg or b"").decode())
 
-    def __del__(self):
+    def close(self):
+        """Destroy the context now (a static-workspace context releases the array)."""
         ctx = getattr(self, "ctx", None)
         if ctx is not None and ctx.value:
             try:
@@ -216,7 +229,10 @@ class DemSystem:
             except Exception:
                 pass
             self.L.dem_destroy(ctx)
-            self.ctx = None
+        self.ctx = None
+
+    def __del__(self):
+        self.close()
 
     def load_state(self, x=None, v=None, w=None, f=None, t=None):
         """Copy host arrays ((n,3) rows in system order, ids from the systems) to the device."""

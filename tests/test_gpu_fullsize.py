@@ -1,18 +1,28 @@
 """Parity at the workloads' full sizes, in the launch configuration bench.py
 times (4 lanes per particle, 256-thread blocks, resident grid, graph replay).
 
-  * 1e6-sphere settled bed: forces of the first evaluation against the oracle,
-    every particle (1e-12 of the sum of its contact-force magnitudes); 10
-    steps against the oracle's 10 steps (positions within 1e-9 of the box);
-    graph replay of 64-step groups bit for bit equal to launch-by-launch
+  * 1e6-sphere settled bed: the neighbour list of all spheres bit for bit
+    equal to the oracle's grid pairs; forces of the first evaluation against
+    the oracle, every particle (1e-12 of the sum of its contact-force
+    magnitudes); 10 steps against the oracle's 10 steps and 100 steps against
+    a seeded sample of the oracle's 100 steps (positions within 1e-9 of the
+    box); graph replay of 64-step groups bit for bit equal to launch-by-launch
     stepping over 130 steps.
   * two-level chute (2e5 + 5e5 spheres): the 2-system batch bit for bit
-    equal to each system stepped alone.
+    equal to each system stepped alone, and each system against the oracle
+    over 10 steps.
+  * 64-system batch (3.8e6 spheres): bit for bit equal to each system stepped
+    alone over 300 steps (with list rebuilds), and two systems against the
+    oracle.
   * 5e4-sphere adjoint chute: 40 steps against the oracle's dual-number
     tangent (1e-9), with and without list rebuilds between windows, and in
-    kept mode; the 200-step flux-loss gradient independent of the window
-    length, and kept mode bit for bit equal to recomputation.
+    kept mode; the 200-step, 10-window flux-loss gradient against the
+    oracle's tangent (1e-9), independent of the window length, kept mode bit
+    for bit equal to recomputation, and central differences.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -38,6 +48,9 @@ def dem():
 @pytest.fixture(scope="module")
 def bed():
     return W.settled_bed()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def bench_system(s, **kw):
@@ -93,6 +106,54 @@ def test_full_bed_ten_steps_against_oracle(bed):
     assert np.max(np.abs(d)) <= 1e-9 * L
 
 
+def directed(lo, hi):
+    a = np.concatenate([lo, hi]); b = np.concatenate([hi, lo])
+    order = np.lexsort((b, a))
+    return a[order], b[order]
+
+
+def test_full_bed_list_bitexact_against_oracle(bed):
+    """All 1e6 rows: every directed pair within the cut-off r_i + r_j + skin,
+    against the oracle's grid search on the same state."""
+    s = bed
+    g = bench_system(s)
+    g.build_list()
+    a, b = g.export_neighbors()
+    o = O.Oracle(s)
+    lo, hi = o.pairs(s.skin, brute=False)
+    ea, eb = directed(lo, hi)
+    assert len(a) > 6_000_000
+    assert np.array_equal(a, ea) and np.array_equal(b, eb)
+
+
+def test_full_bed_hundred_steps_against_oracle_sample(bed):
+    """100 steps (bench launch configuration, graph replay) against the oracle's
+    100 steps at 2,000 seeded spheres (tests/golden/make_bed_hundred_steps.py):
+    positions within 1e-9 of the box (minimum image across the periodic
+    seams), and every position inside the periodic footprint."""
+    import hashlib
+    with open(os.path.join(GOLDEN, "bed_hundred_steps.json")) as fh:
+        gold = json.load(fh)
+    h = hashlib.sha256()
+    for arr in (bed.x, bed.r, bed.id):
+        h.update(np.ascontiguousarray(arr).tobytes())
+    assert h.hexdigest()[:32] == gold["bed_digest"], "the bed generator's output differs from the golden input"
+    s = bed
+    g = bench_system(s)
+    g.prime()
+    g.step(gold["steps"])
+    st = g.host()
+    L = s.hi[0] - s.lo[0]
+    assert np.all(st["x"][:, :2] >= s.lo[0]) and np.all(st["x"][:, :2] < s.hi[0])
+    ids = np.array(gold["ids"])
+    assert np.array_equal(st["id"][ids], ids)           # host() rows are in id order, ids 0..n-1
+    d = st["x"][ids] - np.array(gold["x"])
+    d[:, :2] -= L * np.round(d[:, :2] / L)
+    assert np.max(np.abs(d)) <= 1e-9 * L, np.max(np.abs(d))
+    dv = np.abs(st["v"][ids] - np.array(gold["v"]))
+    assert np.max(dv) <= 1e-9 * np.abs(np.array(gold["v"])).max(), np.max(dv)
+
+
 def test_full_bed_graph_replay_bitwise(bed):
     s = bed
     g1 = bench_system(s)
@@ -122,6 +183,69 @@ def test_two_level_chute_batch_equals_separate():
         sel = (hb["id"] >= off) if k else (hb["id"] < off)
         for key in ("x", "v", "w", "f", "t"):
             assert np.array_equal(hb[key][sel], h[key]), (k, key)
+
+
+def test_two_level_chute_against_oracle():
+    """Both systems of the two-level chute at full size (2e5 spheres at alpha = 4,
+    5e5 at alpha = 1), stepped as one batch in the bench configuration, against
+    the oracle: 10 steps, positions within 1e-9 of the largest box edge."""
+    systems = W.chute_two_level()
+    g = dem().DemSystem(systems, use_graph=True, chunk=64)
+    g.prime()
+    g.step(10)
+    hb = g.host()
+    for k, s in enumerate(systems):
+        o = O.Oracle(s)
+        o.forces(False)
+        o.step(10)
+        X = by_id(s, o.state()["x"])
+        sl = slice(int(g.offsets[k]), int(g.offsets[k + 1]))
+        d = hb["x"][sl] - X
+        for ax in (0, 1):
+            Lk = s.hi[ax] - s.lo[ax]
+            d[:, ax] -= Lk * np.round(d[:, ax] / Lk)
+        assert np.max(np.abs(d)) <= 1e-9 * max(s.hi[a] - s.lo[a] for a in range(3)), (k, np.max(np.abs(d)))
+
+
+def test_full_batch_of_64_systems():
+    """The 64-system batch at full size (3.8e6 spheres, alpha 1-8, dt = alpha
+    1e-6 s): 300 steps with graph replay equal bit for bit to every system
+    stepped alone, with a skin of 0.002 r_max so that single systems rebuild
+    their lists inside the batch (the settling beds move a few micrometres),
+    and the smallest and the largest system against the oracle over 20
+    steps."""
+    systems = W.batch_systems()
+    assert len(systems) == 64 and sum(s.n for s in systems) > 3_000_000
+    skins = [0.002 * float(s.r.max()) for s in systems]
+    bg = dem().DemSystem(systems, use_graph=True, chunk=64, skin=skins)
+    bg.prime()
+    bg.step(300)
+    assert bg.stats()["builds"] >= 3                          # the first build of all, then rebuilds
+    hb = bg.host()
+    for k, s in enumerate(systems):
+        g = dem().DemSystem(s, use_graph=True, chunk=64, skin=skins[k])
+        g.prime()
+        g.step(300)
+        h = g.host()
+        sl = slice(int(bg.offsets[k]), int(bg.offsets[k + 1]))
+        for key in ("x", "v", "w", "f", "t"):
+            assert np.array_equal(hb[key][sl], h[key]), (k, key)
+        del g
+    sizes = [s.n for s in systems]
+    for k in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        s = systems[k]
+        g = dem().DemSystem(s, use_graph=True, chunk=64)
+        g.prime()
+        g.step(20)
+        h = g.host()
+        o = O.Oracle(s)
+        o.forces(False)
+        o.step(20)
+        d = h["x"] - by_id(s, o.state()["x"])
+        for ax in (0, 1):
+            Lk = s.hi[ax] - s.lo[ax]
+            d[:, ax] -= Lk * np.round(d[:, ax] / Lk)
+        assert np.max(np.abs(d)) <= 1e-9 * max(s.hi[a] - s.lo[a] for a in range(3)), (k, np.max(np.abs(d)))
 
 
 def device_by_id(g, a_by_id):
@@ -161,18 +285,27 @@ def test_full_adjoint_chute_against_oracle_tangent(skin, keep):
 
 
 def test_full_adjoint_chute_200_steps():
-    """The calibration objective at full size: 200 steps, flux loss.  Windows
-    of 20 and of 50 give the same gradient (1e-12) and bit-identical
-    initial-state adjoints, kept mode at window 50 the same gradient bit for
-    bit; central differences of the rollout (h = 1e-7
-    relative) agree within 5e-2 -- at this size the loss has many kinks
-    (contact onsets, Coulomb switches), and differences scatter by 1e-4 to
-    1e-2 whatever the step, which is why the exact check is the one above."""
+    """The calibration objective at full size: 200 steps in 10 windows of 20,
+    flux loss against the seeded target (tests/golden/chute_flux_target.json).
+    The gradient with respect to E, e and mu of both types equals the oracle's
+    dual-number tangent chained through the same loss
+    (tests/golden/make_chute_flux_gradient.py) to 1e-9.  Windows of 50 give
+    the same gradient (1e-12) and bit-identical initial-state adjoints; kept
+    mode at window 50 the same gradient bit for bit.  Central differences of
+    the rollout at h = 1e-6 relative agree with the gradient within the bounds
+    listed per parameter (see DIFF_TOL): the loss has many kinks at this size
+    (contact onsets, Coulomb switches inside the difference step), so the
+    exact check is the tangent one."""
     from paper_1705_03850_amd import rollout as R
+    with open(os.path.join(GOLDEN, "chute_flux_target.json")) as fh:
+        tgt = json.load(fh)
+    with open(os.path.join(GOLDEN, "chute_flux_gradient.json")) as fh:
+        gold = json.load(fh)
     s = W.chute_adjoint()
-    nsteps = 200
+    nsteps = tgt["steps"]
     H0, Lx, Ly = s.meta["H0"], s.hi[0] - s.lo[0], s.hi[1] - s.lo[1]
-    target = torch.zeros(20, dtype=torch.float64, device="cuda")
+    assert H0 == tgt["H0"] == gold["H0"]
+    target = torch.tensor(tgt["target_flux"], dtype=torch.float64, device="cuda")
     g = dem().DemSystem(s)
     res = []
     for window, keep in ((20, False), (50, False), (50, True)):
@@ -181,9 +314,16 @@ def test_full_adjoint_chute_200_steps():
         x, v, w = R.rollout(theta, adj, (s.x, s.v, s.w))
         loss = ((R.mass_flux_profile(x, v, R.masses(g), H0, Lx, Ly) - target) ** 2).mean()
         loss.backward()
+        if window == 20:
+            assert adj.info()["windows"] == 10, adj.info()
+            assert abs(float(loss) - gold["loss"]) <= 1e-9 * gold["loss"]
         res.append((theta.grad.numpy().copy(), adj, adj.initial_by_id(adj.last)))
     g20, g50 = res[0][0], res[1][0]
-    assert np.all(np.abs(g20 - g50) <= 1e-12 * np.abs(g20).max())
+    ref = np.array([gold["grad"]["E"], gold["grad"]["e"], gold["grad"]["mu"]])
+    for row in range(3):
+        for t in range(2):
+            assert abs(g20[row, t] - ref[row, t]) <= 1e-9 * abs(ref[row, t]), (row, t, g20[row, t], ref[row, t])
+    assert np.all(np.abs(g20 - g50) <= 1e-12 * np.abs(g20))
     for k in ("x0", "v0", "w0"):
         assert np.array_equal(res[0][2][k], res[1][2][k]), k
         assert np.array_equal(res[1][2][k], res[2][2][k]), ("keep", k)
@@ -197,11 +337,23 @@ def test_full_adjoint_chute_200_steps():
             xx, vv, ww = R.rollout(torch.from_numpy(q), adj, (s.x, s.v, s.w))
             return float(((R.mass_flux_profile(xx, vv, R.masses(g), H0, Lx, Ly) - target) ** 2).mean())
 
-    for row in range(3):
+    errs = {}
+    for row, name in enumerate(("E", "e", "mu")):
         for t in range(2):
-            h = 1e-7 * th[row, t]
+            h = 1e-6 * th[row, t]
             qp, qm = th.copy(), th.copy()
             qp[row, t] += h
             qm[row, t] -= h
             fd = (L(qp) - L(qm)) / (2 * h)
-            assert abs(fd - g20[row, t]) <= 5e-2 * abs(g20[row, t]), (row, t, fd, g20[row, t])
+            errs[(name, t)] = abs(fd - g20[row, t]) / abs(g20[row, t])
+    print("central differences, relative error per parameter:", {f"{k[0]}{k[1]}": f"{v:.1e}" for k, v in errs.items()})
+    for (name, t), err in errs.items():
+        assert err <= DIFF_TOL[name], (name, t, err)
+
+
+# central differences (h = 1e-6 relative) of the 200-step flux loss against the
+# exact gradient, per parameter.  Measured on the MI355X (deterministic, so the
+# same every run): E of the two types 9.3e-4 and 6.9e-3, e 5.8e-3 and 9.3e-2,
+# mu 1.8e-3 and 1.3e-1 -- the second type (e = 0.7, mu = 0.3) has the most
+# contacts that switch between sticking and sliding inside the difference step.
+DIFF_TOL = {"E": 2e-2, "e": 2e-1, "mu": 2.5e-1}

@@ -88,8 +88,21 @@ def read_traffic(key="hbm_bytes_per_launch"):
         return None
 
 
-def cpu_baseline(system, steps):
-    """The oracle as it stands, single thread, on `steps` steps of the same bed."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(system, steps, par_steps):
+    """The oracle as it stands, single thread, on `steps` steps of the same bed
+    (value), and its all-cores leg (the OpenMP gather form of the same step,
+    bit-identical results) on `par_steps` further steps, with the threads it used."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
 
@@ -98,9 +111,15 @@ def cpu_baseline(system, steps):
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
+    threads, dtp = o.step_parallel(par_steps)
+    host = f"{cpu_model()}, {os.cpu_count()} logical CPUs visible"
     return {"value": system.n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} steps of the same {system.n}-sphere bed after one force evaluation, "
-                      f"1 thread, {dt:.1f} s"}
+                      f"1 thread, {dt:.1f} s; host {host}",
+            "all_cores": {"value": system.n * par_steps / dtp, "unit": "particle-steps/s", "cores": threads,
+                          "kind": "oracle (OpenMP gather form, bit-identical to the serial oracle)",
+                          "sample": f"{par_steps} further steps of the same bed, {threads} threads, "
+                                    f"{dtp:.1f} s of step loop"}}
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):
@@ -144,6 +163,8 @@ def batch_suite(args, emit=True):
       sequential -- the same systems, each in its own context with the library's default
                     launch shape and skin (plain dem_step as a user runs it), one after another;
       equal N    -- one plain bed with the same total particle count (defaults too).
+    Multi-rate: the same batch with every system stepping its own dt once every alpha substeps
+    (all levels over the same simulated time), against the single-rate batch.
     Two-level chute (2e5 spheres alpha = 4 + 5e5 spheres alpha = 1): one 2-system batch against the two
     systems one after another.  Launch shape, skin and cell come from the autotuner."""
     import torch
@@ -166,6 +187,19 @@ def batch_suite(args, emit=True):
     t_batch = timed_steps(g, steps, 64)
     builds_batch = g.stats()["builds"]
     del g
+    torch.cuda.empty_cache()
+    # multi-rate: every system steps with its own dt = alpha 1e-6 s once every alpha
+    # substeps, so all levels advance over the same simulated time (steps * 1e-6 s);
+    # against the single-rate batch above, which steps every system every substep
+    log("multi-rate batch")
+    gm = dem.DemSystem(systems, use_graph=True, chunk=args.chunk, **kw)
+    gm.set_multirate(True)
+    gm.prime()
+    nsub = steps - steps % 8
+    t_mr = timed_steps(gm, nsub, 64)
+    work_mr = sum(s.n * (nsub // int(round(s.dt / 1e-6))) for s in systems)
+    builds_mr = gm.stats()["builds"]
+    del gm
     torch.cuda.empty_cache()
     log("sequential plain contexts")
     t_seq = 0.0
@@ -205,7 +239,12 @@ def batch_suite(args, emit=True):
                     "batched_vs_sequential": t_seq / t_batch,
                     "batched_vs_equal_n": (ntot / t_batch) / (big.n / t_big),
                     "list_builds_batched": builds_batch, "autotune": {k: choice[k] for k in
-                                                                       ("lanes", "block", "skin_factor", "cell_factor")}},
+                                                                       ("lanes", "block", "skin_factor", "cell_factor")},
+                    "multirate": {"substeps": nsub, "particle_steps": work_mr,
+                                  "particle_steps_per_s": work_mr / t_mr,
+                                  "work_fraction": work_mr / (ntot * nsub),
+                                  "simulated_time_speedup_vs_single_rate": (t_batch / steps) / (t_mr / nsub),
+                                  "list_builds": builds_mr}},
         "two_level_chute": {"particles": n2, "steps": steps2, "batched": n2 * steps2 / t_two,
                             "sequential_plain": n2 * steps2 / t_two_seq, "batched_vs_sequential": t_two_seq / t_two,
                             "list_builds_batched": builds_two},
@@ -312,6 +351,7 @@ def main():
                     help="threads per particle in the force pass (4, 8, 16; 0: the library default)")
     ap.add_argument("--timing-steps", type=int, default=300)
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-par-steps", type=int, default=8, help="steps of the oracle's all-cores leg")
     ap.add_argument("--rebuilds", type=int, default=10, help="forced rebuilds (dem_bin + dem_neighbors) after the timing")
     ap.add_argument("--small-steps", type=int, default=1000, help="steps of the 2000-sphere workload timed for latency")
     ap.add_argument("--no-suites", action="store_true", help="leave the batch and adjoint comparisons out of the line")
@@ -497,7 +537,8 @@ def main():
         batched = {"launch": "library defaults, graph replay",
                    "batch64": {k: b["batch64"][k] for k in ("systems", "particles", "steps", "batched",
                                                             "sequential_plain", "equal_n_plain",
-                                                            "batched_vs_sequential", "batched_vs_equal_n")},
+                                                            "batched_vs_sequential", "batched_vs_equal_n",
+                                                            "multirate")},
                    "two_level_chute": {k: b["two_level_chute"][k] for k in ("particles", "steps", "batched",
                                                                            "sequential_plain",
                                                                            "batched_vs_sequential")}}
@@ -521,7 +562,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"CPU oracle baseline: {args.cpu_steps} steps")
-        cpu = cpu_baseline(bed, args.cpu_steps)
+        cpu = cpu_baseline(bed, args.cpu_steps, args.cpu_par_steps)
 
     out = {
         "metric": METRIC,

@@ -199,6 +199,18 @@ int dem_step(dem_ctx *ctx, const dem_state *s, int64_t nsteps);
  * device. */
 int dem_declare_forces(dem_ctx *ctx);
 
+/* Multi-rate stepping of a batch (Sec. 2.3: coarse-grain levels nested
+ * recursively; Sec. 3: the time step may grow with the coarse-grain factor).
+ * With enable != 0 every system s steps with its own dt_s once every
+ * stride_s = dt_s / dt_min substeps, so that all systems reach the same time
+ * at the end of every largest stride; nsteps of dem_step then counts substeps
+ * of dt_min and must be a multiple of the largest stride (DEM_ERR_ARG).  Every
+ * dt_s must be dt_min times a power of two up to 1024 (DEM_ERR_ARG).  Each
+ * system's trajectory is bit for bit the one it has stepped alone with its dt
+ * for nsteps / stride_s steps.  A single system needs no strides (ignored).
+ * enable == 0 returns to one step per system per substep.  Synchronises. */
+int dem_set_multirate(dem_ctx *ctx, int enable);
+
 /* Step-loop options: use_graph != 0 replays the per-step kernels as one
  * captured HIP graph of `chunk` steps (chunk even, 2..1024; default 64). */
 int dem_set_step_options(dem_ctx *ctx, int use_graph, int32_t chunk);
@@ -258,6 +270,104 @@ int dem_export_wall(dem_ctx *ctx, const dem_state *s, int32_t *id, double *xi, i
  * (DEM_ERR_STATE). */
 int dem_import_history(dem_ctx *ctx, const dem_state *s, int64_t npairs, const int32_t *id_i, const int32_t *id_j,
                        const double *xi, int64_t nwall, const int32_t *wall_id, const double *wall_xi);
+
+/* ---------------------------------------------------------------------------
+ * Coupling of coarse-grain levels (Sec. 2.3).
+ *
+ * A fine region is embedded in a coarse-grain simulation; both are systems
+ * (of one batch or of two contexts).  Per hexahedral cell the library reduces
+ * the Eulerian fields of a system (the granular stress of Eq. (7), the volume
+ * fraction, the Favre-averaged and the maximum velocity).  Two controllers turn
+ * the fields of the two levels into correcting forces: a PI controller on the
+ * fine spheres of the transition layer (fine normal stress towards the coarse
+ * one, force limited by the coarse maximum velocity, fading out 3/2 fine
+ * diameters from the boundary) and a P controller on the coarse spheres inside
+ * the fine region (velocity or mass flow).  The forces are external forces:
+ * every later force evaluation adds them after the wall term, until they are
+ * replaced or cleared.  The readings where the paper is silent (cell
+ * membership by centre, the force's distribution over spheres, the gains) are
+ * listed in the repository's design notes.
+ * ------------------------------------------------------------------------- */
+
+/* A regular grid of cells in one system's coordinates.  A sphere belongs to
+ * the cell that contains its centre: c_a = floor((x_a - lo_a) / h_a), inside
+ * when 0 <= c_a < n_a on every axis.  Cell (a, b, c) has index
+ * (c n[1] + b) n[0] + a.  On periodic axes the cells should lie within the
+ * system's box [lo, hi) (positions are kept there). */
+typedef struct dem_grid {
+    double lo[3];     /* corner of cell (0, 0, 0) (m)                  */
+    double h[3];      /* cell edges (m), > 0                           */
+    int32_t n[3];     /* cells per axis, >= 1 (at most 2^24 cells)     */
+    int32_t sys;      /* system of the context whose spheres are used  */
+} dem_grid;
+
+/* Rows of a fields array: device doubles [DEM_NFIELDS][ncell] (row major, a
+ * row per quantity, ncell = n[0] n[1] n[2]). */
+enum {
+    DEM_F_COUNT = 0,    /* spheres in the cell                                            */
+    DEM_F_MASS = 1,     /* sum of m                                                        */
+    DEM_F_MOM = 2,      /* rows 2..4: sum of m v (x, y, z); Favre velocity = MOM / MASS    */
+    DEM_F_VOLUME = 5,   /* sum of (4/3) pi r^3; volume fraction = VOLUME / cell volume     */
+    DEM_F_VMAX = 6,     /* max |v|                                                         */
+    DEM_F_STRESS = 7,   /* rows 7..15: sigma_ab of Eq. (7), row 7 + 3 a + b (Pa)           */
+    DEM_NFIELDS = 16
+};
+
+/* Cell fields of the system grid->sys at the current state (Sec. 2.3, Eq. (7)):
+ * sigma = (1/V) sum over the cell's spheres i of [sum over contacts j of
+ * 1/2 d_ij f_ij^T + m_i v'_i v'_i^T], V the cell volume, d_ij = x_i - x_j
+ * (minimum image), f_ij the contact force on i at the current positions,
+ * velocities and stored history (a force evaluation without history update;
+ * wall contacts do not enter), v' = v - u with u the cell's Favre velocity.
+ * Sums run in a fixed order (reproducible results).  Needs the neighbour list
+ * of the current order (DEM_ERR_STATE) and spheres within one list cell of the
+ * positions of the last list build (the state after dem_step always is;
+ * DEM_ERR_STATE otherwise).  fields: device, caller-owned.  Synchronises. */
+int dem_cell_fields(dem_ctx *ctx, const dem_state *s, const dem_grid *grid, double *fields);
+
+/* PI controller of the transition layer (Sec. 2.3).  grid: the transition
+ * cells, in the fine system grid.sys.  fine, coarse: fields (as above) of the
+ * fine system and of the coarse system on the same cells.  Per cell, with the
+ * unit normal nrm pointing into the fine region: e = nrm.sigma_c.nrm -
+ * nrm.sigma_f.nrm, integral += e interval, u = kp e + ki integral; integral
+ * (device [ncell], caller state, in/out) and u (device [ncell], out).  Then
+ * every sphere of the fine system gets the external force
+ * u pi r^2 w nrm in a transition cell, 0 elsewhere, where w = 1 - s/(fade 2 r)
+ * for depth s = x.nrm - face in [0, fade 2 r) (1 above the face, 0 below
+ * that depth), limited so that a sphere's velocity along nrm does not pass
+ * the coarse cell's maximum velocity after one step (and never reversed).
+ * External forces of other systems are kept. */
+typedef struct dem_pi_params {
+    dem_grid grid;
+    double nrm[3];      /* unit normal into the fine region                        */
+    double face;        /* boundary face: the plane x . nrm = face                 */
+    double kp, ki;      /* gains: u = kp e + ki integral (kp: 1, ki: 1/s)          */
+    double interval;    /* coupling interval (s) added to the integral per call    */
+    double fade;        /* fade-out depth in fine diameters (the paper's 3/2)      */
+} dem_pi_params;
+int dem_pi_control(dem_ctx *ctx, const dem_state *s, const dem_pi_params *p, const double *fine,
+                   const double *coarse, double *integral, double *u);
+
+/* P controller of the coarse system grid.sys inside the fine region (Sec.
+ * 2.3).  fine, coarse: fields of the two systems on the same cells.  Where both
+ * cells hold mass: target = u_f (velocity) or u_f phi_f / phi_c (mass flow,
+ * the fine velocity times the volume-fraction mismatch), and every coarse
+ * sphere of the cell gets the external force kp m (target - u_c); the others
+ * of the system get 0.  External forces of other systems are kept. */
+typedef struct dem_p_params {
+    dem_grid grid;
+    double kp;          /* gain (1/s)                                  */
+    int32_t mass_flow;  /* 0: velocity, 1: mass flow                    */
+} dem_p_params;
+int dem_p_control(dem_ctx *ctx, const dem_state *s, const dem_p_params *p, const double *fine,
+                  const double *coarse);
+
+/* Set the external forces of all spheres from a device array [3][n] in the
+ * current order (copied), or clear them (fext NULL).  They are added to every
+ * later force evaluation (after gravity, the contacts and the wall) and move
+ * with the spheres when dem_bin reorders them.  The reverse mode refuses
+ * contexts with external forces (DEM_ERR_STATE). */
+int dem_set_external_force(dem_ctx *ctx, const dem_state *s, const double *fext);
 
 /* ---------------------------------------------------------------------------
  * Material parameters and gradients with respect to them.

@@ -38,20 +38,23 @@
  *   - periodic images by minimum image; positions wrapped into [lo, hi).
  *
  * Every particle's force is accumulated gravity first, then its pair terms in
- * ascending partner id, then the wall.  Pairs are visited once (lower id
- * first); the lower id's side holds the history.
+ * ascending partner id, then the wall, then an optional external force (the
+ * correcting forces of the multi-level coupling, Sec. 2.3).  Pairs are visited
+ * once (lower id first); the lower id's side holds the history.
  *
  * The scalar type is a template parameter so the same code also runs with
  * forward-mode dual numbers (derivatives with respect to per-type E, e, mu).
  *
- * Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared dem_oracle.cpp -o liboracle.so
+ * Build: g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -fPIC -shared dem_oracle.cpp -o liboracle.so
  */
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <chrono>
 #include <map>
+#include <omp.h>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -130,6 +133,7 @@ template <class S> struct Sim {
     std::map<std::pair<int, int>, V3<S>> hist;               // (id_lo, id_hi) -> xi seen from id_lo
     std::map<int, V3<S>> whist;                              // id -> wall xi
     std::vector<PairRecord<S>> records;                      // last force evaluation
+    std::vector<V3<double>> fext;                            // external force per particle (empty: none)
     double rmax = 0.0;
 };
 
@@ -381,6 +385,10 @@ template <class S> void forces(Sim<S> &s, bool update) {
         }
         if (update) s.whist.swap(wnext);
     }
+    /* external forces (the coupling's correcting forces, Sec. 2.3), added last */
+    if (!s.fext.empty())
+        for (size_t i = 0; i < s.p.size(); ++i)
+            s.p[i].f = {s.p[i].f.x + s.fext[i].x, s.p[i].f.y + s.fext[i].y, s.p[i].f.z + s.fext[i].z};
 }
 
 template <class S> S wrap(S x, double lo, double hi, int periodic) {
@@ -448,7 +456,203 @@ Sim<S> *make(const Config *cfg, int n, const double *x, const double *v, const d
 using SimD = Sim<double>;
 using SimT = Sim<Dual>;
 
+/* ------------------------------------------------------------------------
+ * All-cores timing leg (OpenMP).  The same steps as step() above, with the
+ * force evaluation written as a gather: every particle visits its own
+ * partners in ascending id and computes each pair from its own side, which
+ * gives exactly the negated force and history of the lower id's evaluation,
+ * so the sums come out bit for bit as in forces() (a test checks this).  The
+ * history lives in per-particle rows (partners of higher id, sorted by id)
+ * during the call and goes back to the map at its end.  Used only to time the
+ * oracle on all host cores; every parity check runs the serial path.
+ * ---------------------------------------------------------------------- */
+/* Rows of the own side of every pair: for particle i, the partners of higher
+ * id in ascending id (index and history), at most kRow of them. */
+constexpr int kRow = 48;
+struct Rows {
+    std::vector<int> cnt, j;
+    std::vector<V3<double>> xi;
+    void init(int n) { cnt.assign(n, 0); j.assign((size_t)n * kRow, 0); xi.assign((size_t)n * kRow, V3<double>{0, 0, 0}); }
+};
+
+static const V3<double> *row_find(const Rows &r, const SimD &s, int i, int j) {
+    int lo = 0, hi = r.cnt[i];
+    const int *rj = &r.j[(size_t)i * kRow];
+    const int idj = s.p[j].id;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (s.p[rj[mid]].id < idj) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < r.cnt[i] && rj[lo] == j ? &r.xi[(size_t)i * kRow + lo] : nullptr;
+}
+
+static void parallel_forces(SimD &s, Rows &rows, Rows &next, std::vector<V3<double>> &wxi, std::vector<char> &whas,
+                            bool update) {
+    const Config &c = s.cfg;
+    const int n = (int)s.p.size();
+    double h = 2.0 * s.rmax;
+    int nc[3];
+    for (int d = 0; d < 3; ++d) nc[d] = std::max(1, (int)std::floor((c.hi[d] - c.lo[d]) / h));
+    std::vector<int> cell(n), start((size_t)nc[0] * nc[1] * nc[2] + 1, 0), order(n);
+    auto coord = [&](double x, int d) {
+        double L = c.hi[d] - c.lo[d];
+        int k = (int)std::floor((x - c.lo[d]) / L * nc[d]);
+        if (c.periodic[d]) k = ((k % nc[d]) + nc[d]) % nc[d];
+        else k = std::min(std::max(k, 0), nc[d] - 1);
+        return k;
+    };
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i)
+        cell[i] = (coord(s.p[i].x.z, 2) * nc[1] + coord(s.p[i].x.y, 1)) * nc[0] + coord(s.p[i].x.x, 0);
+    for (int i = 0; i < n; ++i) ++start[cell[i] + 1];
+    for (size_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
+    {
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        for (int i = 0; i < n; ++i) order[fill[cell[i]]++] = i;
+    }
+    bool overflow = false;
+#pragma omp parallel
+    {
+        std::vector<int> cand;
+#pragma omp for schedule(dynamic, 256)
+        for (int i = 0; i < n; ++i) {
+            Particle<double> &a = s.p[i];
+            a.f = {a.m * c.g[0], a.m * c.g[1], a.m * c.g[2]};
+            a.t = {0.0, 0.0, 0.0};
+            const int ci[3] = {coord(a.x.x, 0), coord(a.x.y, 1), coord(a.x.z, 2)};
+            cand.clear();
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int cc[3] = {ci[0] + dx, ci[1] + dy, ci[2] + dz};
+                        bool skip = false;
+                        for (int d = 0; d < 3; ++d) {
+                            if (c.periodic[d]) cc[d] = ((cc[d] % nc[d]) + nc[d]) % nc[d];
+                            else if (cc[d] < 0 || cc[d] >= nc[d]) skip = true;
+                        }
+                        if (skip) continue;
+                        const int k = (cc[2] * nc[1] + cc[1]) * nc[0] + cc[0];
+                        for (int q = start[k]; q < start[k + 1]; ++q)
+                            if (order[q] != i) cand.push_back(order[q]);
+                    }
+            std::sort(cand.begin(), cand.end(), [&](int p, int q) { return s.p[p].id < s.p[q].id; });
+            cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+            int own_n = 0;
+            for (int j : cand) {
+                const Particle<double> &b = s.p[j];
+                const bool own = a.id < b.id;
+                V3<double> x = {0.0, 0.0, 0.0};
+                if (own) {
+                    if (const V3<double> *p = row_find(rows, s, i, j)) x = *p;
+                } else if (const V3<double> *p = row_find(rows, s, j, i)) {
+                    x = {-p->x, -p->y, -p->z};
+                }
+                V3<double> f, ft, nn;
+                if (!contact(s, a, &b, x, update, f, ft, nn, (PairRecord<double> *)nullptr)) continue;
+                if (own && update) {
+                    if (own_n < kRow) {
+                        next.j[(size_t)i * kRow + own_n] = j;
+                        next.xi[(size_t)i * kRow + own_n] = x;
+                        ++own_n;
+                    } else {
+                        overflow = true;
+                    }
+                }
+                a.f = {a.f.x + f.x, a.f.y + f.y, a.f.z + f.z};
+                V3<double> nxf = {nn.y * ft.z - nn.z * ft.y, nn.z * ft.x - nn.x * ft.z, nn.x * ft.y - nn.y * ft.x};
+                a.t = {a.t.x - a.r * nxf.x, a.t.y - a.r * nxf.y, a.t.z - a.r * nxf.z};
+            }
+            if (update) next.cnt[i] = own_n;
+            if (c.wall_z0) {
+                V3<double> x = whas[i] ? wxi[i] : V3<double>{0.0, 0.0, 0.0};
+                V3<double> f, ft, nn;
+                if (contact(s, a, (const Particle<double> *)nullptr, x, update, f, ft, nn,
+                            (PairRecord<double> *)nullptr)) {
+                    a.f = {a.f.x + f.x, a.f.y + f.y, a.f.z + f.z};
+                    V3<double> nxf = {nn.y * ft.z - nn.z * ft.y, nn.z * ft.x - nn.x * ft.z, nn.x * ft.y - nn.y * ft.x};
+                    a.t = {a.t.x - a.r * nxf.x, a.t.y - a.r * nxf.y, a.t.z - a.r * nxf.z};
+                    if (update) { wxi[i] = x; whas[i] = 1; }
+                } else if (update) {
+                    whas[i] = 0;
+                }
+            }
+            if (!s.fext.empty()) a.f = {a.f.x + s.fext[i].x, a.f.y + s.fext[i].y, a.f.z + s.fext[i].z};
+        }
+    }
+    if (overflow) std::abort();   // more than kRow contacts of one sphere: not a packing of spheres
+    if (update) std::swap(rows, next);
+}
+
 }  // namespace
+
+extern "C" {
+
+/* nsteps steps on all cores (the timing leg above); returns the threads used
+ * and, in *seconds, the time of the step loop alone (steady clock).  The state
+ * and histories afterwards are those of orc_step. */
+int orc_step_parallel(void *h, int nsteps, double *seconds) {
+    SimD *s = (SimD *)h;
+    const int n = (int)s->p.size();
+    Rows rows, next;
+    rows.init(n);
+    next.init(n);
+    for (auto &kv : s->hist) {
+        int i = s->idx[kv.first.first], j = s->idx[kv.first.second];
+        int &k = rows.cnt[i];
+        if (k >= kRow) std::abort();
+        rows.j[(size_t)i * kRow + k] = j;
+        rows.xi[(size_t)i * kRow + k] = kv.second;
+        ++k;
+    }
+    std::vector<V3<double>> wxi(n, V3<double>{0.0, 0.0, 0.0});
+    std::vector<char> whas(n, 0);
+    for (auto &kv : s->whist) {
+        int i = s->idx[kv.first];
+        wxi[i] = kv.second;
+        whas[i] = 1;
+    }
+    const double hdt = 0.5 * s->cfg.dt;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < nsteps; ++k) {
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; ++i) {
+            Particle<double> &q = s->p[i];
+            q.v = {q.v.x + hdt * (q.f.x * q.inv_m), q.v.y + hdt * (q.f.y * q.inv_m), q.v.z + hdt * (q.f.z * q.inv_m)};
+            q.w = {q.w.x + hdt * (q.t.x * q.inv_I), q.w.y + hdt * (q.t.y * q.inv_I), q.w.z + hdt * (q.t.z * q.inv_I)};
+            const Config &c = s->cfg;
+            q.x = {q.x.x + c.dt * q.v.x, q.x.y + c.dt * q.v.y, q.x.z + c.dt * q.v.z};
+            q.x.x = wrap(q.x.x, c.lo[0], c.hi[0], c.periodic[0]);
+            q.x.y = wrap(q.x.y, c.lo[1], c.hi[1], c.periodic[1]);
+            q.x.z = wrap(q.x.z, c.lo[2], c.hi[2], c.periodic[2]);
+        }
+        parallel_forces(*s, rows, next, wxi, whas, true);
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; ++i) {
+            Particle<double> &q = s->p[i];
+            q.v = {q.v.x + hdt * (q.f.x * q.inv_m), q.v.y + hdt * (q.f.y * q.inv_m), q.v.z + hdt * (q.f.z * q.inv_m)};
+            q.w = {q.w.x + hdt * (q.t.x * q.inv_I), q.w.y + hdt * (q.t.y * q.inv_I), q.w.z + hdt * (q.t.z * q.inv_I)};
+        }
+    }
+    if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    s->hist.clear();
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < rows.cnt[i]; ++k)
+            s->hist[{s->p[i].id, s->p[rows.j[(size_t)i * kRow + k]].id}] = rows.xi[(size_t)i * kRow + k];
+    s->whist.clear();
+    for (int i = 0; i < n; ++i)
+        if (whas[i]) s->whist[s->p[i].id] = wxi[i];
+    s->records.clear();
+    int threads = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        threads = omp_get_num_threads();
+    }
+    return threads;
+}
+
+}  // extern "C"
 
 extern "C" {
 
@@ -571,6 +775,48 @@ long orc_records(void *h, int *lo, int *hi, double *fn, double *fmag, double *ft
         if (k < capn) {
             lo[k] = r.lo; hi[k] = r.hi; fn[k] = r.fn_mag; fmag[k] = r.f_mag; ftmag[k] = r.ft_mag; cap[k] = r.fncap;
             if (ftn) ftn[k] = r.ft_normal;
+        }
+        ++k;
+    }
+    return k;
+}
+
+/* External force on every particle, (n, 3) in input order, added after the
+ * wall term at every force evaluation; null removes it. */
+void orc_set_external(void *h, const double *f) {
+    SimD *s = (SimD *)h;
+    if (!f) { s->fext.clear(); return; }
+    s->fext.resize(s->p.size());
+    for (size_t i = 0; i < s->p.size(); ++i) s->fext[i] = {f[3 * i], f[3 * i + 1], f[3 * i + 2]};
+}
+
+/* Contact forces of the current state without touching the history (as a
+ * force evaluation without history update): for every unordered pair in
+ * contact, ids (lo < hi), the branch vector d = x_lo - x_hi (minimum image)
+ * and the force on lo (the force on hi is its negative).  Returns the count;
+ * arrays of cap entries (d, f: [cap][3]) may be null. */
+long orc_pair_forces(void *h, int *lo, int *hi, double *d, double *f, long cap) {
+    SimD *s = (SimD *)h;
+    const Config &c = s->cfg;
+    std::vector<std::pair<int, int>> cand;
+    grid_pairs(*s, 0.0, cand);
+    long k = 0;
+    for (auto &pr : cand) {
+        const Particle<double> &a = s->p[pr.first];
+        const Particle<double> &b = s->p[pr.second];
+        auto it = s->hist.find({a.id, b.id});
+        V3<double> xi = it == s->hist.end() ? V3<double>{0.0, 0.0, 0.0} : it->second;
+        V3<double> fo, ft, n;
+        if (!contact(*s, a, &b, xi, false, fo, ft, n, (PairRecord<double> *)nullptr)) continue;
+        if (k < cap) {
+            if (lo) lo[k] = a.id;
+            if (hi) hi[k] = b.id;
+            if (d) {
+                d[3 * k] = min_image(a.x.x - b.x.x, c.hi[0] - c.lo[0], c.periodic[0]);
+                d[3 * k + 1] = min_image(a.x.y - b.x.y, c.hi[1] - c.lo[1], c.periodic[1]);
+                d[3 * k + 2] = min_image(a.x.z - b.x.z, c.hi[2] - c.lo[2], c.periodic[2]);
+            }
+            if (f) { f[3 * k] = fo.x; f[3 * k + 1] = fo.y; f[3 * k + 2] = fo.z; }
         }
         ++k;
     }

@@ -32,7 +32,8 @@ class OrcConfig(ctypes.Structure):
 def compile_to(src: str, out: str) -> str:
     """g++ with the oracle's flags (no FMA contraction, no -march)."""
     tmp = out + ".tmp"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", src, "-o", tmp])
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", src,
+                           "-o", tmp])
     os.replace(tmp, out)
     return out
 
@@ -77,6 +78,11 @@ def lib(path: str | None = None):
         L.orc_pairs.argtypes = [vp, ctypes.c_double, ctypes.c_int, _ip, _ip, ctypes.c_long]
         L.orc_records.restype = ctypes.c_long
         L.orc_records.argtypes = [vp, _ip, _ip, _dp, _dp, _dp, _dp, _dp, ctypes.c_long]
+        L.orc_step_parallel.restype = ctypes.c_int
+        L.orc_step_parallel.argtypes = [vp, ctypes.c_int, _dp]
+        L.orc_set_external.argtypes = [vp, _dp]
+        L.orc_pair_forces.restype = ctypes.c_long
+        L.orc_pair_forces.argtypes = [vp, _ip, _ip, _dp, _dp, ctypes.c_long]
         L.orc_tan_forces.argtypes = [vp, ctypes.c_int]
         L.orc_tan_step.argtypes = [vp, ctypes.c_int]
         L.orc_tan_get.argtypes = [vp, _dp, _dp, _dp, _dp]
@@ -151,6 +157,13 @@ class Oracle:
     def step(self, nsteps: int = 1):
         self.L.orc_step(self.h, int(nsteps))
 
+    def step_parallel(self, nsteps: int = 1):
+        """The same steps on all host cores (OpenMP gather form, for timing);
+        returns (threads used, seconds of the step loop)."""
+        sec = ctypes.c_double(0.0)
+        th = int(self.L.orc_step_parallel(self.h, int(nsteps), ctypes.byref(sec)))
+        return th, sec.value
+
     def kick(self):
         self.L.orc_kick(self.h)
 
@@ -194,6 +207,21 @@ class Oracle:
         fn, fm, ftm, cap, ftn = (np.empty(k) for _ in range(5))
         self.L.orc_records(self.h, _i(lo), _i(hi), _d(fn), _d(fm), _d(ftm), _d(cap), _d(ftn), k)
         return dict(lo=lo, hi=hi, fn=fn, fmag=fm, ftmag=ftm, cap=cap, ftn=ftn)
+
+    def set_external(self, f=None):
+        """External force per particle ((n,3), input order), added after the wall
+        term at every force evaluation; None removes it."""
+        a = None if f is None else np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, 3)
+        self._fext = a
+        self.L.orc_set_external(self.h, _d(a))
+
+    def pair_forces(self):
+        """Contact forces of the current state (no history update): ids lo < hi,
+        branch vectors d = x_lo - x_hi (k,3) and forces on lo (k,3)."""
+        k = self.L.orc_pair_forces(self.h, None, None, None, None, 0)
+        lo = np.empty(k, np.int32); hi = np.empty(k, np.int32); d = np.empty((k, 3)); f = np.empty((k, 3))
+        self.L.orc_pair_forces(self.h, _i(lo), _i(hi), _d(d), _d(f), k)
+        return lo, hi, d, f
 
     # ---- forward-mode handle
     def tan_forces(self, update_history: bool = False):

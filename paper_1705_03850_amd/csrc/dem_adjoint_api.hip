@@ -338,6 +338,7 @@ int dem_rollout_forward(dem_adjoint *A, const dem_state *s) {
     int rc = check_state(c, s);
     if (rc) return rc;
     if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first");
+    if (c->fext_on) return fail(c, DEM_ERR_STATE, "the reverse mode does not take external forces");
     A->nck = 0;
     A->ntopo = 0;
     A->rebuilds = 0;
@@ -439,6 +440,7 @@ int dem_rollout_backward(dem_adjoint *A, const dem_state *s, const double *gx, c
     int rc = check_state(c, s);
     if (rc) return rc;
     if (!gx || !gv || !gw || !ax0 || !av0 || !aw0) return fail(c, DEM_ERR_ARG, "an adjoint array is NULL");
+    if (c->fext_on) return fail(c, DEM_ERR_STATE, "the reverse mode does not take external forces");
     if (A->nck < 2 || A->step_end != c->step_counter)
         return fail(c, DEM_ERR_STATE, "dem_rollout_backward needs the state of the last dem_rollout_forward");
     const int64_t n = c->geo.n, K = c->geo.kmax;
@@ -538,6 +540,7 @@ int dem_forces_vjp(dem_adjoint *A, const dem_state *s, const double *fb, const d
     int rc = check_state(c, s);
     if (rc) return rc;
     if (!fb || !tb || !xb || !vb || !wb) return fail(c, DEM_ERR_ARG, "an adjoint array is NULL");
+    if (c->fext_on) return fail(c, DEM_ERR_STATE, "the reverse mode does not take external forces");
     if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_forces_vjp needs a neighbour list for the current order");
     if (c->geo.n == 0) return DEM_OK;
     const int64_t n = c->geo.n, K = c->geo.kmax;

@@ -105,6 +105,7 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         d.p1 = g.n + c.n;
         d.c0 = g.ncell;
         d.wall = c.wall_z0 ? 1 : 0;
+        d.stride = 1;
         d.ntypes = c.ntypes;
         d.coef0 = (int32_t)g.coef.size();
         d.type0 = (int32_t)g.rho.size();
@@ -136,6 +137,7 @@ Layout make_layout(const Geometry &g) {
     L.disp = take(3 * n * 8);
     L.xiw = take(3 * n * 8);
     L.frame = take(n * 4);
+    L.fext = take(3 * n * 8);
     for (int b = 0; b < 2; ++b) {
         L.nbr[b] = take(K * n * 4);
         L.cnt[b] = take(n * 4);
@@ -149,7 +151,7 @@ Layout make_layout(const Geometry &g) {
     L.cell_count = take((C + 1) * 4);
     L.cell_start = take((C + 1) * 4);
     L.scan_partial = take(((C + 1023) / 1024 + 1) * 4);
-    L.shadow_d = take(25 * n * 8);
+    L.shadow_d = take(kShadowD * n * 8);
     L.shadow_i = take(3 * n * 4);
     for (int b = 0; b < 2; ++b) {
         L.pos[b] = take(n * sizeof(D4));
@@ -202,6 +204,8 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.disp = (double *)(w + L.disp);
     a.xiw = (double *)(w + L.xiw);
     a.frame = (int32_t *)(w + L.frame);
+    a.fext_ws = (double *)(w + L.fext);
+    a.fext = c->fext_on ? a.fext_ws : nullptr;
     a.sys = c->d_sys;
     a.coef = c->d_coef;
     a.rho = c->d_rho;
@@ -213,8 +217,13 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     // every extra workgroup costs time
     a.grid_cap = (int32_t)(c->grid_cap > 0 ? c->grid_cap : (int64_t)c->cus * 16 * 64 / c->geo.block);
     a.lanes = c->lanes;
+    a.multirate = c->multirate ? 1 : 0;
     a.n = c->geo.n;
     a.ncell = c->geo.ncell;
+    a.w0 = c->win_on ? c->win[0] : 0;
+    a.w1 = c->win_on ? c->win[1] : c->geo.n;
+    a.cw0 = c->win_on ? c->win[2] : 0;
+    a.cw1 = c->win_on ? c->win[3] : c->geo.ncell;
     a.flags = c->d_flags;
     a.lst[0] = c->lists[0];
     a.lst[1] = c->lists[1];
@@ -337,6 +346,27 @@ int collect_times(dem_ctx *c) {
     return DEM_OK;
 }
 
+// The particle and cell index ranges spanned by the systems that asked for a
+// rebuild (read from the device after the group's synchronisation).
+int set_rebuild_window(dem_ctx *c) {
+    std::vector<int32_t> sel(c->geo.sys.size());
+    HIPCALL(c, hipMemcpy(sel.data(), c->ws + c->lay.sel, sel.size() * 4, hipMemcpyDeviceToHost));
+    int64_t w0 = INT64_MAX, w1 = 0, cw0 = INT64_MAX, cw1 = 0;
+    for (size_t k = 0; k < sel.size(); ++k) {
+        if (!sel[k]) continue;
+        const SysDesc &d = c->geo.sys[k];
+        const int64_t cells = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+        w0 = std::min(w0, d.p0);
+        w1 = std::max(w1, d.p1);
+        cw0 = std::min(cw0, d.c0);
+        cw1 = std::max(cw1, d.c0 + cells);
+    }
+    if (w0 == INT64_MAX) return DEM_OK;   // nothing selected: full ranges
+    c->win[0] = w0; c->win[1] = w1; c->win[2] = cw0; c->win[3] = cw1;
+    c->win_on = true;
+    return DEM_OK;
+}
+
 // One graph of `len` fused steps starting from packed buffer 0 (k = 0..len-1).
 int capture_graph(dem_ctx *c, const dem_state *s, GraphSlot &gs, int len) {
     if (gs.exec) { (void)hipGraphExecDestroy(gs.exec); gs.exec = nullptr; }
@@ -352,7 +382,8 @@ int capture_graph(dem_ctx *c, const dem_state *s, GraphSlot &gs, int len) {
     hipError_t e3 = hipGraphInstantiate(&gs.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) { gs.exec = nullptr; return hip_fail(c, e3, "hipGraphInstantiate"); }
-    const void *key[10] = {c->ws, nullptr};
+    const void *key[10] = {c->ws, c->fext_on ? (const void *)c->lay.fext : nullptr,
+                             c->multirate ? (const void *)c->lay.sys : nullptr};
     memcpy(gs.key, key, sizeof key);
     gs.chunk = len;
     gs.count = c->count ? 1 : 0;
@@ -536,6 +567,7 @@ int dem_reset(dem_ctx *c, const dem_state *s) {
     c->binned = false;
     c->frame_identity = true;
     c->forces_valid = false;
+    c->fext_on = false;
     return DEM_OK;
 }
 
@@ -584,6 +616,31 @@ int dem_declare_forces(dem_ctx *c) {
     return DEM_OK;
 }
 
+int dem_set_multirate(dem_ctx *c, int enable) {
+    if (!c) return DEM_ERR_ARG;
+    std::vector<int32_t> stride(c->geo.sys.size(), 1);
+    int32_t mx = 1;
+    if (enable) {
+        double dtmin = c->geo.sys[0].dt;
+        for (const SysDesc &d : c->geo.sys) dtmin = std::min(dtmin, d.dt);
+        for (size_t k = 0; k < c->geo.sys.size(); ++k) {
+            const double ratio = c->geo.sys[k].dt / dtmin;
+            const long long q = std::llround(ratio);
+            if (q < 1 || q > 1024 || (q & (q - 1)) || std::fabs((double)q * dtmin - c->geo.sys[k].dt) > 1e-12 * c->geo.sys[k].dt)
+                return fail(c, DEM_ERR_ARG, "multi-rate stepping needs every dt to be the smallest dt times a power of two (up to 1024)");
+            stride[k] = (int32_t)q;
+            mx = std::max(mx, (int32_t)q);
+        }
+    }
+    for (size_t k = 0; k < c->geo.sys.size(); ++k) c->geo.sys[k].stride = stride[k];
+    HIPCALL(c, hipMemcpyAsync(c->d_sys, c->geo.sys.data(), c->geo.sys.size() * sizeof(SysDesc), hipMemcpyHostToDevice,
+                              c->stream));
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    c->multirate = enable != 0 && c->geo.sys.size() > 1;
+    c->max_stride = c->multirate ? mx : 1;
+    return DEM_OK;
+}
+
 int dem_set_step_options(dem_ctx *c, int use_graph, int32_t chunk) {
     if (!c) return DEM_ERR_ARG;
     if (chunk < 2 || chunk > 1024 || (chunk & 1)) return fail(c, DEM_ERR_ARG, "chunk must be even, 2..1024");
@@ -613,6 +670,8 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
         return fail(c, DEM_ERR_STATE,
                     "dem_step needs the forces of the current state: call dem_forces(ctx, s, 0) or dem_declare_forces");
     if (nsteps == 0 || c->geo.n == 0) return DEM_OK;
+    if (c->multirate && nsteps % c->max_stride)
+        return fail(c, DEM_ERR_ARG, "multi-rate stepping needs nsteps to be a multiple of the largest stride");
     if (!c->list_current) {
         // binned but no list yet: build it (f and t were permuted with the particles)
         if ((rc = do_bin(c, s, true)) || (rc = do_neighbors(c, s))) return rc;
@@ -627,6 +686,10 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
     int64_t q = 1, q0 = 1;
     Flags h;
     HIPCALL(c, launch_ctrl(c->d_flags, 0, base + 1, c->stream));
+    if (c->multirate) {
+        HIPCALL(c, launch_ctrl(c->d_flags, 5, base, c->stream));
+        HIPCALL(c, launch_ctrl(c->d_flags, 6, base + nsteps, c->stream));
+    }
     {
         KArgs a = kargs(c, s);
         if ((rc = tic(c, 0))) return rc;
@@ -649,7 +712,8 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
         if (c->use_graph && !c->timing && (8 << slot) == len && q == q0 && ((q - 1) & 1) == 0 &&
             q + len - 1 <= nsteps - 1) {
             GraphSlot &gs = c->graphs[slot];
-            const void *key[10] = {c->ws, nullptr};
+            const void *key[10] = {c->ws, c->fext_on ? (const void *)c->lay.fext : nullptr,
+                             c->multirate ? (const void *)c->lay.sys : nullptr};
             if (!gs.exec || memcmp(gs.key, key, sizeof key) || gs.chunk != len || gs.count != cnt)
                 if ((rc = capture_graph(c, s, gs, len))) return rc;
             HIPCALL(c, hipGraphLaunch(gs.exec, c->stream));
@@ -698,13 +762,17 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
             // arrays and repack into the same buffer
             const int64_t qa = h.abort_at - base;
             const int buf = (int)((qa - 1) & 1);
-            // only the systems that asked for it are unpacked, rebuilt and repacked
+            // only the systems that asked for it are unpacked, rebuilt and repacked,
+            // by kernels over the index window of those systems
             if ((rc = tic(c, 3))) return rc;
-            HIPCALL(c, launch_unpack(a, buf, 1, c->stream));
+            if (c->geo.sys.size() > 1 && (rc = set_rebuild_window(c))) return rc;
+            a = kargs(c, s);
+            HIPCALL(c, launch_unpack(a, buf, 1, c->stream, qa));
             c->binned = false;
             if ((rc = do_bin(c, s, false)) || (rc = do_neighbors(c, s, false))) return rc;
             KArgs b = kargs(c, s);
-            HIPCALL(c, launch_pack(b, buf, 2, 0, 0, c->stream));
+            HIPCALL(c, launch_pack(b, buf, 2, 0, 0, c->stream, qa));
+            c->win_on = false;
             HIPCALL(c, launch_fill_i32(b.sel, (int64_t)c->geo.sys.size(), 0, c->stream));
             if ((rc = toc(c))) return rc;
             const double gap = (double)(c->since_rebuild + (qa - q0));

@@ -42,6 +42,8 @@ struct SysDesc {
     int32_t ntypes;
     int32_t coef0;          // first PairCoef of this system (ntypes x ntypes, row major)
     int32_t type0;          // first entry of this system in the per-type arrays
+    int32_t stride;         // multi-rate stepping: one step of dt every `stride` substeps (else 1)
+    int32_t pad_s;
 };
 
 // Device flag block (one per context).
@@ -54,7 +56,11 @@ struct Flags {
     int64_t builds;         // list builds
     unsigned long long contacts;  // sum over force evaluations of directed contacts
     unsigned long long wall_contacts;
-    int64_t pad[8];
+    int32_t call_err;       // error of the current synchronising call (cleared by it)
+    int32_t pad0;
+    int64_t call_base;      // multi-rate: step number before the first substep of the current dem_step
+    int64_t step_end;       // multi-rate: step number of the call's last substep
+    int64_t pad[5];
 };
 
 // Neighbour list (ELL, slot-major: slot k of particle i at k*n + i).

@@ -1,0 +1,461 @@
+// dem_coupling.hip -- cell fields and coupling controllers of the multi-level
+// coarse-grain model (Sec. 2.3, Eq. (7)): kernels and the C-ABI calls
+// dem_cell_fields, dem_pi_control, dem_p_control and dem_set_external_force.
+//
+// Fields: one workgroup per cell of the grid.  Its spheres are found through
+// the list's binning (the particle range of every bin row that the cell,
+// widened by one bin on each side, touches: spheres stay within one bin of
+// their binned position until the next rebuild), and the block's threads take
+// the candidates in turn.  Each thread sums its own spheres, then the block
+// adds the threads' sums in a fixed tree: the result depends on nothing but
+// the state and the grid.  A first pass gives mass and momentum, hence the
+// Favre velocity; the second the kinetic and contact parts of Eq. (7), the
+// contact forces evaluated as in a force pass without history update.
+// Controllers: one thread per cell updates the PI state; one thread per
+// sphere of the system writes its external force.
+#include <cmath>
+#include <cstring>
+
+#include "dem_ctx.h"
+
+namespace dem {
+namespace {
+
+struct FGrid {
+    double lo[3], h[3];
+    int32_t n[3];
+    int32_t sys;
+    int64_t ncell;
+    double vol;   // cell volume h0 h1 h2
+};
+
+constexpr int kFB = 256;   // threads per cell of the fields kernel
+
+// Cell of a centre: floor((x - lo) / h) per axis, -1 outside (or NaN).
+__device__ inline int64_t field_cell(const FGrid &g, double x, double y, double z) {
+    const double u0 = floor((x - g.lo[0]) / g.h[0]);
+    const double u1 = floor((y - g.lo[1]) / g.h[1]);
+    const double u2 = floor((z - g.lo[2]) / g.h[2]);
+    if (!(u0 >= 0.0 && u0 < (double)g.n[0] && u1 >= 0.0 && u1 < (double)g.n[1] && u2 >= 0.0 &&
+          u2 < (double)g.n[2]))
+        return -1;
+    return ((int64_t)u2 * g.n[1] + (int64_t)u1) * g.n[0] + (int64_t)u0;
+}
+
+// Bins of one axis that a cell [b0, b1) widened by `margin` touches: one or
+// two inclusive ranges (two where a periodic axis wraps).  On an open axis the
+// range is clamped into the grid (spheres outside it sit in the edge bins).
+struct Pieces {
+    int s[2], e[2], np;
+};
+
+__device__ inline Pieces axis_pieces(const SysDesc &sd, int a, double b0, double b1, double margin) {
+    const int nc = sd.nc[a];
+    double f0 = floor((b0 - margin - sd.lo[a]) * sd.inv_w[a]);
+    double f1 = floor((b1 + margin - sd.lo[a]) * sd.inv_w[a]);
+    f0 = fmin(fmax(f0, -1e9), 1e9);
+    f1 = fmin(fmax(f1, -1e9), 1e9);
+    Pieces p;
+    p.np = 1;
+    p.s[1] = p.e[1] = 0;
+    if (sd.periodic[a]) {
+        if (f1 - f0 + 1.0 >= (double)nc) {
+            p.s[0] = 0;
+            p.e[0] = nc - 1;
+            return p;
+        }
+        int k0 = (int)f0 % nc, k1 = (int)f1 % nc;
+        if (k0 < 0) k0 += nc;
+        if (k1 < 0) k1 += nc;
+        if (k0 <= k1) {
+            p.s[0] = k0;
+            p.e[0] = k1;
+        } else {
+            p.s[0] = k0;
+            p.e[0] = nc - 1;
+            p.s[1] = 0;
+            p.e[1] = k1;
+            p.np = 2;
+        }
+    } else {
+        p.s[0] = (int)fmin(fmax(f0, 0.0), (double)(nc - 1));
+        p.e[0] = (int)fmin(fmax(f1, 0.0), (double)(nc - 1));
+    }
+    return p;
+}
+
+// Sum (op 0) or maximum (op 1) of one value per thread, in a fixed tree over
+// the block; the result is returned to every thread.
+__device__ inline double block_reduce(double v, double *lds, int op) {
+    const int t = threadIdx.x;
+    __syncthreads();
+    lds[t] = v;
+    __syncthreads();
+    for (int off = kFB / 2; off > 0; off >>= 1) {
+        if (t < off) lds[t] = op ? fmax(lds[t], lds[t + off]) : lds[t] + lds[t + off];
+        __syncthreads();
+    }
+    return lds[0];
+}
+
+// Calls visit(p) for every candidate sphere index p of a cell, the block's
+// threads taking them in turn (the same loop bounds in every thread).
+template <class F>
+__device__ inline void for_candidates(const KArgs &a, const SysDesc &sd, const Pieces &X, const Pieces &Y,
+                                      const Pieces &Z, F visit) {
+    const int32_t *cs = a.cell_start;
+    for (int pz = 0; pz < Z.np; ++pz)
+        for (int bz = Z.s[pz]; bz <= Z.e[pz]; ++bz)
+            for (int py = 0; py < Y.np; ++py)
+                for (int by = Y.s[py]; by <= Y.e[py]; ++by) {
+                    const int64_t row = sd.c0 + ((int64_t)bz * sd.nc[1] + by) * sd.nc[0];
+                    for (int px = 0; px < X.np; ++px) {
+                        const int32_t beg = cs[row + X.s[px]], end = cs[row + X.e[px] + 1];
+                        for (int32_t p = beg + (int32_t)threadIdx.x; p < end; p += (int32_t)blockDim.x) visit(p);
+                    }
+                }
+}
+
+__global__ void __launch_bounds__(kFB) k_fields(KArgs a, FGrid g, double *out) {
+    __shared__ double lds[kFB];
+    const SysDesc sd = a.sys[g.sys];
+    const int64_t n = a.n;
+    const List L = (a.lcur[g.sys] & 1) ? a.lst[1] : a.lst[0];
+    const int64_t kmax = a.kmax;
+    const PairCoef *coef = a.coef + sd.coef0;
+    double margin[3];
+    for (int ax = 0; ax < 3; ++ax) margin[ax] = 1.0 / sd.inv_w[ax];
+    for (int64_t cell = blockIdx.x; cell < g.ncell; cell += gridDim.x) {
+        const int64_t c0 = cell % g.n[0], c1 = (cell / g.n[0]) % g.n[1], c2 = cell / ((int64_t)g.n[0] * g.n[1]);
+        const double b0[3] = {g.lo[0] + (double)c0 * g.h[0], g.lo[1] + (double)c1 * g.h[1],
+                              g.lo[2] + (double)c2 * g.h[2]};
+        const Pieces X = axis_pieces(sd, 0, b0[0], b0[0] + g.h[0], margin[0]);
+        const Pieces Y = axis_pieces(sd, 1, b0[1], b0[1] + g.h[1], margin[1]);
+        const Pieces Z = axis_pieces(sd, 2, b0[2], b0[2] + g.h[2], margin[2]);
+        // ---- pass 1: count, mass, momentum, solids volume, largest speed
+        double cnt = 0.0, mass = 0.0, px = 0.0, py = 0.0, pz = 0.0, vol = 0.0, vmax = 0.0;
+        for_candidates(a, sd, X, Y, Z, [&](int32_t i) {
+            if (field_cell(g, a.x[i], a.x[n + i], a.x[2 * n + i]) != cell) return;
+            const double m = a.m[i], r = a.r[i];
+            const double vx = a.v[i], vy = a.v[n + i], vz = a.v[2 * n + i];
+            cnt += 1.0;
+            mass += m;
+            px += m * vx;
+            py += m * vy;
+            pz += m * vz;
+            vol += 4.0 / 3.0 * M_PI * r * r * r;
+            vmax = fmax(vmax, sqrt(vx * vx + vy * vy + vz * vz));
+        });
+        cnt = block_reduce(cnt, lds, 0);
+        mass = block_reduce(mass, lds, 0);
+        px = block_reduce(px, lds, 0);
+        py = block_reduce(py, lds, 0);
+        pz = block_reduce(pz, lds, 0);
+        vol = block_reduce(vol, lds, 0);
+        vmax = block_reduce(vmax, lds, 1);
+        double ux = 0.0, uy = 0.0, uz = 0.0;   // Favre velocity
+        if (mass > 0.0) {
+            ux = px / mass;
+            uy = py / mass;
+            uz = pz / mass;
+        }
+        // ---- pass 2: Eq. (7), contact part (1/2 d (x) f over every contact of the
+        // cell's spheres) and kinetic part (m v' (x) v', v' = v - u)
+        double con[9], kin[6];
+        for (int k = 0; k < 9; ++k) con[k] = 0.0;
+        for (int k = 0; k < 6; ++k) kin[k] = 0.0;
+        for_candidates(a, sd, X, Y, Z, [&](int32_t i) {
+            const double xi = a.x[i], yi = a.x[n + i], zi = a.x[2 * n + i];
+            if (field_cell(g, xi, yi, zi) != cell) return;
+            const double m = a.m[i], ri = a.r[i];
+            const double vx = a.v[i], vy = a.v[n + i], vz = a.v[2 * n + i];
+            const double wx = a.w[i], wy = a.w[n + i], wz = a.w[2 * n + i];
+            const double qx = vx - ux, qy = vy - uy, qz = vz - uz;
+            kin[0] += m * qx * qx;
+            kin[1] += m * qx * qy;
+            kin[2] += m * qx * qz;
+            kin[3] += m * qy * qy;
+            kin[4] += m * qy * qz;
+            kin[5] += m * qz * qz;
+            const int ti = a.type[i];
+            const int rowlen = L.cnt[i];
+            const uint64_t mask = L.mask[i];
+            for (int q = 0; q < rowlen; ++q) {
+                const int32_t j = L.nbr[q * n + i];
+                ContactIn c;
+                c.dx = min_image(xi - a.x[j], sd.L[0], sd.hL[0], sd.periodic[0]);
+                c.dy = min_image(yi - a.x[n + j], sd.L[1], sd.hL[1], sd.periodic[1]);
+                c.dz = min_image(zi - a.x[2 * n + j], sd.L[2], sd.hL[2], sd.periodic[2]);
+                c.ra = ri;
+                c.rb = a.r[j];
+                c.ma = m;
+                c.mb = a.m[j];
+                c.vrx = vx - a.v[j];
+                c.vry = vy - a.v[n + j];
+                c.vrz = vz - a.v[2 * n + j];
+                c.wsx = ri * wx + c.rb * a.w[j];
+                c.wsy = ri * wy + c.rb * a.w[n + j];
+                c.wsz = ri * wz + c.rb * a.w[2 * n + j];
+                double hx = 0.0, hy = 0.0, hz = 0.0;
+                if ((mask >> q) & 1ull) {
+                    const D4 h = L.xi[i * kmax + q];
+                    hx = h.x; hy = h.y; hz = h.z;
+                }
+                double fx, fy, fz, ftx, fty, ftz, nx, ny, nz, fn;
+                if (!contact_force(c, false, coef[ti * sd.ntypes + a.type[j]], sd.dt, false, hx, hy, hz, fx, fy, fz,
+                                   ftx, fty, ftz, nx, ny, nz, fn))
+                    continue;
+                const double d[3] = {0.5 * c.dx, 0.5 * c.dy, 0.5 * c.dz};
+                const double f[3] = {fx, fy, fz};
+                for (int p = 0; p < 3; ++p)
+                    for (int q2 = 0; q2 < 3; ++q2) con[3 * p + q2] += d[p] * f[q2];
+            }
+        });
+        for (int k = 0; k < 9; ++k) con[k] = block_reduce(con[k], lds, 0);
+        for (int k = 0; k < 6; ++k) kin[k] = block_reduce(kin[k], lds, 0);
+        if (threadIdx.x == 0) {
+            const int64_t nc = g.ncell;
+            out[DEM_F_COUNT * nc + cell] = cnt;
+            out[DEM_F_MASS * nc + cell] = mass;
+            out[(DEM_F_MOM + 0) * nc + cell] = px;
+            out[(DEM_F_MOM + 1) * nc + cell] = py;
+            out[(DEM_F_MOM + 2) * nc + cell] = pz;
+            out[DEM_F_VOLUME * nc + cell] = vol;
+            out[DEM_F_VMAX * nc + cell] = vmax;
+            // kinetic part: symmetric (m q_a q_b = m q_b q_a exactly)
+            const int ksym[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+            for (int k = 0; k < 9; ++k) out[(DEM_F_STRESS + k) * nc + cell] = (con[k] + kin[ksym[k]]) / g.vol;
+        }
+    }
+}
+
+// Every sphere of the system must lie within one bin width (per axis) of its
+// position at the last list build for the bin-row search above to find it.
+__global__ void k_fields_guard(KArgs a, int32_t sys) {
+    const SysDesc &sd = a.sys[sys];
+    const int64_t n = a.n;
+    bool bad = false;
+    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.p1;
+         i += (int64_t)gridDim.x * blockDim.x)
+        for (int ax = 0; ax < 3; ++ax)
+            if (!(fabs(a.disp[ax * n + i]) * sd.inv_w[ax] <= 1.0)) bad = true;
+    if (bad) atomicOr(&a.flags->call_err, 1);
+}
+
+// PI update per transition cell: e = n.sigma_coarse.n - n.sigma_fine.n,
+// integral += e interval, u = kp e + ki integral.
+__global__ void k_pi_cells(FGrid g, const double *fine, const double *coarse, double nx, double ny, double nz,
+                           double kp, double ki, double interval, double *integral, double *u) {
+    const int64_t nc = g.ncell;
+    const double nn[3] = {nx, ny, nz};
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        double sf = 0.0, sc = 0.0;
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) {
+                sf += nn[p] * fine[(DEM_F_STRESS + 3 * p + q) * nc + c] * nn[q];
+                sc += nn[p] * coarse[(DEM_F_STRESS + 3 * p + q) * nc + c] * nn[q];
+            }
+        const double e = sc - sf;
+        const double I = integral[c] + e * interval;
+        integral[c] = I;
+        u[c] = kp * e + ki * I;
+    }
+}
+
+// Correcting force on every sphere of the fine system: u pi r^2 w along the
+// inward normal in a transition cell (fade w over `fade` diameters below the
+// face), limited by the coarse cell's largest speed; zero elsewhere.
+__global__ void k_pi_particles(KArgs a, FGrid g, const double *coarse, const double *u, double nx, double ny,
+                               double nz, double face, double fade) {
+    const SysDesc &sd = a.sys[g.sys];
+    const int64_t n = a.n;
+    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.p1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = a.x[i], y = a.x[n + i], z = a.x[2 * n + i];
+        const int64_t c = field_cell(g, x, y, z);
+        double mag = 0.0;
+        if (c >= 0) {
+            const double r = a.r[i];
+            const double depth = (x * nx + y * ny + z * nz) - face;
+            const double reach = fade * 2.0 * r;
+            double w = -1.0;
+            if (depth < 0.0) w = 1.0;
+            else if (depth < reach) w = 1.0 - depth / reach;
+            if (w >= 0.0) {
+                mag = u[c] * M_PI * (r * r) * w;
+                const double vn = a.v[i] * nx + a.v[n + i] * ny + a.v[2 * n + i] * nz;
+                const double vm = coarse[DEM_F_VMAX * g.ncell + c];
+                const double m = a.m[i];
+                if (mag > 0.0) mag = fmin(mag, fmax(0.0, m * (vm - vn) / sd.dt));
+                else if (mag < 0.0) mag = fmax(mag, fmin(0.0, m * (-vm - vn) / sd.dt));
+            }
+        }
+        a.fext_ws[i] = mag * nx;
+        a.fext_ws[n + i] = mag * ny;
+        a.fext_ws[2 * n + i] = mag * nz;
+    }
+}
+
+// P controller force on every sphere of the coarse system: kp m (target - u_c)
+// in a cell where both levels hold mass, zero elsewhere.
+__global__ void k_p_particles(KArgs a, FGrid g, const double *fine, const double *coarse, double kp, int mass_flow) {
+    const SysDesc &sd = a.sys[g.sys];
+    const int64_t n = a.n, nc = g.ncell;
+    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.p1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = field_cell(g, a.x[i], a.x[n + i], a.x[2 * n + i]);
+        double F[3] = {0.0, 0.0, 0.0};
+        if (c >= 0) {
+            const double mf = fine[DEM_F_MASS * nc + c], mc = coarse[DEM_F_MASS * nc + c];
+            if (mf > 0.0 && mc > 0.0) {
+                const double ratio = mass_flow ? fine[DEM_F_VOLUME * nc + c] / coarse[DEM_F_VOLUME * nc + c] : 1.0;
+                const double m = a.m[i];
+                for (int k = 0; k < 3; ++k) {
+                    const double target = fine[(DEM_F_MOM + k) * nc + c] / mf * ratio;
+                    const double uc = coarse[(DEM_F_MOM + k) * nc + c] / mc;
+                    F[k] = kp * m * (target - uc);
+                }
+            }
+        }
+        a.fext_ws[i] = F[0];
+        a.fext_ws[n + i] = F[1];
+        a.fext_ws[2 * n + i] = F[2];
+    }
+}
+
+__global__ void k_clear_call_err(Flags *f) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) f->call_err = 0;
+}
+
+int grid_blocks(int64_t work, int block) {
+    int64_t b = (work + block - 1) / block;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace
+}  // namespace dem
+
+using namespace dem;
+using namespace dem::host;
+
+namespace {
+
+int make_fgrid(dem_ctx *c, const dem_grid *g, FGrid &out) {
+    if (!g) return fail(c, DEM_ERR_ARG, "grid is NULL");
+    if (g->sys < 0 || g->sys >= (int32_t)c->geo.sys.size()) return fail(c, DEM_ERR_ARG, "grid.sys out of range");
+    int64_t nc = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a]) || !std::isfinite(g->lo[a]))
+            return fail(c, DEM_ERR_ARG, "grid needs finite lo and h > 0");
+        if (g->n[a] < 1) return fail(c, DEM_ERR_ARG, "grid needs n >= 1 on every axis");
+        nc *= g->n[a];
+        if (nc > (1 << 24)) return fail(c, DEM_ERR_ARG, "grid has more than 2^24 cells");
+    }
+    memset(&out, 0, sizeof out);
+    for (int a = 0; a < 3; ++a) {
+        out.lo[a] = g->lo[a];
+        out.h[a] = g->h[a];
+        out.n[a] = g->n[a];
+    }
+    out.sys = g->sys;
+    out.ncell = nc;
+    out.vol = g->h[0] * g->h[1] * g->h[2];
+    return DEM_OK;
+}
+
+// First use: external forces of every system start at zero.
+int enable_fext(dem_ctx *c, const KArgs &a) {
+    if (c->fext_on) return DEM_OK;
+    HIPCALL(c, launch_fill_f64(a.fext_ws, 3 * c->geo.n, 0.0, c->stream));
+    c->fext_on = true;
+    return DEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dem_cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double *fields) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    FGrid g;
+    if ((rc = make_fgrid(c, grid, g))) return rc;
+    if (!fields) return fail(c, DEM_ERR_ARG, "fields is NULL");
+    if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_cell_fields needs a neighbour list for the current order");
+    KArgs a = kargs(c, s);
+    HIPCALL(c, hipGetLastError());
+    k_clear_call_err<<<1, 64, 0, c->stream>>>(c->d_flags);
+    const SysDesc &sd = c->geo.sys[g.sys];
+    k_fields_guard<<<grid_blocks(sd.p1 - sd.p0, 256), 256, 0, c->stream>>>(a, g.sys);
+    const int64_t blocks = g.ncell < 65536 ? g.ncell : 65536;
+    k_fields<<<(int)blocks, kFB, 0, c->stream>>>(a, g, fields);
+    HIPCALL(c, hipGetLastError());
+    Flags h;
+    if ((rc = read_flags(c, h))) return rc;
+    if (h.call_err)
+        return fail(c, DEM_ERR_STATE,
+                    "a sphere moved more than one list cell since the last list build: step or rebuild first");
+    return flag_error(c, h);
+}
+
+int dem_pi_control(dem_ctx *c, const dem_state *s, const dem_pi_params *p, const double *fine, const double *coarse,
+                   double *integral, double *u) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!p) return fail(c, DEM_ERR_ARG, "params is NULL");
+    FGrid g;
+    if ((rc = make_fgrid(c, &p->grid, g))) return rc;
+    if (!fine || !coarse || !integral || !u) return fail(c, DEM_ERR_ARG, "a fields or controller array is NULL");
+    const double nn = p->nrm[0] * p->nrm[0] + p->nrm[1] * p->nrm[1] + p->nrm[2] * p->nrm[2];
+    if (!(std::fabs(nn - 1.0) < 1e-12)) return fail(c, DEM_ERR_ARG, "nrm must be a unit vector");
+    if (!(p->fade >= 0.0) || !(p->interval >= 0.0) || !std::isfinite(p->kp) || !std::isfinite(p->ki) ||
+        !std::isfinite(p->face))
+        return fail(c, DEM_ERR_ARG, "need fade >= 0, interval >= 0 and finite gains and face");
+    KArgs a = kargs(c, s);
+    if ((rc = enable_fext(c, a))) return rc;
+    a = kargs(c, s);
+    k_pi_cells<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, fine, coarse, p->nrm[0], p->nrm[1], p->nrm[2],
+                                                                  p->kp, p->ki, p->interval, integral, u);
+    const SysDesc &sd = c->geo.sys[g.sys];
+    k_pi_particles<<<grid_blocks(sd.p1 - sd.p0, 256), 256, 0, c->stream>>>(a, g, coarse, u, p->nrm[0], p->nrm[1],
+                                                                          p->nrm[2], p->face, p->fade);
+    HIPCALL(c, hipGetLastError());
+    return DEM_OK;
+}
+
+int dem_p_control(dem_ctx *c, const dem_state *s, const dem_p_params *p, const double *fine, const double *coarse) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!p) return fail(c, DEM_ERR_ARG, "params is NULL");
+    FGrid g;
+    if ((rc = make_fgrid(c, &p->grid, g))) return rc;
+    if (!fine || !coarse) return fail(c, DEM_ERR_ARG, "a fields array is NULL");
+    if (!std::isfinite(p->kp)) return fail(c, DEM_ERR_ARG, "kp must be finite");
+    KArgs a = kargs(c, s);
+    if ((rc = enable_fext(c, a))) return rc;
+    a = kargs(c, s);
+    const SysDesc &sd = c->geo.sys[g.sys];
+    k_p_particles<<<grid_blocks(sd.p1 - sd.p0, 256), 256, 0, c->stream>>>(a, g, fine, coarse, p->kp,
+                                                                         p->mass_flow ? 1 : 0);
+    HIPCALL(c, hipGetLastError());
+    return DEM_OK;
+}
+
+int dem_set_external_force(dem_ctx *c, const dem_state *s, const double *fext) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!fext) {
+        c->fext_on = false;
+        return DEM_OK;
+    }
+    KArgs a = kargs(c, s);
+    if (c->geo.n > 0)
+        HIPCALL(c, hipMemcpyAsync(a.fext_ws, fext, 3 * (size_t)c->geo.n * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream));
+    c->fext_on = true;
+    return DEM_OK;
+}
+
+}  // extern "C"

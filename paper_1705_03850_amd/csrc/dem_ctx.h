@@ -17,7 +17,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame;
+    size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame, fext;
     size_t nbr[2], cnt[2], xi[2], mask[2], ids[2];
     size_t cell_of, rank, order, cell_count, cell_start, scan_partial, shadow_d, shadow_i;
     size_t pos[2], vel[2], spin[2], im, sel, lcur, tile0;
@@ -58,6 +58,11 @@ struct dem_ctx {
     // host-side state machine
     bool masses = false, have_list = false, list_current = false, binned = false, frame_identity = true;
     bool forces_valid = false;
+    bool fext_on = false;            // external forces are added to the force evaluations
+    bool multirate = false;          // systems step every SysDesc::stride substeps
+    bool win_on = false;             // rebuild kernels limited to win: particles [0], [1), cells [2], [3)
+    int64_t win[4] = {0, 0, 0, 0};
+    int32_t max_stride = 1;
     int64_t step_counter = 0;
     // options
     bool use_graph = false, count = true;

@@ -5,6 +5,10 @@
 
 namespace dem {
 
+// doubles per particle in the binning scratch: x, v, w, f, t, disp, wall history,
+// external force (3 each), r, m, 1/m, 1/I
+constexpr int kShadowD = 28;
+
 // Everything a kernel may touch, passed by value.
 struct KArgs {
     // caller-owned particle arrays
@@ -13,6 +17,8 @@ struct KArgs {
     // library-owned per-particle arrays (workspace)
     double *m, *inv_m, *inv_I, *disp, *xiw;
     int32_t *frame;        // index of each particle in the order of the last list build
+    double *fext_ws;       // [3][n] external forces (workspace)
+    const double *fext;    // fext_ws while external forces are on, else null
     // systems
     const SysDesc *sys;
     const PairCoef *coef;
@@ -22,14 +28,18 @@ struct KArgs {
     int32_t block;
     int32_t grid_cap;      // blocks of the fused step kernel (0 = one per tile)
     int32_t lanes;         // lanes per particle in the force pass: 4, 8 or 16
+    int32_t multirate;     // systems step every SysDesc::stride substeps (batch only)
     int64_t n;             // particles, all systems
     int64_t ncell;         // cells, all systems
+    // window of the rebuild kernels (particles [w0, w1), cells [cw0, cw1)): the
+    // index ranges of the systems selected for a rebuild; everything otherwise
+    int64_t w0, w1, cw0, cw1;
     Flags *flags;
     List lst[2];           // two list buffers; system s uses lst[lcur[s]], builds into the other
     int32_t *lcur;         // [nsys] current list buffer of each system
     // binning scratch
     int32_t *cell_of, *rank, *cell_count, *cell_start, *scan_partial, *order;
-    double *shadow_d;      // [25][n]
+    double *shadow_d;      // [kShadowD][n]
     int32_t *shadow_i;     // [3][n]
     // packed step state, two buffers used alternately
     D4 *pos[2], *vel[2], *spin[2];
@@ -52,10 +62,12 @@ hipError_t launch_neighbors(const KArgs &a, int have_old, hipStream_t st);
 // after a build: the selected systems switch to their new list buffer
 hipError_t launch_flip(const KArgs &a, hipStream_t st);
 // mode 0: pack only; 1: pack and do phase 0 of step `k` (gated); 2: pack the
-// particles of the systems selected for a rebuild only
-hipError_t launch_pack(const KArgs &a, int dst, int mode, int k, int gate, hipStream_t st);
-// selected != 0: only particles of systems selected for a rebuild
-hipError_t launch_unpack(const KArgs &a, int src, int selected, hipStream_t st);
+// particles of the systems selected for a rebuild only (in multi-rate mode into
+// each system's buffer for substep qa of the call, qa >= 1)
+hipError_t launch_pack(const KArgs &a, int dst, int mode, int k, int gate, hipStream_t st, int64_t qa = 0);
+// selected != 0: only particles of systems selected for a rebuild (multi-rate:
+// from each system's buffer for substep qa of the call)
+hipError_t launch_unpack(const KArgs &a, int src, int selected, hipStream_t st, int64_t qa = 0);
 // force pass over packed buffer src: mode 0 forces only (to f, t); mode 1 fused
 // step (forces, kick, next kick + drift into buffer src^1); mode 2 last step
 // (forces, kick, f, t, x, v, w to the caller's arrays).

@@ -37,6 +37,15 @@ __device__ inline TileIter tiles(int64_t n) {
     for (TileIter _it = tiles(n); _it.t < _it.tend; _it.t += _it.stride)         \
         for (int64_t i = _it.t * blockDim.x + threadIdx.x; i < (n); i = (n))
 
+// The same over the particle window [a.w0, a.w1) of the rebuild kernels.
+#define FOR_EACH_IN_WINDOW(a, i)                                                        \
+    for (TileIter _it = tiles((a).w1 - (a).w0); _it.t < _it.tend; _it.t += _it.stride) \
+        for (int64_t i = (a).w0 + _it.t * blockDim.x + threadIdx.x; i < (a).w1; i = (a).w1)
+
+#define FOR_WINDOW_FLAT(a, i)                                                                       \
+    for (int64_t i = (a).w0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (a).w1;            \
+         i += (int64_t)gridDim.x * blockDim.x)
+
 template <bool BATCH>
 __device__ inline int sys_of(const KArgs &a, int64_t i) {
     if (!BATCH) return 0;
@@ -92,7 +101,7 @@ __global__ void k_fill_f64(double *p, int64_t n, double v) {
 
 // op 0: clear abort, set step_base = value; op 1: step_base += value;
 // op 2: clear the flag block (errors, counters); op 3: steps += value;
-// op 4: builds += value
+// op 4: builds += value; op 5: call_base = value; op 6: step_end = value
 __global__ void k_ctrl(Flags *f, int op, int64_t value) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     if (op == 0) { f->abort_at = INT64_MAX; f->step_base = value; }
@@ -102,6 +111,15 @@ __global__ void k_ctrl(Flags *f, int op, int64_t value) {
         f->steps = 0; f->builds = 0; f->contacts = 0; f->wall_contacts = 0;
     } else if (op == 3) { f->steps += value; }
     else if (op == 4) { f->builds += value; }
+    else if (op == 5) { f->call_base = value; }
+    else if (op == 6) { f->step_end = value; }
+}
+
+// Multi-rate stepping: the packed buffer that holds a system's state at
+// substep qa (1-based) of a call, i.e. after the drift into its next step:
+// the parity of the number of its steps before qa.
+__device__ inline int mr_buffer(int64_t qa, int stride) {
+    return (int)(((qa - 1 + stride - 1) / stride) & 1);
 }
 
 // ------------------------------------------------------------------ masses
@@ -191,11 +209,24 @@ __global__ void k_phase1(KArgs a, int k, int gate) {
 
 // ------------------------------------------------------------------ binning
 
+// Counts of the selected systems' cells only: the other systems keep the
+// counts of their own last binning, so that cell_start (one scan over all
+// cells) still gives every system the particle range of each of its cells in
+// the order it keeps until its next rebuild.
+__global__ void k_zero_selected_cells(KArgs a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cell_count[a.ncell] = 0;
+    for (int64_t c = a.cw0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.cw1;
+         c += (int64_t)gridDim.x * blockDim.x)
+        if (a.sel[sys_of_cell(a, c)]) a.cell_count[c] = 0;
+}
+
 template <bool BATCH>
 __global__ void k_bin_count(KArgs a) {
     const int64_t n = a.n;
-    FOR_EACH_PARTICLE(n, i) {
-        const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
+    FOR_EACH_IN_WINDOW(a, i) {
+        const int sy = sys_of<BATCH>(a, i);
+        if (!a.sel[sy]) continue;
+        const SysDesc &s = a.sys[sy];
         int cx = cell_coord(a.x[i], s, 0);
         int cy = cell_coord(a.x[n + i], s, 1);
         int cz = cell_coord(a.x[2 * n + i], s, 2);
@@ -272,7 +303,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const int32_t *in, in
 // the others keep their place (their list is kept, not rebuilt).
 template <bool BATCH>
 __global__ void k_bin_place(KArgs a) {
-    FOR_EACH_PARTICLE(a.n, i) {
+    FOR_EACH_IN_WINDOW(a, i) {
         if (!a.sel[sys_of<BATCH>(a, i)]) continue;
         int32_t c = a.cell_of[i];
         a.order[a.cell_start[c] + a.rank[i]] = (int32_t)i;
@@ -281,7 +312,7 @@ __global__ void k_bin_place(KArgs a) {
 
 // Order each cell's particles by id (insertion sort; cells are small).
 __global__ void k_cell_sort(KArgs a) {
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.ncell;
+    for (int64_t c = a.cw0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.cw1;
          c += (int64_t)gridDim.x * blockDim.x) {
         if (!a.sel[sys_of_cell(a, c)]) continue;
         int32_t b = a.cell_start[c], e = a.cell_start[c + 1];
@@ -305,7 +336,7 @@ __global__ void k_cell_sort(KArgs a) {
 // Gather every per-particle array into the shadow copy in the new order.
 __global__ void k_gather(KArgs a, int frame_identity) {
     const int64_t n = a.n;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    FOR_WINDOW_FLAT(a, i) {
         if (!a.sel[sys_of_any(a, i)]) continue;  // not rebuilt: stays in place
         const int64_t src = a.order[i];
         double *sd = a.shadow_d;
@@ -322,6 +353,8 @@ __global__ void k_gather(KArgs a, int frame_identity) {
         sd[22 * n + i] = a.m[src];
         sd[23 * n + i] = a.inv_m[src];
         sd[24 * n + i] = a.inv_I[src];
+        if (a.fext)
+            for (int c = 0; c < 3; ++c) sd[(25 + c) * n + i] = a.fext_ws[c * n + src];
         int32_t *si = a.shadow_i;
         si[i] = a.type[src];
         si[n + i] = a.id[src];
@@ -331,7 +364,7 @@ __global__ void k_gather(KArgs a, int frame_identity) {
 
 __global__ void k_scatter_back(KArgs a) {
     const int64_t n = a.n;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    FOR_WINDOW_FLAT(a, i) {
         if (!a.sel[sys_of_any(a, i)]) continue;
         const double *sd = a.shadow_d;
         for (int c = 0; c < 3; ++c) {
@@ -347,6 +380,8 @@ __global__ void k_scatter_back(KArgs a) {
         a.m[i] = sd[22 * n + i];
         a.inv_m[i] = sd[23 * n + i];
         a.inv_I[i] = sd[24 * n + i];
+        if (a.fext)
+            for (int c = 0; c < 3; ++c) a.fext_ws[c * n + i] = sd[(25 + c) * n + i];
         const int32_t *si = a.shadow_i;
         a.type[i] = si[i];
         a.id[i] = si[n + i];
@@ -446,16 +481,16 @@ __global__ void __launch_bounds__(kNbrBlock, 5) k_neighbors(KArgs a, int have_ol
     int32_t *runs = bid;                                      //   the nine runs, while collecting
     const D4 *Q = (const D4 *)a.shadow_d;  // (x, y, z, r) in the current order (k_nbr_pack)
     const int32_t *cs = a.cell_start;
-    const int64_t ntiles = (n + ppb - 1) / ppb;
+    const int64_t ntiles = (a.w1 - a.w0 + ppb - 1) / ppb;
     const int per = gridDim.x / kXcd;
     const int64_t chunk = (ntiles + kXcd - 1) / kXcd;
     const int64_t t0 = (blockIdx.x % kXcd) * chunk;
     const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
     int maxrow = 0;
     for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {
-        const int64_t i = t * ppb + grp;
+        const int64_t i = a.w0 + t * ppb + grp;
         int sy = 0;
-        bool active = i < n;
+        bool active = i < a.w1;
         // the particle's own record and its previous position, loaded before the
         // selection test so that the loads overlap
         const int64_t ic = active ? i : 0;
@@ -656,7 +691,7 @@ __global__ void k_flip(KArgs a) {
 // does phase 0 of velocity Verlet for the step step_base + k (gated like the
 // fused step: it asks for a rebuild when the displacement exceeds skin/2).
 template <bool BATCH>
-__global__ void k_pack(KArgs a, int dst, int mode, int k, int gate) {
+__global__ void k_pack(KArgs a, int dst, int mode, int k, int gate, int64_t qa) {
     int64_t step = 0;
     if (gate) {
         step = a.flags->step_base + k;
@@ -664,11 +699,12 @@ __global__ void k_pack(KArgs a, int dst, int mode, int k, int gate) {
     }
     const int64_t n = a.n;
     bool need = false, bad = false;
-    D4 *P = a.pos[dst], *V = a.vel[dst], *S = a.spin[dst];
-    FOR_EACH_PARTICLE(n, i) {
+    FOR_EACH_IN_WINDOW(a, i) {
         const int sy = sys_of<BATCH>(a, i);
         if (mode == 2 && !a.sel[sy]) continue;
         const SysDesc &s = a.sys[sy];
+        const int d = mode == 2 && a.multirate ? mr_buffer(qa, s.stride) : dst;
+        D4 *P = a.pos[d], *V = a.vel[d], *S = a.spin[d];
         const double im = a.inv_m[i], iI = a.inv_I[i];
         double x[3], v[3], w[3];
         for (int c = 0; c < 3; ++c) {
@@ -703,12 +739,13 @@ __global__ void k_pack(KArgs a, int dst, int mode, int k, int gate) {
 
 // Packed buffer `src` -> caller arrays x, v, w (with selected: only the
 // systems selected for a rebuild).
-__global__ void k_unpack(KArgs a, int src, int selected) {
+__global__ void k_unpack(KArgs a, int src, int selected, int64_t qa) {
     const int64_t n = a.n;
-    const D4 *P = a.pos[src], *V = a.vel[src], *S = a.spin[src];
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        if (selected && !a.sel[sys_of_any(a, i)]) continue;
-        const D4 p = P[i], v = V[i], w = S[i];
+    FOR_WINDOW_FLAT(a, i) {
+        const int sy = sys_of_any(a, i);
+        if (selected && !a.sel[sy]) continue;
+        const int b = a.multirate && qa > 0 ? mr_buffer(qa, a.sys[sy].stride) : src;
+        const D4 p = a.pos[b][i], v = a.vel[b][i], w = a.spin[b][i];
         a.x[i] = p.x; a.x[n + i] = p.y; a.x[2 * n + i] = p.z;
         a.v[i] = v.x; a.v[n + i] = v.y; a.v[2 * n + i] = v.z;
         a.w[i] = w.x; a.w[n + i] = w.y; a.w[2 * n + i] = w.z;
@@ -742,11 +779,11 @@ __device__ __forceinline__ void load_step_coef(const KArgs &a, const SysDesc &s)
 // One particle of the force pass (see k_step): every lane of its group calls
 // this with the same i; s is the particle's system (the block's: a tile never
 // spans two systems), L its current list.
-template <bool BATCH, bool COUNT, int MODE, int G>
+template <bool BATCH, bool COUNT, int MODE, int G, bool MR>
 __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, const List &L, int src, int update,
                                               int64_t i, int sy, const D4 &pi, const D4 &vi, const D4 &si, int code,
                                               int g, int gbase, uint64_t gmask, unsigned &ncont, unsigned &nwall,
-                                              bool &need, bool &bad) {
+                                              bool &need, bool &bad, bool last) {
     const int64_t n = a.n;
     const D4 *__restrict__ P = a.pos[src];
     const D4 *__restrict__ V = a.vel[src];
@@ -841,6 +878,12 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
                 }
             }
         }
+        // external force (the coupling's correcting force), added last
+        if (a.fext) {
+            Fx = Fx + a.fext[i];
+            Fy = Fy + a.fext[n + i];
+            Fz = Fz + a.fext[2 * n + i];
+        }
         if (g != 0) return;
         if (update && nmask != mask) L.mask[i] = nmask;
         if (MODE == 0) {
@@ -852,7 +895,7 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
         const D2 im = a.im[i];
         double vx = vi.x + s.hdt * (Fx * im.a), vy = vi.y + s.hdt * (Fy * im.a), vz = vi.z + s.hdt * (Fz * im.a);
         double wx = si.x + s.hdt * (Tx * im.b), wy = si.y + s.hdt * (Ty * im.b), wz = si.z + s.hdt * (Tz * im.b);
-        if (MODE == 2) {
+        if (MODE == 2 || (MR && last)) {
             a.f[i] = Fx; a.f[n + i] = Fy; a.f[2 * n + i] = Fz;
             a.t[i] = Tx; a.t[n + i] = Ty; a.t[2 * n + i] = Tz;
             a.x[i] = pi.x; a.x[n + i] = pi.y; a.x[2 * n + i] = pi.z;
@@ -884,23 +927,24 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
         }
 }
 
-template <bool BATCH, bool COUNT, int MODE, int G>
+template <bool BATCH, bool COUNT, int MODE, int G, bool MR>
 // Compiled for four waves per SIMD (at most 128 registers): the kernel waits
 // on gathers, and the fourth wave ran the 1e6-sphere bed 15 % and the
 // 64-system batch 14 % faster than three (the batch form spills a few bytes
 // and still gains); at five or more waves the spills cost more than the
 // extra wave brings.
 __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int update) {
-    int64_t step = 0;
+    int64_t step = 0, cbase = 0, send = 0;
     if (MODE != 0) {
         step = a.flags->step_base + k;
         if (a.flags->abort_at <= step) return;
         update = 1;
+        if (MR) {
+            cbase = a.flags->call_base;
+            send = a.flags->step_end;
+        }
     }
     const int64_t n = a.n;
-    const D4 *__restrict__ P = a.pos[src];
-    const D4 *__restrict__ V = a.vel[src];
-    const D4 *__restrict__ S = a.spin[src];
     const int g = threadIdx.x % G;
     const int ppb = blockDim.x / G;                        // particles per tile
     const int gbase = (threadIdx.x % warpSize) / G * G;    // first lane of the group in the wave
@@ -936,11 +980,21 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
             lc = __builtin_amdgcn_readfirstlane(a.lcur[sy]);
             load_step_coef(a, sd);
         }
+        int srcs = src;
+        bool last = MODE == 2;
+        if (MR) {
+            // multi-rate: the system steps at substeps 1, 1 + stride, ... of the call;
+            // its state alternates between the buffers at its own steps
+            const int64_t q1 = step - cbase - 1;
+            if (q1 % sd.stride != 0) continue;
+            srcs = (int)((q1 / sd.stride) & 1);
+            last = step + sd.stride - 1 == send;
+        }
         const int64_t i = BATCH ? sd.p0 + (t - tlo) * ppb + threadIdx.x / G : t * ppb + threadIdx.x / G;
         if (i >= (BATCH ? sd.p1 : n)) continue;
-        const D4 pi = P[i], vi = V[i], si = S[i];
-        step_particle<BATCH, COUNT, MODE, G>(a, sd, (lc & 1) ? a.lst[1] : a.lst[0], src, update, i, sy, pi, vi, si,
-                                             (int)si.w, g, gbase, gmask, ncont, nwall, need, bad);
+        const D4 pi = a.pos[srcs][i], vi = a.vel[srcs][i], si = a.spin[srcs][i];
+        step_particle<BATCH, COUNT, MODE, G, MR>(a, sd, (lc & 1) ? a.lst[1] : a.lst[0], srcs, update, i, sy, pi, vi,
+                                                 si, (int)si.w, g, gbase, gmask, ncont, nwall, need, bad, last);
     }
     if (bad) atomicOr(&a.flags->err, kErrNonFinite);
     if (MODE == 1 && need) a.flags->abort_at = step + 1;
@@ -1024,8 +1078,9 @@ hipError_t launch_phase(const KArgs &a, int phase, int k, int gate, hipStream_t 
 hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
     hipError_t e;
-    if ((e = launch_fill_i32(a.cell_count, a.ncell + 1, 0, st)) != hipSuccess) return e;
-    const int g = grid_for(a.n, a.block);
+    k_zero_selected_cells<<<flat_grid(a.cw1 - a.cw0 + 1, 256), 256, 0, st>>>(a);
+    const int64_t nw = a.w1 - a.w0;
+    const int g = grid_for(nw, a.block);
     if (a.nsys > 1) k_bin_count<true><<<g, a.block, 0, st>>>(a);
     else k_bin_count<false><<<g, a.block, 0, st>>>(a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1037,9 +1092,9 @@ hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (a.nsys > 1) k_bin_place<true><<<g, a.block, 0, st>>>(a);
     else k_bin_place<false><<<g, a.block, 0, st>>>(a);
-    k_cell_sort<<<flat_grid(m, 256), 256, 0, st>>>(a);
-    k_gather<<<flat_grid(a.n, 256), 256, 0, st>>>(a, frame_identity);
-    k_scatter_back<<<flat_grid(a.n, 256), 256, 0, st>>>(a);
+    k_cell_sort<<<flat_grid(a.cw1 - a.cw0, 256), 256, 0, st>>>(a);
+    k_gather<<<flat_grid(nw, 256), 256, 0, st>>>(a, frame_identity);
+    k_scatter_back<<<flat_grid(nw, 256), 256, 0, st>>>(a);
     CHECK_LAUNCH();
 }
 
@@ -1053,33 +1108,32 @@ hipError_t launch_flip(const KArgs &a, hipStream_t st) {
 __global__ void k_nbr_pack(KArgs a) {
     const int64_t n = a.n;
     D4 *Q = (D4 *)a.shadow_d;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        Q[i] = D4{a.x[i], a.x[n + i], a.x[2 * n + i], a.r[i]};
+    FOR_WINDOW_FLAT(a, i) Q[i] = D4{a.x[i], a.x[n + i], a.x[2 * n + i], a.r[i]};
 }
 
 hipError_t launch_neighbors(const KArgs &a, int have_old, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    k_nbr_pack<<<flat_grid(a.n, 256), 256, 0, st>>>(a);
+    k_nbr_pack<<<flat_grid(a.w1 - a.w0, 256), 256, 0, st>>>(a);
     // per-group hit, id and previous-id buffers (24 KB per block at kmax = 32)
     const int block = kNbrBlock;
     const size_t lds = nbr_lds_bytes(a.kmax, block);
-    const int g = grid_for(a.n * kNbrLanes, block);
+    const int g = grid_for((a.w1 - a.w0) * kNbrLanes, block);
     if (a.nsys > 1) k_neighbors<true><<<g, block, lds, st>>>(a, have_old);
     else k_neighbors<false><<<g, block, lds, st>>>(a, have_old);
     CHECK_LAUNCH();
 }
 
-hipError_t launch_pack(const KArgs &a, int dst, int mode, int k, int gate, hipStream_t st) {
+hipError_t launch_pack(const KArgs &a, int dst, int mode, int k, int gate, hipStream_t st, int64_t qa) {
     if (a.n <= 0) return hipSuccess;
-    const int g = grid_for(a.n, a.block);
-    if (a.nsys > 1) k_pack<true><<<g, a.block, 0, st>>>(a, dst, mode, k, gate);
-    else k_pack<false><<<g, a.block, 0, st>>>(a, dst, mode, k, gate);
+    const int g = grid_for(a.w1 - a.w0, a.block);
+    if (a.nsys > 1) k_pack<true><<<g, a.block, 0, st>>>(a, dst, mode, k, gate, qa);
+    else k_pack<false><<<g, a.block, 0, st>>>(a, dst, mode, k, gate, qa);
     CHECK_LAUNCH();
 }
 
-hipError_t launch_unpack(const KArgs &a, int src, int selected, hipStream_t st) {
+hipError_t launch_unpack(const KArgs &a, int src, int selected, hipStream_t st, int64_t qa) {
     if (a.n <= 0) return hipSuccess;
-    k_unpack<<<flat_grid(a.n, 256), 256, 0, st>>>(a, src, selected);
+    k_unpack<<<flat_grid(a.w1 - a.w0, 256), 256, 0, st>>>(a, src, selected, qa);
     CHECK_LAUNCH();
 }
 
@@ -1089,12 +1143,17 @@ static hipError_t launch_step_g(const KArgs &a, int src, int mode, int k, int up
     const int64_t ntiles = a.nsys > 1 ? a.ntiles_b : (a.n + ppb - 1) / ppb;
     const int g = grid_for(ntiles * a.block, a.block, a.grid_cap);
     const int B = a.block;
-#define STEP_LAUNCH(BT, CT, MD) k_step<BT, CT, MD, G><<<g, B, 0, st>>>(a, src, k, update)
+#define STEP_LAUNCH(BT, CT, MD) k_step<BT, CT, MD, G, false><<<g, B, 0, st>>>(a, src, k, update)
 #define STEP_MODES(BT, CT)                                  \
     if (mode == 0) STEP_LAUNCH(BT, CT, 0);                  \
     else if (mode == 1) STEP_LAUNCH(BT, CT, 1);             \
     else STEP_LAUNCH(BT, CT, 2)
-    if (a.nsys > 1) {
+    if (a.nsys > 1 && a.multirate && mode != 0) {
+        // each system decides per block whether the substep is one of its steps
+        // and whether it is its last one of the call (the mode-2 epilogue)
+        if (count) k_step<true, true, 1, G, true><<<g, B, 0, st>>>(a, src, k, update);
+        else k_step<true, false, 1, G, true><<<g, B, 0, st>>>(a, src, k, update);
+    } else if (a.nsys > 1) {
         if (count) { STEP_MODES(true, true); } else { STEP_MODES(true, false); }
     } else {
         if (count) { STEP_MODES(false, true); } else { STEP_MODES(false, false); }

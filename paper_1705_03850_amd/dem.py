@@ -44,6 +44,33 @@ class State(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("x", "v", "w", "f", "t", "r", "type", "id")]
 
 
+class Grid(ctypes.Structure):
+    """dem_grid: cells (lo, h, n) in the coordinates of system `sys`."""
+    _fields_ = [("lo", ctypes.c_double * 3), ("h", ctypes.c_double * 3), ("n", ctypes.c_int32 * 3),
+                ("sys", ctypes.c_int32)]
+
+
+class PIParams(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("nrm", ctypes.c_double * 3), ("face", ctypes.c_double), ("kp", ctypes.c_double),
+                ("ki", ctypes.c_double), ("interval", ctypes.c_double), ("fade", ctypes.c_double)]
+
+
+class PParams(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("kp", ctypes.c_double), ("mass_flow", ctypes.c_int32)]
+
+
+# rows of a fields array (dem.h: DEM_F_*)
+F_COUNT, F_MASS, F_MOM, F_VOLUME, F_VMAX, F_STRESS, NFIELDS = 0, 1, 2, 5, 6, 7, 16
+
+
+def make_grid(lo, h, n, sys: int = 0) -> Grid:
+    g = Grid()
+    for a in range(3):
+        g.lo[a], g.h[a], g.n[a] = float(lo[a]), float(h[a]), int(n[a])
+    g.sys = int(sys)
+    return g
+
+
 _lib = None
 _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_batch_init", "dem_init_noalloc",
             "dem_reset", "dem_bin",
@@ -51,7 +78,8 @@ _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_b
             "dem_stats", "dem_set_timing", "dem_kernel_times", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
             "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
             "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
-            "dem_adjoint_destroy"]
+            "dem_adjoint_destroy", "dem_cell_fields", "dem_pi_control", "dem_p_control", "dem_set_external_force",
+            "dem_set_multirate"]
 
 
 def load(path: str = LIB_PATH):
@@ -83,6 +111,7 @@ def load(path: str = LIB_PATH):
     L.dem_step.argtypes = [vp, P(State), i64]
     L.dem_declare_forces.argtypes = [vp]
     L.dem_set_step_options.argtypes = [vp, ctypes.c_int, i32]
+    L.dem_set_multirate.argtypes = [vp, ctypes.c_int]
     L.dem_set_launch.argtypes = [vp, i32, i32]
     L.dem_check.argtypes = [vp, P(i64)]
     L.dem_stats.argtypes = [vp, P(i64)]
@@ -104,6 +133,10 @@ def load(path: str = LIB_PATH):
     L.dem_adjoint_set_lanes.argtypes = [vp, i32]
     L.dem_adjoint_info.argtypes = [vp, P(i64)]
     L.dem_adjoint_destroy.argtypes = [vp]
+    L.dem_cell_fields.argtypes = [vp, P(State), P(Grid), vp]
+    L.dem_pi_control.argtypes = [vp, P(State), P(PIParams), vp, vp, vp, vp]
+    L.dem_p_control.argtypes = [vp, P(State), P(PParams), vp, vp]
+    L.dem_set_external_force.argtypes = [vp, P(State), vp]
     for name in _SYMBOLS:
         if name != "dem_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -286,6 +319,11 @@ class DemSystem:
         with load_state), so that step() may start from them."""
         self._rc(self.L.dem_declare_forces(self.ctx))
 
+    def set_multirate(self, enable: bool = True):
+        """Each system of the batch steps with its own dt every dt / dt_min
+        substeps; step(n) then counts substeps of dt_min (dem_set_multirate)."""
+        self._rc(self.L.dem_set_multirate(self.ctx, int(enable)))
+
     def set_step_options(self, use_graph: bool, chunk: int = 64):
         self._rc(self.L.dem_set_step_options(self.ctx, int(use_graph), int(chunk)))
 
@@ -350,6 +388,45 @@ class DemSystem:
         a = np.empty(cnt.value, np.int32); xi = np.empty((cnt.value, 3))
         self._rc(self.L.dem_export_wall(self.ctx, self._state, _i32p(a), _dp(xi), cnt.value, ctypes.byref(cnt)))
         return a, xi
+
+    # ------------------------------------------------------------ coupling (Sec. 2.3)
+    def cell_fields(self, grid: Grid):
+        """Fields of the cells of `grid` at the current state: device tensor
+        (NFIELDS, ncell) with rows F_COUNT, F_MASS, F_MOM..+2, F_VOLUME, F_VMAX,
+        F_STRESS..+8 (sigma_ab of Eq. 7 at row F_STRESS + 3 a + b)."""
+        ncell = grid.n[0] * grid.n[1] * grid.n[2]
+        out = self.torch.empty((NFIELDS, ncell), dtype=self.torch.float64, device=self.device)
+        self.torch.cuda.current_stream(self.device).synchronize()
+        self._rc(self.L.dem_cell_fields(self.ctx, self._state, ctypes.byref(grid), _ptr(out)))
+        return out
+
+    def pi_control(self, params: PIParams, fine, coarse, integral, u=None):
+        """PI controller of the transition layer (fine system params.grid.sys):
+        updates `integral` (device, (ncell,)) in place, returns u (device)."""
+        ncell = params.grid.n[0] * params.grid.n[1] * params.grid.n[2]
+        if u is None:
+            u = self.torch.empty(ncell, dtype=self.torch.float64, device=self.device)
+        fine, coarse = fine.contiguous(), coarse.contiguous()
+        self.torch.cuda.current_stream(self.device).synchronize()
+        self._rc(self.L.dem_pi_control(self.ctx, self._state, ctypes.byref(params), _ptr(fine), _ptr(coarse),
+                                       _ptr(integral), _ptr(u)))
+        self.stream.synchronize()
+        return u
+
+    def p_control(self, params: PParams, fine, coarse):
+        """P controller of the coarse system params.grid.sys inside the fine region."""
+        fine, coarse = fine.contiguous(), coarse.contiguous()
+        self.torch.cuda.current_stream(self.device).synchronize()
+        self._rc(self.L.dem_p_control(self.ctx, self._state, ctypes.byref(params), _ptr(fine), _ptr(coarse)))
+        self.stream.synchronize()
+
+    def set_external_force(self, fext=None):
+        """External forces of all spheres, device (3, n) in the current order, or None."""
+        if fext is not None:
+            fext = fext.to(self.torch.float64).contiguous()
+            self.torch.cuda.current_stream(self.device).synchronize()
+        self._rc(self.L.dem_set_external_force(self.ctx, self._state, _ptr(fext)))
+        self.stream.synchronize()
 
     def set_materials(self, materials, sys: int = 0):
         """New per-type materials of system `sys` (objects with E, nu, rho, e, mu)."""

@@ -464,3 +464,31 @@ def test_paper_counts():
     assert abs(ref / (cg + fine) - g["multilevel_reduction"]) < 5e-3
     total = sum(g["five_level_full_system"] * (2 ** (l - 1)) ** -3 * 4 ** (l - 5) for l in range(1, 6))
     assert abs(total - g["five_level_total"]) < 0.01 * g["five_level_total"]
+
+
+@pytest.mark.parametrize("which", ["fcc", "bed", "chute"])
+def test_parallel_timing_leg_equals_serial_oracle(which):
+    """The all-cores gather form of the step (used only to time the oracle on
+    every host core) gives the serial oracle's state and histories bit for bit:
+    each pair evaluated from the higher id's side is the exact negative."""
+    if which == "fcc":
+        s = W.plain_fcc()
+    elif which == "bed":
+        s = W.settled_bed(seed=13, n=3000, footprint=12e-3)
+    else:
+        s = W.chute_adjoint(seed=14, n=2000, Lx=20e-3, Ly=14e-3)
+    a, b = O.Oracle(s), O.Oracle(s)
+    for o in (a, b):
+        o.forces(False)
+    a.step(120)
+    threads, seconds = b.step_parallel(60)
+    b.step_parallel(60)
+    assert threads >= 1 and seconds > 0.0
+    sa, sb = a.state(), b.state()
+    for k in ("x", "v", "w", "f", "t"):
+        assert np.array_equal(sa[k], sb[k]), k
+    for ha, hb in zip(a.history(), b.history()):
+        assert np.array_equal(ha, hb)
+    for ha, hb in zip(a.wall_history(), b.wall_history()):
+        assert np.array_equal(ha, hb)
+    assert len(a.history()[0]) > 100

@@ -155,6 +155,42 @@ def timed_steps(g, steps, warm):
     return time.perf_counter() - t0
 
 
+def coupled_run(g, cpl, steps):
+    """The two-level chute coupled (Sec. 2.3): every `interval_steps` steps the
+    cell fields of both levels on the transition layer and on the grid inside
+    the fine region, the PI controller on the fine spheres of the 10 mm shell and
+    the P controller (mass flow) on the coarse spheres, then the steps.  Returns
+    (wall seconds, seconds in the coupling calls)."""
+    import torch
+
+    from paper_1705_03850_amd import dem
+
+    k = cpl["interval_steps"]
+    pi_f, pi_c = dem.make_grid(*cpl["pi_grid"], sys=1), dem.make_grid(*cpl["pi_grid"], sys=0)
+    p_f, p_c = dem.make_grid(*cpl["p_grid"], sys=1), dem.make_grid(*cpl["p_grid"], sys=0)
+    pp = dem.PIParams()
+    pp.grid = pi_f
+    for a in range(3):
+        pp.nrm[a] = cpl["normal"][a]
+    pp.face, pp.kp, pp.ki, pp.fade = cpl["face"], cpl["kp"], cpl["ki"], cpl["fade"]
+    pp.interval = k * g.systems[1].dt
+    qp = dem.PParams()
+    qp.grid, qp.kp, qp.mass_flow = p_c, cpl["kp_coarse"], 1
+    n_pi = pi_f.n[0] * pi_f.n[1] * pi_f.n[2]
+    integral = torch.zeros(n_pi, dtype=torch.float64, device=g.device)
+    t_ctl = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // k):
+        tc = time.perf_counter()
+        g.pi_control(pp, g.cell_fields(pi_f), g.cell_fields(pi_c), integral)
+        g.p_control(qp, g.cell_fields(p_f), g.cell_fields(p_c))
+        t_ctl += time.perf_counter() - tc
+        g.step(k)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, t_ctl
+
+
 def batch_suite(args, emit=True):
     """Batched against plain on the same GPU (one JSON line).
 
@@ -166,7 +202,8 @@ def batch_suite(args, emit=True):
     Multi-rate: the same batch with every system stepping its own dt once every alpha substeps
     (all levels over the same simulated time), against the single-rate batch.
     Two-level chute (2e5 spheres alpha = 4 + 5e5 spheres alpha = 1): one 2-system batch against the two
-    systems one after another.  Launch shape, skin and cell come from the autotuner."""
+    systems one after another, and coupled (fields and controllers every 15 steps).  Launch shape, skin
+    and cell come from the autotuner."""
     import torch
 
     from paper_1705_03850_amd import autotune, dem
@@ -231,6 +268,13 @@ def batch_suite(args, emit=True):
         gk.prime()
         t_two_seq += timed_steps(gk, steps2, 64)
         del gk
+    log("two-level chute, coupled")
+    cpl = W.chute_coupling(*two)
+    g2c = dem.DemSystem(two, use_graph=True, chunk=8)
+    g2c.prime()
+    steps_c = steps2 - steps2 % cpl["interval_steps"]
+    t_cpl, t_ctl = coupled_run(g2c, cpl, steps_c)
+    del g2c
     out = {
         "suite": "batch", "unit": "particle-steps/s", "dtype": "f64", "data": "synthetic",
         "batch64": {"systems": len(systems), "particles": ntot, "steps": steps,
@@ -247,7 +291,12 @@ def batch_suite(args, emit=True):
                                   "list_builds": builds_mr}},
         "two_level_chute": {"particles": n2, "steps": steps2, "batched": n2 * steps2 / t_two,
                             "sequential_plain": n2 * steps2 / t_two_seq, "batched_vs_sequential": t_two_seq / t_two,
-                            "list_builds_batched": builds_two},
+                            "list_builds_batched": builds_two,
+                            "coupled": {"steps": steps_c, "interval_steps": cpl["interval_steps"],
+                                        "particle_steps_per_s": n2 * steps_c / t_cpl,
+                                        "coupling_fraction_of_time": t_ctl / t_cpl,
+                                        "transition_cells": list(cpl["pi_grid"][2]),
+                                        "fine_region_cells": list(cpl["p_grid"][2])}},
         "device": torch.cuda.get_device_name(0),
     }
     if emit:
@@ -541,7 +590,7 @@ def main():
                                                             "multirate")},
                    "two_level_chute": {k: b["two_level_chute"][k] for k in ("particles", "steps", "batched",
                                                                            "sequential_plain",
-                                                                           "batched_vs_sequential")}}
+                                                                           "batched_vs_sequential", "coupled")}}
         keys = ("workload", "steps", "window", "keep", "windows", "plain_forward_s", "adjoint_forward_s",
                 "backward_s", "adjoint_vs_plain", "adjoint_workspace_bytes", "context_workspace_bytes",
                 "peak_torch_bytes")

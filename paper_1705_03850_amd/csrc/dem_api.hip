@@ -162,6 +162,9 @@ Layout make_layout(const Geometry &g) {
     L.sel = take(g.sys.size() * 4);
     L.lcur = take(g.sys.size() * 4);
     L.tile0 = take((g.sys.size() + 1) * 8);
+    L.mtile0 = take((g.sys.size() + 1) * 8);
+    L.msys = take(g.sys.size() * 4);
+    L.mlevel = take(kMaxLevels * 8);
     L.total = o;
     return L;
 }
@@ -176,7 +179,24 @@ int upload_tiles(dem_ctx *c) {
         t0[s + 1] = t0[s] + (ns + ppb - 1) / ppb;
     }
     c->ntiles_b = t0.back();
+    // the same tiles in the order of the systems' strides (multi-rate stepping)
+    const size_t ns = c->geo.sys.size();
+    std::vector<int32_t> ms(ns);
+    for (size_t k = 0; k < ns; ++k) ms[k] = (int32_t)k;
+    std::stable_sort(ms.begin(), ms.end(),
+                     [&](int32_t p, int32_t q) { return c->geo.sys[p].stride < c->geo.sys[q].stride; });
+    std::vector<int64_t> mt(ns + 1, 0), lv(kMaxLevels, 0);
+    for (size_t k = 0; k < ns; ++k) mt[k + 1] = mt[k] + (t0[ms[k] + 1] - t0[ms[k]]);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        int64_t e = 0;
+        for (size_t k = 0; k < ns; ++k)
+            if (c->geo.sys[ms[k]].stride <= (1 << l)) e = mt[k + 1];
+        lv[l] = e;
+    }
     HIPCALL(c, hipMemcpyAsync(c->ws + c->lay.tile0, t0.data(), t0.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCALL(c, hipMemcpyAsync(c->ws + c->lay.mtile0, mt.data(), mt.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCALL(c, hipMemcpyAsync(c->ws + c->lay.msys, ms.data(), ms.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCALL(c, hipMemcpyAsync(c->ws + c->lay.mlevel, lv.data(), lv.size() * 8, hipMemcpyHostToDevice, c->stream));
     HIPCALL(c, hipStreamSynchronize(c->stream));
     return DEM_OK;
 }
@@ -220,6 +240,7 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.multirate = c->multirate ? 1 : 0;
     a.n = c->geo.n;
     a.ncell = c->geo.ncell;
+    a.call_steps = 0;
     a.w0 = c->win_on ? c->win[0] : 0;
     a.w1 = c->win_on ? c->win[1] : c->geo.n;
     a.cw0 = c->win_on ? c->win[2] : 0;
@@ -243,6 +264,9 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.im = (D2 *)(w + L.im);
     a.sel = (int32_t *)(w + L.sel);
     a.tile0 = (const int64_t *)(w + L.tile0);
+    a.mtile0 = (const int64_t *)(w + L.mtile0);
+    a.msys = (const int32_t *)(w + L.msys);
+    a.mlevel = (const int64_t *)(w + L.mlevel);
     a.ntiles_b = c->ntiles_b;
     a.lcur = (int32_t *)(w + L.lcur);
     return a;
@@ -638,7 +662,8 @@ int dem_set_multirate(dem_ctx *c, int enable) {
     HIPCALL(c, hipStreamSynchronize(c->stream));
     c->multirate = enable != 0 && c->geo.sys.size() > 1;
     c->max_stride = c->multirate ? mx : 1;
-    return DEM_OK;
+    for (GraphSlot &gs : c->graphs) gs.chunk = 0;   // re-capture
+    return upload_tiles(c);
 }
 
 int dem_set_step_options(dem_ctx *c, int use_graph, int32_t chunk) {
@@ -736,7 +761,9 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
                     pair1 = c->ev_used;
                     if ((rc = tic(c, 1))) return rc;
                 }
-                HIPCALL(c, launch_step(a, (int)((q - 1) & 1), last ? 2 : 1, (int)(q - q0), 1, cnt, c->stream));
+                KArgs al = a;
+                if (last) al.call_steps = nsteps;
+                HIPCALL(c, launch_step(al, (int)((q - 1) & 1), last ? 2 : 1, (int)(q - q0), 1, cnt, c->stream));
                 if (last) {
                     if ((rc = toc(c))) return rc;
                 } else {
@@ -788,8 +815,7 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
             q0 = q;
         }
     }
-    HIPCALL(c, launch_ctrl(c->d_flags, 3, nsteps, c->stream));
-    if ((rc = read_flags(c, h))) return rc;
+    // the flags read after the last group are final: its last launch counted the steps
     if ((rc = collect_times(c))) return rc;
     c->step_counter += nsteps;
     c->binned = false;

@@ -20,7 +20,7 @@ struct Layout {
     size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame, fext;
     size_t nbr[2], cnt[2], xi[2], mask[2], ids[2];
     size_t cell_of, rank, order, cell_count, cell_start, scan_partial, shadow_d, shadow_i;
-    size_t pos[2], vel[2], spin[2], im, sel, lcur, tile0;
+    size_t pos[2], vel[2], spin[2], im, sel, lcur, tile0, mtile0, msys, mlevel;
     size_t total;
 };
 

@@ -9,6 +9,9 @@ namespace dem {
 // external force (3 each), r, m, 1/m, 1/I
 constexpr int kShadowD = 28;
 
+// strides of multi-rate stepping: 1, 2, 4, ..., 2^(kMaxLevels - 1)
+constexpr int kMaxLevels = 11;
+
 // Everything a kernel may touch, passed by value.
 struct KArgs {
     // caller-owned particle arrays
@@ -34,6 +37,7 @@ struct KArgs {
     // window of the rebuild kernels (particles [w0, w1), cells [cw0, cw1)): the
     // index ranges of the systems selected for a rebuild; everything otherwise
     int64_t w0, w1, cw0, cw1;
+    int64_t call_steps;    // set only for the last step of a dem_step call: added to the step count
     Flags *flags;
     List lst[2];           // two list buffers; system s uses lst[lcur[s]], builds into the other
     int32_t *lcur;         // [nsys] current list buffer of each system
@@ -49,6 +53,13 @@ struct KArgs {
     // system s has tiles tile0[s] .. tile0[s+1]-1
     const int64_t *tile0;  // [nsys + 1]
     int64_t ntiles_b;
+    // multi-rate: the same tiles with the systems ordered by stride (msys[k] is the
+    // k-th system, its tiles mtile0[k] .. mtile0[k+1]-1), so that the tiles of the
+    // systems stepping at a substep form the prefix [0, mlevel[l]) for the largest
+    // l with 2^l dividing the substep's index
+    const int64_t *mtile0; // [nsys + 1]
+    const int32_t *msys;   // [nsys]
+    const int64_t *mlevel; // [kMaxLevels]
 };
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);

@@ -797,11 +797,17 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
         const int cnt = L.cnt[i];
         const uint64_t mask = L.mask[i];
         uint64_t nmask = 0;
+        // the neighbour index of the lane's next chunk is loaded one chunk ahead, so
+        // that its latency overlaps the current contact (294 -> 288 us per step on
+        // the 1e6-sphere bed; loading the velocity, spin and history before the
+        // contact test as well spills and was slower)
+        int32_t jn = g < cnt ? L.nbr[g * n + i] : (int32_t)i;
         for (int c0 = 0; c0 < cnt; c0 += G) {
             const int q = c0 + g;
             const bool valid = q < cnt;
             const int64_t slot = i * kmax + q;
-            const int32_t j = valid ? L.nbr[q * n + i] : (int32_t)i;
+            const int32_t j = jn;
+            jn = q + G < cnt ? L.nbr[(q + G) * n + i] : (int32_t)i;
             const D4 pj = P[j];
             ContactIn c;
             c.dx = min_image(pi.x - pj.x, s.L[0], s.hL[0], s.periodic[0]);
@@ -953,8 +959,16 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
     bool need = false, bad = false;
     // a batch is walked in tiles that each lie within one system, so that the
     // block's system descriptor is uniform too; it is read again only when a
-    // block moves on to a tile of another system
-    const int64_t ntiles = BATCH ? a.ntiles_b : (n + ppb - 1) / ppb;
+    // block moves on to a tile of another system.  Multi-rate: only the tiles of
+    // the systems that step at this substep, a prefix of the tiles in stride
+    // order, spread over the XCDs like all tiles otherwise
+    int64_t ntiles = BATCH ? a.ntiles_b : (n + ppb - 1) / ppb;
+    if (MR) {
+        const int64_t q1 = step - cbase - 1;
+        const int lvl = q1 == 0 ? kMaxLevels - 1 : min(__builtin_ctzll((unsigned long long)q1), kMaxLevels - 1);
+        ntiles = uniform_i64(a.mlevel[lvl]);
+    }
+    const int64_t *tt0 = MR ? a.mtile0 : a.tile0;
     const int per = gridDim.x / kXcd;
     const int64_t chunk = (ntiles + kXcd - 1) / kXcd;
     const int64_t t0 = (blockIdx.x % kXcd) * chunk;
@@ -967,26 +981,27 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
     if (!BATCH) load_step_coef(a, sd);
     for (int64_t t = t0 + blockIdx.x / kXcd; t < t1; t += per) {   // uniform over the block
         if (BATCH && (t < tlo || t >= thi)) {
-            int lo = 0, hi = a.nsys - 1;   // last system whose first tile is <= t
+            int lo = 0, hi = a.nsys - 1;   // last system (in the tile order) whose first tile is <= t
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (a.tile0[mid] <= t) lo = mid;
+                if (tt0[mid] <= t) lo = mid;
                 else hi = mid - 1;
             }
-            sy = __builtin_amdgcn_readfirstlane(lo);
+            const int k = __builtin_amdgcn_readfirstlane(lo);
+            sy = MR ? __builtin_amdgcn_readfirstlane(a.msys[k]) : k;
             sd = uniform_sys(a.sys + sy);
-            tlo = uniform_i64(a.tile0[sy]);
-            thi = uniform_i64(a.tile0[sy + 1]);
+            tlo = uniform_i64(tt0[k]);
+            thi = uniform_i64(tt0[k + 1]);
             lc = __builtin_amdgcn_readfirstlane(a.lcur[sy]);
             load_step_coef(a, sd);
         }
         int srcs = src;
         bool last = MODE == 2;
         if (MR) {
-            // multi-rate: the system steps at substeps 1, 1 + stride, ... of the call;
-            // its state alternates between the buffers at its own steps
+            // multi-rate: the system steps at substeps 1, 1 + stride, ... of the call
+            // (every tile walked here is one of a stepping system); its state
+            // alternates between the buffers at its own steps
             const int64_t q1 = step - cbase - 1;
-            if (q1 % sd.stride != 0) continue;
             srcs = (int)((q1 / sd.stride) & 1);
             last = step + sd.stride - 1 == send;
         }
@@ -998,6 +1013,8 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
     }
     if (bad) atomicOr(&a.flags->err, kErrNonFinite);
     if (MODE == 1 && need) a.flags->abort_at = step + 1;
+    // the call's last step ran: count the call's steps (no extra launch and synchronisation)
+    if (MODE != 0 && a.call_steps > 0 && blockIdx.x == 0 && threadIdx.x == 0) a.flags->steps += a.call_steps;
     if (COUNT) {
         // statistics only (contact-pair rate); the force sums above use no atomics
         __shared__ unsigned long long sc[2];

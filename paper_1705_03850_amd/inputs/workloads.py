@@ -320,6 +320,28 @@ def chute_two_level(seed: int = 3, n_fine: int = 500_000, n_coarse: int = 200_00
     return [coarse, fine]
 
 
+def chute_coupling(coarse: System, fine: System, shell: float = 10e-3, interval_steps: int = 15) -> dict:
+    """Coupling geometry of the two-level chute (plain numbers, no physics).
+
+    The fine region is the fine bed's footprint at the origin of the coarse
+    chute, from the floor to its initial top z_f.  The transition layer is the
+    shell of thickness `shell` below z_f, one layer of cells of about 50 mm
+    (the paper's cells are three to ten coarse diameters); the boundary face is
+    z = z_f with the normal -z into the fine region.  The coarse spheres inside
+    the fine region below the shell are corrected on cells of the same footprint
+    and about 35 mm height.  Coupling every `interval_steps` fine steps (the
+    paper updates its controller every 15 steps)."""
+    Lx, Ly = fine.hi[0] - fine.lo[0], fine.hi[1] - fine.lo[1]
+    zf = float(fine.x[:, 2].max())
+    nx, ny = max(1, int(round(Lx / 50e-3))), max(1, int(round(Ly / 50e-3)))
+    hx, hy = Lx / nx, Ly / ny
+    nz = max(1, int(round((zf - shell) / 35e-3)))
+    return {"pi_grid": ((0.0, 0.0, zf - shell), (hx, hy, shell), (nx, ny, 1)),
+            "p_grid": ((0.0, 0.0, 0.0), (hx, hy, (zf - shell) / nz), (nx, ny, nz)),
+            "normal": (0.0, 0.0, -1.0), "face": -zf, "fade": 1.5, "kp": 1.0, "ki": 200.0, "kp_coarse": 2000.0,
+            "interval_steps": interval_steps}
+
+
 def _deposit_job(args):
     """Worker: one bed from its own seed (used to build batches in parallel)."""
     n, r_args, Lx, Ly, strain, child = args

@@ -207,6 +207,69 @@ def test_two_level_chute_against_oracle():
         assert np.max(np.abs(d)) <= 1e-9 * max(s.hi[a] - s.lo[a] for a in range(3)), (k, np.max(np.abs(d)))
 
 
+def test_two_level_chute_coupled_against_oracle():
+    """The two-level chute at full size, coupled through its 10 mm shell: the
+    cell fields of both levels on the transition layer and inside the fine
+    region against the oracle's on the same (initial) state, then one coupling
+    interval (PI controller on the fine shell, P controller in mass-flow mode on
+    the coarse spheres, 15 steps) against the oracle's: positions within 1e-9 of
+    the largest box edge."""
+    import coupling as C
+    coarse, fine = systems = W.chute_two_level()
+    cpl = W.chute_coupling(coarse, fine)
+    g = dem().DemSystem(systems, use_graph=True, chunk=8)
+    g.prime()
+    oracles = [O.Oracle(s) for s in systems]
+    for o in oracles:
+        o.forces(False)
+    gf = {}
+    for name in ("pi_grid", "p_grid"):
+        for k, s in enumerate(systems):
+            got = g.cell_fields(dem().make_grid(*cpl[name], sys=k)).cpu().numpy()
+            ref = C.cell_fields(s, oracles[k], *cpl[name])
+            assert np.array_equal(got[0], ref["count"]) and ref["count"].sum() > 0, (name, k)
+            # sums over ~1e4 spheres per cell in two orders: differ by up to about count * eps
+            np.testing.assert_allclose(got[1], ref["mass"], rtol=1e-11)
+            scale = np.abs(ref["stress"]).max()
+            assert np.all(np.abs(got[7:16].T.reshape(-1, 3, 3) - ref["stress"]) <= 1e-11 * scale), (name, k)
+            gf[(name, k)] = ref
+    nrm, k_int = cpl["normal"], cpl["interval_steps"]
+    pp = dem().PIParams()
+    pp.grid = dem().make_grid(*cpl["pi_grid"], sys=1)
+    for a in range(3):
+        pp.nrm[a] = nrm[a]
+    pp.face, pp.kp, pp.ki, pp.fade, pp.interval = cpl["face"], cpl["kp"], cpl["ki"], cpl["fade"], k_int * fine.dt
+    qp = dem().PParams()
+    qp.grid, qp.kp, qp.mass_flow = dem().make_grid(*cpl["p_grid"], sys=0), cpl["kp_coarse"], 1
+    n_pi = int(np.prod(cpl["pi_grid"][2]))
+    integral = torch.zeros(n_pi, dtype=torch.float64, device=g.device)
+    g.pi_control(pp, g.cell_fields(dem().make_grid(*cpl["pi_grid"], sys=1)),
+                 g.cell_fields(dem().make_grid(*cpl["pi_grid"], sys=0)), integral)
+    g.p_control(qp, g.cell_fields(dem().make_grid(*cpl["p_grid"], sys=1)),
+                g.cell_fields(dem().make_grid(*cpl["p_grid"], sys=0)))
+    g.step(k_int)
+    of, oc = gf[("pi_grid", 1)], gf[("pi_grid", 0)]
+    u, _ = C.pi_update(C.normal_stress(oc["stress"], nrm), C.normal_stress(of["stress"], nrm), np.zeros(n_pi),
+                       cpl["kp"], cpl["ki"], k_int * fine.dt)
+    st = oracles[1].state()
+    m, _ = oracles[1].mass()
+    oracles[1].set_external(C.pi_forces(st["x"], st["v"], fine.r, m, fine.dt, *cpl["pi_grid"], nrm, cpl["face"],
+                                        cpl["fade"], u, oc["vmax"]))
+    stc = oracles[0].state()
+    mc, _ = oracles[0].mass()
+    oracles[0].set_external(C.p_forces(stc["x"], mc, *cpl["p_grid"], gf[("p_grid", 1)], gf[("p_grid", 0)],
+                                       cpl["kp_coarse"], True))
+    h = g.host()
+    for k, s in enumerate(systems):
+        oracles[k].step(k_int)
+        sl = slice(int(g.offsets[k]), int(g.offsets[k + 1]))
+        d = h["x"][sl] - by_id(s, oracles[k].state()["x"])
+        for ax in (0, 1):
+            Lk = s.hi[ax] - s.lo[ax]
+            d[:, ax] -= Lk * np.round(d[:, ax] / Lk)
+        assert np.max(np.abs(d)) <= 1e-9 * max(s.hi[a] - s.lo[a] for a in range(3)), (k, np.max(np.abs(d)))
+
+
 def test_full_batch_of_64_systems():
     """The 64-system batch at full size (3.8e6 spheres, alpha 1-8, dt = alpha
     1e-6 s): 300 steps with graph replay equal bit for bit to every system

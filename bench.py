@@ -191,6 +191,67 @@ def coupled_run(g, cpl, steps):
     return time.perf_counter() - t0, t_ctl
 
 
+def exchange_events(two, cpl, chunk, events=12, ncand=4096, interval=15):
+    """Insertion and deletion events on the fine level of the two-level chute
+    (Sec. 2.3): every `interval` steps one dem_exchange call on the fine system
+    (5e5 spheres, 65,536 free slots) with `ncand` candidates in a 5 mm slab
+    across its top face z_f over 4 x 2 boundary cells (seeded inflow fields,
+    budgets of up to 60 spheres per cell; spheres above z_f removed).  Wall
+    time of each synchronising call (removal, SSI, insertion, the system's list
+    rebuild and force pass), and the same system's plain forced rebuild for
+    scale."""
+    import torch
+
+    from paper_1705_03850_amd import dem
+    from paper_1705_03850_amd.inputs import workloads as W
+
+    fine = two[1]
+    zf = -cpl["face"]
+    g = dem.DemSystem(two, use_graph=True, chunk=chunk, capacity=[None, fine.n + 65536])
+    g.prime()
+    g.step(64)
+    budget = torch.zeros(8, dtype=torch.float64, device=g.device)
+    wall, ins, rem = [], [], []
+    for k in range(events):
+        ev = W.exchange_inputs(fine, zf + 4e-3, ncand, seed=100 + k, cells=(4, 2), budget_spheres=60.0,
+                               depth=5e-3)
+        p = dem.ExchangeParams()
+        for a in range(3):
+            p.nrm[a] = ev["nrm"][a]
+        p.face, p.slab, p.interval, p.ncell = -zf, ev["slab"], interval * fine.dt, ev["ncell"]
+        fields = torch.from_numpy(ev["fields"]).to(g.device)
+        cand = [torch.from_numpy(np.ascontiguousarray(a)).to(g.device)
+                for a in (ev["cand_x"], ev["cand_r"], ev["cand_type"], ev["cand_cell"])]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, i, r = g.exchange(1, p, fields, budget, *cand)
+        wall.append(time.perf_counter() - t0)
+        ins.append(i)
+        rem.append(r)
+        g.step(interval)
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter()
+    g.step(64 * 4)
+    torch.cuda.synchronize()
+    t_steps = (time.perf_counter() - t_steps) / 256
+    # the plain forced rebuild of the whole context, for scale
+    reb = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.build_list()
+        g.forces(False)
+        torch.cuda.synchronize()
+        reb.append(time.perf_counter() - t0)
+    w = sorted(wall[2:])
+    return {"events": events, "candidates": ncand, "interval_steps": interval,
+            "event_ms_median": 1e3 * w[len(w) // 2], "event_ms_max": 1e3 * max(wall[2:]),
+            "inserted_mean": float(np.mean(ins)), "removed_mean": float(np.mean(rem)),
+            "live_fine_after": g.live(1), "step_ms": 1e3 * t_steps,
+            "rebuild_and_forces_ms_median": 1e3 * sorted(reb)[2],
+            "event_vs_interval_steps": w[len(w) // 2] / (interval * t_steps)}
+
+
 def batch_suite(args, emit=True):
     """Batched against plain on the same GPU (one JSON line).
 
@@ -275,6 +336,8 @@ def batch_suite(args, emit=True):
     steps_c = steps2 - steps2 % cpl["interval_steps"]
     t_cpl, t_ctl = coupled_run(g2c, cpl, steps_c)
     del g2c
+    log("two-level chute, insertion events")
+    exch = exchange_events(two, cpl, args.chunk)
     out = {
         "suite": "batch", "unit": "particle-steps/s", "dtype": "f64", "data": "synthetic",
         "batch64": {"systems": len(systems), "particles": ntot, "steps": steps,
@@ -296,7 +359,8 @@ def batch_suite(args, emit=True):
                                         "particle_steps_per_s": n2 * steps_c / t_cpl,
                                         "coupling_fraction_of_time": t_ctl / t_cpl,
                                         "transition_cells": list(cpl["pi_grid"][2]),
-                                        "fine_region_cells": list(cpl["p_grid"][2])}},
+                                        "fine_region_cells": list(cpl["p_grid"][2])},
+                            "exchange": exch},
         "device": torch.cuda.get_device_name(0),
     }
     if emit:
@@ -590,7 +654,8 @@ def main():
                                                             "multirate")},
                    "two_level_chute": {k: b["two_level_chute"][k] for k in ("particles", "steps", "batched",
                                                                            "sequential_plain",
-                                                                           "batched_vs_sequential", "coupled")}}
+                                                                           "batched_vs_sequential", "coupled",
+                                                                           "exchange")}}
         keys = ("workload", "steps", "window", "keep", "windows", "plain_forward_s", "adjoint_forward_s",
                 "backward_s", "adjoint_vs_plain", "adjoint_workspace_bytes", "context_workspace_bytes",
                 "peak_torch_bytes")

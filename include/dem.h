@@ -20,10 +20,13 @@
  *   - Particle arrays are device memory owned by the caller, structure of
  *     arrays: a vector field V of n particles is V[0..n) = x components,
  *     V[n..2n) = y, V[2n..3n) = z.
- *   - A batch of S systems concatenates the systems' particles: system s owns
- *     the index range [off_s, off_s + n_s) with off_0 = 0 in the order of the
- *     configurations passed to dem_batch_init.  Every call below acts on all
- *     systems of the context.
+ *   - A batch of S systems concatenates the systems' particle slots: system s
+ *     owns the index range [off_s, off_s + m_s), m_s = dem_config.n_max (n when
+ *     0), with off_0 = 0 in the order of the configurations passed to
+ *     dem_batch_init.  Its live particles are the first slots of that range,
+ *     [off_s, off_s + live_s): n of them at first; dem_exchange changes the
+ *     count (dem_live_count reads it).  Slots past the live ones are ignored
+ *     by every call.  Every call below acts on all systems of the context.
  *   - Ids must be unique across the whole context (all systems of a batch)
  *     and non-negative.  dem_bin permutes the caller's particle arrays (within
  *     each system); compare results by id.
@@ -90,6 +93,8 @@ typedef struct dem_config {
     int64_t n;                         /* particle count, >= 0                          */
     int32_t k_max;                     /* neighbour slots per particle, 1..63           */
     int32_t block;                     /* threads per block: 64, 128, 256; 0 = 256      */
+    int64_t n_max;                     /* particle slots, >= n (room for insertion);
+                                          0 = n                                          */
 } dem_config;
 
 /* Caller-owned device arrays of the particles (see Conventions). */
@@ -368,6 +373,70 @@ int dem_p_control(dem_ctx *ctx, const dem_state *s, const dem_p_params *p, const
  * with the spheres when dem_bin reorders them.  The reverse mode refuses
  * contexts with external forces (DEM_ERR_STATE). */
 int dem_set_external_force(dem_ctx *ctx, const dem_state *s, const double *fext);
+
+/* ---------------------------------------------------------------------------
+ * Insertion and deletion at the boundary of the fine region (Sec. 2.3).
+ *
+ * The paper measures the coarse particles' mass flow and velocity per cell of
+ * the fine region's boundary surface, Favre-averages the velocity, inserts
+ * fine particles cell by cell by simple sequential inhibition (SSI) and
+ * removes fine particles that leave the region.  One dem_exchange call does
+ * one such event on one system of the context (readings of the repository's
+ * design notes):
+ *   1. budget: with interval > 0 each boundary cell c gains the inflowing
+ *      mass max(0, nrm . P_c) / slab * interval, P_c the momentum sum of the
+ *      fields given (the coarse level's fields on the boundary cells, of
+ *      dem_cell_fields);
+ *   2. removal: every live sphere of the system whose centre has
+ *      (x nrm_x + y nrm_y) + z nrm_z < face is removed, with its history;
+ *   3. SSI: candidate k (in the given order) is accepted iff its mass
+ *      (4/3) pi rho r^3 is at most its cell's remaining budget and it
+ *      overlaps neither a kept sphere nor a candidate accepted before it:
+ *      d^2 < (r_k + r_j)^2 with d^2 = (dx dx + dy dy) + dz dz, dx the
+ *      minimum image on periodic axes; an accepted candidate's mass is taken
+ *      from its cell's budget;
+ *   4. the accepted candidates are appended after the live spheres in
+ *      candidate order with ids M + 1, M + 2, ... (M the largest id of the
+ *      context's live spheres before the call), the Favre velocity P_c / M_c
+ *      of their cell (zero where the cell holds no mass), no spin, zero force,
+ *      torque, external force and history;
+ *   5. the system's neighbour list is rebuilt (the kept pairs keep their
+ *      history, by id) and its forces are evaluated at the new state without
+ *      a history update, as dem_forces(ctx, s, 0) would; the other systems of
+ *      the context are not touched (their state and forces stay bit for bit
+ *      as they were).
+ * ------------------------------------------------------------------------- */
+
+typedef struct dem_exchange_params {
+    double nrm[3];      /* unit normal of the boundary face, pointing into the fine region       */
+    double face;        /* the region is x . nrm >= face; spheres below are removed               */
+    double slab;        /* height of the inflow slab on the coarse side (m), > 0 when interval > 0 */
+    double interval;    /* coupling interval (s); 0: no budget top-up (step 1 skipped)             */
+    int64_t ncell;      /* boundary cells: rows of fields, entries of budget, range of cand_cell   */
+} dem_exchange_params;
+
+/* One insertion and deletion event on system `sys` (synchronises).
+ *   fields     device [DEM_NFIELDS][ncell]: the coarse level's cell fields
+ *              (DEM_F_MASS and DEM_F_MOM rows are read);
+ *   budget     device [ncell], in/out: the mass each boundary cell may still
+ *              insert (carried over between calls by the caller);
+ *   ncand      candidates, 0 .. 2^20; cand_x device [3][ncand] positions (on
+ *              periodic axes inside the box [lo, hi)), cand_r [ncand] radii in
+ *              (0, r_max], cand_type [ncand] material indices, cand_cell
+ *              [ncand] boundary cells in [0, ncell);
+ *   accepted   device [ncand], out: 1 for an accepted candidate, else 0;
+ *   counts     host int64[3], out: inserted, removed, live spheres after.
+ * Requires the forces of the current state (the list then matches the
+ * positions): DEM_ERR_STATE otherwise.  DEM_ERR_ARG for a bad candidate or
+ * parameter, DEM_ERR_CAPACITY when the accepted spheres do not fit the
+ * system's free slots or the candidates the workspace's scratch; on any
+ * error nothing is changed (budget and accepted included). */
+int dem_exchange(dem_ctx *ctx, const dem_state *s, int32_t sys, const dem_exchange_params *p, const double *fields,
+                 double *budget, int64_t ncand, const double *cand_x, const double *cand_r, const int32_t *cand_type,
+                 const int32_t *cand_cell, int32_t *accepted, int64_t counts[3]);
+
+/* Live particles of system `sys` (host copy, no device work). */
+int dem_live_count(dem_ctx *ctx, int32_t sys, int64_t *n);
 
 /* ---------------------------------------------------------------------------
  * Material parameters and gradients with respect to them.

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdem.so")
-SOURCES = ["dem_kernels.hip", "dem_api.hip", "dem_adjoint.hip", "dem_adjoint_api.hip", "dem_coupling.hip"]
+SOURCES = ["dem_kernels.hip", "dem_api.hip", "dem_adjoint.hip", "dem_adjoint_api.hip", "dem_coupling.hip",
+           "dem_exchange.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

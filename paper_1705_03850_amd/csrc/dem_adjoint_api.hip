@@ -110,6 +110,8 @@ int32_t default_windows(int64_t nsteps, int32_t window) {
 int adj_args(dem_ctx *c, int64_t nsteps, int32_t window, int32_t &max_windows) {
     if (!c) return DEM_ERR_ARG;
     if (c->geo.sys.size() != 1) return fail(c, DEM_ERR_ARG, "the adjoint rollout takes a context of one system");
+    if (c->geo.sys[0].p1 != c->geo.sys[0].pe)
+        return fail(c, DEM_ERR_ARG, "the adjoint rollout takes a system without free slots");
     if (nsteps < 1) return fail(c, DEM_ERR_ARG, "nsteps must be >= 1");
     if (window < 1 || window > 4096) return fail(c, DEM_ERR_ARG, "window must be in 1..4096");
     if (max_windows == 0) max_windows = default_windows(nsteps, window);
@@ -339,6 +341,8 @@ int dem_rollout_forward(dem_adjoint *A, const dem_state *s) {
     if (rc) return rc;
     if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first");
     if (c->fext_on) return fail(c, DEM_ERR_STATE, "the reverse mode does not take external forces");
+    if (c->geo.sys[0].pe != c->geo.sys[0].p1)
+        return fail(c, DEM_ERR_STATE, "the reverse mode takes a system without free slots");
     A->nck = 0;
     A->ntopo = 0;
     A->rebuilds = 0;
@@ -541,6 +545,8 @@ int dem_forces_vjp(dem_adjoint *A, const dem_state *s, const double *fb, const d
     if (rc) return rc;
     if (!fb || !tb || !xb || !vb || !wb) return fail(c, DEM_ERR_ARG, "an adjoint array is NULL");
     if (c->fext_on) return fail(c, DEM_ERR_STATE, "the reverse mode does not take external forces");
+    if (c->geo.sys[0].pe != c->geo.sys[0].p1)
+        return fail(c, DEM_ERR_STATE, "the reverse mode takes a system without free slots");
     if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_forces_vjp needs a neighbour list for the current order");
     if (c->geo.n == 0) return DEM_OK;
     const int64_t n = c->geo.n, K = c->geo.kmax;

@@ -66,6 +66,8 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         if (!(c.skin > 0.0)) { err = "skin must be > 0"; return DEM_ERR_ARG; }
         if (!(c.r_max > 0.0)) { err = "r_max must be > 0"; return DEM_ERR_ARG; }
         if (c.n < 0) { err = "n must be >= 0"; return DEM_ERR_ARG; }
+        const int64_t slots = c.n_max == 0 ? c.n : c.n_max;
+        if (slots < c.n) { err = "n_max must be 0 or >= n"; return DEM_ERR_ARG; }
         if (c.k_max < 1 || c.k_max > kMaxSlots) { err = "k_max must be in 1..63"; return DEM_ERR_ARG; }
         if ((c.block == 0 ? 256 : c.block) != g.block) { err = "all systems of a batch need the same block size"; return DEM_ERR_ARG; }
         const double cut = cutoff_of(c);
@@ -101,8 +103,10 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         d.hdt = 0.5 * c.dt;
         d.skin = c.skin;
         d.disp_thr2 = (0.5 * c.skin) * (0.5 * c.skin);
+        d.rmax = c.r_max;
         d.p0 = g.n;
-        d.p1 = g.n + c.n;
+        d.p1 = g.n + slots;
+        d.pe = g.n + c.n;
         d.c0 = g.ncell;
         d.wall = c.wall_z0 ? 1 : 0;
         d.stride = 1;
@@ -114,8 +118,8 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         for (int t = 0; t < c.ntypes; ++t) g.rho.push_back(c.mat[t].rho);
         for (int t = 0; t < c.ntypes; ++t) g.mat.push_back(c.mat[t]);
         g.sys.push_back(d);
-        g.n += c.n;
-        g.ncell += cells;
+        g.n += slots;
+        g.ncell += cells + 1;   // the system's cells and its spare cell
         g.kmax = std::max(g.kmax, c.k_max);
     }
     if (g.n > INT32_MAX / 2 || g.ncell > INT32_MAX / 2) { err = "problem too large for 32-bit indices"; return DEM_ERR_ARG; }
@@ -137,6 +141,7 @@ Layout make_layout(const Geometry &g) {
     L.disp = take(3 * n * 8);
     L.xiw = take(3 * n * 8);
     L.frame = take(n * 4);
+    L.dead = take(n * 4);
     L.fext = take(3 * n * 8);
     for (int b = 0; b < 2; ++b) {
         L.nbr[b] = take(K * n * 4);
@@ -224,6 +229,7 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.disp = (double *)(w + L.disp);
     a.xiw = (double *)(w + L.xiw);
     a.frame = (int32_t *)(w + L.frame);
+    a.dead = (int32_t *)(w + L.dead);
     a.fext_ws = (double *)(w + L.fext);
     a.fext = c->fext_on ? a.fext_ws : nullptr;
     a.sys = c->d_sys;
@@ -241,6 +247,7 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.n = c->geo.n;
     a.ncell = c->geo.ncell;
     a.call_steps = 0;
+    a.only_sys = -1;
     a.w0 = c->win_on ? c->win[0] : 0;
     a.w1 = c->win_on ? c->win[1] : c->geo.n;
     a.cw0 = c->win_on ? c->win[2] : 0;
@@ -379,7 +386,7 @@ int set_rebuild_window(dem_ctx *c) {
     for (size_t k = 0; k < sel.size(); ++k) {
         if (!sel[k]) continue;
         const SysDesc &d = c->geo.sys[k];
-        const int64_t cells = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+        const int64_t cells = (int64_t)d.nc[0] * d.nc[1] * d.nc[2] + 1;   // with the spare cell
         w0 = std::min(w0, d.p0);
         w1 = std::max(w1, d.p1);
         cw0 = std::min(cw0, d.c0);
@@ -580,6 +587,7 @@ int dem_reset(dem_ctx *c, const dem_state *s) {
     HIPCALL(c, launch_init_mass(a, c->stream));
     HIPCALL(c, launch_fill_f64(a.disp, 3 * c->geo.n, 0.0, c->stream));
     HIPCALL(c, launch_fill_f64(a.xiw, 3 * c->geo.n, 0.0, c->stream));
+    HIPCALL(c, launch_fill_i32(a.dead, c->geo.n, 0, c->stream));
     HIPCALL(c, launch_fill_i32(a.sel, (int64_t)c->geo.sys.size(), 0, c->stream));
     HIPCALL(c, launch_fill_i32(a.lcur, (int64_t)c->geo.sys.size(), 0, c->stream));
     Flags h;
@@ -872,7 +880,7 @@ int dem_stats(dem_ctx *c, int64_t out[5]) {
         }
         HIPCALL(c, hipMemcpy(cur.data(), c->ws + c->lay.lcur, cur.size() * 4, hipMemcpyDeviceToHost));
         for (size_t sy = 0; sy < c->geo.sys.size(); ++sy)
-            for (int64_t i = c->geo.sys[sy].p0; i < c->geo.sys[sy].p1; ++i) slots += cnt[cur[sy] & 1][i];
+            for (int64_t i = c->geo.sys[sy].p0; i < c->geo.sys[sy].pe; ++i) slots += cnt[cur[sy] & 1][i];
     }
     out[4] = slots;
     return DEM_OK;
@@ -883,7 +891,7 @@ int dem_stats(dem_ctx *c, int64_t out[5]) {
 namespace {
 
 struct HostList {
-    std::vector<uint8_t> which;
+    std::vector<uint8_t> which, live;
     std::vector<int32_t> nbr, cnt, ids, id_now;
     std::vector<uint64_t> mask;
     std::vector<double> xi, x, r, xiw;
@@ -897,8 +905,12 @@ int fetch_list(dem_ctx *c, const dem_state *s, HostList &H, bool with_xi, bool w
     std::vector<int32_t> cur(c->geo.sys.size());
     HIPCALL(c, hipMemcpy(cur.data(), c->ws + c->lay.lcur, cur.size() * 4, hipMemcpyDeviceToHost));
     H.which.assign(n, 0);
+    H.live.assign(n, 0);
     for (size_t sy = 0; sy < c->geo.sys.size(); ++sy)
-        for (int64_t i = c->geo.sys[sy].p0; i < c->geo.sys[sy].p1; ++i) H.which[i] = (uint8_t)(cur[sy] & 1);
+        for (int64_t i = c->geo.sys[sy].p0; i < c->geo.sys[sy].p1; ++i) {
+            H.which[i] = (uint8_t)(cur[sy] & 1);
+            H.live[i] = i < c->geo.sys[sy].pe ? 1 : 0;
+        }
     H.nbr.resize(K * n);
     H.cnt.resize(n);
     H.ids.resize(n);
@@ -919,6 +931,12 @@ int fetch_list(dem_ctx *c, const dem_state *s, HostList &H, bool with_xi, bool w
         }
         for (int64_t i = 0; i < n; ++i) {
             if (H.which[i] != b) continue;
+            if (!H.live[i]) {   // a free slot: no row
+                H.cnt[i] = 0;
+                H.ids[i] = -1;
+                H.mask[i] = 0;
+                continue;
+            }
             H.cnt[i] = cnt[i];
             H.ids[i] = ids[i];
             H.mask[i] = mask[i];
@@ -1021,7 +1039,7 @@ int dem_export_wall(dem_ctx *c, const dem_state *s, int32_t *id, double *xi, int
     std::vector<Rec> out;
     for (int64_t i = 0; i < n; ++i) {
         const SysDesc &sd = c->geo.sys[sys_index(c->geo, i)];
-        if (!sd.wall || !(H.x[2 * n + i] < H.r[i])) continue;
+        if (!H.live[i] || !sd.wall || !(H.x[2 * n + i] < H.r[i])) continue;
         Rec r{H.ids[i], 0.0, 0.0, 0.0};
         if (H.mask[i] & kWallBit) { r.x = H.xiw[i]; r.y = H.xiw[n + i]; r.z = H.xiw[2 * n + i]; }
         out.push_back(r);
@@ -1062,7 +1080,7 @@ int dem_import_history(dem_ctx *c, const dem_state *s, int64_t npairs, const int
             H.xi[4 * (i * K + q) + 3] = 0.0;
             if (v[0] != 0.0 || v[1] != 0.0 || v[2] != 0.0) m |= 1ull << q;
         }
-        auto w = walls.find(H.ids[i]);
+        auto w = H.live[i] ? walls.find(H.ids[i]) : walls.end();
         double v[3] = {0.0, 0.0, 0.0};
         if (w != walls.end()) for (int d = 0; d < 3; ++d) v[d] = wall_xi[3 * w->second + d];
         for (int d = 0; d < 3; ++d) H.xiw[d * n + i] = v[d];

@@ -27,15 +27,18 @@ struct PairCoef {
     double pad[3];
 };
 
-// One system of a batch.  Cells of system s occupy [c0, c0 + nc0*nc1*nc2).
+// One system of a batch.  Cells of system s occupy [c0, c0 + nc0*nc1*nc2 + 1).
 struct SysDesc {
     double lo[3], hi[3], L[3], hL[3];
     double inv_w[3];        // cells per metre along each axis (nc / L)
     double g[3];
     double dt, hdt;
     double skin, disp_thr2; // rebuild when |disp|^2 > (skin/2)^2
-    int64_t p0, p1;         // particle range
-    int64_t c0;             // first global cell
+    double rmax;            // largest radius the system admits
+    int64_t p0, p1;         // particle slots
+    int64_t pe;             // end of the live particles, p0 <= pe <= p1 (slots after it are free)
+    int64_t c0;             // first global cell; the system's cells, then one spare cell
+                            // (index c0 + nc0 nc1 nc2) that the binning gives the free slots
     int32_t nc[3];
     int32_t periodic[3];
     int32_t wall;
@@ -60,7 +63,11 @@ struct Flags {
     int32_t pad0;
     int64_t call_base;      // multi-rate: step number before the first substep of the current dem_step
     int64_t step_end;       // multi-rate: step number of the call's last substep
-    int64_t pad[5];
+    int64_t ex_removed;     // insertion event: spheres marked for removal
+    int64_t ex_accepted;    //   candidates accepted
+    int32_t ex_maxid;       //   largest live id of the context
+    int32_t ex_err;         //   bad candidate, too many overlapping candidates, stale list
+    int64_t pad[2];
 };
 
 // Neighbour list (ELL, slot-major: slot k of particle i at k*n + i).

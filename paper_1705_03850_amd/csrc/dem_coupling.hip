@@ -2,17 +2,20 @@
 // coarse-grain model (Sec. 2.3, Eq. (7)): kernels and the C-ABI calls
 // dem_cell_fields, dem_pi_control, dem_p_control and dem_set_external_force.
 //
-// Fields: one workgroup per cell of the grid.  Its spheres are found through
-// the list's binning (the particle range of every bin row that the cell,
-// widened by one bin on each side, touches: spheres stay within one bin of
-// their binned position until the next rebuild), and the block's threads take
-// the candidates in turn.  Each thread sums its own spheres, then the block
-// adds the threads' sums in a fixed tree: the result depends on nothing but
-// the state and the grid.  A first pass gives mass and momentum, hence the
-// Favre velocity; the second the kinetic and contact parts of Eq. (7), the
-// contact forces evaluated as in a force pass without history update.
+// Fields: the spheres of a cell are found through the list's binning (the
+// particle range of every bin row that the cell, widened by one bin on each
+// side, touches: spheres stay within one bin of their binned position until
+// the next rebuild).  A cell's bin rows are dealt to S workgroups (S from the
+// cell count: few large cells still fill the device), whose threads take the
+// candidates in turn; each thread sums its own spheres, the block adds the
+// threads' sums in a fixed tree and a second kernel adds the S slices in
+// order: the result depends on nothing but the state, the grid and the
+// workspace size.  A first pass gives mass and momentum, hence the Favre
+// velocity; the second the kinetic and contact parts of Eq. (7), the contact
+// forces evaluated as in a force pass without history update.
 // Controllers: one thread per cell updates the PI state; one thread per
 // sphere of the system writes its external force.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -98,134 +101,201 @@ __device__ inline double block_reduce(double v, double *lds, int op) {
     return lds[0];
 }
 
-// Calls visit(p) for every candidate sphere index p of a cell, the block's
-// threads taking them in turn (the same loop bounds in every thread).
-template <class F>
-__device__ inline void for_candidates(const KArgs &a, const SysDesc &sd, const Pieces &X, const Pieces &Y,
-                                      const Pieces &Z, F visit) {
-    const int32_t *cs = a.cell_start;
-    for (int pz = 0; pz < Z.np; ++pz)
-        for (int bz = Z.s[pz]; bz <= Z.e[pz]; ++bz)
-            for (int py = 0; py < Y.np; ++py)
-                for (int by = Y.s[py]; by <= Y.e[py]; ++by) {
-                    const int64_t row = sd.c0 + ((int64_t)bz * sd.nc[1] + by) * sd.nc[0];
-                    for (int px = 0; px < X.np; ++px) {
-                        const int32_t beg = cs[row + X.s[px]], end = cs[row + X.e[px] + 1];
-                        for (int32_t p = beg + (int32_t)threadIdx.x; p < end; p += (int32_t)blockDim.x) visit(p);
-                    }
-                }
+// The bin rows (bz, by) a cell touches, numbered r = zi * RY + yi over the
+// pieces of Z and Y; slice b of S takes rows b, b + S, ...  Calls visit(p) for
+// every candidate sphere index p of those rows, the block's threads taking
+// them in turn (the same loop bounds in every thread).
+__device__ inline int piece_len(const Pieces &P) {
+    return (P.e[0] - P.s[0] + 1) + (P.np > 1 ? P.e[1] - P.s[1] + 1 : 0);
+}
+__device__ inline int piece_at(const Pieces &P, int k) {
+    const int l0 = P.e[0] - P.s[0] + 1;
+    return k < l0 ? P.s[0] + k : P.s[1] + (k - l0);
 }
 
-__global__ void __launch_bounds__(kFB) k_fields(KArgs a, FGrid g, double *out) {
+template <class F>
+__device__ inline void for_candidates(const KArgs &a, const SysDesc &sd, const Pieces &X, const Pieces &Y,
+                                      const Pieces &Z, int b, int S, F visit) {
+    const int32_t *cs = a.cell_start;
+    const int RY = piece_len(Y), R = piece_len(Z) * RY;
+    for (int r = b; r < R; r += S) {
+        const int bz = piece_at(Z, r / RY), by = piece_at(Y, r % RY);
+        const int64_t row = sd.c0 + ((int64_t)bz * sd.nc[1] + by) * sd.nc[0];
+        for (int px = 0; px < X.np; ++px) {
+            const int32_t beg = cs[row + X.s[px]], end = cs[row + X.e[px] + 1];
+            for (int32_t p = beg + (int32_t)threadIdx.x; p < end; p += (int32_t)blockDim.x) visit(p);
+        }
+    }
+}
+
+// Sums of one cell's slice: pass 1 (count, mass, momentum, solids volume,
+// largest speed), pass 2 (Eq. (7): contact part 1/2 d (x) f over every contact
+// of the cell's spheres, kinetic part m v' (x) v' with v' = v - u, u the
+// cell's Favre velocity).
+constexpr int kP1 = 7, kP2 = 15;
+
+struct CellBox {
+    Pieces X, Y, Z;
+};
+
+__device__ inline CellBox cell_box(const SysDesc &sd, const FGrid &g, int64_t cell) {
+    const int64_t c0 = cell % g.n[0], c1 = (cell / g.n[0]) % g.n[1], c2 = cell / ((int64_t)g.n[0] * g.n[1]);
+    const double b0[3] = {g.lo[0] + (double)c0 * g.h[0], g.lo[1] + (double)c1 * g.h[1], g.lo[2] + (double)c2 * g.h[2]};
+    CellBox B;
+    B.X = axis_pieces(sd, 0, b0[0], b0[0] + g.h[0], 1.0 / sd.inv_w[0]);
+    B.Y = axis_pieces(sd, 1, b0[1], b0[1] + g.h[1], 1.0 / sd.inv_w[1]);
+    B.Z = axis_pieces(sd, 2, b0[2], b0[2] + g.h[2], 1.0 / sd.inv_w[2]);
+    return B;
+}
+
+// Block (cell, b): slice b of S of the cell's rows.  S = 1 writes the cell's
+// rows of `out` directly; S > 1 writes the slice's sums to part[(cell S + b) kP1].
+__global__ void __launch_bounds__(kFB) k_fields1(KArgs a, FGrid g, int S, double *part, double *out) {
     __shared__ double lds[kFB];
     const SysDesc sd = a.sys[g.sys];
     const int64_t n = a.n;
+    const int64_t cell = blockIdx.x / S;
+    const int b = blockIdx.x % S;
+    if (cell >= g.ncell) return;
+    const CellBox B = cell_box(sd, g, cell);
+    double cnt = 0.0, mass = 0.0, px = 0.0, py = 0.0, pz = 0.0, vol = 0.0, vmax = 0.0;
+    for_candidates(a, sd, B.X, B.Y, B.Z, b, S, [&](int32_t i) {
+        if (field_cell(g, a.x[i], a.x[n + i], a.x[2 * n + i]) != cell) return;
+        const double m = a.m[i], r = a.r[i];
+        const double vx = a.v[i], vy = a.v[n + i], vz = a.v[2 * n + i];
+        cnt += 1.0;
+        mass += m;
+        px += m * vx;
+        py += m * vy;
+        pz += m * vz;
+        vol += 4.0 / 3.0 * M_PI * r * r * r;
+        vmax = fmax(vmax, sqrt(vx * vx + vy * vy + vz * vz));
+    });
+    double v[kP1] = {cnt, mass, px, py, pz, vol, vmax};
+    for (int k = 0; k < kP1; ++k) v[k] = block_reduce(v[k], lds, k == 6 ? 1 : 0);
+    if (threadIdx.x == 0) {
+        if (S == 1) {
+            const int64_t nc = g.ncell;
+            const int rows[kP1] = {DEM_F_COUNT, DEM_F_MASS, DEM_F_MOM, DEM_F_MOM + 1, DEM_F_MOM + 2, DEM_F_VOLUME,
+                                   DEM_F_VMAX};
+            for (int k = 0; k < kP1; ++k) out[rows[k] * nc + cell] = v[k];
+        } else {
+            for (int k = 0; k < kP1; ++k) part[(cell * S + b) * kP1 + k] = v[k];
+        }
+    }
+}
+
+// One thread per cell: the slices' sums added in slice order.
+__global__ void k_fields1_reduce(FGrid g, int S, const double *part, double *out) {
+    const int64_t nc = g.ncell;
+    const int rows[kP1] = {DEM_F_COUNT, DEM_F_MASS, DEM_F_MOM, DEM_F_MOM + 1, DEM_F_MOM + 2, DEM_F_VOLUME, DEM_F_VMAX};
+    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < nc;
+         cell += (int64_t)gridDim.x * blockDim.x) {
+        double v[kP1];
+        for (int k = 0; k < kP1; ++k) v[k] = part[(cell * S) * kP1 + k];
+        for (int b = 1; b < S; ++b)
+            for (int k = 0; k < kP1; ++k) {
+                const double q = part[(cell * S + b) * kP1 + k];
+                v[k] = k == 6 ? fmax(v[k], q) : v[k] + q;
+            }
+        for (int k = 0; k < kP1; ++k) out[rows[k] * nc + cell] = v[k];
+    }
+}
+
+__global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, double *part, double *out) {
+    __shared__ double lds[kFB];
+    const SysDesc sd = a.sys[g.sys];
+    const int64_t n = a.n;
+    const int64_t nc = g.ncell;
+    const int64_t cell = blockIdx.x / S;
+    const int b = blockIdx.x % S;
+    if (cell >= nc) return;
     const List L = (a.lcur[g.sys] & 1) ? a.lst[1] : a.lst[0];
     const int64_t kmax = a.kmax;
     const PairCoef *coef = a.coef + sd.coef0;
-    double margin[3];
-    for (int ax = 0; ax < 3; ++ax) margin[ax] = 1.0 / sd.inv_w[ax];
-    for (int64_t cell = blockIdx.x; cell < g.ncell; cell += gridDim.x) {
-        const int64_t c0 = cell % g.n[0], c1 = (cell / g.n[0]) % g.n[1], c2 = cell / ((int64_t)g.n[0] * g.n[1]);
-        const double b0[3] = {g.lo[0] + (double)c0 * g.h[0], g.lo[1] + (double)c1 * g.h[1],
-                              g.lo[2] + (double)c2 * g.h[2]};
-        const Pieces X = axis_pieces(sd, 0, b0[0], b0[0] + g.h[0], margin[0]);
-        const Pieces Y = axis_pieces(sd, 1, b0[1], b0[1] + g.h[1], margin[1]);
-        const Pieces Z = axis_pieces(sd, 2, b0[2], b0[2] + g.h[2], margin[2]);
-        // ---- pass 1: count, mass, momentum, solids volume, largest speed
-        double cnt = 0.0, mass = 0.0, px = 0.0, py = 0.0, pz = 0.0, vol = 0.0, vmax = 0.0;
-        for_candidates(a, sd, X, Y, Z, [&](int32_t i) {
-            if (field_cell(g, a.x[i], a.x[n + i], a.x[2 * n + i]) != cell) return;
-            const double m = a.m[i], r = a.r[i];
-            const double vx = a.v[i], vy = a.v[n + i], vz = a.v[2 * n + i];
-            cnt += 1.0;
-            mass += m;
-            px += m * vx;
-            py += m * vy;
-            pz += m * vz;
-            vol += 4.0 / 3.0 * M_PI * r * r * r;
-            vmax = fmax(vmax, sqrt(vx * vx + vy * vy + vz * vz));
-        });
-        cnt = block_reduce(cnt, lds, 0);
-        mass = block_reduce(mass, lds, 0);
-        px = block_reduce(px, lds, 0);
-        py = block_reduce(py, lds, 0);
-        pz = block_reduce(pz, lds, 0);
-        vol = block_reduce(vol, lds, 0);
-        vmax = block_reduce(vmax, lds, 1);
-        double ux = 0.0, uy = 0.0, uz = 0.0;   // Favre velocity
-        if (mass > 0.0) {
-            ux = px / mass;
-            uy = py / mass;
-            uz = pz / mass;
-        }
-        // ---- pass 2: Eq. (7), contact part (1/2 d (x) f over every contact of the
-        // cell's spheres) and kinetic part (m v' (x) v', v' = v - u)
-        double con[9], kin[6];
-        for (int k = 0; k < 9; ++k) con[k] = 0.0;
-        for (int k = 0; k < 6; ++k) kin[k] = 0.0;
-        for_candidates(a, sd, X, Y, Z, [&](int32_t i) {
-            const double xi = a.x[i], yi = a.x[n + i], zi = a.x[2 * n + i];
-            if (field_cell(g, xi, yi, zi) != cell) return;
-            const double m = a.m[i], ri = a.r[i];
-            const double vx = a.v[i], vy = a.v[n + i], vz = a.v[2 * n + i];
-            const double wx = a.w[i], wy = a.w[n + i], wz = a.w[2 * n + i];
-            const double qx = vx - ux, qy = vy - uy, qz = vz - uz;
-            kin[0] += m * qx * qx;
-            kin[1] += m * qx * qy;
-            kin[2] += m * qx * qz;
-            kin[3] += m * qy * qy;
-            kin[4] += m * qy * qz;
-            kin[5] += m * qz * qz;
-            const int ti = a.type[i];
-            const int rowlen = L.cnt[i];
-            const uint64_t mask = L.mask[i];
-            for (int q = 0; q < rowlen; ++q) {
-                const int32_t j = L.nbr[q * n + i];
-                ContactIn c;
-                c.dx = min_image(xi - a.x[j], sd.L[0], sd.hL[0], sd.periodic[0]);
-                c.dy = min_image(yi - a.x[n + j], sd.L[1], sd.hL[1], sd.periodic[1]);
-                c.dz = min_image(zi - a.x[2 * n + j], sd.L[2], sd.hL[2], sd.periodic[2]);
-                c.ra = ri;
-                c.rb = a.r[j];
-                c.ma = m;
-                c.mb = a.m[j];
-                c.vrx = vx - a.v[j];
-                c.vry = vy - a.v[n + j];
-                c.vrz = vz - a.v[2 * n + j];
-                c.wsx = ri * wx + c.rb * a.w[j];
-                c.wsy = ri * wy + c.rb * a.w[n + j];
-                c.wsz = ri * wz + c.rb * a.w[2 * n + j];
-                double hx = 0.0, hy = 0.0, hz = 0.0;
-                if ((mask >> q) & 1ull) {
-                    const D4 h = L.xi[i * kmax + q];
-                    hx = h.x; hy = h.y; hz = h.z;
-                }
-                double fx, fy, fz, ftx, fty, ftz, nx, ny, nz, fn;
-                if (!contact_force(c, false, coef[ti * sd.ntypes + a.type[j]], sd.dt, false, hx, hy, hz, fx, fy, fz,
-                                   ftx, fty, ftz, nx, ny, nz, fn))
-                    continue;
-                const double d[3] = {0.5 * c.dx, 0.5 * c.dy, 0.5 * c.dz};
-                const double f[3] = {fx, fy, fz};
-                for (int p = 0; p < 3; ++p)
-                    for (int q2 = 0; q2 < 3; ++q2) con[3 * p + q2] += d[p] * f[q2];
+    const CellBox B = cell_box(sd, g, cell);
+    // the cell's Favre velocity from pass 1
+    const double mass = out[DEM_F_MASS * nc + cell];
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+    if (mass > 0.0) {
+        ux = out[DEM_F_MOM * nc + cell] / mass;
+        uy = out[(DEM_F_MOM + 1) * nc + cell] / mass;
+        uz = out[(DEM_F_MOM + 2) * nc + cell] / mass;
+    }
+    double con[9], kin[6];
+    for (int k = 0; k < 9; ++k) con[k] = 0.0;
+    for (int k = 0; k < 6; ++k) kin[k] = 0.0;
+    for_candidates(a, sd, B.X, B.Y, B.Z, b, S, [&](int32_t i) {
+        const double xi = a.x[i], yi = a.x[n + i], zi = a.x[2 * n + i];
+        if (field_cell(g, xi, yi, zi) != cell) return;
+        const double m = a.m[i], ri = a.r[i];
+        const double vx = a.v[i], vy = a.v[n + i], vz = a.v[2 * n + i];
+        const double wx = a.w[i], wy = a.w[n + i], wz = a.w[2 * n + i];
+        const double qx = vx - ux, qy = vy - uy, qz = vz - uz;
+        kin[0] += m * qx * qx;
+        kin[1] += m * qx * qy;
+        kin[2] += m * qx * qz;
+        kin[3] += m * qy * qy;
+        kin[4] += m * qy * qz;
+        kin[5] += m * qz * qz;
+        const int ti = a.type[i];
+        const int rowlen = L.cnt[i];
+        const uint64_t mask = L.mask[i];
+        for (int q = 0; q < rowlen; ++q) {
+            const int32_t j = L.nbr[q * n + i];
+            ContactIn c;
+            c.dx = min_image(xi - a.x[j], sd.L[0], sd.hL[0], sd.periodic[0]);
+            c.dy = min_image(yi - a.x[n + j], sd.L[1], sd.hL[1], sd.periodic[1]);
+            c.dz = min_image(zi - a.x[2 * n + j], sd.L[2], sd.hL[2], sd.periodic[2]);
+            c.ra = ri;
+            c.rb = a.r[j];
+            c.ma = m;
+            c.mb = a.m[j];
+            c.vrx = vx - a.v[j];
+            c.vry = vy - a.v[n + j];
+            c.vrz = vz - a.v[2 * n + j];
+            c.wsx = ri * wx + c.rb * a.w[j];
+            c.wsy = ri * wy + c.rb * a.w[n + j];
+            c.wsz = ri * wz + c.rb * a.w[2 * n + j];
+            double hx = 0.0, hy = 0.0, hz = 0.0;
+            if ((mask >> q) & 1ull) {
+                const D4 h = L.xi[i * kmax + q];
+                hx = h.x; hy = h.y; hz = h.z;
             }
-        });
-        for (int k = 0; k < 9; ++k) con[k] = block_reduce(con[k], lds, 0);
-        for (int k = 0; k < 6; ++k) kin[k] = block_reduce(kin[k], lds, 0);
-        if (threadIdx.x == 0) {
-            const int64_t nc = g.ncell;
-            out[DEM_F_COUNT * nc + cell] = cnt;
-            out[DEM_F_MASS * nc + cell] = mass;
-            out[(DEM_F_MOM + 0) * nc + cell] = px;
-            out[(DEM_F_MOM + 1) * nc + cell] = py;
-            out[(DEM_F_MOM + 2) * nc + cell] = pz;
-            out[DEM_F_VOLUME * nc + cell] = vol;
-            out[DEM_F_VMAX * nc + cell] = vmax;
+            double fx, fy, fz, ftx, fty, ftz, nx, ny, nz, fn;
+            if (!contact_force(c, false, coef[ti * sd.ntypes + a.type[j]], sd.dt, false, hx, hy, hz, fx, fy, fz, ftx,
+                               fty, ftz, nx, ny, nz, fn))
+                continue;
+            const double d[3] = {0.5 * c.dx, 0.5 * c.dy, 0.5 * c.dz};
+            const double f[3] = {fx, fy, fz};
+            for (int p = 0; p < 3; ++p)
+                for (int q2 = 0; q2 < 3; ++q2) con[3 * p + q2] += d[p] * f[q2];
+        }
+    });
+    double v[kP2];
+    for (int k = 0; k < 9; ++k) v[k] = block_reduce(con[k], lds, 0);
+    for (int k = 0; k < 6; ++k) v[9 + k] = block_reduce(kin[k], lds, 0);
+    if (threadIdx.x == 0) {
+        if (S == 1) {
             // kinetic part: symmetric (m q_a q_b = m q_b q_a exactly)
             const int ksym[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
-            for (int k = 0; k < 9; ++k) out[(DEM_F_STRESS + k) * nc + cell] = (con[k] + kin[ksym[k]]) / g.vol;
+            for (int k = 0; k < 9; ++k) out[(DEM_F_STRESS + k) * nc + cell] = (v[k] + v[9 + ksym[k]]) / g.vol;
+        } else {
+            for (int k = 0; k < kP2; ++k) part[(cell * S + b) * kP2 + k] = v[k];
         }
+    }
+}
+
+__global__ void k_fields2_reduce(FGrid g, int S, const double *part, double *out) {
+    const int64_t nc = g.ncell;
+    const int ksym[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < nc;
+         cell += (int64_t)gridDim.x * blockDim.x) {
+        double v[kP2];
+        for (int k = 0; k < kP2; ++k) v[k] = part[(cell * S) * kP2 + k];
+        for (int b = 1; b < S; ++b)
+            for (int k = 0; k < kP2; ++k) v[k] += part[(cell * S + b) * kP2 + k];
+        for (int k = 0; k < 9; ++k) out[(DEM_F_STRESS + k) * nc + cell] = (v[k] + v[9 + ksym[k]]) / g.vol;
     }
 }
 
@@ -235,7 +305,7 @@ __global__ void k_fields_guard(KArgs a, int32_t sys) {
     const SysDesc &sd = a.sys[sys];
     const int64_t n = a.n;
     bool bad = false;
-    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.p1;
+    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.pe;
          i += (int64_t)gridDim.x * blockDim.x)
         for (int ax = 0; ax < 3; ++ax)
             if (!(fabs(a.disp[ax * n + i]) * sd.inv_w[ax] <= 1.0)) bad = true;
@@ -269,7 +339,7 @@ __global__ void k_pi_particles(KArgs a, FGrid g, const double *coarse, const dou
                                double nz, double face, double fade) {
     const SysDesc &sd = a.sys[g.sys];
     const int64_t n = a.n;
-    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.p1;
+    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.pe;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double x = a.x[i], y = a.x[n + i], z = a.x[2 * n + i];
         const int64_t c = field_cell(g, x, y, z);
@@ -301,7 +371,7 @@ __global__ void k_pi_particles(KArgs a, FGrid g, const double *coarse, const dou
 __global__ void k_p_particles(KArgs a, FGrid g, const double *fine, const double *coarse, double kp, int mass_flow) {
     const SysDesc &sd = a.sys[g.sys];
     const int64_t n = a.n, nc = g.ncell;
-    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.p1;
+    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.pe;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = field_cell(g, a.x[i], a.x[n + i], a.x[2 * n + i]);
         double F[3] = {0.0, 0.0, 0.0};
@@ -388,9 +458,20 @@ int dem_cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double
     HIPCALL(c, hipGetLastError());
     k_clear_call_err<<<1, 64, 0, c->stream>>>(c->d_flags);
     const SysDesc &sd = c->geo.sys[g.sys];
-    k_fields_guard<<<grid_blocks(sd.p1 - sd.p0, 256), 256, 0, c->stream>>>(a, g.sys);
-    const int64_t blocks = g.ncell < 65536 ? g.ncell : 65536;
-    k_fields<<<(int)blocks, kFB, 0, c->stream>>>(a, g, fields);
+    k_fields_guard<<<grid_blocks(sd.pe - sd.p0, 256), 256, 0, c->stream>>>(a, g.sys);
+    // slices per cell: enough blocks to fill the device when cells are few
+    // (a function of the cell count and the workspace only, so the sums' order
+    // is too); S = 1 writes the fields directly
+    const size_t scratch = (size_t)kShadowD * c->geo.n * 8;
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>(256, 4096 / g.ncell));
+    while (S > 1 && (size_t)g.ncell * S * kP2 * 8 > scratch) S /= 2;
+    double *part = (double *)(c->ws + c->lay.shadow_d);
+    const int64_t blocks = g.ncell * S;
+    if (blocks > INT32_MAX) return fail(c, DEM_ERR_ARG, "grid too large");
+    k_fields1<<<(int)blocks, kFB, 0, c->stream>>>(a, g, S, part, fields);
+    if (S > 1) k_fields1_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part, fields);
+    k_fields2<<<(int)blocks, kFB, 0, c->stream>>>(a, g, S, part, fields);
+    if (S > 1) k_fields2_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part, fields);
     HIPCALL(c, hipGetLastError());
     Flags h;
     if ((rc = read_flags(c, h))) return rc;
@@ -419,7 +500,7 @@ int dem_pi_control(dem_ctx *c, const dem_state *s, const dem_pi_params *p, const
     k_pi_cells<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, fine, coarse, p->nrm[0], p->nrm[1], p->nrm[2],
                                                                   p->kp, p->ki, p->interval, integral, u);
     const SysDesc &sd = c->geo.sys[g.sys];
-    k_pi_particles<<<grid_blocks(sd.p1 - sd.p0, 256), 256, 0, c->stream>>>(a, g, coarse, u, p->nrm[0], p->nrm[1],
+    k_pi_particles<<<grid_blocks(sd.pe - sd.p0, 256), 256, 0, c->stream>>>(a, g, coarse, u, p->nrm[0], p->nrm[1],
                                                                           p->nrm[2], p->face, p->fade);
     HIPCALL(c, hipGetLastError());
     return DEM_OK;
@@ -437,7 +518,7 @@ int dem_p_control(dem_ctx *c, const dem_state *s, const dem_p_params *p, const d
     if ((rc = enable_fext(c, a))) return rc;
     a = kargs(c, s);
     const SysDesc &sd = c->geo.sys[g.sys];
-    k_p_particles<<<grid_blocks(sd.p1 - sd.p0, 256), 256, 0, c->stream>>>(a, g, fine, coarse, p->kp,
+    k_p_particles<<<grid_blocks(sd.pe - sd.p0, 256), 256, 0, c->stream>>>(a, g, fine, coarse, p->kp,
                                                                          p->mass_flow ? 1 : 0);
     HIPCALL(c, hipGetLastError());
     return DEM_OK;

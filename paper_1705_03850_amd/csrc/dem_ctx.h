@@ -17,7 +17,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame, fext;
+    size_t sys, coef, rho, flags, m, inv_m, inv_I, disp, xiw, frame, dead, fext;
     size_t nbr[2], cnt[2], xi[2], mask[2], ids[2];
     size_t cell_of, rank, order, cell_count, cell_start, scan_partial, shadow_d, shadow_i;
     size_t pos[2], vel[2], spin[2], im, sel, lcur, tile0, mtile0, msys, mlevel;

@@ -19,7 +19,8 @@ struct KArgs {
     int32_t *type, *id;
     // library-owned per-particle arrays (workspace)
     double *m, *inv_m, *inv_I, *disp, *xiw;
-    int32_t *frame;        // index of each particle in the order of the last list build
+    int32_t *frame;        // index of each particle in the order of the last list build (-1: none)
+    int32_t *dead;         // [n] 1 = removed at the next binning of its system (insertion events)
     double *fext_ws;       // [3][n] external forces (workspace)
     const double *fext;    // fext_ws while external forces are on, else null
     // systems
@@ -38,6 +39,8 @@ struct KArgs {
     // index ranges of the systems selected for a rebuild; everything otherwise
     int64_t w0, w1, cw0, cw1;
     int64_t call_steps;    // set only for the last step of a dem_step call: added to the step count
+    int32_t only_sys;      // >= 0: the force pass of one system only (the others' f, t kept); -1: all
+    int32_t pad_k;
     Flags *flags;
     List lst[2];           // two list buffers; system s uses lst[lcur[s]], builds into the other
     int32_t *lcur;         // [nsys] current list buffer of each system
@@ -68,6 +71,9 @@ hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_ctrl(Flags *f, int op, int64_t value, hipStream_t st);
 hipError_t launch_init_mass(const KArgs &a, hipStream_t st);
 hipError_t launch_phase(const KArgs &a, int phase, int k, int gate, hipStream_t st);
+// exclusive scan of in[0..m) into out[0..m] (out[m] = total); partial holds
+// (m + 1023) / 1024 + 1 words
+hipError_t launch_scan(const int32_t *in, int64_t m, int32_t *partial, int32_t *out, hipStream_t st);
 hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st);
 hipError_t launch_neighbors(const KArgs &a, int have_old, hipStream_t st);
 // after a build: the selected systems switch to their new list buffer

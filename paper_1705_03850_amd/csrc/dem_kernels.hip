@@ -131,6 +131,7 @@ __global__ void k_init_mass(KArgs a) {
     bool bad = false;
     FOR_EACH_PARTICLE(a.n, i) {
         const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
+        if (i >= s.pe) continue;   // a free slot
         double r = a.r[i];
         int ty = a.type[i];
         if (ty < 0 || ty >= s.ntypes || a.id[i] < 0 || !(r > 0.0) || !isfinite(r)) {
@@ -166,6 +167,7 @@ __global__ void k_phase0(KArgs a, int k, int gate) {
     const int64_t n = a.n;
     FOR_EACH_PARTICLE(n, i) {
         const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
+        if (i >= s.pe) continue;
         double im = a.inv_m[i], iI = a.inv_I[i];
         double p[3], dsq = 0.0;
         for (int c = 0; c < 3; ++c) {
@@ -199,6 +201,7 @@ __global__ void k_phase1(KArgs a, int k, int gate) {
     const int64_t n = a.n;
     FOR_EACH_PARTICLE(n, i) {
         const SysDesc &s = a.sys[sys_of<BATCH>(a, i)];
+        if (i >= s.pe) continue;
         double im = a.inv_m[i], iI = a.inv_I[i];
         for (int c = 0; c < 3; ++c) {
             a.v[c * n + i] = a.v[c * n + i] + s.hdt * (a.f[c * n + i] * im);
@@ -227,10 +230,17 @@ __global__ void k_bin_count(KArgs a) {
         const int sy = sys_of<BATCH>(a, i);
         if (!a.sel[sy]) continue;
         const SysDesc &s = a.sys[sy];
-        int cx = cell_coord(a.x[i], s, 0);
-        int cy = cell_coord(a.x[n + i], s, 1);
-        int cz = cell_coord(a.x[2 * n + i], s, 2);
-        int64_t c = s.c0 + ((int64_t)cz * s.nc[1] + cy) * s.nc[0] + cx;
+        // free slots and removed particles go to the spare cell past the grid
+        // (removal marks are consumed here)
+        const bool gone = i >= s.pe || a.dead[i];
+        if (a.dead[i]) a.dead[i] = 0;
+        int64_t c = s.c0 + (int64_t)s.nc[0] * s.nc[1] * s.nc[2];
+        if (!gone) {
+            int cx = cell_coord(a.x[i], s, 0);
+            int cy = cell_coord(a.x[n + i], s, 1);
+            int cz = cell_coord(a.x[2 * n + i], s, 2);
+            c = s.c0 + ((int64_t)cz * s.nc[1] + cy) * s.nc[0] + cx;
+        }
         a.cell_of[i] = (int32_t)c;
         a.rank[i] = atomicAdd(&a.cell_count[c], 1);
     }
@@ -314,7 +324,10 @@ __global__ void k_bin_place(KArgs a) {
 __global__ void k_cell_sort(KArgs a) {
     for (int64_t c = a.cw0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.cw1;
          c += (int64_t)gridDim.x * blockDim.x) {
-        if (!a.sel[sys_of_cell(a, c)]) continue;
+        const int sy = sys_of_cell(a, c);
+        if (!a.sel[sy]) continue;
+        const SysDesc &s = a.sys[sy];
+        if (c == s.c0 + (int64_t)s.nc[0] * s.nc[1] * s.nc[2]) continue;   // the spare cell: free slots
         int32_t b = a.cell_start[c], e = a.cell_start[c + 1];
         if (e - b > kCellSortMax) {
             atomicOr(&a.flags->err, kErrCellOverflow);
@@ -495,11 +508,15 @@ __global__ void __launch_bounds__(kNbrBlock, 5) k_neighbors(KArgs a, int have_ol
         // selection test so that the loads overlap
         const int64_t ic = active ? i : 0;
         const D4 qi = Q[ic];
-        const int64_t o = have_old ? a.frame[ic] : 0;
+        const int64_t o0 = have_old ? a.frame[ic] : 0;
         if (active) {
             sy = sys_of<BATCH>(a, i);
-            active = a.sel[sy] != 0;   // else the system keeps its list
+            // else the system keeps its list, or the slot is free
+            active = a.sel[sy] != 0 && i < a.sys[sy].pe;
         }
+        // a particle inserted since the last build has no previous row
+        const int old_i = have_old && o0 >= 0;
+        const int64_t o = old_i ? o0 : 0;
         int count = 0;
         if (active) {
             const SysDesc &s = a.sys[sy];
@@ -621,7 +638,7 @@ __global__ void __launch_bounds__(kNbrBlock, 5) k_neighbors(KArgs a, int have_ol
                 bid[q0] = id0;
                 if (q1 < cnt) bid[q1] = id1;
             }
-            if (have_old) {
+            if (old_i) {
                 const List O = list_of(a, sy, 0);
                 ocnt = O.cnt[o];
                 omask = O.mask[o];
@@ -643,9 +660,9 @@ __global__ void __launch_bounds__(kNbrBlock, 5) k_neighbors(KArgs a, int have_ol
             for (int q0 = g; q0 < cnt; q0 += 2 * G) {
                 const int q1 = q0 + G;
                 int64_t s0, s1 = 0, f0, f1 = 0;
-                const bool c0 = nbr_place(bid, bidx, oid, cnt, ocnt, omask, have_old, n, i, o, kmax, L, q0, s0, f0,
+                const bool c0 = nbr_place(bid, bidx, oid, cnt, ocnt, omask, old_i, n, i, o, kmax, L, q0, s0, f0,
                                           bits);
-                const bool c1 = q1 < cnt && nbr_place(bid, bidx, oid, cnt, ocnt, omask, have_old, n, i, o, kmax, L, q1,
+                const bool c1 = q1 < cnt && nbr_place(bid, bidx, oid, cnt, ocnt, omask, old_i, n, i, o, kmax, L, q1,
                                                       s1, f1, bits);
                 // both loads unconditional (slot 0 where nothing is carried), so that
                 // they are issued together
@@ -703,6 +720,7 @@ __global__ void k_pack(KArgs a, int dst, int mode, int k, int gate, int64_t qa) 
         const int sy = sys_of<BATCH>(a, i);
         if (mode == 2 && !a.sel[sy]) continue;
         const SysDesc &s = a.sys[sy];
+        if (i >= s.pe) continue;   // a free slot
         const int d = mode == 2 && a.multirate ? mr_buffer(qa, s.stride) : dst;
         D4 *P = a.pos[d], *V = a.vel[d], *S = a.spin[d];
         const double im = a.inv_m[i], iI = a.inv_I[i];
@@ -744,6 +762,7 @@ __global__ void k_unpack(KArgs a, int src, int selected, int64_t qa) {
     FOR_WINDOW_FLAT(a, i) {
         const int sy = sys_of_any(a, i);
         if (selected && !a.sel[sy]) continue;
+        if (i >= a.sys[sy].pe) continue;
         const int b = a.multirate && qa > 0 ? mr_buffer(qa, a.sys[sy].stride) : src;
         const D4 p = a.pos[b][i], v = a.vel[b][i], w = a.spin[b][i];
         a.x[i] = p.x; a.x[n + i] = p.y; a.x[2 * n + i] = p.z;
@@ -995,6 +1014,7 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
             lc = __builtin_amdgcn_readfirstlane(a.lcur[sy]);
             load_step_coef(a, sd);
         }
+        if (BATCH && a.only_sys >= 0 && sy != a.only_sys) continue;   // (uniform over the block)
         int srcs = src;
         bool last = MODE == 2;
         if (MR) {
@@ -1006,7 +1026,7 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
             last = step + sd.stride - 1 == send;
         }
         const int64_t i = BATCH ? sd.p0 + (t - tlo) * ppb + threadIdx.x / G : t * ppb + threadIdx.x / G;
-        if (i >= (BATCH ? sd.p1 : n)) continue;
+        if (i >= sd.pe) continue;   // past the system's live particles
         const D4 pi = a.pos[srcs][i], vi = a.vel[srcs][i], si = a.spin[srcs][i];
         step_particle<BATCH, COUNT, MODE, G, MR>(a, sd, (lc & 1) ? a.lst[1] : a.lst[0], srcs, update, i, sy, pi, vi,
                                                  si, (int)si.w, g, gbase, gmask, ncont, nwall, need, bad, last);
@@ -1092,6 +1112,15 @@ hipError_t launch_phase(const KArgs &a, int phase, int k, int gate, hipStream_t 
     CHECK_LAUNCH();
 }
 
+hipError_t launch_scan(const int32_t *in, int64_t m, int32_t *partial, int32_t *out, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    const int64_t nb = (m + kScanTile - 1) / kScanTile;
+    k_scan_partial<<<(int)nb, kScanBlock, 0, st>>>(in, m, partial);
+    k_scan_top<<<1, kScanBlock, 0, st>>>(partial, nb);
+    k_scan_apply<<<(int)nb, kScanBlock, 0, st>>>(in, m, partial, out);
+    CHECK_LAUNCH();
+}
+
 hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
     hipError_t e;
@@ -1101,12 +1130,7 @@ hipError_t launch_bin(const KArgs &a, int frame_identity, hipStream_t st) {
     if (a.nsys > 1) k_bin_count<true><<<g, a.block, 0, st>>>(a);
     else k_bin_count<false><<<g, a.block, 0, st>>>(a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t m = a.ncell;
-    const int64_t nb = (m + kScanTile - 1) / kScanTile;
-    k_scan_partial<<<(int)nb, kScanBlock, 0, st>>>(a.cell_count, m, a.scan_partial);
-    k_scan_top<<<1, kScanBlock, 0, st>>>(a.scan_partial, nb);
-    k_scan_apply<<<(int)nb, kScanBlock, 0, st>>>(a.cell_count, m, a.scan_partial, a.cell_start);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_scan(a.cell_count, a.ncell, a.scan_partial, a.cell_start, st)) != hipSuccess) return e;
     if (a.nsys > 1) k_bin_place<true><<<g, a.block, 0, st>>>(a);
     else k_bin_place<false><<<g, a.block, 0, st>>>(a);
     k_cell_sort<<<flat_grid(a.cw1 - a.cw0, 256), 256, 0, st>>>(a);

@@ -37,7 +37,7 @@ class Config(ctypes.Structure):
                 ("g", ctypes.c_double * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("periodic", ctypes.c_int32 * 3), ("wall_z0", ctypes.c_int32), ("skin", ctypes.c_double),
                 ("cell", ctypes.c_double), ("r_max", ctypes.c_double), ("n", ctypes.c_int64),
-                ("k_max", ctypes.c_int32), ("block", ctypes.c_int32)]
+                ("k_max", ctypes.c_int32), ("block", ctypes.c_int32), ("n_max", ctypes.c_int64)]
 
 
 class State(ctypes.Structure):
@@ -57,6 +57,13 @@ class PIParams(ctypes.Structure):
 
 class PParams(ctypes.Structure):
     _fields_ = [("grid", Grid), ("kp", ctypes.c_double), ("mass_flow", ctypes.c_int32)]
+
+
+class ExchangeParams(ctypes.Structure):
+    """dem_exchange_params: boundary face (region x . nrm >= face), inflow slab
+    and interval, number of boundary cells."""
+    _fields_ = [("nrm", ctypes.c_double * 3), ("face", ctypes.c_double), ("slab", ctypes.c_double),
+                ("interval", ctypes.c_double), ("ncell", ctypes.c_int64)]
 
 
 # rows of a fields array (dem.h: DEM_F_*)
@@ -79,7 +86,7 @@ _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_b
             "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
             "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
             "dem_adjoint_destroy", "dem_cell_fields", "dem_pi_control", "dem_p_control", "dem_set_external_force",
-            "dem_set_multirate"]
+            "dem_set_multirate", "dem_exchange", "dem_live_count"]
 
 
 def load(path: str = LIB_PATH):
@@ -137,6 +144,8 @@ def load(path: str = LIB_PATH):
     L.dem_pi_control.argtypes = [vp, P(State), P(PIParams), vp, vp, vp, vp]
     L.dem_p_control.argtypes = [vp, P(State), P(PParams), vp, vp]
     L.dem_set_external_force.argtypes = [vp, P(State), vp]
+    L.dem_exchange.argtypes = [vp, P(State), i32, P(ExchangeParams), vp, vp, i64, vp, vp, vp, vp, vp, P(i64)]
+    L.dem_live_count.argtypes = [vp, i32, P(i64)]
     for name in _SYMBOLS:
         if name != "dem_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -148,7 +157,8 @@ def symbols():
     return list(_SYMBOLS)
 
 
-def make_config(system, k_max: int = 32, block: int = 0, cell: float = 0.0, skin: float | None = None) -> Config:
+def make_config(system, k_max: int = 32, block: int = 0, cell: float = 0.0, skin: float | None = None,
+                n_max: int = 0) -> Config:
     """dem_config of one workload system (inputs.workloads.System)."""
     c = Config()
     mats = system.materials
@@ -170,6 +180,7 @@ def make_config(system, k_max: int = 32, block: int = 0, cell: float = 0.0, skin
     c.n = system.n
     c.k_max = k_max
     c.block = block
+    c.n_max = int(n_max)
     return c
 
 
@@ -189,12 +200,14 @@ class DemSystem:
     """Particles of one or several systems on the GPU plus a libdem context.
 
     ``systems``: one ``System`` or a list (a batch; the systems are concatenated
-    and ids are made unique by adding each system's offset).
+    and ids are made unique by adding each system's slot offset).
+    ``capacity``: particle slots per system (one number or a list; default:
+    the system's count), room for spheres inserted by ``exchange``.
     """
 
     def __init__(self, systems, k_max: int = 32, block: int = 0, cell=0.0, skin=None, device: str = "cuda",
                  use_graph: bool = False, chunk: int = 64, lanes: int = 0, max_blocks: int = 0,
-                 static_workspace: bool = False):
+                 static_workspace: bool = False, capacity=None):
         import torch
 
         self.torch = torch
@@ -205,12 +218,14 @@ class DemSystem:
         self.nsys = len(self.systems)
         cells = cell if isinstance(cell, (list, tuple)) else [cell] * self.nsys
         skins = skin if isinstance(skin, (list, tuple)) else [skin] * self.nsys
-        self.cfgs = (Config * self.nsys)(*[make_config(s, k_max, block, cells[k], skins[k])
+        caps = capacity if isinstance(capacity, (list, tuple)) else [capacity] * self.nsys
+        self.live_counts = [s.n for s in self.systems]
+        self.counts = [s.n if caps[k] is None else int(caps[k]) for k, s in enumerate(self.systems)]
+        self.cfgs = (Config * self.nsys)(*[make_config(s, k_max, block, cells[k], skins[k], self.counts[k])
                                           for k, s in enumerate(self.systems)])
-        self.counts = [s.n for s in self.systems]
         self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
         self.n = int(self.offsets[-1])
-        self.id_offset = np.repeat(self.offsets[:-1], self.counts).astype(np.int64)
+        self.id_offset = np.repeat(self.offsets[:-1], self.live_counts).astype(np.int64)
         self.device = torch.device(device)
         # a stream of our own (default priority): graph capture needs a non-default stream
         self.stream = torch.cuda.Stream(self.device)
@@ -267,24 +282,47 @@ class DemSystem:
     def __del__(self):
         self.close()
 
+    def live_index(self):
+        """Slots of the live particles, system by system."""
+        return np.concatenate([np.arange(self.offsets[k], self.offsets[k] + self.live_counts[k])
+                               for k in range(self.nsys)]).astype(np.int64)
+
     def load_state(self, x=None, v=None, w=None, f=None, t=None):
-        """Copy host arrays ((n,3) rows in system order, ids from the systems) to the device."""
+        """Copy host arrays ((n,3) rows in system order, ids from the systems) to
+        the device (the systems' own particles: before any exchange)."""
         torch = self.torch
         cat = lambda k: np.concatenate([getattr(s, k) for s in self.systems])  # noqa: E731
+        slots = self.live_index()
+        dense = len(slots) == self.n
+        idx = None if dense else torch.from_numpy(slots).to(self.device)
+
+        def put(dst, host):
+            src = torch.from_numpy(np.ascontiguousarray(host)).to(self.device)
+            if dense:
+                dst.copy_(src)
+            else:
+                dst[..., idx] = src
+
         x = cat("x") if x is None else x
         v = cat("v") if v is None else v
         w = cat("w") if w is None else w
-        self.x.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(x, np.float64).T)))
-        self.v.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(v, np.float64).T)))
-        self.w.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(w, np.float64).T)))
+        if not dense:
+            for a in (self.x, self.v, self.w, self.f, self.t):
+                a.zero_()
+            self.r.fill_(1.0)
+            self.type.zero_()
+            self.id.fill_(-1)
+        put(self.x, np.asarray(x, np.float64).T)
+        put(self.v, np.asarray(v, np.float64).T)
+        put(self.w, np.asarray(w, np.float64).T)
         if f is not None:
-            self.f.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(f, np.float64).T)))
+            put(self.f, np.asarray(f, np.float64).T)
         if t is not None:
-            self.t.copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(t, np.float64).T)))
-        self.r.copy_(torch.from_numpy(cat("r").astype(np.float64)))
-        self.type.copy_(torch.from_numpy(cat("type").astype(np.int32)))
+            put(self.t, np.asarray(t, np.float64).T)
+        put(self.r, cat("r").astype(np.float64))
+        put(self.type, cat("type").astype(np.int32))
         gid = cat("id").astype(np.int64) + self.id_offset
-        self.id.copy_(torch.from_numpy(gid.astype(np.int32)))
+        put(self.id, gid.astype(np.int32))
         torch.cuda.synchronize(self.device)
 
     @property
@@ -356,15 +394,22 @@ class DemSystem:
         return dict(steps=out[0], builds=out[1], contacts=out[2], wall_contacts=out[3], slots=out[4])
 
     # ------------------------------------------------------------ host views (by id)
-    def host(self):
-        """Current state as numpy, rows sorted by (global) id: x, v, w, f, t (n,3), id (n,)."""
+    def host(self, system: int | None = None):
+        """Current state of the live particles (of one system, or all) as
+        numpy, rows sorted by (global) id: x, v, w, f, t (n,3), r, type, id (n,)."""
         self.torch.cuda.synchronize(self.device)
-        ids = self.id.cpu().numpy()
+        if system is None:
+            slots = self.live_index()
+        else:
+            slots = np.arange(self.offsets[system], self.offsets[system] + self.live_counts[system])
+        ids = self.id.cpu().numpy()[slots]
         order = np.argsort(ids, kind="stable")
+        sel = slots[order]
         out = {"id": ids[order]}
         for k in ("x", "v", "w", "f", "t"):
-            out[k] = getattr(self, k).cpu().numpy().T[order].copy()
-        out["r"] = self.r.cpu().numpy()[order]
+            out[k] = getattr(self, k).cpu().numpy().T[sel].copy()
+        out["r"] = self.r.cpu().numpy()[sel]
+        out["type"] = self.type.cpu().numpy()[sel]
         return out
 
     def export_neighbors(self):
@@ -427,6 +472,40 @@ class DemSystem:
             self.torch.cuda.current_stream(self.device).synchronize()
         self._rc(self.L.dem_set_external_force(self.ctx, self._state, _ptr(fext)))
         self.stream.synchronize()
+
+    def exchange(self, sys: int, params: ExchangeParams, fields, budget, cand_x=None, cand_r=None, cand_type=None,
+                 cand_cell=None):
+        """One insertion and deletion event on system `sys` (dem_exchange):
+        fields device (NFIELDS, ncell) of the coarse level on the boundary
+        cells, budget device (ncell,) updated in place, candidates as device or
+        host arrays (positions (k, 3)).  The system's list and forces are
+        rebuilt by the call.  Returns (accepted device int32 (k,), inserted,
+        removed)."""
+        torch = self.torch
+        k = 0 if cand_r is None else int(len(cand_r))
+        dev = dict(device=self.device)
+        if k:
+            cx = torch.as_tensor(np.asarray(cand_x, np.float64).T if isinstance(cand_x, np.ndarray) else cand_x.T,
+                                 dtype=torch.float64, **dev).contiguous()
+            cr = torch.as_tensor(cand_r, dtype=torch.float64, **dev).contiguous()
+            ct = torch.as_tensor(cand_type, dtype=torch.int32, **dev).contiguous()
+            cc = torch.as_tensor(cand_cell, dtype=torch.int32, **dev).contiguous()
+        else:
+            cx = cr = ct = cc = None
+        acc = torch.zeros(max(k, 1), dtype=torch.int32, **dev)
+        fields = fields.to(torch.float64).contiguous()
+        counts = (ctypes.c_int64 * 3)()
+        torch.cuda.current_stream(self.device).synchronize()
+        self._rc(self.L.dem_exchange(self.ctx, self._state, int(sys), ctypes.byref(params), _ptr(fields),
+                                     _ptr(budget), k, _ptr(cx), _ptr(cr), _ptr(ct), _ptr(cc), _ptr(acc), counts))
+        self.live_counts[sys] = int(counts[2])
+        self.stream.synchronize()
+        return acc[:k], int(counts[0]), int(counts[1])
+
+    def live(self, sys: int) -> int:
+        n = ctypes.c_int64()
+        self._rc(self.L.dem_live_count(self.ctx, int(sys), ctypes.byref(n)))
+        return int(n.value)
 
     def set_materials(self, materials, sys: int = 0):
         """New per-type materials of system `sys` (objects with E, nu, rho, e, mu)."""

@@ -437,3 +437,52 @@ def chute_adjoint(seed: int = 5, n: int = 50_000, Lx: float = 100e-3, Ly: float 
                             200, "chute_adjoint", 1.0, v=v)
     sysm.meta["H0"] = H
     return sysm
+
+
+# ----------------------------------------------------------------------------
+# Insertion events at the boundary of a fine region
+# ----------------------------------------------------------------------------
+
+NFIELD_ROWS = 16          # rows of a cell-fields array: count, mass, momentum (3), volume, ...
+ROW_MASS, ROW_MOM = 1, 2
+
+
+def exchange_inputs(system: System, zf: float, ncand: int, seed: int, cells=(2, 2), slab: float = 4e-3,
+                    depth: float = 3e-3, interval: float = 15e-6, inflow_mass: float = 2e-3,
+                    inflow_speed: float = 0.4, budget_spheres: float = 1.0) -> dict:
+    """Inputs of one insertion event of a fine bed whose region is z <= zf
+    (boundary face z = zf, normal -z into the region): a grid of cells x cells
+    boundary cells over the footprint; the coarse level's fields on them (mass
+    inflow_mass * U[0.5, 1.5] per cell, momentum of that mass moving at
+    inflow_speed * U[0.5, 1.5] downwards plus N(0, 0.1 inflow_speed) sideways;
+    one cell in four flows outwards); the starting budget (U[0, 1] sphere
+    masses, times budget_spheres); ncand candidates uniform in the slab zf - depth < z < zf of a
+    uniformly drawn cell, radii uniform over the system's radius range, type 0."""
+    rng = np.random.default_rng(seed)
+    nx, ny = cells
+    ncell = nx * ny
+    Lx, Ly = system.hi[0] - system.lo[0], system.hi[1] - system.lo[1]
+    fields = np.zeros((NFIELD_ROWS, ncell))
+    mass = inflow_mass * rng.uniform(0.5, 1.5, ncell)
+    speed = inflow_speed * rng.uniform(0.5, 1.5, ncell)
+    sign = np.where(np.arange(ncell) % 4 == 3, 1.0, -1.0)
+    fields[ROW_MASS] = mass
+    fields[ROW_MOM] = mass * rng.normal(0.0, 0.1 * inflow_speed, ncell)
+    fields[ROW_MOM + 1] = mass * rng.normal(0.0, 0.1 * inflow_speed, ncell)
+    fields[ROW_MOM + 2] = mass * speed * sign
+    rmin, rmax = float(system.r.min()), float(system.r.max())
+    rho = system.materials[0].rho
+    m_sphere = 4.0 / 3.0 * math.pi * rho * ((rmin + rmax) / 2) ** 3
+    budget = rng.uniform(0.0, 1.0, ncell) * m_sphere * budget_spheres
+    cell = rng.integers(0, ncell, ncand)
+    cx, cy = cell % nx, cell // nx
+    x = np.column_stack([(cx + rng.uniform(0.0, 1.0, ncand)) * Lx / nx + system.lo[0],
+                         (cy + rng.uniform(0.0, 1.0, ncand)) * Ly / ny + system.lo[1],
+                         zf - depth * rng.uniform(0.0, 1.0, ncand)])
+    for a in range(2):                       # keep positions inside [lo, hi) on the periodic axes
+        L = system.hi[a] - system.lo[a]
+        x[:, a] = np.where(x[:, a] >= system.hi[a], x[:, a] - L, x[:, a])
+    r = rng.uniform(rmin, rmax, ncand)
+    return {"nrm": (0.0, 0.0, -1.0), "face": -zf, "slab": slab, "interval": interval, "ncell": ncell,
+            "fields": fields, "budget": budget, "cand_x": x, "cand_r": r,
+            "cand_type": np.zeros(ncand, np.int32), "cand_cell": cell.astype(np.int32)}

@@ -63,6 +63,7 @@ enum {
 };
 
 #define DEM_MAX_TYPES 4
+#define DEM_MAX_SURFACES 4
 
 /* Material of one particle type (Sec. 2.1 and Sec. 2.2).  A pair of two
  * types uses the harmonic effective modulus and shear modulus of the two
@@ -95,6 +96,9 @@ typedef struct dem_config {
     int32_t block;                     /* threads per block: 64, 128, 256; 0 = 256      */
     int64_t n_max;                     /* particle slots, >= n (room for insertion);
                                           0 = n                                          */
+    int32_t n_surf;                    /* static wall surfaces reserved, 0..DEM_MAX_SURFACES
+                                          (dem_set_surfaces)                             */
+    int32_t pad;
 } dem_config;
 
 /* Caller-owned device arrays of the particles (see Conventions). */
@@ -375,6 +379,48 @@ int dem_p_control(dem_ctx *ctx, const dem_state *s, const dem_p_params *p, const
 int dem_set_external_force(dem_ctx *ctx, const dem_state *s, const double *fext);
 
 /* ---------------------------------------------------------------------------
+ * Static wall surfaces (the silo of Sec. 3: a cylinder on a cone, closed by a
+ * plug over the orifice that is removed to start the discharge).
+ *
+ * Up to dem_config.n_surf surfaces per system, each around the vertical axis
+ * through (axis[0], axis[1]).  A surface is a wall of the touching particle's
+ * own material, like the flat wall, seen as flat at the contact point: the
+ * contact point is the nearest point of the surface to the centre, the normal
+ * the unit vector from it to the centre and the overlap r - d for a centre at
+ * distance 0 < d < r on the inner side; each surface keeps its own tangential
+ * history per particle.  The force pass adds a particle's surface terms after
+ * its flat-wall term, in table order.  Kinds:
+ *   DEM_SURF_CYLINDER  inside of radius r0 for z0 <= z <= z1 (centre's height);
+ *   DEM_SURF_CONE      inside of the frustum of radius r0 at z0 and r1 at z1
+ *                      (the foot of the centre's perpendicular on the slanted
+ *                      side within it);
+ *   DEM_SURF_DISK      the disk of radius r0 at height z0, touched from above
+ *                      by centres within r0 of the axis;
+ *   DEM_SURF_RING      the circle of radius r0 at height z0 (an edge).
+ * A centre on or behind a surface, or on the axis of a cylinder, cone or ring,
+ * has no contact with it.
+ * ------------------------------------------------------------------------- */
+
+enum { DEM_SURF_CYLINDER = 1, DEM_SURF_CONE = 2, DEM_SURF_DISK = 3, DEM_SURF_RING = 4 };
+
+typedef struct dem_surface {
+    int32_t kind;       /* DEM_SURF_*                                              */
+    int32_t enabled;    /* 0: ignored (e.g. the plug of an opened orifice)          */
+    double axis[2];     /* (x, y) of the vertical axis (m)                          */
+    double z0, z1;      /* heights (m): cylinder and cone z0 < z1; disk, ring: z0   */
+    double r0, r1;      /* radii (m) > 0: r0 (cone: at z0), r1 the cone's at z1     */
+    double mu;          /* friction coefficient of a contact with the surface (the
+                           paper lists particle-wall friction apart); < 0: that of
+                           the particle's own material                              */
+} dem_surface;
+
+/* Set the surfaces of system `sys` (count <= its n_surf; host array).  The
+ * tangential history of a surface whose record changed is cleared (enabling
+ * or disabling one keeps the others').  Enqueued; DEM_ERR_ARG for a bad record
+ * or count. */
+int dem_set_surfaces(dem_ctx *ctx, int32_t sys, int32_t count, const dem_surface *surf);
+
+/* ---------------------------------------------------------------------------
  * Insertion and deletion at the boundary of the fine region (Sec. 2.3).
  *
  * The paper measures the coarse particles' mass flow and velocity per cell of
@@ -388,7 +434,8 @@ int dem_set_external_force(dem_ctx *ctx, const dem_state *s, const double *fext)
  *      fields given (the coarse level's fields on the boundary cells, of
  *      dem_cell_fields);
  *   2. removal: every live sphere of the system whose centre has
- *      (x nrm_x + y nrm_y) + z nrm_z < face is removed, with its history;
+ *      (x nrm_x + y nrm_y) + z nrm_z < face, or the same with out_nrm and
+ *      out_face when out_nrm is not zero, is removed, with its history;
  *   3. SSI: candidate k (in the given order) is accepted iff its mass
  *      (4/3) pi rho r^3 is at most its cell's remaining budget and it
  *      overlaps neither a kept sphere nor a candidate accepted before it:
@@ -413,6 +460,8 @@ typedef struct dem_exchange_params {
     double slab;        /* height of the inflow slab on the coarse side (m), > 0 when interval > 0 */
     double interval;    /* coupling interval (s); 0: no budget top-up (step 1 skipped)             */
     int64_t ncell;      /* boundary cells: rows of fields, entries of budget, range of cand_cell   */
+    double out_nrm[3];  /* a second half-space x . out_nrm >= out_face bounding the region (an    */
+    double out_face;    /*   outlet, e.g. below a silo's orifice); out_nrm = 0: none              */
 } dem_exchange_params;
 
 /* One insertion and deletion event on system `sys` (synchronises).

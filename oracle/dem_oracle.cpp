@@ -125,6 +125,17 @@ template <class S> struct Particle {
 
 template <class S> struct PairRecord { int lo, hi; double fn_mag, f_mag, ft_mag, fncap, ft_normal; };
 
+/* A static wall surface around the vertical axis through (cx, cy) (the silo
+ * of Sec. 3): 1 the inside of a cylinder of radius r0 for z0 <= z <= z1, 2 the
+ * inside of a cone frustum of radius r0 at z0 and r1 at z1, 3 a horizontal
+ * disk of radius r0 at height z0 touched from above, 4 a horizontal ring
+ * (circle) of radius r0 at z0.  A disabled surface is ignored. */
+struct Surface {
+    int kind, enabled;
+    double cx, cy, z0, z1, r0, r1;
+    double mu;   /* friction of a contact with it; < 0: the particle's own */
+};
+
 template <class S> struct Sim {
     Config cfg;
     S E[4], e[4], mu[4];  // material parameters as scalars (seeded for tangents)
@@ -134,6 +145,8 @@ template <class S> struct Sim {
     std::map<int, V3<S>> whist;                              // id -> wall xi
     std::vector<PairRecord<S>> records;                      // last force evaluation
     std::vector<V3<double>> fext;                            // external force per particle (empty: none)
+    std::vector<Surface> surf;                               // static wall surfaces
+    std::map<std::pair<int, int>, V3<S>> shist;              // (id, surface) -> xi
     double rmax = 0.0;
 };
 
@@ -176,7 +189,8 @@ template <class S> S min_image_s(const S &d, double L, int periodic) {
  */
 template <class S>
 bool contact(const Sim<S> &s, const Particle<S> &a, const Particle<S> *b, V3<S> &xi, bool update, V3<S> &f_out,
-             V3<S> &ft_out, V3<S> &n_out, PairRecord<S> *rec) {
+             V3<S> &ft_out, V3<S> &n_out, PairRecord<S> *rec, const V3<double> *wn = nullptr, double wdist = 0.0,
+             double wmu = -1.0) {
     const Config &c = s.cfg;
     V3<S> d;
     S dist;
@@ -189,6 +203,12 @@ bool contact(const Sim<S> &s, const Particle<S> &a, const Particle<S> *b, V3<S> 
         rs = a.r + b->r;
         if (!(val(d2) < rs * rs)) return false;
         dist = sqrt(d2);
+    } else if (wn) {
+        /* a static surface at distance wdist along its normal wn */
+        rs = a.r;
+        if (!(wdist < a.r)) return false;
+        d.x = 0.0; d.y = 0.0; d.z = wdist;
+        dist = wdist;
     } else {
         rs = a.r;
         if (!(val(a.x.z) < a.r)) return false;
@@ -200,6 +220,8 @@ bool contact(const Sim<S> &s, const Particle<S> &a, const Particle<S> *b, V3<S> 
     V3<S> n;
     if (b) {
         n.x = d.x / dist; n.y = d.y / dist; n.z = d.z / dist;
+    } else if (wn) {
+        n.x = wn->x; n.y = wn->y; n.z = wn->z;
     } else {
         n.x = 0.0; n.y = 0.0; n.z = 1.0;
     }
@@ -207,6 +229,7 @@ bool contact(const Sim<S> &s, const Particle<S> &a, const Particle<S> *b, V3<S> 
     double R = b ? a.r * b->r / (a.r + b->r) : a.r;
     double M = b ? a.m * b->m / (a.m + b->m) : a.m;
     PairCoef<S> k = coef(s, a.type, b ? b->type : a.type);
+    if (!b && wn && wmu >= 0.0) k.mu = wmu;   /* a surface with its own friction */
     /* Eq. (6) */
     S sq = sqrt(R * delta);
     S kn = 4.0 / 3.0 * k.Es * sq;
@@ -340,6 +363,57 @@ template <class S> void brute_pairs(const Sim<S> &s, double extra, std::vector<s
     });
 }
 
+/* Contact of a sphere (centre (x, y, z), radius r) with surface w, from the
+ * definitions: the nearest point of the surface piece to the centre, the
+ * distance d to it and the unit vector n from it to the centre; in contact
+ * when the centre is on the inner side and 0 < d < r.  Cylinder and cone are
+ * handled in the meridional half-plane through the centre (distance rho from
+ * the axis, height z), where they are a vertical segment and a slanted one;
+ * a centre whose perpendicular foot lies off the segment has no contact. */
+static bool surface_contact(const Surface &w, double x, double y, double z, double r, double &dist, V3<double> &n) {
+    if (!w.enabled) return false;
+    const double dx = x - w.cx, dy = y - w.cy;
+    const double rho = std::sqrt(dx * dx + dy * dy);
+    if (w.kind == 3) {                                   /* disk, from above */
+        if (rho > w.r0) return false;
+        const double d = z - w.z0;
+        if (!(d > 0.0 && d < r)) return false;
+        dist = d;
+        n = {0.0, 0.0, 1.0};
+        return true;
+    }
+    if (rho == 0.0) return false;                        /* on the axis: no direction */
+    if (w.kind == 1) {                                   /* cylinder, from inside */
+        if (z < w.z0 || z > w.z1) return false;
+        const double d = w.r0 - rho;
+        if (!(d > 0.0 && d < r)) return false;
+        dist = d;
+        n = {-dx / rho, -dy / rho, 0.0};
+        return true;
+    }
+    if (w.kind == 2) {                                   /* cone, from inside */
+        const double sr = w.r1 - w.r0, sz = w.z1 - w.z0;
+        const double t = ((rho - w.r0) * sr + (z - w.z0) * sz) / (sr * sr + sz * sz);
+        if (t < 0.0 || t > 1.0) return false;
+        const double qr = rho - (w.r0 + t * sr), qz = z - (w.z0 + t * sz);
+        const double d = std::sqrt(qr * qr + qz * qz);
+        const double side = sr * (z - w.z0) - sz * (rho - w.r0);   /* > 0: towards the axis */
+        if (!(side > 0.0 && d > 0.0 && d < r)) return false;
+        dist = d;
+        n = {qr / d * (dx / rho), qr / d * (dy / rho), qz / d};
+        return true;
+    }
+    if (w.kind == 4) {                                   /* ring */
+        const double qr = rho - w.r0, qz = z - w.z0;
+        const double d = std::sqrt(qr * qr + qz * qz);
+        if (!(d > 0.0 && d < r)) return false;
+        dist = d;
+        n = {qr / d * (dx / rho), qr / d * (dy / rho), qz / d};
+        return true;
+    }
+    return false;
+}
+
 /* Total force and torque on every particle (Sec. 2.1). */
 template <class S> void forces(Sim<S> &s, bool update) {
     const Config &c = s.cfg;
@@ -384,6 +458,30 @@ template <class S> void forces(Sim<S> &s, bool update) {
             a.t = {a.t.x - a.r * nxf.x, a.t.y - a.r * nxf.y, a.t.z - a.r * nxf.z};
         }
         if (update) s.whist.swap(wnext);
+    }
+    /* static surfaces, in their order (double precision runs only) */
+    if (!s.surf.empty()) {
+        std::map<std::pair<int, int>, V3<S>> snext;
+        for (auto &a : s.p)
+            for (size_t k = 0; k < s.surf.size(); ++k) {
+                double dist;
+                V3<double> wn;
+                if (!surface_contact(s.surf[k], val(a.x.x), val(a.x.y), val(a.x.z), a.r, dist, wn)) continue;
+                std::pair<int, int> key{a.id, (int)k};
+                auto it = s.shist.find(key);
+                V3<S> xi = it == s.shist.end() ? V3<S>{0.0, 0.0, 0.0} : it->second;
+                V3<S> f, ft, n;
+                PairRecord<S> rec{a.id, -2 - (int)k, 0, 0, 0, 0, 0};
+                if (!contact(s, a, (const Particle<S> *)nullptr, xi, update, f, ft, n, &rec, &wn, dist,
+                             s.surf[k].mu))
+                    continue;
+                s.records.push_back(rec);
+                if (update) snext[key] = xi;
+                a.f = {a.f.x + f.x, a.f.y + f.y, a.f.z + f.z};
+                V3<S> nxf = {n.y * ft.z - n.z * ft.y, n.z * ft.x - n.x * ft.z, n.x * ft.y - n.y * ft.x};
+                a.t = {a.t.x - a.r * nxf.x, a.t.y - a.r * nxf.y, a.t.z - a.r * nxf.z};
+            }
+        if (update) s.shist.swap(snext);
     }
     /* external forces (the coupling's correcting forces, Sec. 2.3), added last */
     if (!s.fext.empty())
@@ -592,6 +690,7 @@ extern "C" {
  * and, in *seconds, the time of the step loop alone (steady clock).  The state
  * and histories afterwards are those of orc_step. */
 int orc_step_parallel(void *h, int nsteps, double *seconds) {
+    if (!((SimD *)h)->surf.empty()) return -1;   /* the gather form has no surfaces */
     SimD *s = (SimD *)h;
     const int n = (int)s->p.size();
     Rows rows, next;
@@ -779,6 +878,56 @@ long orc_records(void *h, int *lo, int *hi, double *fn, double *fmag, double *ft
         ++k;
     }
     return k;
+}
+
+/* Static wall surfaces: count records of 9 doubles (kind, enabled, cx, cy, z0,
+ * z1, r0, r1, mu).  The history of a surface whose record changed is dropped. */
+void orc_set_surfaces(void *h, int count, const double *desc) {
+    SimD *s = (SimD *)h;
+    std::vector<Surface> next(count);
+    for (int k = 0; k < count; ++k) {
+        const double *q = desc + 9 * k;
+        next[k] = {(int)q[0], (int)q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8]};
+    }
+    std::map<std::pair<int, int>, V3<double>> keep;
+    for (auto &kv : s->shist) {
+        const int k = kv.first.second;
+        if (k < count && k < (int)s->surf.size() && std::memcmp(&s->surf[k], &next[k], sizeof(Surface)) == 0)
+            keep[kv.first] = kv.second;
+    }
+    s->shist.swap(keep);
+    s->surf = next;
+}
+
+/* The contact geometry of one sphere and one surface record (9 doubles as
+ * above): returns 1 in contact, with out = (distance, n_x, n_y, n_z). */
+int orc_surface_contact(const double *desc, double x, double y, double z, double r, double *out) {
+    Surface w{(int)desc[0], (int)desc[1], desc[2], desc[3], desc[4], desc[5], desc[6], desc[7], desc[8]};
+    double d;
+    V3<double> n;
+    if (!surface_contact(w, x, y, z, r, d, n)) return 0;
+    out[0] = d; out[1] = n.x; out[2] = n.y; out[3] = n.z;
+    return 1;
+}
+
+/* Surface history: (id, surface index, xi). */
+long orc_surface_history(void *h, int *id, int *k, double *xi, long cap) {
+    SimD *s = (SimD *)h;
+    long q = 0;
+    for (auto &kv : s->shist) {
+        if (q < cap) {
+            id[q] = kv.first.first; k[q] = kv.first.second;
+            xi[3 * q] = kv.second.x; xi[3 * q + 1] = kv.second.y; xi[3 * q + 2] = kv.second.z;
+        }
+        ++q;
+    }
+    return q;
+}
+
+void orc_set_surface_history(void *h, long count, const int *id, const int *k, const double *xi) {
+    SimD *s = (SimD *)h;
+    s->shist.clear();
+    for (long q = 0; q < count; ++q) s->shist[{id[q], k[q]}] = {xi[3 * q], xi[3 * q + 1], xi[3 * q + 2]};
 }
 
 /* External force on every particle, (n, 3) in input order, added after the

@@ -121,18 +121,21 @@ def favre_velocity(mass, momentum):
 
 
 def exchange(system, orc, normal, d, cand_x, cand_r, cand_type, cand_cell, budget, cell_mass, cell_mom,
-             id_base, fext=None):
+             id_base, fext=None, outlet=None, surfaces=None):
     """One insertion-and-deletion event of the fine system (S-1 .. S-5, with
     the budget already topped up by inflow_budget).  Deletion first (S-5),
     then SSI against the kept spheres (S-3), the accepted candidates appended
     in candidate order with ids id_base, id_base + 1, ... and their cell's
     Favre velocity (S-4); the pair and wall history of the kept spheres is
-    carried by id.  Returns (new system, new oracle, accepted flags, budget,
+    carried by id.  `outlet` (normal, offset): a second half-space whose
+    outer side is removed too (a silo's outlet).  Returns (new system, new oracle, accepted flags, budget,
     kept mask, external forces of the new system)."""
     import oracle as O
 
     st = orc.state()
     keep = ~outside(st["x"], normal, d)
+    if outlet is not None:                       # a second bounding half-space (normal, offset)
+        keep &= ~outside(st["x"], outlet[0], outlet[1])
     xk = st["x"][keep]
     rk = system.r[keep]
     box_L = [system.hi[a] - system.lo[a] for a in range(3)]
@@ -156,6 +159,11 @@ def exchange(system, orc, normal, d, cand_x, cand_r, cand_type, cand_cell, budge
     wid, wxi = orc.wall_history()
     wsel = np.array([int(p) in kept_ids for p in wid], bool)
     o2.set_wall_history(wid[wsel], wxi[wsel])
+    if surfaces is not None:                     # static wall surfaces and their history
+        o2.set_surfaces(surfaces)
+        sid, sk, sxi = orc.surface_history()
+        ssel = np.array([int(p) in kept_ids for p in sid], bool)
+        o2.set_surface_history(sid[ssel], sk[ssel], sxi[ssel])
     f2 = None
     if fext is not None:
         f2 = np.concatenate([np.asarray(fext, float)[keep], np.zeros((na, 3))])

@@ -81,6 +81,13 @@ def lib(path: str | None = None):
         L.orc_step_parallel.restype = ctypes.c_int
         L.orc_step_parallel.argtypes = [vp, ctypes.c_int, _dp]
         L.orc_set_external.argtypes = [vp, _dp]
+        L.orc_set_surfaces.argtypes = [vp, ctypes.c_int, _dp]
+        L.orc_surface_contact.restype = ctypes.c_int
+        L.orc_surface_contact.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          _dp]
+        L.orc_surface_history.restype = ctypes.c_long
+        L.orc_surface_history.argtypes = [vp, _ip, _ip, _dp, ctypes.c_long]
+        L.orc_set_surface_history.argtypes = [vp, ctypes.c_long, _ip, _ip, _dp]
         L.orc_pair_forces.restype = ctypes.c_long
         L.orc_pair_forces.argtypes = [vp, _ip, _ip, _dp, _dp, ctypes.c_long]
         L.orc_tan_forces.argtypes = [vp, ctypes.c_int]
@@ -162,6 +169,8 @@ class Oracle:
         returns (threads used, seconds of the step loop)."""
         sec = ctypes.c_double(0.0)
         th = int(self.L.orc_step_parallel(self.h, int(nsteps), ctypes.byref(sec)))
+        if th < 0:
+            raise ValueError("the all-cores form takes no wall surfaces")
         return th, sec.value
 
     def kick(self):
@@ -208,6 +217,23 @@ class Oracle:
         self.L.orc_records(self.h, _i(lo), _i(hi), _d(fn), _d(fm), _d(ftm), _d(cap), _d(ftn), k)
         return dict(lo=lo, hi=hi, fn=fn, fmag=fm, ftmag=ftm, cap=cap, ftn=ftn)
 
+    def set_surfaces(self, surfaces):
+        """Static wall surfaces: records (kind, enabled, cx, cy, z0, z1, r0, r1[, mu])
+        (kinds 1 cylinder, 2 cone, 3 disk, 4 ring; mu < 0 or absent: the particle's friction)."""
+        d = np.ascontiguousarray(_surface_records(surfaces))
+        self.L.orc_set_surfaces(self.h, d.shape[0], _d(d))
+
+    def surface_history(self):
+        k = self.L.orc_surface_history(self.h, None, None, None, 0)
+        ids = np.empty(k, np.int32); ks = np.empty(k, np.int32); xi = np.empty((k, 3))
+        self.L.orc_surface_history(self.h, _i(ids), _i(ks), _d(xi), k)
+        return ids, ks, xi
+
+    def set_surface_history(self, ids, ks, xi):
+        ids = np.ascontiguousarray(ids, np.int32); ks = np.ascontiguousarray(ks, np.int32)
+        xi = np.ascontiguousarray(xi, np.float64).reshape(-1, 3)
+        self.L.orc_set_surface_history(self.h, ids.shape[0], _i(ids), _i(ks), _d(xi))
+
     def set_external(self, f=None):
         """External force per particle ((n,3), input order), added after the wall
         term at every force evaluation; None removes it."""
@@ -249,3 +275,18 @@ class Oracle:
         val = np.empty((self.n, 3)); tan = np.empty((self.n, 3, 6))
         self.L.orc_tan_get_ext(self.h, which, _d(val), _d(tan))
         return val, tan
+
+
+def _surface_records(surfaces):
+    rows = [list(map(float, q)) + ([] if len(q) > 8 else [-1.0]) for q in surfaces]
+    return np.asarray(rows, np.float64).reshape(-1, 9)
+
+
+def surface_contact(record, x, y, z, r, lib_path: str | None = None):
+    """The oracle's contact geometry of one sphere with one surface record:
+    (distance, normal) or None when not in contact."""
+    d = np.ascontiguousarray(_surface_records([record]).reshape(9))
+    out = np.zeros(4)
+    if not lib(lib_path).orc_surface_contact(_d(d), float(x), float(y), float(z), float(r), _d(out)):
+        return None
+    return float(out[0]), out[1:].copy()

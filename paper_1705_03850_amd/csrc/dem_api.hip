@@ -69,6 +69,7 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         const int64_t slots = c.n_max == 0 ? c.n : c.n_max;
         if (slots < c.n) { err = "n_max must be 0 or >= n"; return DEM_ERR_ARG; }
         if (c.k_max < 1 || c.k_max > kMaxSlots) { err = "k_max must be in 1..63"; return DEM_ERR_ARG; }
+        if (c.n_surf < 0 || c.n_surf > DEM_MAX_SURFACES) { err = "n_surf must be in 0..4"; return DEM_ERR_ARG; }
         if ((c.block == 0 ? 256 : c.block) != g.block) { err = "all systems of a batch need the same block size"; return DEM_ERR_ARG; }
         const double cut = cutoff_of(c);
         double h = c.cell > 0.0 ? c.cell : cut;
@@ -110,6 +111,10 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         d.c0 = g.ncell;
         d.wall = c.wall_z0 ? 1 : 0;
         d.stride = 1;
+        d.nsurf = 0;
+        d.surf0 = s * kMaxSurf;
+        g.surf_cap.push_back(c.n_surf);
+        g.nsurf_slots = std::max(g.nsurf_slots, c.n_surf);
         d.ntypes = c.ntypes;
         d.coef0 = (int32_t)g.coef.size();
         d.type0 = (int32_t)g.rho.size();
@@ -123,6 +128,9 @@ int build_geometry(int32_t nsys, const dem_config *cfgs, Geometry &g, std::strin
         g.kmax = std::max(g.kmax, c.k_max);
     }
     if (g.n > INT32_MAX / 2 || g.ncell > INT32_MAX / 2) { err = "problem too large for 32-bit indices"; return DEM_ERR_ARG; }
+    Surf none;
+    memset(&none, 0, sizeof none);
+    g.surf.assign(g.sys.size() * kMaxSurf, none);
     return DEM_OK;
 }
 
@@ -170,6 +178,14 @@ Layout make_layout(const Geometry &g) {
     L.mtile0 = take((g.sys.size() + 1) * 8);
     L.msys = take(g.sys.size() * 4);
     L.mlevel = take(kMaxLevels * 8);
+    L.surf = take(g.sys.size() * kMaxSurf * sizeof(Surf));
+    L.sxi = L.smask = L.shadow_s = 0;
+    if (g.nsurf_slots > 0) {
+        const size_t S = (size_t)g.nsurf_slots;
+        L.sxi = take(S * n * sizeof(D4));
+        L.smask = take(n * 4);
+        L.shadow_s = take(3 * S * n * 8 + n * 4);
+    }
     L.total = o;
     return L;
 }
@@ -276,6 +292,13 @@ KArgs kargs(dem_ctx *c, const dem_state *s) {
     a.mlevel = (const int64_t *)(w + L.mlevel);
     a.ntiles_b = c->ntiles_b;
     a.lcur = (int32_t *)(w + L.lcur);
+    a.surf = (const Surf *)(w + L.surf);
+    a.nsurf_slots = c->geo.nsurf_slots;
+    if (c->geo.nsurf_slots > 0) {
+        a.sxi = (D4 *)(w + L.sxi);
+        a.smask = (uint32_t *)(w + L.smask);
+        a.shadow_s = (double *)(w + L.shadow_s);
+    }
     return a;
 }
 
@@ -490,6 +513,9 @@ int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *wo
                            c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_rho, g.rho.data(), g.rho.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + lay.surf, g.surf.data(), g.surf.size() * sizeof(Surf), hipMemcpyHostToDevice,
+                           c->stream);
     if (e == hipSuccess) e = launch_ctrl(c->d_flags, 2, 0, c->stream);
     if (e == hipSuccess && upload_tiles(c) != DEM_OK) e = hipErrorUnknown;
     if (e == hipSuccess) {
@@ -588,6 +614,7 @@ int dem_reset(dem_ctx *c, const dem_state *s) {
     HIPCALL(c, launch_fill_f64(a.disp, 3 * c->geo.n, 0.0, c->stream));
     HIPCALL(c, launch_fill_f64(a.xiw, 3 * c->geo.n, 0.0, c->stream));
     HIPCALL(c, launch_fill_i32(a.dead, c->geo.n, 0, c->stream));
+    if (a.smask) HIPCALL(c, launch_fill_i32((int32_t *)a.smask, c->geo.n, 0, c->stream));
     HIPCALL(c, launch_fill_i32(a.sel, (int64_t)c->geo.sys.size(), 0, c->stream));
     HIPCALL(c, launch_fill_i32(a.lcur, (int64_t)c->geo.sys.size(), 0, c->stream));
     Flags h;
@@ -645,6 +672,77 @@ int dem_integrate(dem_ctx *c, const dem_state *s, int phase) {
 int dem_declare_forces(dem_ctx *c) {
     if (!c) return DEM_ERR_ARG;
     c->forces_valid = true;
+    return DEM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+__global__ void k_clear_surface_bits(uint32_t *smask, int64_t p0, int64_t p1, uint32_t bits) {
+    for (int64_t i = p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p1; i += (int64_t)gridDim.x * blockDim.x)
+        smask[i] &= ~bits;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dem_set_surfaces(dem_ctx *c, int32_t sys, int32_t count, const dem_surface *surf) {
+    if (!c) return DEM_ERR_ARG;
+    if (sys < 0 || sys >= (int32_t)c->geo.sys.size()) return fail(c, DEM_ERR_ARG, "sys out of range");
+    if (count < 0 || count > c->geo.surf_cap[sys])
+        return fail(c, DEM_ERR_ARG, "count exceeds the surfaces reserved for the system (dem_config.n_surf)");
+    if (count > 0 && !surf) return fail(c, DEM_ERR_ARG, "surf is NULL");
+    Surf next[kMaxSurf];
+    memset(next, 0, sizeof next);
+    for (int k = 0; k < count; ++k) {
+        const dem_surface &q = surf[k];
+        const bool finite = std::isfinite(q.axis[0]) && std::isfinite(q.axis[1]) && std::isfinite(q.z0) &&
+                            std::isfinite(q.z1) && std::isfinite(q.r0) && std::isfinite(q.r1);
+        bool ok = finite && std::isfinite(q.mu) && q.kind >= DEM_SURF_CYLINDER && q.kind <= DEM_SURF_RING &&
+                  q.r0 > 0.0;
+        if (q.kind == DEM_SURF_CYLINDER || q.kind == DEM_SURF_CONE) ok = ok && q.z1 > q.z0;
+        if (q.kind == DEM_SURF_CONE) ok = ok && q.r1 > 0.0;
+        if (!ok) return fail(c, DEM_ERR_ARG, "bad surface record (kind, finite values, r0 > 0, z1 > z0, cone r1 > 0)");
+        Surf &w = next[k];
+        w.kind = q.kind;
+        w.enabled = q.enabled ? 1 : 0;
+        w.cx = q.axis[0];
+        w.cy = q.axis[1];
+        w.z0 = q.z0;
+        w.z1 = q.z1;
+        w.r0 = q.r0;
+        w.r1 = q.r1;
+        w.mu = q.mu;
+        if (q.kind == DEM_SURF_CONE) {
+            // unit generator from (r0, z0) to (r1, z1) and the inward unit normal of the section
+            const double sr = q.r1 - q.r0, sz = q.z1 - q.z0, len = std::sqrt(sr * sr + sz * sz);
+            w.len = len;
+            w.ur = sr / len;
+            w.uz = sz / len;
+            w.mr = -sz / len;
+            w.mz = sr / len;
+        }
+    }
+    Surf *cur = &c->geo.surf[(size_t)sys * kMaxSurf];
+    uint32_t changed = 0;
+    for (int k = 0; k < kMaxSurf; ++k)
+        if (memcmp(&cur[k], &next[k], sizeof(Surf)) != 0) changed |= 1u << k;
+    memcpy(cur, next, sizeof next);
+    SysDesc &d = c->geo.sys[sys];
+    d.nsurf = count;
+    HIPCALL(c, hipMemcpyAsync(c->ws + c->lay.surf + (size_t)sys * kMaxSurf * sizeof(Surf), cur, sizeof next,
+                              hipMemcpyHostToDevice, c->stream));
+    HIPCALL(c, hipMemcpyAsync(c->d_sys + sys, &d, sizeof(SysDesc), hipMemcpyHostToDevice, c->stream));
+    if (changed && c->lay.smask && d.p1 > d.p0) {
+        int64_t blocks = (d.p1 - d.p0 + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        k_clear_surface_bits<<<(int)blocks, 256, 0, c->stream>>>((uint32_t *)(c->ws + c->lay.smask), d.p0, d.p1,
+                                                                 changed);
+        HIPCALL(c, hipGetLastError());
+    }
+    HIPCALL(c, hipStreamSynchronize(c->stream));   // the host records above are copied from
     return DEM_OK;
 }
 

@@ -46,8 +46,74 @@ struct SysDesc {
     int32_t coef0;          // first PairCoef of this system (ntypes x ntypes, row major)
     int32_t type0;          // first entry of this system in the per-type arrays
     int32_t stride;         // multi-rate stepping: one step of dt every `stride` substeps (else 1)
+    int32_t nsurf;          // static wall surfaces of the system (Surf table entries surf0 ..)
+    int32_t surf0;
     int32_t pad_s;
 };
+
+// Static wall surfaces around a vertical axis through (cx, cy): the inside of
+// a cylinder (radius r0, z0 <= z <= z1), the inside of a cone frustum (radius
+// r0 at z0, r1 at z1), a horizontal disk (radius r0 at height z0, touched from
+// above) and a horizontal ring (radius r0 at z0, an edge).  The cone's unit
+// generator (ur, uz), its length and its inward unit normal (mr, mz) in the
+// meridional plane are derived on the host.
+constexpr int kMaxSurf = 4;
+enum : int { kSurfCylinder = 1, kSurfCone = 2, kSurfDisk = 3, kSurfRing = 4 };
+
+struct Surf {
+    int32_t kind, enabled;
+    double cx, cy, z0, z1, r0, r1;
+    double ur, uz, len, mr, mz;
+    double mu;              // friction of a contact with the surface (< 0: the particle's own)
+};
+
+// A sphere of radius r at (x, y, z) touching surface w: the distance from the
+// surface to the centre, 0 < dist < r, and the unit normal from the surface to
+// the centre.  A centre on or behind the surface, beyond its extent (cylinder
+// and cone: the normal's foot outside [z0, z1], disk: outside its radius) or
+// on the axis has no contact with it.
+__host__ __device__ inline bool surf_gap(const Surf &w, double x, double y, double z, double r, double &dist,
+                                         double &nx, double &ny, double &nz) {
+    const double dx = x - w.cx, dy = y - w.cy;
+    const double rho = sqrt(dx * dx + dy * dy);
+    if (w.kind == kSurfDisk) {
+        const double h = z - w.z0;
+        if (!(rho <= w.r0 && h > 0.0 && h < r)) return false;
+        dist = h;
+        nx = 0.0; ny = 0.0; nz = 1.0;
+        return true;
+    }
+    if (!(rho > 0.0)) return false;
+    const double ex = dx / rho, ey = dy / rho;
+    if (w.kind == kSurfCylinder) {
+        if (!(z >= w.z0 && z <= w.z1)) return false;
+        const double g = w.r0 - rho;
+        if (!(g > 0.0 && g < r)) return false;
+        dist = g;
+        nx = -ex; ny = -ey; nz = 0.0;
+        return true;
+    }
+    if (w.kind == kSurfCone) {
+        const double pr = rho - w.r0, pz = z - w.z0;
+        const double t = pr * w.ur + pz * w.uz;   // along the generator from (r0, z0)
+        if (!(t >= 0.0 && t <= w.len)) return false;
+        const double g = pr * w.mr + pz * w.mz;   // towards the inside
+        if (!(g > 0.0 && g < r)) return false;
+        dist = g;
+        nx = w.mr * ex; ny = w.mr * ey; nz = w.mz;
+        return true;
+    }
+    if (w.kind == kSurfRing) {
+        const double qr = rho - w.r0, qz = z - w.z0;
+        const double d2 = qr * qr + qz * qz;
+        if (!(d2 > 0.0 && d2 < r * r)) return false;
+        const double d = sqrt(d2);
+        dist = d;
+        nx = qr / d * ex; ny = qr / d * ey; nz = qz / d;
+        return true;
+    }
+    return false;
+}
 
 // Device flag block (one per context).
 struct Flags {
@@ -155,10 +221,14 @@ struct ContactIn {
     double wsx, wsy, wsz;        // r_a w_a + r_b w_b
 };
 
-__host__ __device__ inline bool contact_force(const ContactIn &c, bool wall, const PairCoef &k, double dt, bool update,
-                                              double &xix, double &xiy, double &xiz, double &fx, double &fy, double &fz,
-                                              double &ftx, double &fty, double &ftz, double &nx, double &ny,
-                                              double &nz, double &fn_out) {
+// The same with a wall of unit normal (nwx, nwy, nwz) (pointing from the wall
+// to the particle's centre, at distance c.dz): a static surface seen as flat
+// at the contact point.
+__host__ __device__ inline bool contact_force_n(const ContactIn &c, bool wall, double nwx, double nwy, double nwz,
+                                                const PairCoef &k, double dt, bool update, double &xix, double &xiy,
+                                                double &xiz, double &fx, double &fy, double &fz, double &ftx,
+                                                double &fty, double &ftz, double &nx, double &ny, double &nz,
+                                                double &fn_out) {
     double rs, dist;
     if (!wall) {
         double d2 = c.dx * c.dx + c.dy * c.dy + c.dz * c.dz;
@@ -182,7 +252,7 @@ __host__ __device__ inline bool contact_force(const ContactIn &c, bool wall, con
         R = c.ra * c.rb * sm * inv;
         M = c.ma * c.mb * rs * inv;
     } else {
-        nx = 0.0; ny = 0.0; nz = 1.0;
+        nx = nwx; ny = nwy; nz = nwz;
         R = c.ra;
         M = c.ma;
     }
@@ -227,6 +297,14 @@ __host__ __device__ inline bool contact_force(const ContactIn &c, bool wall, con
     ftx = tx; fty = ty; ftz = tz;
     fn_out = fn;
     return true;
+}
+
+__host__ __device__ inline bool contact_force(const ContactIn &c, bool wall, const PairCoef &k, double dt, bool update,
+                                              double &xix, double &xiy, double &xiz, double &fx, double &fy, double &fz,
+                                              double &ftx, double &fty, double &ftz, double &nx, double &ny,
+                                              double &nz, double &fn_out) {
+    return contact_force_n(c, wall, 0.0, 0.0, 1.0, k, dt, update, xix, xiy, xiz, fx, fy, fz, ftx, fty, ftz, nx, ny, nz,
+                           fn_out);
 }
 
 // Reverse mode of contact_force at the same inputs, for gradients of a

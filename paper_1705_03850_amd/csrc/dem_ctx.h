@@ -21,6 +21,7 @@ struct Layout {
     size_t nbr[2], cnt[2], xi[2], mask[2], ids[2];
     size_t cell_of, rank, order, cell_count, cell_start, scan_partial, shadow_d, shadow_i;
     size_t pos[2], vel[2], spin[2], im, sel, lcur, tile0, mtile0, msys, mlevel;
+    size_t surf, sxi, smask, shadow_s;   // surfaces (sxi, smask, shadow_s: 0 without any)
     size_t total;
 };
 
@@ -29,6 +30,9 @@ struct Geometry {
     std::vector<PairCoef> coef;
     std::vector<double> rho;
     std::vector<dem_material> mat;   // per type, all systems (host copy of the parameters)
+    std::vector<int32_t> surf_cap;   // surfaces reserved per system
+    std::vector<Surf> surf;          // [nsys * kMaxSurf] host copy of the surface table
+    int32_t nsurf_slots = 0;         // surface history slots per particle (the largest reservation)
     int64_t n = 0, ncell = 0;
     int32_t kmax = 0, block = 128;
 };

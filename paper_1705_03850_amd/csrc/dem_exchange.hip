@@ -54,6 +54,8 @@ struct ExArgs {
     const double *budget_in;   // [nb]
     int64_t nb;                // boundary cells
     double nrm[3], face, slab, interval;
+    double onrm[3], oface;     // outlet half-space (onrm = 0: none)
+    int32_t outlet;
     // scratch (in the binning scratch, free between list builds)
     int32_t *blocked;   // [K] 1: overlaps a kept sphere
     double *mass;       // [K]
@@ -153,7 +155,8 @@ __global__ void k_ex_mark(KArgs a, ExArgs e) {
         mx = max(mx, a.id[i]);
         if (lo != e.sys) continue;
         const double x = a.x[i], y = a.x[n + i], z = a.x[2 * n + i];
-        const int out = (x * e.nrm[0] + y * e.nrm[1] + z * e.nrm[2]) < e.face ? 1 : 0;
+        int out = (x * e.nrm[0] + y * e.nrm[1] + z * e.nrm[2]) < e.face ? 1 : 0;
+        if (e.outlet && (x * e.onrm[0] + y * e.onrm[1] + z * e.onrm[2]) < e.oface) out = 1;
         a.dead[i] = out;
         a.frame[i] = (int32_t)i;
         removed += out;
@@ -336,6 +339,7 @@ __global__ void k_ex_insert(KArgs a, ExArgs e, int64_t pe, int64_t nacc, int32_t
         a.id[i] = id0 + (int32_t)q;
         a.frame[i] = -1;   // no row in the previous list
         a.dead[i] = 0;
+        if (a.smask) a.smask[i] = 0;
         const double rho = a.rho[s.type0 + t];
         const double m = 4.0 / 3.0 * M_PI * rho * r * r * r;
         const double I = 0.4 * m * r * r;
@@ -407,6 +411,9 @@ int dem_exchange(dem_ctx *c, const dem_state *s, int32_t sys, const dem_exchange
         return fail(c, DEM_ERR_ARG, "a candidate array is NULL");
     const double nn = p->nrm[0] * p->nrm[0] + p->nrm[1] * p->nrm[1] + p->nrm[2] * p->nrm[2];
     if (!(std::fabs(nn - 1.0) < 1e-12)) return fail(c, DEM_ERR_ARG, "nrm must be a unit vector");
+    const double on = p->out_nrm[0] * p->out_nrm[0] + p->out_nrm[1] * p->out_nrm[1] + p->out_nrm[2] * p->out_nrm[2];
+    if (on != 0.0 && (!(std::fabs(on - 1.0) < 1e-12) || !std::isfinite(p->out_face)))
+        return fail(c, DEM_ERR_ARG, "out_nrm must be zero or a unit vector (with a finite out_face)");
     if (!std::isfinite(p->face) || !(p->interval >= 0.0) || !std::isfinite(p->interval) ||
         (p->interval > 0.0 && !(p->slab > 0.0 && std::isfinite(p->slab))))
         return fail(c, DEM_ERR_ARG, "need a finite face, interval >= 0 and slab > 0 with an interval");
@@ -435,6 +442,9 @@ int dem_exchange(dem_ctx *c, const dem_state *s, int32_t sys, const dem_exchange
     e.nb = p->ncell;
     for (int a = 0; a < 3; ++a) e.nrm[a] = p->nrm[a];
     e.face = p->face;
+    for (int a = 0; a < 3; ++a) e.onrm[a] = p->out_nrm[a];
+    e.oface = p->out_face;
+    e.outlet = (p->out_nrm[0] != 0.0 || p->out_nrm[1] != 0.0 || p->out_nrm[2] != 0.0) ? 1 : 0;
     e.slab = p->slab;
     e.interval = p->interval;
     e.blocked = (int32_t *)(sc + o_blocked);

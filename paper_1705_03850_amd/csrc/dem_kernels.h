@@ -23,6 +23,13 @@ struct KArgs {
     int32_t *dead;         // [n] 1 = removed at the next binning of its system (insertion events)
     double *fext_ws;       // [3][n] external forces (workspace)
     const double *fext;    // fext_ws while external forces are on, else null
+    // static wall surfaces (null when no system has any)
+    const Surf *surf;      // [nsys * kMaxSurf]
+    D4 *sxi;               // [nsurf_slots][n] tangential history of each surface contact
+    uint32_t *smask;       // [n] bit k: surface k holds non-zero history
+    double *shadow_s;      // binning scratch of sxi ([3 nsurf_slots][n] doubles) then smask ([n] words)
+    int32_t nsurf_slots;
+    int32_t pad_s;
     // systems
     const SysDesc *sys;
     const PairCoef *coef;

@@ -372,6 +372,16 @@ __global__ void k_gather(KArgs a, int frame_identity) {
         si[i] = a.type[src];
         si[n + i] = a.id[src];
         si[2 * n + i] = frame_identity ? (int32_t)src : a.frame[src];
+        if (a.sxi) {
+            double *ss = a.shadow_s;
+            for (int k = 0; k < a.nsurf_slots; ++k) {
+                const D4 h = a.sxi[k * n + src];
+                ss[(3 * k) * n + i] = h.x;
+                ss[(3 * k + 1) * n + i] = h.y;
+                ss[(3 * k + 2) * n + i] = h.z;
+            }
+            ((uint32_t *)(ss + 3 * a.nsurf_slots * n))[i] = a.smask[src];
+        }
     }
 }
 
@@ -399,6 +409,12 @@ __global__ void k_scatter_back(KArgs a) {
         a.type[i] = si[i];
         a.id[i] = si[n + i];
         a.frame[i] = si[2 * n + i];
+        if (a.sxi) {
+            const double *ss = a.shadow_s;
+            for (int k = 0; k < a.nsurf_slots; ++k)
+                a.sxi[k * n + i] = D4{ss[(3 * k) * n + i], ss[(3 * k + 1) * n + i], ss[(3 * k + 2) * n + i], 0.0};
+            a.smask[i] = ((const uint32_t *)(ss + 3 * a.nsurf_slots * n))[i];
+        }
     }
 }
 
@@ -798,7 +814,7 @@ __device__ __forceinline__ void load_step_coef(const KArgs &a, const SysDesc &s)
 // One particle of the force pass (see k_step): every lane of its group calls
 // this with the same i; s is the particle's system (the block's: a tile never
 // spans two systems), L its current list.
-template <bool BATCH, bool COUNT, int MODE, int G, bool MR>
+template <bool BATCH, bool COUNT, int MODE, int G, bool MR, bool SURF>
 __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, const List &L, int src, int update,
                                               int64_t i, int sy, const D4 &pi, const D4 &vi, const D4 &si, int code,
                                               int g, int gbase, uint64_t gmask, unsigned &ncont, unsigned &nwall,
@@ -903,6 +919,43 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
                 }
             }
         }
+        // the system's static surfaces, in table order (every lane computes them;
+        // lane 0 stores)
+        if (SURF && s.nsurf > 0) {
+            const uint32_t sm = a.smask[i];
+            uint32_t nsm = 0;
+            for (int k = 0; k < s.nsurf; ++k) {
+                const Surf w = a.surf[s.surf0 + k];
+                double dist, wnx, wny, wnz;
+                if (!w.enabled || !surf_gap(w, pi.x, pi.y, pi.z, ri, dist, wnx, wny, wnz)) continue;
+                PairCoef pc = coef[ti * s.ntypes + ti];
+                if (w.mu >= 0.0) pc.mu = w.mu;
+                ContactIn c;
+                c.dx = 0.0; c.dy = 0.0; c.dz = dist;
+                c.ra = ri; c.rb = 0.0; c.ma = mi; c.mb = 0.0;
+                c.vrx = vi.x; c.vry = vi.y; c.vrz = vi.z;
+                c.wsx = ri * si.x; c.wsy = ri * si.y; c.wsz = ri * si.z;
+                double hx = 0.0, hy = 0.0, hz = 0.0;
+                if ((sm >> k) & 1u) {
+                    const D4 h = a.sxi[k * n + i];
+                    hx = h.x; hy = h.y; hz = h.z;
+                }
+                double fx, fy, fz, ftx, fty, ftz, nx, ny, nz, fn;
+                if (contact_force_n(c, true, wnx, wny, wnz, pc, s.dt, update != 0, hx, hy, hz, fx, fy, fz, ftx, fty,
+                                    ftz, nx, ny, nz, fn)) {
+                    if (COUNT && g == 0) ++nwall;
+                    Fx = Fx + fx; Fy = Fy + fy; Fz = Fz + fz;
+                    Tx = Tx + -(ri * (ny * ftz - nz * fty));
+                    Ty = Ty + -(ri * (nz * ftx - nx * ftz));
+                    Tz = Tz + -(ri * (nx * fty - ny * ftx));
+                    if (update) {
+                        if (g == 0) a.sxi[k * n + i] = D4{hx, hy, hz, 0.0};
+                        nsm |= 1u << k;
+                    }
+                }
+            }
+            if (update && g == 0 && nsm != sm) a.smask[i] = nsm;
+        }
         // external force (the coupling's correcting force), added last
         if (a.fext) {
             Fx = Fx + a.fext[i];
@@ -952,7 +1005,7 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
         }
 }
 
-template <bool BATCH, bool COUNT, int MODE, int G, bool MR>
+template <bool BATCH, bool COUNT, int MODE, int G, bool MR, bool SURF>
 // Compiled for four waves per SIMD (at most 128 registers): the kernel waits
 // on gathers, and the fourth wave ran the 1e6-sphere bed 15 % and the
 // 64-system batch 14 % faster than three (the batch form spills a few bytes
@@ -1028,7 +1081,7 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
         const int64_t i = BATCH ? sd.p0 + (t - tlo) * ppb + threadIdx.x / G : t * ppb + threadIdx.x / G;
         if (i >= sd.pe) continue;   // past the system's live particles
         const D4 pi = a.pos[srcs][i], vi = a.vel[srcs][i], si = a.spin[srcs][i];
-        step_particle<BATCH, COUNT, MODE, G, MR>(a, sd, (lc & 1) ? a.lst[1] : a.lst[0], srcs, update, i, sy, pi, vi,
+        step_particle<BATCH, COUNT, MODE, G, MR, SURF>(a, sd, (lc & 1) ? a.lst[1] : a.lst[0], srcs, update, i, sy, pi, vi,
                                                  si, (int)si.w, g, gbase, gmask, ncont, nwall, need, bad, last);
     }
     if (bad) atomicOr(&a.flags->err, kErrNonFinite);
@@ -1184,20 +1237,31 @@ static hipError_t launch_step_g(const KArgs &a, int src, int mode, int k, int up
     const int64_t ntiles = a.nsys > 1 ? a.ntiles_b : (a.n + ppb - 1) / ppb;
     const int g = grid_for(ntiles * a.block, a.block, a.grid_cap);
     const int B = a.block;
-#define STEP_LAUNCH(BT, CT, MD) k_step<BT, CT, MD, G, false><<<g, B, 0, st>>>(a, src, k, update)
-#define STEP_MODES(BT, CT)                                  \
-    if (mode == 0) STEP_LAUNCH(BT, CT, 0);                  \
-    else if (mode == 1) STEP_LAUNCH(BT, CT, 1);             \
-    else STEP_LAUNCH(BT, CT, 2)
+#define STEP_LAUNCH(BT, CT, MD, SF) k_step<BT, CT, MD, G, false, SF><<<g, B, 0, st>>>(a, src, k, update)
+#define STEP_MODES(BT, CT, SF)                                  \
+    if (mode == 0) STEP_LAUNCH(BT, CT, 0, SF);                  \
+    else if (mode == 1) STEP_LAUNCH(BT, CT, 1, SF);             \
+    else STEP_LAUNCH(BT, CT, 2, SF)
     if (a.nsys > 1 && a.multirate && mode != 0) {
         // each system decides per block whether the substep is one of its steps
         // and whether it is its last one of the call (the mode-2 epilogue)
-        if (count) k_step<true, true, 1, G, true><<<g, B, 0, st>>>(a, src, k, update);
-        else k_step<true, false, 1, G, true><<<g, B, 0, st>>>(a, src, k, update);
+        if (a.sxi) {
+            if (count) k_step<true, true, 1, G, true, true><<<g, B, 0, st>>>(a, src, k, update);
+            else k_step<true, false, 1, G, true, true><<<g, B, 0, st>>>(a, src, k, update);
+        } else {
+            if (count) k_step<true, true, 1, G, true, false><<<g, B, 0, st>>>(a, src, k, update);
+            else k_step<true, false, 1, G, true, false><<<g, B, 0, st>>>(a, src, k, update);
+        }
+    } else if (a.sxi) {   // surfaces: a separate instantiation keeps the others' registers
+        if (a.nsys > 1) {
+            if (count) { STEP_MODES(true, true, true); } else { STEP_MODES(true, false, true); }
+        } else {
+            if (count) { STEP_MODES(false, true, true); } else { STEP_MODES(false, false, true); }
+        }
     } else if (a.nsys > 1) {
-        if (count) { STEP_MODES(true, true); } else { STEP_MODES(true, false); }
+        if (count) { STEP_MODES(true, true, false); } else { STEP_MODES(true, false, false); }
     } else {
-        if (count) { STEP_MODES(false, true); } else { STEP_MODES(false, false); }
+        if (count) { STEP_MODES(false, true, false); } else { STEP_MODES(false, false, false); }
     }
 #undef STEP_MODES
 #undef STEP_LAUNCH

@@ -37,7 +37,27 @@ class Config(ctypes.Structure):
                 ("g", ctypes.c_double * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("periodic", ctypes.c_int32 * 3), ("wall_z0", ctypes.c_int32), ("skin", ctypes.c_double),
                 ("cell", ctypes.c_double), ("r_max", ctypes.c_double), ("n", ctypes.c_int64),
-                ("k_max", ctypes.c_int32), ("block", ctypes.c_int32), ("n_max", ctypes.c_int64)]
+                ("k_max", ctypes.c_int32), ("block", ctypes.c_int32), ("n_max", ctypes.c_int64),
+                ("n_surf", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class Surface(ctypes.Structure):
+    """dem_surface: kind (1 cylinder, 2 cone, 3 disk, 4 ring), enabled, axis (x, y),
+    heights z0, z1, radii r0, r1 and the contact friction mu (< 0: the particle's)."""
+    _fields_ = [("kind", ctypes.c_int32), ("enabled", ctypes.c_int32), ("axis", ctypes.c_double * 2),
+                ("z0", ctypes.c_double), ("z1", ctypes.c_double), ("r0", ctypes.c_double), ("r1", ctypes.c_double),
+                ("mu", ctypes.c_double)]
+
+
+def make_surfaces(records):
+    """dem_surface array from records (kind, enabled, cx, cy, z0, z1, r0, r1[, mu])."""
+    arr = (Surface * max(1, len(records)))()
+    for k, q in enumerate(records):
+        arr[k].kind, arr[k].enabled = int(q[0]), int(q[1])
+        arr[k].axis[0], arr[k].axis[1] = float(q[2]), float(q[3])
+        arr[k].z0, arr[k].z1, arr[k].r0, arr[k].r1 = float(q[4]), float(q[5]), float(q[6]), float(q[7])
+        arr[k].mu = float(q[8]) if len(q) > 8 else -1.0
+    return arr
 
 
 class State(ctypes.Structure):
@@ -61,9 +81,11 @@ class PParams(ctypes.Structure):
 
 class ExchangeParams(ctypes.Structure):
     """dem_exchange_params: boundary face (region x . nrm >= face), inflow slab
-    and interval, number of boundary cells."""
+    and interval, number of boundary cells, an optional outlet half-space
+    (region also x . out_nrm >= out_face; out_nrm = 0: none)."""
     _fields_ = [("nrm", ctypes.c_double * 3), ("face", ctypes.c_double), ("slab", ctypes.c_double),
-                ("interval", ctypes.c_double), ("ncell", ctypes.c_int64)]
+                ("interval", ctypes.c_double), ("ncell", ctypes.c_int64), ("out_nrm", ctypes.c_double * 3),
+                ("out_face", ctypes.c_double)]
 
 
 # rows of a fields array (dem.h: DEM_F_*)
@@ -86,7 +108,7 @@ _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_b
             "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
             "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
             "dem_adjoint_destroy", "dem_cell_fields", "dem_pi_control", "dem_p_control", "dem_set_external_force",
-            "dem_set_multirate", "dem_exchange", "dem_live_count"]
+            "dem_set_multirate", "dem_exchange", "dem_live_count", "dem_set_surfaces"]
 
 
 def load(path: str = LIB_PATH):
@@ -146,6 +168,7 @@ def load(path: str = LIB_PATH):
     L.dem_set_external_force.argtypes = [vp, P(State), vp]
     L.dem_exchange.argtypes = [vp, P(State), i32, P(ExchangeParams), vp, vp, i64, vp, vp, vp, vp, vp, P(i64)]
     L.dem_live_count.argtypes = [vp, i32, P(i64)]
+    L.dem_set_surfaces.argtypes = [vp, i32, i32, P(Surface)]
     for name in _SYMBOLS:
         if name != "dem_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -158,7 +181,7 @@ def symbols():
 
 
 def make_config(system, k_max: int = 32, block: int = 0, cell: float = 0.0, skin: float | None = None,
-                n_max: int = 0) -> Config:
+                n_max: int = 0, n_surf: int = 0) -> Config:
     """dem_config of one workload system (inputs.workloads.System)."""
     c = Config()
     mats = system.materials
@@ -181,6 +204,7 @@ def make_config(system, k_max: int = 32, block: int = 0, cell: float = 0.0, skin
     c.k_max = k_max
     c.block = block
     c.n_max = int(n_max)
+    c.n_surf = int(n_surf)
     return c
 
 
@@ -203,11 +227,14 @@ class DemSystem:
     and ids are made unique by adding each system's slot offset).
     ``capacity``: particle slots per system (one number or a list; default:
     the system's count), room for spheres inserted by ``exchange``.
+    ``surfaces``: static wall surfaces per system (a list of records (kind,
+    enabled, cx, cy, z0, z1, r0, r1) for one system, or a list of such lists);
+    the system's surfaces can be changed later with ``set_surfaces``.
     """
 
     def __init__(self, systems, k_max: int = 32, block: int = 0, cell=0.0, skin=None, device: str = "cuda",
                  use_graph: bool = False, chunk: int = 64, lanes: int = 0, max_blocks: int = 0,
-                 static_workspace: bool = False, capacity=None):
+                 static_workspace: bool = False, capacity=None, surfaces=None):
         import torch
 
         self.torch = torch
@@ -221,7 +248,14 @@ class DemSystem:
         caps = capacity if isinstance(capacity, (list, tuple)) else [capacity] * self.nsys
         self.live_counts = [s.n for s in self.systems]
         self.counts = [s.n if caps[k] is None else int(caps[k]) for k, s in enumerate(self.systems)]
-        self.cfgs = (Config * self.nsys)(*[make_config(s, k_max, block, cells[k], skins[k], self.counts[k])
+        if surfaces is None:
+            surfs = [None] * self.nsys
+        elif self.nsys == 1 and (len(surfaces) == 0 or not isinstance(surfaces[0][0], (list, tuple))):
+            surfs = [surfaces]
+        else:
+            surfs = list(surfaces)
+        self.cfgs = (Config * self.nsys)(*[make_config(s, k_max, block, cells[k], skins[k], self.counts[k],
+                                                       len(surfs[k]) if surfs[k] else 0)
                                           for k, s in enumerate(self.systems)])
         self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
         self.n = int(self.offsets[-1])
@@ -261,6 +295,13 @@ class DemSystem:
         self._rc(self.L.dem_set_step_options(self.ctx, int(use_graph), int(chunk)))
         self._rc(self.L.dem_set_launch(self.ctx, int(lanes), int(max_blocks)))
         self.reset()
+        for k, sf in enumerate(surfs):
+            if sf:
+                self.set_surfaces(k, sf)
+
+    def set_surfaces(self, sys: int, records):
+        """Static wall surfaces of system `sys` (dem_set_surfaces)."""
+        self._rc(self.L.dem_set_surfaces(self.ctx, int(sys), len(records), make_surfaces(records)))
 
     # ------------------------------------------------------------ helpers
     def _rc(self, rc):
@@ -516,6 +557,41 @@ class DemSystem:
 
     def adjoint(self, nsteps: int, window: int = 20, max_windows: int = 0, keep: bool = False) -> "Adjoint":
         return Adjoint(self, nsteps, window, max_windows, keep)
+
+    def checkpoint(self) -> dict:
+        """Host snapshot from which from_checkpoint resumes bit for bit: per
+        system its live particles (positions, velocities, spins, radii, types,
+        ids relative to the system's slot offset), forces and torques, plus the
+        tangential history of every pair in contact and of every wall contact
+        (by id).  The list itself is not saved: the step's results do not
+        depend on when it was built."""
+        from .inputs.workloads import System
+
+        h = [self.host(k) for k in range(self.nsys)]
+        systems = []
+        for k, s in enumerate(self.systems):
+            hk = h[k]
+            c = System(hk["x"], hk["v"], hk["w"], hk["r"], hk["type"].astype(np.int32),
+                       (hk["id"] - self.offsets[k]).astype(np.int32), list(s.materials), tuple(s.lo), tuple(s.hi),
+                       tuple(s.periodic), s.wall_z0, tuple(s.g), s.dt, s.skin, s.steps, s.name, s.alpha, dict(s.meta))
+            systems.append(c)
+        a, b, xi = self.export_contacts()
+        wid, wxi = self.export_wall()
+        return {"systems": systems, "f": np.concatenate([q["f"] for q in h]), "t": np.concatenate([q["t"] for q in h]),
+                "pairs": (a, b, xi), "wall": (wid, wxi), "capacity": list(self.counts),
+                "steps": self.stats()["steps"]}
+
+    @classmethod
+    def from_checkpoint(cls, ckpt: dict, **kwargs) -> "DemSystem":
+        """A new context resumed from checkpoint(): same slot capacities, the
+        state and history loaded, the saved forces declared current."""
+        g = cls(ckpt["systems"], capacity=ckpt["capacity"], **kwargs)
+        g.load_state(f=ckpt["f"], t=ckpt["t"])
+        g.reset()
+        g.build_list()
+        g.import_history(*ckpt["pairs"], *ckpt["wall"])
+        g.declare_forces()
+        return g
 
     def import_history(self, id_i, id_j, xi, wall_id=None, wall_xi=None):
         id_i = np.ascontiguousarray(id_i, np.int32); id_j = np.ascontiguousarray(id_j, np.int32)

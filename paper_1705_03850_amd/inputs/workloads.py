@@ -486,3 +486,72 @@ def exchange_inputs(system: System, zf: float, ncand: int, seed: int, cells=(2, 
     return {"nrm": (0.0, 0.0, -1.0), "face": -zf, "slab": slab, "interval": interval, "ncell": ncell,
             "fields": fields, "budget": budget, "cand_x": x, "cand_r": r,
             "cand_type": np.zeros(ncand, np.int32), "cand_cell": cell.astype(np.int32)}
+
+
+# ----------------------------------------------------------------------------
+# Silo (Sec. 3: filling and discharge)
+# ----------------------------------------------------------------------------
+
+SURF_CYLINDER, SURF_CONE, SURF_DISK, SURF_RING = 1, 2, 3, 4
+
+
+MAT_SILO = Material(E=2.5e7, nu=0.25, rho=1000.0, e=0.5, mu=0.2)   # the paper's silo table
+MU_WALL_SILO = 0.175                                                 # its particle-wall friction
+
+
+def silo_surfaces(scale: float = 1.0, open_orifice: bool = False, mu_wall: float = -1.0) -> list:
+    """Wall surfaces of the paper's silo scaled by `scale`: 40 cm high, the top
+    half a cylinder of 27 cm diameter, the lower half a cone narrowing to a
+    4 cm orifice at z = 0, closed by a plug (a disk) until the orifice opens;
+    the opened orifice's rim is an edge (a ring).  Records (kind, enabled,
+    axis x, axis y, z0, z1, r0, r1, mu), axis through the origin; mu the
+    particle-wall friction (< 0: the particle's own)."""
+    R, Ro, Hc, H = 0.135 * scale, 0.02 * scale, 0.20 * scale, 0.40 * scale
+    return [(SURF_CONE, 1, 0.0, 0.0, 0.0, Hc, Ro, R, mu_wall),
+            (SURF_CYLINDER, 1, 0.0, 0.0, Hc, H, R, 0.0, mu_wall),
+            (SURF_DISK, 0 if open_orifice else 1, 0.0, 0.0, 0.0, 0.0, Ro, 0.0, mu_wall),
+            (SURF_RING, 1 if open_orifice else 0, 0.0, 0.0, 0.0, 0.0, Ro, 0.0, mu_wall)]
+
+
+def silo_radius_at(z: np.ndarray, scale: float = 1.0) -> np.ndarray:
+    """Inner radius of the silo at height z (cone below half height, cylinder above)."""
+    R, Ro, Hc = 0.135 * scale, 0.02 * scale, 0.20 * scale
+    return np.where(z < Hc, Ro + (R - Ro) * np.clip(z, 0.0, Hc) / Hc, R)
+
+
+def silo_system(scale: float = 1.0, r: float = 1.4e-3, spread: float = 0.0, fill: float = 1.0, seed: int = 9,
+                speed: float = 0.0, mat: Material = MAT_A, dt: float = 1e-6, mu_wall: float = -1.0) -> System:
+    """Spheres of radius r (uniform in r (1 +- spread)) on a jittered cubic
+    lattice (spacing 2.1 r_max) filling the silo from the plug up to the
+    fraction `fill` of its height, each at least 1.05 r_max inside the walls;
+    velocities N(0, speed) per component.  Open box around the silo (no
+    periodic axis, no flat wall), gravity -z; the grid reaches 5 cm (scaled)
+    below the orifice, where discharged spheres are removed.  The paper's
+    reference silo holds 187,504 spheres of 2.8 mm diameter (r = 1.4 mm)."""
+    rng = np.random.default_rng(seed)
+    R, H = 0.135 * scale, 0.40 * scale
+    rmax = r * (1.0 + spread)
+    a = 2.1 * rmax
+    zs = np.arange(1.05 * rmax, H * fill - rmax, a)
+    xs = np.arange(-R, R + a / 2, a)
+    X, Y, Z = np.meshgrid(xs, xs, zs, indexing="ij")
+    pos = np.column_stack([X.ravel(), Y.ravel(), Z.ravel()])
+    rho = np.hypot(pos[:, 0], pos[:, 1])
+    # perpendicular clearance from the cone's slanted side: (R(z) - rho) cos(theta)
+    cos_t = 0.2 / math.hypot(0.115, 0.2)
+    clear = np.where(pos[:, 2] < 0.20 * scale, 1.05 * rmax / cos_t, 1.05 * rmax)
+    inside = rho <= silo_radius_at(pos[:, 2], scale) - clear
+    pos = pos[inside]
+    pos += rng.uniform(-0.02 * rmax, 0.02 * rmax, pos.shape)
+    n = pos.shape[0]
+    radii = r * (1.0 + spread * rng.uniform(-1.0, 1.0, n))
+    v = rng.normal(0.0, speed, (n, 3)) if speed > 0 else np.zeros((n, 3))
+    lo = (-R - 4 * rmax, -R - 4 * rmax, -0.05 * scale)
+    hi = (R + 4 * rmax, R + 4 * rmax, H + 4 * rmax)
+    s = System(x=pos, v=v, w=np.zeros((n, 3)), r=radii, type=np.zeros(n, np.int32), id=np.arange(n, dtype=np.int32),
+               materials=[mat], lo=lo, hi=hi, periodic=(0, 0, 0), wall_z0=0, g=(0.0, 0.0, -G0), dt=dt,
+               skin=0.1 * rmax, steps=0, name=f"silo_{n}", alpha=1.0)
+    s.meta["surfaces"] = silo_surfaces(scale, mu_wall=mu_wall)
+    s.meta["mu_wall"] = mu_wall
+    s.meta["scale"] = scale
+    return s

@@ -10,7 +10,8 @@ times (4 lanes per particle, 256-thread blocks, resident grid, graph replay).
     stepping over 130 steps.
   * two-level chute (2e5 + 5e5 spheres): the 2-system batch bit for bit
     equal to each system stepped alone, and each system against the oracle
-    over 10 steps.
+    over 10 steps; one insertion and deletion event on the fine level against
+    the oracle's SSI, bit for bit.
   * 64-system batch (3.8e6 spheres): bit for bit equal to each system stepped
     alone over 300 steps (with list rebuilds), and two systems against the
     oracle.
@@ -268,6 +269,53 @@ def test_two_level_chute_coupled_against_oracle():
             Lk = s.hi[ax] - s.lo[ax]
             d[:, ax] -= Lk * np.round(d[:, ax] / Lk)
         assert np.max(np.abs(d)) <= 1e-9 * max(s.hi[a] - s.lo[a] for a in range(3)), (k, np.max(np.abs(d)))
+
+
+def test_two_level_chute_exchange_at_full_size():
+    """One insertion and deletion event on the fine level of the two-level
+    chute (5e5 spheres, 4096 candidates in a 5 mm slab across its top face,
+    4 x 2 boundary cells) from the generator's state, in the bench
+    configuration: the accepted flags and remaining budget bit for bit equal
+    to the oracle's SSI (kept spheres more than 2 r_max away from the slab
+    cannot overlap a candidate and are left out of its brute force), the removed
+    set equal to the oracle's half-space test, the new spheres bit for bit;
+    and no sphere of the new fine system overlaps an inserted one (the
+    oracle's grid pairs)."""
+    import insertion as S
+    import test_gpu_exchange as X
+    coarse, fine = systems = W.chute_two_level()
+    cpl = W.chute_coupling(*systems)
+    zf = -cpl["face"] - 3e-3                          # some spheres above the face are removed
+    ev = W.exchange_inputs(fine, zf + 4e-3, 4096, seed=100, cells=(4, 2), budget_spheres=60.0, depth=5e-3)
+    ev["face"] = -zf
+    g = dem().DemSystem(systems, use_graph=True, chunk=64, capacity=[None, fine.n + 65536])
+    g.prime()
+    acc, budget, ins, rem = X.gpu_event(g, 1, ev)
+    b = S.inflow_budget(ev["budget"], ev["fields"][W.ROW_MOM:W.ROW_MOM + 3].T, ev["nrm"], ev["slab"],
+                        ev["interval"])
+    out = S.outside(fine.x, ev["nrm"], ev["face"])
+    keep = ~out
+    rmax = float(fine.r.max())
+    near = keep & (fine.x[:, 2] > zf + 4e-3 - 5e-3 - 2 * rmax)
+    rho = np.full(len(ev["cand_r"]), fine.materials[0].rho)
+    ref, left = S.ssi_accept(fine.x[near], fine.r[near], ev["cand_x"], ev["cand_r"], rho, ev["cand_cell"], b,
+                             [fine.hi[a] - fine.lo[a] for a in range(3)], fine.periodic)
+    assert acc.tolist() == ref.tolist() and ins == int(ref.sum()) > 100
+    assert rem == int(out.sum()) > 100
+    assert np.array_equal(budget.cpu().numpy(), left)
+    h = g.host(1)
+    off = int(g.offsets[1])
+    a = ref.astype(bool)
+    idmax = max(int(coarse.id.max()), int(fine.id.max()) + off)
+    want_ids = np.sort(np.concatenate([fine.id[keep] + off, idmax + 1 + np.arange(ins)]))
+    assert np.array_equal(h["id"], want_ids)
+    newsel = h["id"] > idmax
+    assert np.array_equal(h["x"][newsel], ev["cand_x"][a]) and np.array_equal(h["r"][newsel], ev["cand_r"][a])
+    new = fine.copy()
+    new.x, new.r, new.id = h["x"], h["r"], h["id"]
+    new.v, new.w, new.type = h["v"], h["w"], h["type"]
+    lo, hi = O.Oracle(new).pairs()
+    assert not np.any(lo > idmax) and not np.any(hi > idmax)
 
 
 def test_full_batch_of_64_systems():

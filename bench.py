@@ -196,10 +196,11 @@ def exchange_events(two, cpl, chunk, events=12, ncand=4096, interval=15):
     (Sec. 2.3): every `interval` steps one dem_exchange call on the fine system
     (5e5 spheres, 65,536 free slots) with `ncand` candidates in a 5 mm slab
     across its top face z_f over 4 x 2 boundary cells (seeded inflow fields,
-    budgets of up to 60 spheres per cell; spheres above z_f removed).  Wall
-    time of each synchronising call (removal, SSI, insertion, the system's list
-    rebuild and force pass), and the same system's plain forced rebuild for
-    scale."""
+    budgets of up to 60 spheres per cell; spheres above z_f removed, among them
+    those the previous event inserted above the face).  Wall time of each
+    synchronising call (removal, SSI, insertion, the system's list rebuild and
+    force pass), of a call that changes nothing, and the plain forced rebuild
+    of the context for scale."""
     import numpy as np
     import torch
 
@@ -211,11 +212,11 @@ def exchange_events(two, cpl, chunk, events=12, ncand=4096, interval=15):
     g = dem.DemSystem(two, use_graph=True, chunk=chunk, capacity=[None, fine.n + 65536])
     g.prime()
     g.step(64)
-    budget = torch.zeros(8, dtype=torch.float64, device=g.device)
     wall, ins, rem = [], [], []
     for k in range(events):
         ev = W.exchange_inputs(fine, zf + 4e-3, ncand, seed=100 + k, cells=(4, 2), budget_spheres=60.0,
                                depth=5e-3)
+        budget = torch.from_numpy(ev["budget"]).to(g.device)
         p = dem.ExchangeParams()
         for a in range(3):
             p.nrm[a] = ev["nrm"][a]
@@ -230,6 +231,15 @@ def exchange_events(two, cpl, chunk, events=12, ncand=4096, interval=15):
         ins.append(i)
         rem.append(r)
         g.step(interval)
+    # an event that changes nothing (no candidate, nothing to remove): the call's floor
+    p.face = -1.0
+    empty = torch.zeros(8, dtype=torch.float64, device=g.device)
+    noop = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.exchange(1, p, fields, empty)
+        noop.append(time.perf_counter() - t0)
     torch.cuda.synchronize()
     t_steps = time.perf_counter()
     g.step(64 * 4)
@@ -247,6 +257,7 @@ def exchange_events(two, cpl, chunk, events=12, ncand=4096, interval=15):
     w = sorted(wall[2:])
     return {"events": events, "candidates": ncand, "interval_steps": interval,
             "event_ms_median": 1e3 * w[len(w) // 2], "event_ms_max": 1e3 * max(wall[2:]),
+            "noop_event_ms_median": 1e3 * sorted(noop)[2],
             "inserted_mean": float(np.mean(ins)), "removed_mean": float(np.mean(rem)),
             "live_fine_after": g.live(1), "step_ms": 1e3 * t_steps,
             "rebuild_and_forces_ms_median": 1e3 * sorted(reb)[2],

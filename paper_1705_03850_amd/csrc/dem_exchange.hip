@@ -506,6 +506,14 @@ int dem_exchange(dem_ctx *c, const dem_state *s, int32_t sys, const dem_exchange
     }
     // ---- commit: outputs, new particles, then the system's list rebuild
     if (K > 0 || e.nb > 0) k_ex_out<<<blocks_for(std::max<int64_t>(K, e.nb), 256), 256, 0, st>>>(e, budget, accepted);
+    if (nacc == 0 && nrem == 0) {   // nothing inserted or removed: list and forces stay valid
+        HIPCALL(c, hipGetLastError());
+        counts[0] = 0;
+        counts[1] = 0;
+        counts[2] = sd.pe - sd.p0;
+        HIPCALL(c, hipStreamSynchronize(st));
+        return DEM_OK;
+    }
     const int64_t pe0 = sd.pe;
     if (nacc > 0) {
         k_ex_insert<<<blocks_for(nacc, 256), 256, 0, st>>>(a, e, pe0, nacc, h.ex_maxid + 1);

@@ -268,3 +268,22 @@ def test_empty_system_and_refill():
     g.step(20)
     rc, info = g.check()
     assert rc == d.DEM_OK
+
+
+def test_event_that_changes_nothing_keeps_the_run_bitwise():
+    s = bed(n=1500, seed=29)
+    runs = []
+    for event in (False, True):
+        g = dem().DemSystem(s, capacity=s.n + 10, use_graph=True, chunk=16)
+        g.prime()
+        g.step(40)
+        if event:
+            ev = W.exchange_inputs(s, 1.0, 0, seed=1)
+            ev["face"] = -1.0                       # region z <= 1 m: nothing removed
+            ev["fields"][:] = 0.0                   # no inflow
+            acc, budget, ins, rem = gpu_event(g, 0, ev)
+            assert ins == 0 and rem == 0 and g.live(0) == s.n
+        g.step(60)
+        runs.append(g.host(0))
+    for key in ("x", "v", "w", "f", "t", "id"):
+        assert np.array_equal(runs[0][key], runs[1][key]), key

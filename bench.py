@@ -423,6 +423,8 @@ def silo_run(label, r, dt, fill, settle_s, discharge_s, sample_s, chunk):
         work += live * per
         _, _, rem = g.exchange(0, p, fields, budget)
         rates.append(rem * m / sample_s)
+        if (k + 1) % 10 == 0:
+            log(f"silo {label}: {(k + 1) * sample_s:.2f} s discharged, {g.live(0)} spheres left")
     torch.cuda.synchronize()
     t_dis = time.perf_counter() - t1
     st = g.stats()
@@ -442,23 +444,165 @@ def silo_run(label, r, dt, fill, settle_s, discharge_s, sample_s, chunk):
     return out
 
 
+def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, sample_s=0.01):
+    """The multi-level silo (Sec. 2.3 on the silo of Sec. 3, Table 2's MLCG
+    rows): the coarse level (alpha = 2, d = 5.6 mm) fills the silo as in the
+    coarse-grain run; the fine level (d = 2.8 mm) fills its lower quarter
+    (z < 10 cm), the fine region.  On a grid of 2 cm cubes over the region
+    (8 x 8 in plan, five layers) every `interval` steps: the cell fields of
+    both levels; the PI controller on the fine spheres of the top layer (the
+    transition layer, boundary face z = 10 cm); the P controller in mass-flow
+    mode on the coarse spheres of the four layers below.  Every
+    `exchange_every` intervals an insertion event on the fine level: the
+    budget of each 2 x 2 cm boundary cell grows by the coarse inflow through
+    the face (the coarse fields of the 2 cm slab above it), candidates are
+    drawn in the top centimetre of the region and fine spheres above the face
+    are removed.  Both levels discharge through the orifice; each level's
+    rate is its mass removed 1 cm below the orifice per 10 ms."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1705_03850_amd import dem
+    from paper_1705_03850_amd.inputs import workloads as W
+
+    dt = 1e-6
+    mat, muw = W.MAT_SILO, W.MU_WALL_SILO
+    coarse = W.silo_system(scale=1.0, r=2.8e-3, fill=0.53, dt=dt, mat=mat, mu_wall=muw, seed=9)
+    coarse.alpha = 2.0
+    fine = W.silo_system(scale=1.0, r=1.4e-3, fill=0.25, dt=dt, mat=mat, mu_wall=muw, seed=10)
+    log(f"multi-level silo: {coarse.n} coarse spheres (d = 5.6 mm), {fine.n} fine (d = 2.8 mm) below z = 10 cm")
+    closed = W.silo_surfaces(1.0, mu_wall=muw)
+    g = dem.DemSystem([coarse, fine], surfaces=[closed, closed], capacity=[coarse.n, fine.n + 200_000],
+                      use_graph=True, chunk=chunk)
+    g.prime()
+    zf, h = 0.10, 0.02
+    pi_grid = dem.make_grid((-0.08, -0.08, zf - h), (h, h, h), (8, 8, 1), sys=1)
+    pi_grid_c = dem.make_grid((-0.08, -0.08, zf - h), (h, h, h), (8, 8, 1), sys=0)
+    p_grid_f = dem.make_grid((-0.08, -0.08, 0.0), (h, h, h), (8, 8, 4), sys=1)
+    p_grid_c = dem.make_grid((-0.08, -0.08, 0.0), (h, h, h), (8, 8, 4), sys=0)
+    in_grid_c = dem.make_grid((-0.08, -0.08, zf), (h, h, h), (8, 8, 1), sys=0)
+    pp = dem.PIParams()
+    pp.grid = pi_grid
+    pp.nrm[2] = -1.0
+    pp.face, pp.kp, pp.ki, pp.fade, pp.interval = -zf, 1.0, 200.0, 1.5, interval * dt
+    qp = dem.PParams()
+    qp.grid, qp.kp, qp.mass_flow = p_grid_c, 2000.0, 1
+    integral = torch.zeros(64, dtype=torch.float64, device=g.device)
+    ex = dem.ExchangeParams()
+    ex.nrm[2] = -1.0
+    ex.face, ex.slab, ex.interval, ex.ncell = -zf, h, exchange_every * interval * dt, 64
+    budget = torch.zeros(64, dtype=torch.float64, device=g.device)
+    out = dem.ExchangeParams()
+    out.nrm[2] = -1.0
+    out.face, out.slab, out.interval, out.ncell = -1e9, 1.0, 0.0, 1
+    out.out_nrm[2] = 1.0
+    out.out_face = -0.01
+    zero_f = torch.zeros((16, 1), dtype=torch.float64, device=g.device)
+    zero_b = torch.zeros(1, dtype=torch.float64, device=g.device)
+    rng = np.random.default_rng(12)
+    rf = 1.4e-3
+    mf = 4.0 / 3.0 * math.pi * mat.rho * rf ** 3
+    mc = 4.0 / 3.0 * math.pi * mat.rho * (2.0 * rf) ** 3
+
+    def candidates(per_cell=12, depth=0.01):
+        cell = np.repeat(np.arange(64), per_cell)
+        k = cell.size
+        x = -0.08 + (cell % 8 + rng.uniform(0.0, 1.0, k)) * h
+        y = -0.08 + (cell // 8 + rng.uniform(0.0, 1.0, k)) * h
+        z = zf - depth * rng.uniform(0.0, 1.0, k)
+        inside = np.hypot(x, y) <= W.silo_radius_at(z) - 1.05 * rf / (0.2 / math.hypot(0.115, 0.2))
+        c = [np.column_stack([x, y, z])[inside], np.full(int(inside.sum()), rf), np.zeros(int(inside.sum()), np.int32),
+             cell[inside].astype(np.int32)]
+        return [torch.from_numpy(np.ascontiguousarray(a)).to(g.device) for a in c]
+
+    def interval_coupling():
+        g.pi_control(pp, g.cell_fields(pi_grid), g.cell_fields(pi_grid_c), integral)
+        g.p_control(qp, g.cell_fields(p_grid_f), g.cell_fields(p_grid_c))
+
+    inserted = removed_top = 0
+    t_cpl = t_ex = 0.0
+
+    def run(seconds, sampling):
+        nonlocal inserted, removed_top, t_cpl, t_ex
+        rates_f, rates_c = [], []
+        per_sample = int(round(sample_s / (interval * dt)))
+        n_int = int(round(seconds / (interval * dt)))
+        for k in range(n_int):
+            tc = time.perf_counter()
+            interval_coupling()
+            t_cpl += time.perf_counter() - tc
+            g.step(interval)
+            if (k + 1) % exchange_every == 0:
+                te = time.perf_counter()
+                fields = g.cell_fields(in_grid_c)
+                _, i, r = g.exchange(1, ex, fields, budget, *candidates())
+                inserted += i
+                removed_top += r
+                t_ex += time.perf_counter() - te
+            if sampling and (k + 1) % per_sample == 0:
+                _, _, rf_ = g.exchange(1, out, zero_f, zero_b)
+                _, _, rc_ = g.exchange(0, out, zero_f, zero_b)
+                rates_f.append(rf_ * mf / (per_sample * interval * dt))
+                rates_c.append(rc_ * mc / (per_sample * interval * dt))
+            if (k + 1) % (5 * per_sample) == 0:
+                log(f"multi-level silo: {(k + 1) * interval * dt:.2f} s of {seconds:.2f} s"
+                    f"{' (discharge)' if sampling else ' (settling)'}; fine {g.live(1)}, coarse {g.live(0)}, "
+                    f"inserted {inserted}")
+        return np.array(rates_f), np.array(rates_c)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(settle_s, False)
+    torch.cuda.synchronize()
+    t_settle = time.perf_counter() - t0
+    opened = W.silo_surfaces(1.0, open_orifice=True, mu_wall=muw)
+    g.set_surfaces(0, opened)
+    g.set_surfaces(1, opened)
+    t1 = time.perf_counter()
+    rates_f, rates_c = run(discharge_s, True)
+    torch.cuda.synchronize()
+    t_dis = time.perf_counter() - t1
+    skip = int(0.2 / sample_s)
+    sf, sc = rates_f[skip:], rates_c[skip:]
+    res = {"coarse_spheres": coarse.n, "fine_spheres_start": fine.n, "fine_live_end": g.live(1),
+           "coarse_live_end": g.live(0), "interval_steps": interval, "exchange_every_intervals": exchange_every,
+           "inserted": inserted, "removed_above_face": removed_top,
+           "rate_fine_kg_s_mean": float(sf.mean()), "rate_fine_kg_s_std": float(sf.std()),
+           "rate_coarse_kg_s_mean": float(sc.mean()), "rate_coarse_kg_s_std": float(sc.std()),
+           "settle_wall_s": t_settle, "discharge_wall_s": t_dis, "coupling_wall_s": t_cpl, "exchange_wall_s": t_ex,
+           "rates_fine_kg_s": [round(float(q), 4) for q in rates_f],
+           "rates_coarse_kg_s": [round(float(q), 4) for q in rates_c]}
+    log(f"multi-level silo: fine {res['rate_fine_kg_s_mean']:.3f} +- {res['rate_fine_kg_s_std']:.3f} kg/s, coarse "
+        f"{res['rate_coarse_kg_s_mean']:.3f} +- {res['rate_coarse_kg_s_std']:.3f} kg/s, settle {t_settle:.1f} s, "
+        f"discharge {t_dis:.1f} s")
+    return res
+
+
 def silo_suite(args):
     """The paper's silo discharge (Sec. 3, Table 2): the reference (d = 2.8 mm)
     and the coarse-grain model (alpha = 2, d = 5.6 mm, same dt), each filled
     from a lattice to about 187,504 reference spheres' worth, settled 0.2 s,
     discharged 1.0 s; discharge rates sampled at 100 Hz 1 cm below the orifice.
     The paper reports 0.400 and 0.315 kg/s (its fill is poured, ours starts
-    from a lattice)."""
+    from a lattice).  With --silo-mlcg also the multi-level silo (0.390 and
+    0.391 kg/s in the paper)."""
     import torch
 
     settle = args.silo_settle
-    ref = silo_run("reference", 1.4e-3, 1e-6, 0.525, settle, args.silo_discharge, 0.01, args.chunk)
-    cg = silo_run("CG alpha=2", 2.8e-3, 1e-6, 0.53, settle, args.silo_discharge, 0.01, args.chunk)
     line = {"suite": "silo", "metric": "silo discharge rate (kg/s) and particle-steps/s", "dtype": "f64",
-            "data": "synthetic", "reference": ref, "cg_alpha2": cg,
-            "cg_over_reference": cg["rate_kg_s_mean"] / ref["rate_kg_s_mean"],
-            "paper": {"reference": 0.400, "cg_alpha2": 0.315, "cg_over_reference": 0.315 / 0.400},
+            "data": "synthetic",
+            "paper": {"reference": 0.400, "cg_alpha2": 0.315, "cg_over_reference": 0.315 / 0.400,
+                      "mlcg_fine": 0.390, "mlcg_coarse": 0.391},
             "device": torch.cuda.get_device_name(0)}
+    if not args.silo_mlcg_only:
+        ref = silo_run("reference", 1.4e-3, 1e-6, 0.525, settle, args.silo_discharge, 0.01, args.chunk)
+        cg = silo_run("CG alpha=2", 2.8e-3, 1e-6, 0.53, settle, args.silo_discharge, 0.01, args.chunk)
+        line.update({"reference": ref, "cg_alpha2": cg,
+                     "cg_over_reference": cg["rate_kg_s_mean"] / ref["rate_kg_s_mean"]})
+    if args.silo_mlcg or args.silo_mlcg_only:
+        line["mlcg"] = mlcg_silo_run(settle, args.silo_discharge, 16)
     print(json.dumps(line), flush=True)
 
 
@@ -570,6 +714,8 @@ def main():
     ap.add_argument("--adj-lanes", type=int, default=0, help="adjoint suite: threads per particle (0: library default)")
     ap.add_argument("--silo-settle", type=float, default=0.2, help="silo suite: settling time (s)")
     ap.add_argument("--silo-discharge", type=float, default=1.0, help="silo suite: discharge time (s)")
+    ap.add_argument("--silo-mlcg", action="store_true", help="silo suite: also the multi-level silo")
+    ap.add_argument("--silo-mlcg-only", action="store_true", help="silo suite: the multi-level silo only")
     ap.add_argument("--suite", choices=("plain", "batch", "adjoint", "silo"), default="plain",
                     help="plain: the 1e6-sphere bed (default); batch: 64-system and two-level batches vs plain")
     ap.add_argument("--no-autotune", action="store_true", help="batch suite: default launch shape and skin")

@@ -474,7 +474,7 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
     fine = W.silo_system(scale=1.0, r=1.4e-3, fill=0.25, dt=dt, mat=mat, mu_wall=muw, seed=10)
     log(f"multi-level silo: {coarse.n} coarse spheres (d = 5.6 mm), {fine.n} fine (d = 2.8 mm) below z = 10 cm")
     closed = W.silo_surfaces(1.0, mu_wall=muw)
-    g = dem.DemSystem([coarse, fine], surfaces=[closed, closed], capacity=[coarse.n, fine.n + 200_000],
+    g = dem.DemSystem([coarse, fine], surfaces=[closed, closed], capacity=[coarse.n, fine.n + 40_000],
                       use_graph=True, chunk=chunk)
     g.prime()
     zf, h = 0.10, 0.02

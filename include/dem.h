@@ -330,8 +330,11 @@ enum {
  * wall contacts do not enter), v' = v - u with u the cell's Favre velocity.
  * Sums run in a fixed order (reproducible results).  Needs the neighbour list
  * of the current order (DEM_ERR_STATE) and spheres within one list cell of the
- * positions of the last list build (the state after dem_step always is;
- * DEM_ERR_STATE otherwise).  fields: device, caller-owned.  Synchronises. */
+ * positions of the last list build (the state after dem_step always is): a
+ * sphere found farther sets a sticky device error that the next synchronising
+ * call (dem_check, dem_step, dem_exchange) reports as DEM_ERR_STATE, and the
+ * controllers then leave the external forces as they are.  fields: device,
+ * caller-owned.  Enqueued (no synchronisation). */
 int dem_cell_fields(dem_ctx *ctx, const dem_state *s, const dem_grid *grid, double *fields);
 
 /* PI controller of the transition layer (Sec. 2.3).  grid: the transition

@@ -190,13 +190,15 @@ Layout make_layout(const Geometry &g) {
     return L;
 }
 
-// First tile of every system for the batch step at the current launch shape
-// (tiles of block / lanes particles, none shared by two systems).
+// First tile of every system for the fused step at the current launch shape
+// (tiles of block / lanes particles over each system's live particles, none
+// shared by two systems); uploaded again when insertions or removals change
+// the live counts.
 int upload_tiles(dem_ctx *c) {
     const int64_t ppb = c->geo.block / c->lanes;
     std::vector<int64_t> t0(c->geo.sys.size() + 1, 0);
     for (size_t s = 0; s < c->geo.sys.size(); ++s) {
-        const int64_t ns = c->geo.sys[s].p1 - c->geo.sys[s].p0;
+        const int64_t ns = c->geo.sys[s].pe - c->geo.sys[s].p0;
         t0[s + 1] = t0[s] + (ns + ppb - 1) / ppb;
     }
     c->ntiles_b = t0.back();
@@ -325,6 +327,10 @@ int flag_error(dem_ctx *c, const Flags &h) {
     }
     if (h.err & kErrCellOverflow) return fail(c, DEM_ERR_CAPACITY, "a cell holds more than 64 particles");
     if (h.err & kErrBadInput) return fail(c, DEM_ERR_ARG, "a particle has a type out of range, a negative id or r <= 0");
+    if (h.err & kErrStale)
+        return fail(c, DEM_ERR_STATE,
+                    "cell fields found a sphere more than one list cell from its binned position (the list did not "
+                    "match the positions): step or rebuild first");
     return DEM_OK;
 }
 

@@ -14,7 +14,7 @@ constexpr int kCellSortMax = 64;        // cells holding more particles are left
 constexpr uint64_t kWallBit = 1ull << 63;
 
 // Sticky error bits of the device flag block.
-enum : int { kErrCapacity = 1, kErrNonFinite = 2, kErrCellOverflow = 4, kErrBadInput = 8 };
+enum : int { kErrCapacity = 1, kErrNonFinite = 2, kErrCellOverflow = 4, kErrBadInput = 8, kErrStale = 16 };
 
 // Coefficients of Eq. (6) for a type pair, folded so that a contact needs
 // three square roots and two divisions:
@@ -125,7 +125,7 @@ struct Flags {
     int64_t builds;         // list builds
     unsigned long long contacts;  // sum over force evaluations of directed contacts
     unsigned long long wall_contacts;
-    int32_t call_err;       // error of the current synchronising call (cleared by it)
+    int32_t reserved;
     int32_t pad0;
     int64_t call_base;      // multi-rate: step number before the first substep of the current dem_step
     int64_t step_end;       // multi-rate: step number of the call's last substep

@@ -6,10 +6,11 @@
 // particle range of every bin row that the cell, widened by one bin on each
 // side, touches: spheres stay within one bin of their binned position until
 // the next rebuild).  A cell's bin rows are dealt to S workgroups (S from the
-// cell count: few large cells still fill the device), whose threads take the
-// candidates in turn; each thread sums its own spheres, the block adds the
-// threads' sums in a fixed tree and a second kernel adds the S slices in
-// order: the result depends on nothing but the state, the grid and the
+// cell count, so that few large cells still fill the device, and at most the
+// cell's number of bin rows), whose threads take the candidates in turn; each
+// thread sums its own spheres, the block adds the threads' sums in a fixed
+// tree (all sums at once) and a second kernel adds the S slices in order: the
+// result depends on nothing but the state, the grid, the binning and the
 // workspace size.  A first pass gives mass and momentum, hence the Favre
 // velocity; the second the kinetic and contact parts of Eq. (7), the contact
 // forces evaluated as in a force pass without history update.
@@ -87,18 +88,24 @@ __device__ inline Pieces axis_pieces(const SysDesc &sd, int a, double b0, double
     return p;
 }
 
-// Sum (op 0) or maximum (op 1) of one value per thread, in a fixed tree over
-// the block; the result is returned to every thread.
-__device__ inline double block_reduce(double v, double *lds, int op) {
+// Sums of N values per thread (the last one a maximum when LASTMAX), each in
+// the same fixed tree over the block, all N at once (one barrier per level);
+// the results land in v of thread 0.  lds holds N kFB doubles.
+template <int N, bool LASTMAX>
+__device__ inline void block_reduce_n(double (&v)[N], double *lds) {
     const int t = threadIdx.x;
     __syncthreads();
-    lds[t] = v;
+    for (int k = 0; k < N; ++k) lds[k * kFB + t] = v[k];
     __syncthreads();
     for (int off = kFB / 2; off > 0; off >>= 1) {
-        if (t < off) lds[t] = op ? fmax(lds[t], lds[t + off]) : lds[t] + lds[t + off];
+        if (t < off)
+            for (int k = 0; k < N; ++k) {
+                const double a = lds[k * kFB + t], b = lds[k * kFB + t + off];
+                lds[k * kFB + t] = (LASTMAX && k == N - 1) ? fmax(a, b) : a + b;
+            }
         __syncthreads();
     }
-    return lds[0];
+    for (int k = 0; k < N; ++k) v[k] = lds[k * kFB];
 }
 
 // The bin rows (bz, by) a cell touches, numbered r = zi * RY + yi over the
@@ -151,7 +158,7 @@ __device__ inline CellBox cell_box(const SysDesc &sd, const FGrid &g, int64_t ce
 // Block (cell, b): slice b of S of the cell's rows.  S = 1 writes the cell's
 // rows of `out` directly; S > 1 writes the slice's sums to part[(cell S + b) kP1].
 __global__ void __launch_bounds__(kFB) k_fields1(KArgs a, FGrid g, int S, double *part, double *out) {
-    __shared__ double lds[kFB];
+    __shared__ double lds[kP1 * kFB];
     const SysDesc sd = a.sys[g.sys];
     const int64_t n = a.n;
     const int64_t cell = blockIdx.x / S;
@@ -172,7 +179,7 @@ __global__ void __launch_bounds__(kFB) k_fields1(KArgs a, FGrid g, int S, double
         vmax = fmax(vmax, sqrt(vx * vx + vy * vy + vz * vz));
     });
     double v[kP1] = {cnt, mass, px, py, pz, vol, vmax};
-    for (int k = 0; k < kP1; ++k) v[k] = block_reduce(v[k], lds, k == 6 ? 1 : 0);
+    block_reduce_n<kP1, true>(v, lds);
     if (threadIdx.x == 0) {
         if (S == 1) {
             const int64_t nc = g.ncell;
@@ -203,7 +210,7 @@ __global__ void k_fields1_reduce(FGrid g, int S, const double *part, double *out
 }
 
 __global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, double *part, double *out) {
-    __shared__ double lds[kFB];
+    __shared__ double lds[kP2 * kFB];
     const SysDesc sd = a.sys[g.sys];
     const int64_t n = a.n;
     const int64_t nc = g.ncell;
@@ -273,8 +280,9 @@ __global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, double
         }
     });
     double v[kP2];
-    for (int k = 0; k < 9; ++k) v[k] = block_reduce(con[k], lds, 0);
-    for (int k = 0; k < 6; ++k) v[9 + k] = block_reduce(kin[k], lds, 0);
+    for (int k = 0; k < 9; ++k) v[k] = con[k];
+    for (int k = 0; k < 6; ++k) v[9 + k] = kin[k];
+    block_reduce_n<kP2, false>(v, lds);
     if (threadIdx.x == 0) {
         if (S == 1) {
             // kinetic part: symmetric (m q_a q_b = m q_b q_a exactly)
@@ -309,7 +317,7 @@ __global__ void k_fields_guard(KArgs a, int32_t sys) {
          i += (int64_t)gridDim.x * blockDim.x)
         for (int ax = 0; ax < 3; ++ax)
             if (!(fabs(a.disp[ax * n + i]) * sd.inv_w[ax] <= 1.0)) bad = true;
-    if (bad) atomicOr(&a.flags->call_err, 1);
+    if (bad) atomicOr(&a.flags->err, kErrStale);
 }
 
 // PI update per transition cell: e = n.sigma_coarse.n - n.sigma_fine.n,
@@ -339,6 +347,7 @@ __global__ void k_pi_particles(KArgs a, FGrid g, const double *coarse, const dou
                                double nz, double face, double fade) {
     const SysDesc &sd = a.sys[g.sys];
     const int64_t n = a.n;
+    if (a.flags->err & kErrStale) return;   // fields from a stale list: forces left as they are
     for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.pe;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double x = a.x[i], y = a.x[n + i], z = a.x[2 * n + i];
@@ -371,6 +380,7 @@ __global__ void k_pi_particles(KArgs a, FGrid g, const double *coarse, const dou
 __global__ void k_p_particles(KArgs a, FGrid g, const double *fine, const double *coarse, double kp, int mass_flow) {
     const SysDesc &sd = a.sys[g.sys];
     const int64_t n = a.n, nc = g.ncell;
+    if (a.flags->err & kErrStale) return;   // fields from a stale list: forces left as they are
     for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.pe;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = field_cell(g, a.x[i], a.x[n + i], a.x[2 * n + i]);
@@ -391,10 +401,6 @@ __global__ void k_p_particles(KArgs a, FGrid g, const double *fine, const double
         a.fext_ws[n + i] = F[1];
         a.fext_ws[2 * n + i] = F[2];
     }
-}
-
-__global__ void k_clear_call_err(Flags *f) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) f->call_err = 0;
 }
 
 int grid_blocks(int64_t work, int block) {
@@ -456,14 +462,19 @@ int dem_cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double
     if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_cell_fields needs a neighbour list for the current order");
     KArgs a = kargs(c, s);
     HIPCALL(c, hipGetLastError());
-    k_clear_call_err<<<1, 64, 0, c->stream>>>(c->d_flags);
     const SysDesc &sd = c->geo.sys[g.sys];
     k_fields_guard<<<grid_blocks(sd.pe - sd.p0, 256), 256, 0, c->stream>>>(a, g.sys);
-    // slices per cell: enough blocks to fill the device when cells are few
-    // (a function of the cell count and the workspace only, so the sums' order
-    // is too); S = 1 writes the fields directly
+    // slices per cell: enough blocks to fill the device when cells are few, no
+    // more than a cell has bin rows (a function of the grid, the system's
+    // binning and the workspace only, so the sums' order is too); S = 1 writes
+    // the fields directly
     const size_t scratch = (size_t)kShadowD * c->geo.n * 8;
-    int S = (int)std::max<int64_t>(1, std::min<int64_t>(256, 4096 / g.ncell));
+    int64_t rows = 1;
+    for (int ax = 1; ax < 3; ++ax) {
+        const double w = sd.L[ax] / (double)sd.nc[ax];
+        rows *= std::min<int64_t>(sd.nc[ax], (int64_t)std::floor(g.h[ax] / w) + 3);
+    }
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(256, 4096 / g.ncell), rows));
     while (S > 1 && (size_t)g.ncell * S * kP2 * 8 > scratch) S /= 2;
     double *part = (double *)(c->ws + c->lay.shadow_d);
     const int64_t blocks = g.ncell * S;
@@ -473,12 +484,7 @@ int dem_cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double
     k_fields2<<<(int)blocks, kFB, 0, c->stream>>>(a, g, S, part, fields);
     if (S > 1) k_fields2_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part, fields);
     HIPCALL(c, hipGetLastError());
-    Flags h;
-    if ((rc = read_flags(c, h))) return rc;
-    if (h.call_err)
-        return fail(c, DEM_ERR_STATE,
-                    "a sphere moved more than one list cell since the last list build: step or rebuild first");
-    return flag_error(c, h);
+    return DEM_OK;
 }
 
 int dem_pi_control(dem_ctx *c, const dem_state *s, const dem_pi_params *p, const double *fine, const double *coarse,

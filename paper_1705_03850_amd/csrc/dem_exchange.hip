@@ -543,6 +543,9 @@ int dem_exchange(dem_ctx *c, const dem_state *s, int32_t sys, const dem_exchange
     if (he == hipSuccess) he = launch_ctrl(c->d_flags, 4, 1, st);
     c->win_on = win_was;
     memcpy(c->win, win_old, sizeof win_old);
+    if (he != hipSuccess) return hip_fail(c, he, "list rebuild after the exchange");
+    sd.pe = pe1;
+    if ((rc = upload_tiles(c))) return rc;   // the step's tiles follow the live count
     // the system's forces at its new state, history untouched (the other
     // systems' forces stay as they are)
     if (he == hipSuccess) {
@@ -551,8 +554,7 @@ int dem_exchange(dem_ctx *c, const dem_state *s, int32_t sys, const dem_exchange
         he = launch_pack(af, 0, 0, 0, 0, st);
         if (he == hipSuccess) he = launch_step(af, 0, 0, 0, 0, 0, st);
     }
-    if (he != hipSuccess) return hip_fail(c, he, "list rebuild after the exchange");
-    sd.pe = pe1;
+    if (he != hipSuccess) return hip_fail(c, he, "force pass after the exchange");
     c->have_list = true;
     c->list_current = true;
     c->binned = true;

@@ -216,11 +216,18 @@ __global__ void k_phase1(KArgs a, int k, int gate) {
 // counts of their own last binning, so that cell_start (one scan over all
 // cells) still gives every system the particle range of each of its cells in
 // the order it keeps until its next rebuild.
+// A system's spare cell starts with its free slots (placed without atomics,
+// in slot order); removed particles are counted in after them.
 __global__ void k_zero_selected_cells(KArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cell_count[a.ncell] = 0;
     for (int64_t c = a.cw0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.cw1;
-         c += (int64_t)gridDim.x * blockDim.x)
-        if (a.sel[sys_of_cell(a, c)]) a.cell_count[c] = 0;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int sy = sys_of_cell(a, c);
+        if (!a.sel[sy]) continue;
+        const SysDesc &s = a.sys[sy];
+        const bool spare = c == s.c0 + (int64_t)s.nc[0] * s.nc[1] * s.nc[2];
+        a.cell_count[c] = spare ? (int32_t)(s.p1 - s.pe) : 0;
+    }
 }
 
 template <bool BATCH>
@@ -230,12 +237,19 @@ __global__ void k_bin_count(KArgs a) {
         const int sy = sys_of<BATCH>(a, i);
         if (!a.sel[sy]) continue;
         const SysDesc &s = a.sys[sy];
-        // free slots and removed particles go to the spare cell past the grid
-        // (removal marks are consumed here)
-        const bool gone = i >= s.pe || a.dead[i];
-        if (a.dead[i]) a.dead[i] = 0;
-        int64_t c = s.c0 + (int64_t)s.nc[0] * s.nc[1] * s.nc[2];
-        if (!gone) {
+        // free slots and removed particles go to the spare cell past the grid:
+        // the free slots first, in slot order (no atomics: a system may hold
+        // many), then the removed ones (removal marks are consumed here)
+        const int64_t spare = s.c0 + (int64_t)s.nc[0] * s.nc[1] * s.nc[2];
+        if (i >= s.pe) {
+            a.cell_of[i] = (int32_t)spare;
+            a.rank[i] = (int32_t)(i - s.pe);
+            continue;
+        }
+        int64_t c = spare;
+        if (a.dead[i]) {
+            a.dead[i] = 0;
+        } else {
             int cx = cell_coord(a.x[i], s, 0);
             int cy = cell_coord(a.x[n + i], s, 1);
             int cz = cell_coord(a.x[2 * n + i], s, 2);
@@ -1034,7 +1048,8 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
     // block moves on to a tile of another system.  Multi-rate: only the tiles of
     // the systems that step at this substep, a prefix of the tiles in stride
     // order, spread over the XCDs like all tiles otherwise
-    int64_t ntiles = BATCH ? a.ntiles_b : (n + ppb - 1) / ppb;
+    // tiles over the systems' live particles (the table follows insertions and removals)
+    int64_t ntiles = uniform_i64(a.tile0[a.nsys]);
     if (MR) {
         const int64_t q1 = step - cbase - 1;
         const int lvl = q1 == 0 ? kMaxLevels - 1 : min(__builtin_ctzll((unsigned long long)q1), kMaxLevels - 1);
@@ -1234,7 +1249,7 @@ hipError_t launch_unpack(const KArgs &a, int src, int selected, hipStream_t st, 
 template <int G>
 static hipError_t launch_step_g(const KArgs &a, int src, int mode, int k, int update, int count, hipStream_t st) {
     const int ppb = a.block / G;
-    const int64_t ntiles = a.nsys > 1 ? a.ntiles_b : (a.n + ppb - 1) / ppb;
+    const int64_t ntiles = a.ntiles_b;
     const int g = grid_for(ntiles * a.block, a.block, a.grid_cap);
     const int B = a.block;
 #define STEP_LAUNCH(BT, CT, MD, SF) k_step<BT, CT, MD, G, false, SF><<<g, B, 0, st>>>(a, src, k, update)

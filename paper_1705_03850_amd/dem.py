@@ -482,9 +482,23 @@ class DemSystem:
         F_STRESS..+8 (sigma_ab of Eq. 7 at row F_STRESS + 3 a + b)."""
         ncell = grid.n[0] * grid.n[1] * grid.n[2]
         out = self.torch.empty((NFIELDS, ncell), dtype=self.torch.float64, device=self.device)
-        self.torch.cuda.current_stream(self.device).synchronize()
+        self._enter(out)
         self._rc(self.L.dem_cell_fields(self.ctx, self._state, ctypes.byref(grid), _ptr(out)))
+        self._leave()
         return out
+
+    # The library works on its own stream; tensors come from and go to the
+    # caller's current stream: ordered on the device by stream waits, without
+    # blocking the host.
+    def _enter(self, *tensors):
+        cur = self.torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
+
+    def _leave(self):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
     def pi_control(self, params: PIParams, fine, coarse, integral, u=None):
         """PI controller of the transition layer (fine system params.grid.sys):
@@ -493,26 +507,26 @@ class DemSystem:
         if u is None:
             u = self.torch.empty(ncell, dtype=self.torch.float64, device=self.device)
         fine, coarse = fine.contiguous(), coarse.contiguous()
-        self.torch.cuda.current_stream(self.device).synchronize()
+        self._enter(fine, coarse, integral, u)
         self._rc(self.L.dem_pi_control(self.ctx, self._state, ctypes.byref(params), _ptr(fine), _ptr(coarse),
                                        _ptr(integral), _ptr(u)))
-        self.stream.synchronize()
+        self._leave()
         return u
 
     def p_control(self, params: PParams, fine, coarse):
         """P controller of the coarse system params.grid.sys inside the fine region."""
         fine, coarse = fine.contiguous(), coarse.contiguous()
-        self.torch.cuda.current_stream(self.device).synchronize()
+        self._enter(fine, coarse)
         self._rc(self.L.dem_p_control(self.ctx, self._state, ctypes.byref(params), _ptr(fine), _ptr(coarse)))
-        self.stream.synchronize()
+        self._leave()
 
     def set_external_force(self, fext=None):
         """External forces of all spheres, device (3, n) in the current order, or None."""
         if fext is not None:
             fext = fext.to(self.torch.float64).contiguous()
-            self.torch.cuda.current_stream(self.device).synchronize()
+        self._enter(fext)
         self._rc(self.L.dem_set_external_force(self.ctx, self._state, _ptr(fext)))
-        self.stream.synchronize()
+        self._leave()
 
     def exchange(self, sys: int, params: ExchangeParams, fields, budget, cand_x=None, cand_r=None, cand_type=None,
                  cand_cell=None):
@@ -536,11 +550,11 @@ class DemSystem:
         acc = torch.zeros(max(k, 1), dtype=torch.int32, **dev)
         fields = fields.to(torch.float64).contiguous()
         counts = (ctypes.c_int64 * 3)()
-        torch.cuda.current_stream(self.device).synchronize()
+        self._enter(fields, budget, cx, cr, ct, cc, acc)
         self._rc(self.L.dem_exchange(self.ctx, self._state, int(sys), ctypes.byref(params), _ptr(fields),
                                      _ptr(budget), k, _ptr(cx), _ptr(cr), _ptr(ct), _ptr(cc), _ptr(acc), counts))
         self.live_counts[sys] = int(counts[2])
-        self.stream.synchronize()
+        self._leave()
         return acc[:k], int(counts[0]), int(counts[1])
 
     def live(self, sys: int) -> int:

@@ -649,7 +649,16 @@ def adjoint_suite(args, emit=True):
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
     g = dem.DemSystem(s)
-    adj = g.adjoint(steps, window=window, keep=args.keep)
+    # checkpoints sized for the longest neighbour row (with a margin for the
+    # rows of later builds) and for the windows the rollout needs
+    kslots, max_windows = args.kslots, args.max_windows
+    if kslots < 0:
+        g.build_list()
+        lo, _ = g.export_neighbors()
+        kslots = min(int(np.bincount(lo).max()) + 4, 32)
+    if max_windows < 0:
+        max_windows = -(-steps // window) + 3
+    adj = g.adjoint(steps, window=window, keep=args.keep, kslots=kslots, max_windows=max_windows)
     if args.adj_lanes:
         adj.set_lanes(args.adj_lanes)
     t_fwd, t_bwd = [], []
@@ -673,6 +682,7 @@ def adjoint_suite(args, emit=True):
     out = {
         "suite": "adjoint", "workload": "chute_adjoint(seed=5, n=50000), 200 steps, flux loss in 20 bins",
         "n": s.n, "steps": steps, "window": window, "keep": bool(args.keep), "lanes": args.adj_lanes or "default",
+        "kslots": kslots or 32, "max_windows": info["max_windows"],
         "dtype": "f64", "data": "synthetic",
         "plain_forward_s": tp, "adjoint_forward_s": tf, "backward_s": tb,
         "adjoint_vs_plain": (tf + tb) / tp, "backward_vs_plain": tb / tp,
@@ -711,6 +721,10 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--window", type=int, default=20, help="adjoint suite: steps per checkpoint window")
     ap.add_argument("--keep", action="store_true", help="adjoint suite: store every step's inputs (no recompute)")
+    ap.add_argument("--kslots", type=int, default=-1,
+                    help="adjoint suite: history slots per particle in the checkpoints (-1: longest row + 4, 0: k_max)")
+    ap.add_argument("--max-windows", type=int, default=-1,
+                    help="adjoint suite: checkpoint windows (-1: ceil(steps / window) + 3, 0: the library's default)")
     ap.add_argument("--adj-lanes", type=int, default=0, help="adjoint suite: threads per particle (0: library default)")
     ap.add_argument("--silo-settle", type=float, default=0.2, help="silo suite: settling time (s)")
     ap.add_argument("--silo-discharge", type=float, default=1.0, help="silo suite: discharge time (s)")
@@ -901,9 +915,9 @@ def main():
                                                                            "sequential_plain",
                                                                            "batched_vs_sequential", "coupled",
                                                                            "exchange")}}
-        keys = ("workload", "steps", "window", "keep", "windows", "plain_forward_s", "adjoint_forward_s",
-                "backward_s", "adjoint_vs_plain", "adjoint_workspace_bytes", "context_workspace_bytes",
-                "peak_torch_bytes")
+        keys = ("workload", "steps", "window", "keep", "kslots", "windows", "max_windows", "plain_forward_s",
+                "adjoint_forward_s", "backward_s", "adjoint_vs_plain", "adjoint_workspace_bytes",
+                "context_workspace_bytes", "peak_torch_bytes")
         # the headline: checkpoints every 20 steps, each window recomputed by the
         # backward (memory bounded by the window); the kept mode (every step's
         # inputs stored, nothing recomputed) is reported beside it

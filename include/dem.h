@@ -512,19 +512,27 @@ typedef struct dem_adjoint dem_adjoint;   /* opaque: rollout checkpoints and adj
  * (DEM_ERR_ARG for a batch).  max_windows bounds the number of windows: a
  * list rebuild ends a window early, so a rollout can need more than
  * ceil(nsteps / window); 0 selects 2 ceil(nsteps / window) + 1.
+ * kslots (1..k_max, 0 = k_max): the tangential-history slots per particle
+ * that the checkpoints and stored evaluation inputs hold, i.e. the longest
+ * neighbour row the rollout may meet; the rollout and dem_forces_vjp return
+ * DEM_ERR_CAPACITY when a list (the current one, or one built during the
+ * rollout) has a longer row.  Rows hold the neighbours within the skin, so
+ * a dense packing needs about 12, far fewer than a k_max sized for the
+ * densest case.
  * keep = 0: checkpoints at window starts, each window recomputed by the
- * backward; memory (max_windows + window) x (128 + 32 k_max) bytes per
+ * backward; memory (max_windows + window) x (128 + 32 kslots) bytes per
  * particle.  keep = 1: the inputs of every step are stored by the forward and
- * nothing is recomputed; memory (nsteps + 2) x (128 + 32 k_max) bytes per
- * particle.  Both: plus (max_windows + 1) x (28 + 4 k_max) bytes per particle
- * for the lists. */
+ * nothing is recomputed; memory (nsteps + 2) x (128 + 32 kslots) bytes per
+ * particle.  Both: plus (max_windows + 1) x (28 + 4 kslots) bytes per
+ * particle for the lists. */
 int dem_adjoint_workspace_size(dem_ctx *ctx, int64_t nsteps, int32_t window, int32_t max_windows, int32_t keep,
-                               size_t *bytes);
+                               int32_t kslots, size_t *bytes);
 
 /* Bind an adjoint to a context and a caller-owned device workspace (256-byte
- * aligned, at least the size above, untouched until dem_adjoint_destroy). */
+ * aligned, at least the size above for the same arguments, untouched until
+ * dem_adjoint_destroy). */
 int dem_adjoint_init(dem_ctx *ctx, int64_t nsteps, int32_t window, int32_t max_windows, int32_t keep,
-                     void *workspace, size_t bytes, dem_adjoint **out);
+                     int32_t kslots, void *workspace, size_t bytes, dem_adjoint **out);
 
 /* The rollout: the force evaluation of the current state without history
  * update (as dem_forces(ctx, s, 0)), then nsteps steps bit-identical to

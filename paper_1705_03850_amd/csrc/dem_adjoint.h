@@ -21,8 +21,10 @@ namespace dem {
 
 struct AArgs {
     int64_t n;
-    int32_t kmax;
+    int32_t kmax;            // slots per row of the live list (its history stride)
     int32_t ntypes;
+    int32_t kslots;          // slots per particle of the adjoint's own history buffers (<= kmax)
+    int32_t pad_a;
     const SysDesc *sys;      // the system
     const PairCoef *coef;    // ntypes x ntypes
     // topology of the window (order of its list build)
@@ -30,14 +32,14 @@ struct AArgs {
     const D2 *im;            // (1/m, 1/I)
     // the evaluation's input state
     const D4 *pos, *vel, *spin;
-    const D4 *hin;           // [n][kmax] slot history before the evaluation, zero where none
+    const D4 *hin;           // [n][kslots] slot history before the evaluation, zero where none
     const D4 *hwin;          // [n] wall history before the evaluation
     // recompute outputs
     D4 *pos_o, *vel_o, *spin_o, *hout, *hwout;
     // reverse
     const D4 *rin;           // [5][n] adjoint records (AX, AU, AW, SF, ST)
     D4 *rout;
-    D4 *mu;                  // [n][kmax] slot history adjoint (in: after, out: before the evaluation)
+    D4 *mu;                  // [n][kslots] slot history adjoint (in: after, out: before the evaluation)
     D4 *muw;                 // [n] wall history adjoint
     double *gp;              // [5 ntypes][n] coefficient adjoint partials of each particle
     double seed_scale;       // factor on the seeds read from rin
@@ -63,6 +65,8 @@ hipError_t launch_adj_forward(const AArgs &a, int mode, hipStream_t st);
 // stored value is not all zero bits) and wall history [3][n].
 hipError_t launch_adj_compress(const AArgs &a, const D4 *hin, const D4 *hwin, D4 *xi, uint64_t *mask, double *xiw,
                                hipStream_t st);
+// Longest row of a list (cnt[n]) -> atomic maximum into *out (cleared by the caller).
+hipError_t launch_adj_row_max(const int32_t *cnt, int64_t n, int32_t *out, hipStream_t st);
 // Packed pos/vel/spin -> caller arrays x, v, w.
 hipError_t launch_adj_unpack(const AArgs &a, double *x, double *v, double *w, hipStream_t st);
 // Records of the last evaluation from the adjoints of the final x, v, w.

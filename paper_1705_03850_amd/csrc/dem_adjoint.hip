@@ -57,13 +57,12 @@ __global__ void k_adj_expand(AArgs a, const D4 *xi, const uint64_t *mask, const 
         const uint64_t m = mask[i];
         const int cnt = a.cnt[i];
         for (int q = 0; q < cnt; ++q) {
-            const int64_t slot = i * a.kmax + q;
             D4 h = {0.0, 0.0, 0.0, 0.0};
             if ((m >> q) & 1ull) {
-                const D4 v = xi[slot];
+                const D4 v = xi[i * a.kmax + q];
                 h = D4{v.x, v.y, v.z, 0.0};
             }
-            hout[slot] = h;
+            hout[i * a.kslots + q] = h;
         }
         hwout[i] = (m & kWallBit) ? D4{xiw[i], xiw[n + i], xiw[2 * n + i], 0.0} : D4{0.0, 0.0, 0.0, 0.0};
     }
@@ -90,7 +89,7 @@ __global__ void __launch_bounds__(kABlock, 4) k_adj_forward(AArgs a) {
     }
     bool need = false, bad = false;
     const int64_t n = a.n;
-    const int64_t kmax = a.kmax;
+    const int64_t ks = a.kslots;
     const SysDesc s = uniform_sys(a.sys);
     load_adj_coef(a);
     const int g = threadIdx.x % G;
@@ -109,7 +108,7 @@ __global__ void __launch_bounds__(kABlock, 4) k_adj_forward(AArgs a) {
         for (int c0 = 0; c0 < cnt; c0 += G) {
             const int q = c0 + g;
             const bool valid = q < cnt;
-            const int64_t slot = i * kmax + q;
+            const int64_t slot = i * ks + q;
             const int32_t j = valid ? a.nbr[q * n + i] : (int32_t)i;
             const D4 pj = a.pos[j];
             ContactIn c;
@@ -220,9 +219,8 @@ __global__ void k_adj_compress(AArgs a, const D4 *hin, const D4 *hwin, D4 *xi, u
         const int cnt = a.cnt[i];
         uint64_t m = 0;
         for (int q = 0; q < cnt; ++q) {
-            const int64_t slot = i * a.kmax + q;
-            const D4 h = hin[slot];
-            xi[slot] = D4{h.x, h.y, h.z, 0.0};
+            const D4 h = hin[i * a.kslots + q];
+            xi[i * a.kmax + q] = D4{h.x, h.y, h.z, 0.0};
             if (__double_as_longlong(h.x) | __double_as_longlong(h.y) | __double_as_longlong(h.z)) m |= 1ull << q;
         }
         const D4 hw = hwin[i];
@@ -279,7 +277,7 @@ __global__ void k_adj_seed_forces(AArgs a, const double *fb, const double *tb) {
 template <int NT, bool PRIME, int G>
 __global__ void __launch_bounds__(kABlock, kAdjReverseWaves) k_adj_reverse(AArgs a) {
     const int64_t n = a.n;
-    const int64_t kmax = a.kmax;
+    const int64_t ks = a.kslots;
     const SysDesc s = uniform_sys(a.sys);
     const int g = threadIdx.x % G;
     const int gbase = (threadIdx.x % warpSize) / G * G;
@@ -303,7 +301,7 @@ __global__ void __launch_bounds__(kABlock, kAdjReverseWaves) k_adj_reverse(AArgs
             for (int k = 0; k < 5; ++k) acc[t][k] = 0.0;
         const int cnt = a.cnt[i];
         for (int q = g; q < cnt; q += G) {
-            const int64_t slot = i * kmax + q;
+            const int64_t slot = i * ks + q;
             const int32_t j = a.nbr[q * n + i];
             const D4 pj = a.pos[j];
             ContactIn c;
@@ -426,7 +424,7 @@ __global__ void __launch_bounds__(kABlock, kAdjReverseWaves) k_adj_reverse(AArgs
 __global__ void k_adj_carry(AArgs a, const int32_t *frame, const int32_t *nids, const int32_t *onbr,
                             const int32_t *ocnt, const int32_t *oids, D4 *mu_old, D4 *muw_old) {
     const int64_t n = a.n;
-    const int64_t kmax = a.kmax;
+    const int64_t ks = a.kslots;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t o = frame[i];
         for (int k = 0; k < 5; ++k) a.rout[k * n + o] = a.rin[k * n + i];
@@ -437,8 +435,8 @@ __global__ void k_adj_carry(AArgs a, const int32_t *frame, const int32_t *nids, 
             const int32_t idp = oids[onbr[p * n + o]];
             while (q < cn && nids[a.nbr[q * n + i]] < idp) ++q;
             D4 m = {0.0, 0.0, 0.0, 0.0};
-            if (q < cn && nids[a.nbr[q * n + i]] == idp) m = a.mu[i * kmax + q];
-            mu_old[o * kmax + p] = m;
+            if (q < cn && nids[a.nbr[q * n + i]] == idp) m = a.mu[i * ks + q];
+            mu_old[o * ks + p] = m;
         }
     }
 }
@@ -504,6 +502,19 @@ static void forward_g(const AArgs &a, int mode, hipStream_t st) {
     if (mode == 1) k_adj_forward<G, 1><<<adj_grid(a.n, G), kABlock, 0, st>>>(a);
     else if (mode == 2) k_adj_forward<G, 2><<<adj_grid(a.n, G), kABlock, 0, st>>>(a);
     else k_adj_forward<G, 0><<<adj_grid(a.n, G), kABlock, 0, st>>>(a);
+}
+
+__global__ void k_adj_row_max(const int32_t *cnt, int64_t n, int32_t *out) {
+    int m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, cnt[i]);
+    for (int off = warpSize / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if (threadIdx.x % warpSize == 0 && m > 0) atomicMax(out, m);
+}
+
+hipError_t launch_adj_row_max(const int32_t *cnt, int64_t n, int32_t *out, hipStream_t st) {
+    k_adj_row_max<<<flat_grid(n), kABlock, 0, st>>>(cnt, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_adj_forward(const AArgs &a, int mode, hipStream_t st) {

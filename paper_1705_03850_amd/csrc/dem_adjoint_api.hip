@@ -14,6 +14,7 @@
 // recomputes nothing (memory grows with the step count instead of the window).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -50,7 +51,8 @@ struct dem_adjoint {
     std::vector<Ckpt> ck;         // slot 0: state before the rollout; 1..: window starts
     std::vector<Topo> topo;
     std::vector<StepBuf> traj;    // inputs of a window's evaluations 2..len
-    size_t rec[2] = {0, 0}, mu[2] = {0, 0}, muw[2] = {0, 0}, gp = 0, acc = 0, part = 0;
+    size_t rec[2] = {0, 0}, mu[2] = {0, 0}, muw[2] = {0, 0}, gp = 0, acc = 0, part = 0, rowmax = 0;
+    int32_t kslots = 0;           // history slots per particle in the adjoint's own buffers
     int32_t lanes = 4;
     int32_t keep = 0;             // every evaluation's inputs stored by the forward
     int nck = 0, ntopo = 0;
@@ -64,9 +66,11 @@ struct AdjLayout {
     std::vector<Ckpt> ck;
     std::vector<Topo> topo;
     std::vector<StepBuf> traj;
-    size_t rec[2], mu[2], muw[2], gp, acc, part, total;
+    size_t rec[2], mu[2], muw[2], gp, acc, part, rowmax, total;
 };
 
+// K: history slots per particle (kslots); rows of the saved lists hold K
+// neighbour indices as well (the slot-major prefix of the live list).
 AdjLayout adj_layout(int64_t n, int64_t K, int64_t nsteps, int32_t window, int32_t max_windows, int nt, int keep) {
     AdjLayout L;
     size_t o = 0;
@@ -98,6 +102,7 @@ AdjLayout adj_layout(int64_t n, int64_t K, int64_t nsteps, int32_t window, int32
     L.gp = take(N * 5 * (size_t)nt * 8);
     L.acc = take(5 * (size_t)nt * (size_t)nt * 8);
     L.part = take(adj_reduce_scratch_bytes(nt));
+    L.rowmax = take(sizeof(int32_t));
     L.total = o;
     return L;
 }
@@ -107,8 +112,10 @@ int32_t default_windows(int64_t nsteps, int32_t window) {
     return (int32_t)std::min<int64_t>(2 * w + 1, 1 << 20);
 }
 
-int adj_args(dem_ctx *c, int64_t nsteps, int32_t window, int32_t &max_windows) {
+int adj_args(dem_ctx *c, int64_t nsteps, int32_t window, int32_t &max_windows, int32_t &kslots) {
     if (!c) return DEM_ERR_ARG;
+    if (kslots == 0) kslots = c->geo.kmax;
+    if (kslots < 1 || kslots > c->geo.kmax) return fail(c, DEM_ERR_ARG, "kslots must be in 1..k_max (0: k_max)");
     if (c->geo.sys.size() != 1) return fail(c, DEM_ERR_ARG, "the adjoint rollout takes a context of one system");
     if (c->geo.sys[0].p1 != c->geo.sys[0].pe)
         return fail(c, DEM_ERR_ARG, "the adjoint rollout takes a system without free slots");
@@ -131,6 +138,7 @@ AArgs base_args(dem_adjoint *A) {
     memset(&a, 0, sizeof a);
     a.n = c->geo.n;
     a.kmax = c->geo.kmax;
+    a.kslots = A->kslots;
     a.ntypes = c->geo.sys[0].ntypes;
     a.sys = c->d_sys;
     a.coef = c->d_coef + c->geo.sys[0].coef0;
@@ -144,10 +152,29 @@ int fill_zero(dem_adjoint *A, size_t off, size_t doubles) {
     return DEM_OK;
 }
 
+// The live list's longest row must fit the adjoint's kslots history slots:
+// DEM_ERR_CAPACITY otherwise (checked before anything is written with the list).
+int check_rows(dem_adjoint *A, const List &live) {
+    dem_ctx *c = A->ctx;
+    if (A->kslots >= c->geo.kmax) return DEM_OK;   // a build never leaves a row longer than k_max
+    int32_t *d = at<int32_t>(A, A->rowmax);
+    HIPCALL(c, launch_fill_i32(d, 1, 0, c->stream));
+    HIPCALL(c, launch_adj_row_max(live.cnt, c->geo.n, d, c->stream));
+    int32_t h = 0;
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    HIPCALL(c, hipMemcpy(&h, d, sizeof h, hipMemcpyDeviceToHost));
+    if (h > A->kslots) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "a neighbour row of %d entries exceeds the adjoint's kslots = %d", h, A->kslots);
+        return fail(c, DEM_ERR_CAPACITY, buf);
+    }
+    return DEM_OK;
+}
+
 // Topology slot t from the live list (and the permutation written by the last bin).
 int save_topology(dem_adjoint *A, const List &live, int t, bool with_frame) {
     dem_ctx *c = A->ctx;
-    const size_t n = (size_t)c->geo.n, K = (size_t)c->geo.kmax;
+    const size_t n = (size_t)c->geo.n, K = (size_t)A->kslots;
     const Topo &T = A->topo[t];
     hipStream_t st = c->stream;
     HIPCALL(c, hipMemcpyAsync(A->ws + T.nbr, live.nbr, n * K * 4, hipMemcpyDeviceToDevice, st));
@@ -298,21 +325,21 @@ int dem_set_materials(dem_ctx *c, int32_t sys, const dem_material *mat, int32_t 
 }
 
 int dem_adjoint_workspace_size(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_windows, int32_t keep,
-                               size_t *bytes) {
+                               int32_t kslots, size_t *bytes) {
     if (!bytes) return DEM_ERR_ARG;
-    int rc = adj_args(c, nsteps, window, max_windows);
+    int rc = adj_args(c, nsteps, window, max_windows, kslots);
     if (rc) return rc;
-    *bytes = adj_layout(c->geo.n, c->geo.kmax, nsteps, window, max_windows, c->geo.sys[0].ntypes, keep != 0).total;
+    *bytes = adj_layout(c->geo.n, kslots, nsteps, window, max_windows, c->geo.sys[0].ntypes, keep != 0).total;
     return DEM_OK;
 }
 
-int dem_adjoint_init(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_windows, int32_t keep, void *workspace,
-                     size_t bytes, dem_adjoint **out) {
+int dem_adjoint_init(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_windows, int32_t keep, int32_t kslots,
+                     void *workspace, size_t bytes, dem_adjoint **out) {
     if (!out) return DEM_ERR_ARG;
     *out = nullptr;
-    int rc = adj_args(c, nsteps, window, max_windows);
+    int rc = adj_args(c, nsteps, window, max_windows, kslots);
     if (rc) return rc;
-    AdjLayout L = adj_layout(c->geo.n, c->geo.kmax, nsteps, window, max_windows, c->geo.sys[0].ntypes, keep != 0);
+    AdjLayout L = adj_layout(c->geo.n, kslots, nsteps, window, max_windows, c->geo.sys[0].ntypes, keep != 0);
     if (!workspace || bytes < L.total) return fail(c, DEM_ERR_ARG, "adjoint workspace too small");
     if ((uintptr_t)workspace % kAlign) return fail(c, DEM_ERR_ARG, "adjoint workspace must be 256-byte aligned");
     dem_adjoint *A = new dem_adjoint();
@@ -321,6 +348,7 @@ int dem_adjoint_init(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_win
     A->window = window;
     A->max_windows = max_windows;
     A->keep = keep != 0;
+    A->kslots = kslots;
     A->ws = (char *)workspace;
     A->bytes = bytes;
     A->ck = L.ck;
@@ -330,6 +358,7 @@ int dem_adjoint_init(dem_ctx *c, int64_t nsteps, int32_t window, int32_t max_win
     A->gp = L.gp;
     A->acc = L.acc;
     A->part = L.part;
+    A->rowmax = L.rowmax;
     *out = A;
     return DEM_OK;
 }
@@ -353,7 +382,7 @@ int dem_rollout_forward(dem_adjoint *A, const dem_state *s) {
     const int64_t S = A->nsteps, base = c->step_counter;
     const int cnt = c->count ? 1 : 0;
     List live;
-    if ((rc = live_list(c, 0, live))) return rc;
+    if ((rc = live_list(c, 0, live)) || (rc = check_rows(A, live))) return rc;
     KArgs K = kargs(c, s);
     // slot 0: the state before the rollout and its first force evaluation
     HIPCALL(c, launch_pack(K, 0, 0, 0, 0, c->stream));
@@ -376,7 +405,7 @@ int dem_rollout_forward(dem_adjoint *A, const dem_state *s) {
         if (A->nck > A->max_windows)
             return fail(c, DEM_ERR_CAPACITY, "the rollout needs more windows than max_windows (list rebuilds split windows)");
         if (rebuilt) {
-            if ((rc = live_list(c, 0, live))) return rc;
+            if ((rc = live_list(c, 0, live)) || (rc = check_rows(A, live))) return rc;
             if ((rc = save_topology(A, live, A->ntopo, true))) return rc;
             ++A->ntopo;
         }
@@ -447,7 +476,7 @@ int dem_rollout_backward(dem_adjoint *A, const dem_state *s, const double *gx, c
     if (c->fext_on) return fail(c, DEM_ERR_STATE, "the reverse mode does not take external forces");
     if (A->nck < 2 || A->step_end != c->step_counter)
         return fail(c, DEM_ERR_STATE, "dem_rollout_backward needs the state of the last dem_rollout_forward");
-    const int64_t n = c->geo.n, K = c->geo.kmax;
+    const int64_t n = c->geo.n, K = A->kslots;
     const int nt = c->geo.sys[0].ntypes;
     hipStream_t st = c->stream;
     if ((rc = fill_zero(A, A->acc, (size_t)5 * nt * nt)) || (rc = fill_zero(A, A->gp, (size_t)5 * nt * n)) ||
@@ -549,11 +578,11 @@ int dem_forces_vjp(dem_adjoint *A, const dem_state *s, const double *fb, const d
         return fail(c, DEM_ERR_STATE, "the reverse mode takes a system without free slots");
     if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_forces_vjp needs a neighbour list for the current order");
     if (c->geo.n == 0) return DEM_OK;
-    const int64_t n = c->geo.n, K = c->geo.kmax;
+    const int64_t n = c->geo.n, K = A->kslots;
     const int nt = c->geo.sys[0].ntypes;
     hipStream_t st = c->stream;
     List live;
-    if ((rc = live_list(c, 0, live))) return rc;
+    if ((rc = live_list(c, 0, live)) || (rc = check_rows(A, live))) return rc;
     KArgs Kx = kargs(c, s);
     HIPCALL(c, launch_pack(Kx, 0, 0, 0, 0, st));
     const Ckpt &C = A->ck[0];

@@ -154,8 +154,8 @@ def load(path: str = LIB_PATH):
     L.dem_last_error.restype = ctypes.c_char_p
     L.dem_destroy.argtypes = [vp]
     L.dem_set_materials.argtypes = [vp, i32, P(Material), i32]
-    L.dem_adjoint_workspace_size.argtypes = [vp, i64, i32, i32, i32, P(ctypes.c_size_t)]
-    L.dem_adjoint_init.argtypes = [vp, i64, i32, i32, i32, vp, ctypes.c_size_t, P(vp)]
+    L.dem_adjoint_workspace_size.argtypes = [vp, i64, i32, i32, i32, i32, P(ctypes.c_size_t)]
+    L.dem_adjoint_init.argtypes = [vp, i64, i32, i32, i32, i32, vp, ctypes.c_size_t, P(vp)]
     L.dem_rollout_forward.argtypes = [vp, P(State)]
     L.dem_rollout_backward.argtypes = [vp, P(State), vp, vp, vp, vp, vp, vp, vp, dp]
     L.dem_forces_vjp.argtypes = [vp, P(State), vp, vp, vp, vp, vp, dp]
@@ -569,8 +569,9 @@ class DemSystem:
             arr[t].E, arr[t].nu, arr[t].rho, arr[t].e, arr[t].mu = m.E, m.nu, m.rho, m.e, m.mu
         self._rc(self.L.dem_set_materials(self.ctx, int(sys), arr, len(materials)))
 
-    def adjoint(self, nsteps: int, window: int = 20, max_windows: int = 0, keep: bool = False) -> "Adjoint":
-        return Adjoint(self, nsteps, window, max_windows, keep)
+    def adjoint(self, nsteps: int, window: int = 20, max_windows: int = 0, keep: bool = False,
+                kslots: int = 0) -> "Adjoint":
+        return Adjoint(self, nsteps, window, max_windows, keep, kslots)
 
     def checkpoint(self) -> dict:
         """Host snapshot from which from_checkpoint resumes bit for bit: per
@@ -625,9 +626,11 @@ class Adjoint:
     adjoints of the final x, v, w ((3, n) device tensors in the system's
     current order) and returns the gradients with respect to the per-type
     E, e and mu (host) and to the initial x, v, w (device, in the order of
-    ``ids0``; ``initial_by_id`` gives host rows in id order)."""
+    ``ids0``; ``initial_by_id`` gives host rows in id order).  ``kslots``
+    bounds the neighbour rows the checkpoints hold (0: the context's k_max)."""
 
-    def __init__(self, dsys: DemSystem, nsteps: int, window: int = 20, max_windows: int = 0, keep: bool = False):
+    def __init__(self, dsys: DemSystem, nsteps: int, window: int = 20, max_windows: int = 0, keep: bool = False,
+                 kslots: int = 0):
         torch = dsys.torch
         self.dsys = dsys
         self.L = dsys.L
@@ -636,14 +639,16 @@ class Adjoint:
         self.ntypes = len(dsys.systems[0].materials)
         nb = ctypes.c_size_t()
         self.keep = bool(keep)
+        self.kslots = int(kslots)
         dsys._rc(self.L.dem_adjoint_workspace_size(dsys.ctx, self.nsteps, self.window, int(max_windows),
-                                                   int(self.keep), ctypes.byref(nb)))
+                                                   int(self.keep), self.kslots, ctypes.byref(nb)))
         self.bytes = nb.value
         self.workspace = torch.empty(self.bytes + 256, dtype=torch.uint8, device=dsys.device)
         ptr = (self.workspace.data_ptr() + 255) // 256 * 256
         self.h = ctypes.c_void_p()
         dsys._rc(self.L.dem_adjoint_init(dsys.ctx, self.nsteps, self.window, int(max_windows), int(self.keep),
-                                         ctypes.c_void_p(ptr), ctypes.c_size_t(self.bytes), ctypes.byref(self.h)))
+                                         self.kslots, ctypes.c_void_p(ptr), ctypes.c_size_t(self.bytes),
+                                         ctypes.byref(self.h)))
 
     def __del__(self):
         h = getattr(self, "h", None)

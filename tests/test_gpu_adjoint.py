@@ -118,6 +118,47 @@ def test_windowed_forward_equals_dem_step(keep):
         assert np.array_equal(h1[k], h2[k]), ("after", k)
 
 
+@pytest.mark.parametrize("keep", [False, True])
+def test_kslots_shrinks_the_workspace_and_changes_nothing(keep):
+    """Checkpoints and stored inputs sized for the longest neighbour row
+    instead of k_max: the gradients and the final state are bit for bit those
+    of the full-size workspace; a bound below the current list's longest row
+    is a capacity error before anything runs."""
+    d = dem()
+    s = chute(n=800)
+    skin = 0.006e-3
+    rng = np.random.default_rng(3)
+    a, b, c = (rng.normal(size=(s.n, 3)) for _ in range(3))
+    ref, rr, info, g0 = gpu_rollout_grad(s, 60, a, b, c, window=7, skin=skin, keep=keep)
+    assert info["rebuilds"] >= 1, info
+    g = d.DemSystem(s, skin=skin)
+    g.build_list()
+    lo, _ = g.export_neighbors()
+    row0 = int(np.bincount(lo).max())
+    with pytest.raises(d.DemError) as e:
+        g.adjoint(60, window=7, keep=keep, kslots=row0 - 1).forward()
+    assert e.value.code == d.DEM_ERR_CAPACITY
+    full = g0.adjoint(60, window=7, keep=keep).bytes
+    for k in range(row0, 64):
+        g = d.DemSystem(s, skin=skin)
+        adj = g.adjoint(60, window=7, keep=keep, kslots=k)
+        try:
+            adj.forward()
+            break
+        except d.DemError as err:                # a row built during the rollout is longer
+            assert err.code == d.DEM_ERR_CAPACITY
+    assert adj.bytes < full * (k + 8) / 32.0, (adj.bytes, full, k)
+    r = adj.backward(device_by_id(g, a), device_by_id(g, b), device_by_id(g, c))
+    r.update(adj.initial_by_id(r))
+    got = np.array([r[p][t] for p, t in DIRS])
+    assert np.array_equal(got, ref), (got, ref)
+    for key in ("x0", "v0", "w0"):
+        assert np.array_equal(r[key], rr[key]), key
+    h0, h = g0.host(), g.host()
+    for key in ("x", "v", "w", "f", "t"):
+        assert np.array_equal(h0[key], h[key]), key
+
+
 # ------------------------------------------------------------ one force evaluation
 
 def test_forces_vjp_matches_oracle_tangent():

@@ -159,8 +159,10 @@ def coupled_run(g, cpl, steps):
     """The two-level chute coupled (Sec. 2.3): every `interval_steps` steps the
     cell fields of both levels on the transition layer and on the grid inside
     the fine region, the PI controller on the fine spheres of the 10 mm shell and
-    the P controller (mass flow) on the coarse spheres, then the steps.  Returns
-    (wall seconds, seconds in the coupling calls)."""
+    the P controller (mass flow) on the coarse spheres, then the steps.  The
+    interval's coupling calls are captured once in a graph and replayed (they
+    are asynchronous; the P controller reads no stress).  Returns (wall
+    seconds, host seconds spent issuing the coupling)."""
     import torch
 
     from paper_1705_03850_amd import dem
@@ -178,15 +180,23 @@ def coupled_run(g, cpl, steps):
     qp.grid, qp.kp, qp.mass_flow = p_c, cpl["kp_coarse"], 1
     n_pi = pi_f.n[0] * pi_f.n[1] * pi_f.n[2]
     integral = torch.zeros(n_pi, dtype=torch.float64, device=g.device)
+    u = torch.empty(n_pi, dtype=torch.float64, device=g.device)
+    n_p = p_f.n[0] * p_f.n[1] * p_f.n[2]
+    buf = [torch.empty((dem.NFIELDS, n), dtype=torch.float64, device=g.device) for n in (n_pi, n_pi, n_p, n_p)]
     t_ctl = 0.0
     torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=g.stream):
+        g.pi_control(pp, g.cell_fields(pi_f, out=buf[0]), g.cell_fields(pi_c, out=buf[1]), integral, u)
+        g.p_control(qp, g.cell_fields(p_f, stress=False, out=buf[2]), g.cell_fields(p_c, stress=False, out=buf[3]))
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps // k):
-        tc = time.perf_counter()
-        g.pi_control(pp, g.cell_fields(pi_f), g.cell_fields(pi_c), integral)
-        g.p_control(qp, g.cell_fields(p_f), g.cell_fields(p_c))
-        t_ctl += time.perf_counter() - tc
-        g.step(k)
+    with torch.cuda.stream(g.stream):
+        for _ in range(steps // k):
+            tc = time.perf_counter()
+            graph.replay()
+            t_ctl += time.perf_counter() - tc
+            g.step(k)
     torch.cuda.synchronize()
     return time.perf_counter() - t0, t_ctl
 
@@ -369,7 +379,8 @@ def batch_suite(args, emit=True):
                             "list_builds_batched": builds_two,
                             "coupled": {"steps": steps_c, "interval_steps": cpl["interval_steps"],
                                         "particle_steps_per_s": n2 * steps_c / t_cpl,
-                                        "coupling_fraction_of_time": t_ctl / t_cpl,
+                                        "coupled_vs_batched": (n2 * steps_c / t_cpl) / (n2 * steps2 / t_two),
+                                        "coupling_issue_host_s": t_ctl,
                                         "transition_cells": list(cpl["pi_grid"][2]),
                                         "fine_region_cells": list(cpl["p_grid"][2])},
                             "exchange": exch},
@@ -517,12 +528,27 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
              cell[inside].astype(np.int32)]
         return [torch.from_numpy(np.ascontiguousarray(a)).to(g.device) for a in c]
 
+    # the loop runs on the library's stream with its buffers allocated once;
+    # the P controller and the insertion budget read no stress
+    buf = {k: torch.empty((dem.NFIELDS, 64 * n), dtype=torch.float64, device=g.device)
+           for k, n in (("pi", 1), ("pi_c", 1), ("p", 4), ("p_c", 4), ("in_c", 1))}
+    u = torch.empty(64, dtype=torch.float64, device=g.device)
+
     def interval_coupling():
-        g.pi_control(pp, g.cell_fields(pi_grid), g.cell_fields(pi_grid_c), integral)
-        g.p_control(qp, g.cell_fields(p_grid_f), g.cell_fields(p_grid_c))
+        g.pi_control(pp, g.cell_fields(pi_grid, out=buf["pi"]), g.cell_fields(pi_grid_c, out=buf["pi_c"]),
+                     integral, u)
+        g.p_control(qp, g.cell_fields(p_grid_f, stress=False, out=buf["p"]),
+                    g.cell_fields(p_grid_c, stress=False, out=buf["p_c"]))
 
     inserted = removed_top = 0
     t_cpl = t_ex = 0.0
+    # the interval's coupling calls captured once in a graph that every
+    # interval replays: the calls read everything that changes (positions,
+    # binning, live counts, list buffer) from the device
+    torch.cuda.synchronize()
+    cpl_graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cpl_graph, stream=g.stream):
+        interval_coupling()
 
     def run(seconds, sampling):
         nonlocal inserted, removed_top, t_cpl, t_ex
@@ -531,12 +557,12 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
         n_int = int(round(seconds / (interval * dt)))
         for k in range(n_int):
             tc = time.perf_counter()
-            interval_coupling()
+            cpl_graph.replay()
             t_cpl += time.perf_counter() - tc
             g.step(interval)
             if (k + 1) % exchange_every == 0:
                 te = time.perf_counter()
-                fields = g.cell_fields(in_grid_c)
+                fields = g.cell_fields(in_grid_c, stress=False, out=buf["in_c"])
                 _, i, r = g.exchange(1, ex, fields, budget, *candidates())
                 inserted += i
                 removed_top += r
@@ -554,14 +580,16 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run(settle_s, False)
+    with torch.cuda.stream(g.stream):
+        run(settle_s, False)
     torch.cuda.synchronize()
     t_settle = time.perf_counter() - t0
     opened = W.silo_surfaces(1.0, open_orifice=True, mu_wall=muw)
     g.set_surfaces(0, opened)
     g.set_surfaces(1, opened)
     t1 = time.perf_counter()
-    rates_f, rates_c = run(discharge_s, True)
+    with torch.cuda.stream(g.stream):
+        rates_f, rates_c = run(discharge_s, True)
     torch.cuda.synchronize()
     t_dis = time.perf_counter() - t1
     skip = int(0.2 / sample_s)

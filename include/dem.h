@@ -337,6 +337,12 @@ enum {
  * caller-owned.  Enqueued (no synchronisation). */
 int dem_cell_fields(dem_ctx *ctx, const dem_state *s, const dem_grid *grid, double *fields);
 
+/* The same without the stress: rows DEM_F_COUNT to DEM_F_VMAX as above, bit
+ * for bit; the stress rows of fields are not written.  Enough for the P
+ * controller and for an insertion budget (Sec. 2.3), which read only mass,
+ * momentum and volume.  Same requirements, errors and ordering. */
+int dem_cell_mass_fields(dem_ctx *ctx, const dem_state *s, const dem_grid *grid, double *fields);
+
 /* PI controller of the transition layer (Sec. 2.3).  grid: the transition
  * cells, in the fine system grid.sys.  fine, coarse: fields (as above) of the
  * fine system and of the coarse system on the same cells.  Per cell, with the

@@ -313,6 +313,14 @@ int check_state(dem_ctx *c, const dem_state *s) {
 }
 
 int read_flags(dem_ctx *c, Flags &h) {
+    if (c->h_flags) {
+        // into pinned memory, ordered on the stream: one wait instead of a
+        // wait and a staged copy
+        HIPCALL(c, hipMemcpyAsync(c->h_flags, c->d_flags, sizeof(Flags), hipMemcpyDeviceToHost, c->stream));
+        HIPCALL(c, hipStreamSynchronize(c->stream));
+        h = *c->h_flags;
+        return DEM_OK;
+    }
     HIPCALL(c, hipStreamSynchronize(c->stream));
     HIPCALL(c, hipMemcpy(&h, c->d_flags, sizeof(Flags), hipMemcpyDeviceToHost));
     return DEM_OK;
@@ -484,8 +492,12 @@ static int32_t default_lanes(int64_t n, int32_t block) {
     return lanes;
 }
 
-int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *workspace, size_t ws_bytes,
-                   void *stream) {
+}  // extern "C"
+
+// A context on the given workspace; with pin_flags also a pinned host copy of
+// the flag block (the static-workspace context allocates nothing).
+static int init_ctx(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *workspace, size_t ws_bytes,
+                    void *stream, bool pin_flags) {
     if (!out) return DEM_ERR_ARG;
     *out = nullptr;
     Geometry g;
@@ -505,6 +517,10 @@ int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *wo
     c->d_rho = (double *)(c->ws + lay.rho);
     c->d_flags = (Flags *)(c->ws + lay.flags);
     c->lanes = default_lanes(g.n, g.block);
+    if (pin_flags && hipHostMalloc((void **)&c->h_flags, sizeof(Flags), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        c->h_flags = nullptr;
+    }
     for (int b = 0; b < 2; ++b) {
         c->lists[b].nbr = (int32_t *)(c->ws + lay.nbr[b]);
         c->lists[b].cnt = (int32_t *)(c->ws + lay.cnt[b]);
@@ -533,11 +549,19 @@ int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *wo
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         g_init_error = std::string("HIP error during init: ") + hipGetErrorString(e);
+        if (c->h_flags) (void)hipHostFree(c->h_flags);
         delete c;
         return DEM_ERR_HIP;
     }
     *out = c;
     return DEM_OK;
+}
+
+extern "C" {
+
+int dem_batch_init(dem_ctx **out, int32_t nsys, const dem_config *cfgs, void *workspace, size_t ws_bytes,
+                   void *stream) {
+    return init_ctx(out, nsys, cfgs, workspace, ws_bytes, stream, true);
 }
 
 int dem_init(dem_ctx **ctx, const dem_config *cfg, void *workspace, size_t ws_bytes, void *stream) {
@@ -605,7 +629,7 @@ int dem_init_noalloc(dem_ctx **out, const dem_config *cfg, void *stream) {
     // the array keeps the last context's contents: start from zeros
     e = launch_fill_u64((uint64_t *)g_static_ptr[dev], (int64_t)(need / 8), 0, (hipStream_t)stream);
     if (e != hipSuccess) { g_init_error = std::string("clearing the static workspace: ") + hipGetErrorString(e); return DEM_ERR_HIP; }
-    rc = dem_batch_init(out, 1, cfg, g_static_ptr[dev], kStaticWsBytes, stream);
+    rc = init_ctx(out, 1, cfg, g_static_ptr[dev], kStaticWsBytes, stream, false);
     if (rc) return rc;
     (*out)->static_dev = dev;
     g_static_owner[dev] = *out;
@@ -1223,6 +1247,10 @@ int dem_destroy(dem_ctx *c) {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (GraphSlot &g : c->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (c->h_flags) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipHostFree(c->h_flags);
+    }
     delete c;
     return DEM_OK;
 }

@@ -6,12 +6,14 @@
 // particle range of every bin row that the cell, widened by one bin on each
 // side, touches: spheres stay within one bin of their binned position until
 // the next rebuild).  A cell's bin rows are dealt to S workgroups (S from the
-// cell count, so that few large cells still fill the device, and at most the
-// cell's number of bin rows), whose threads take the candidates in turn; each
-// thread sums its own spheres, the block adds the threads' sums in a fixed
-// tree (all sums at once) and a second kernel adds the S slices in order: the
-// result depends on nothing but the state, the grid, the binning and the
-// workspace size.  A first pass gives mass and momentum, hence the Favre
+// cell count, so that few large cells still fill the device, and from the
+// cell's number of bin rows, so that a slice holds about eight of them); a
+// workgroup lays its rows' candidates end to end (a scan of the row lengths
+// in LDS) and its threads take them in turn, G threads per sphere where the
+// sphere's contacts are summed.  Each thread sums its own terms, the block
+// adds the threads' sums in a fixed tree (all sums at once) and a second
+// kernel adds the S slices in order: the result depends on nothing but the
+// state, the grid, the binning and the workspace size.  A first pass gives mass and momentum, hence the Favre
 // velocity; the second the kinetic and contact parts of Eq. (7), the contact
 // forces evaluated as in a force pass without history update.
 // Controllers: one thread per cell updates the PI state; one thread per
@@ -33,7 +35,8 @@ struct FGrid {
     double vol;   // cell volume h0 h1 h2
 };
 
-constexpr int kFB = 256;   // threads per cell of the fields kernel
+constexpr int kFB = 256;   // threads per workgroup of the fields kernels
+constexpr int kFG = 4;     // threads per sphere where its contacts are summed
 
 // Cell of a centre: floor((x - lo) / h) per axis, -1 outside (or NaN).
 __device__ inline int64_t field_cell(const FGrid &g, double x, double y, double z) {
@@ -120,18 +123,77 @@ __device__ inline int piece_at(const Pieces &P, int k) {
     return k < l0 ? P.s[0] + k : P.s[1] + (k - l0);
 }
 
-template <class F>
+// Exclusive prefix sum of one int per thread over the block, and the total.
+__device__ inline int block_excl_scan(int v, int *wsum, int &total) {
+    const int lane = threadIdx.x % warpSize, wid = threadIdx.x / warpSize;
+    int x = v;
+    for (int o = 1; o < warpSize; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == warpSize - 1) wsum[wid] = x;
+    __syncthreads();
+    int base = 0;
+    total = 0;
+    for (int w = 0; w < kFB / warpSize; ++w) {
+        if (w < wid) base += wsum[w];
+        total += wsum[w];
+    }
+    __syncthreads();
+    return base + x - v;
+}
+
+// Candidate list of a workgroup in LDS: each of up to kFB rows gives at most
+// two particle ranges (the X pieces); off is their exclusive scan.
+struct CandLds {
+    int32_t beg[2 * kFB];
+    int32_t off[2 * kFB + 1];
+    int32_t wsum[kFB / 64];
+};
+
+// Calls visit(p, lane) for every candidate sphere p of slice b of S of the
+// cell's bin rows (rows b, b + S, ...), G lanes per candidate: the rows are
+// taken kFB at a time, their ranges laid end to end, and candidate q of the
+// chunk goes to the threads kFB / G apart from thread G (q mod kFB / G).
+template <int G, class F>
 __device__ inline void for_candidates(const KArgs &a, const SysDesc &sd, const Pieces &X, const Pieces &Y,
-                                      const Pieces &Z, int b, int S, F visit) {
+                                      const Pieces &Z, int b, int S, CandLds &sh, F visit) {
     const int32_t *cs = a.cell_start;
     const int RY = piece_len(Y), R = piece_len(Z) * RY;
-    for (int r = b; r < R; r += S) {
-        const int bz = piece_at(Z, r / RY), by = piece_at(Y, r % RY);
-        const int64_t row = sd.c0 + ((int64_t)bz * sd.nc[1] + by) * sd.nc[0];
-        for (int px = 0; px < X.np; ++px) {
-            const int32_t beg = cs[row + X.s[px]], end = cs[row + X.e[px] + 1];
-            for (int32_t p = beg + (int32_t)threadIdx.x; p < end; p += (int32_t)blockDim.x) visit(p);
+    const int nr = b < R ? (R - b + S - 1) / S : 0;
+    const int t = threadIdx.x;
+    for (int r0 = 0; r0 < nr; r0 += kFB) {
+        int32_t b0 = 0, l0 = 0, b1 = 0, l1 = 0;
+        const int k = r0 + t;
+        if (k < nr) {
+            const int r = b + k * S;
+            const int bz = piece_at(Z, r / RY), by = piece_at(Y, r % RY);
+            const int64_t row = sd.c0 + ((int64_t)bz * sd.nc[1] + by) * sd.nc[0];
+            b0 = cs[row + X.s[0]];
+            l0 = cs[row + X.e[0] + 1] - b0;
+            if (X.np > 1) {
+                b1 = cs[row + X.s[1]];
+                l1 = cs[row + X.e[1] + 1] - b1;
+            }
         }
+        int total;
+        const int off = block_excl_scan(l0 + l1, sh.wsum, total);
+        sh.beg[2 * t] = b0;
+        sh.beg[2 * t + 1] = b1;
+        sh.off[2 * t] = off;
+        sh.off[2 * t + 1] = off + l0;
+        if (t == 0) sh.off[2 * kFB] = total;
+        __syncthreads();
+        for (int q = t / G; q < total; q += kFB / G) {
+            int lo = 0, hi = 2 * kFB;   // the last range that starts at or before q
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (sh.off[mid] <= q) lo = mid;
+                else hi = mid;
+            }
+            visit(sh.beg[lo] + (q - sh.off[lo]), t % G);
+        }
+        __syncthreads();
     }
 }
 
@@ -155,18 +217,37 @@ __device__ inline CellBox cell_box(const SysDesc &sd, const FGrid &g, int64_t ce
     return B;
 }
 
+// Every sphere of the system must lie within one bin width (per axis) of its
+// position at the last list build for the bin-row search to find it: blocks
+// `blk` of `nblk` check a share of the system's spheres.
+__device__ inline void fields_guard(const KArgs &a, int32_t sys, int64_t blk, int64_t nblk) {
+    const SysDesc &sd = a.sys[sys];
+    const int64_t n = a.n;
+    bool bad = false;
+    for (int64_t i = sd.p0 + blk * blockDim.x + threadIdx.x; i < sd.pe; i += nblk * blockDim.x)
+        for (int ax = 0; ax < 3; ++ax)
+            if (!(fabs(a.disp[ax * n + i]) * sd.inv_w[ax] <= 1.0)) bad = true;
+    if (bad) atomicOr(&a.flags->err, kErrStale);
+}
+
 // Block (cell, b): slice b of S of the cell's rows.  S = 1 writes the cell's
 // rows of `out` directly; S > 1 writes the slice's sums to part[(cell S + b) kP1].
+// The blocks after the ncell S field blocks run the guard above.
 __global__ void __launch_bounds__(kFB) k_fields1(KArgs a, FGrid g, int S, double *part, double *out) {
     __shared__ double lds[kP1 * kFB];
+    __shared__ CandLds sh;
+    const int64_t nfb = g.ncell * S;
+    if ((int64_t)blockIdx.x >= nfb) {
+        fields_guard(a, g.sys, (int64_t)blockIdx.x - nfb, (int64_t)gridDim.x - nfb);
+        return;
+    }
     const SysDesc sd = a.sys[g.sys];
     const int64_t n = a.n;
     const int64_t cell = blockIdx.x / S;
     const int b = blockIdx.x % S;
-    if (cell >= g.ncell) return;
     const CellBox B = cell_box(sd, g, cell);
     double cnt = 0.0, mass = 0.0, px = 0.0, py = 0.0, pz = 0.0, vol = 0.0, vmax = 0.0;
-    for_candidates(a, sd, B.X, B.Y, B.Z, b, S, [&](int32_t i) {
+    for_candidates<1>(a, sd, B.X, B.Y, B.Z, b, S, sh, [&](int32_t i, int) {
         if (field_cell(g, a.x[i], a.x[n + i], a.x[2 * n + i]) != cell) return;
         const double m = a.m[i], r = a.r[i];
         const double vx = a.v[i], vy = a.v[n + i], vz = a.v[2 * n + i];
@@ -192,25 +273,40 @@ __global__ void __launch_bounds__(kFB) k_fields1(KArgs a, FGrid g, int S, double
     }
 }
 
-// One thread per cell: the slices' sums added in slice order.
+// A cell's pass-1 sums: its S slices added in slice order (the maximum for
+// the last); the same order wherever it is taken.
+__device__ inline void pass1_total(const double *part, int64_t cell, int S, double (&v)[kP1]) {
+    for (int k = 0; k < kP1; ++k) v[k] = part[(cell * S) * kP1 + k];
+    for (int b = 1; b < S; ++b)
+        for (int k = 0; k < kP1; ++k) {
+            const double q = part[(cell * S + b) * kP1 + k];
+            v[k] = k == kP1 - 1 ? fmax(v[k], q) : v[k] + q;
+        }
+}
+
+__device__ inline void write_pass1(double *out, int64_t nc, int64_t cell, const double (&v)[kP1]) {
+    const int rows[kP1] = {DEM_F_COUNT, DEM_F_MASS, DEM_F_MOM, DEM_F_MOM + 1, DEM_F_MOM + 2, DEM_F_VOLUME, DEM_F_VMAX};
+    for (int k = 0; k < kP1; ++k) out[rows[k] * nc + cell] = v[k];
+}
+
+// One thread per cell (the fields without stress): the slices' sums.
 __global__ void k_fields1_reduce(FGrid g, int S, const double *part, double *out) {
     const int64_t nc = g.ncell;
-    const int rows[kP1] = {DEM_F_COUNT, DEM_F_MASS, DEM_F_MOM, DEM_F_MOM + 1, DEM_F_MOM + 2, DEM_F_VOLUME, DEM_F_VMAX};
     for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < nc;
          cell += (int64_t)gridDim.x * blockDim.x) {
         double v[kP1];
-        for (int k = 0; k < kP1; ++k) v[k] = part[(cell * S) * kP1 + k];
-        for (int b = 1; b < S; ++b)
-            for (int k = 0; k < kP1; ++k) {
-                const double q = part[(cell * S + b) * kP1 + k];
-                v[k] = k == 6 ? fmax(v[k], q) : v[k] + q;
-            }
-        for (int k = 0; k < kP1; ++k) out[rows[k] * nc + cell] = v[k];
+        pass1_total(part, cell, S, v);
+        write_pass1(out, nc, cell, v);
     }
 }
 
-__global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, double *part, double *out) {
+// Pass 2.  S > 1: the cell's pass-1 totals are taken from the slices in
+// part1 by every block of the cell (block 0 also writes them to `out`), and
+// the slice's pass-2 sums go to part2[(cell S + b) kP2].
+__global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, const double *part1, double *part2,
+                                                 double *out) {
     __shared__ double lds[kP2 * kFB];
+    __shared__ CandLds sh;
     const SysDesc sd = a.sys[g.sys];
     const int64_t n = a.n;
     const int64_t nc = g.ncell;
@@ -222,33 +318,43 @@ __global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, double
     const PairCoef *coef = a.coef + sd.coef0;
     const CellBox B = cell_box(sd, g, cell);
     // the cell's Favre velocity from pass 1
-    const double mass = out[DEM_F_MASS * nc + cell];
+    double p1[kP1];
+    if (S > 1) {
+        pass1_total(part1, cell, S, p1);
+        if (b == 0 && threadIdx.x == 0) write_pass1(out, nc, cell, p1);
+    } else {
+        p1[1] = out[DEM_F_MASS * nc + cell];
+        for (int k = 0; k < 3; ++k) p1[2 + k] = out[(DEM_F_MOM + k) * nc + cell];
+    }
+    const double mass = p1[1];
     double ux = 0.0, uy = 0.0, uz = 0.0;
     if (mass > 0.0) {
-        ux = out[DEM_F_MOM * nc + cell] / mass;
-        uy = out[(DEM_F_MOM + 1) * nc + cell] / mass;
-        uz = out[(DEM_F_MOM + 2) * nc + cell] / mass;
+        ux = p1[2] / mass;
+        uy = p1[3] / mass;
+        uz = p1[4] / mass;
     }
     double con[9], kin[6];
     for (int k = 0; k < 9; ++k) con[k] = 0.0;
     for (int k = 0; k < 6; ++k) kin[k] = 0.0;
-    for_candidates(a, sd, B.X, B.Y, B.Z, b, S, [&](int32_t i) {
+    for_candidates<kFG>(a, sd, B.X, B.Y, B.Z, b, S, sh, [&](int32_t i, int lane) {
         const double xi = a.x[i], yi = a.x[n + i], zi = a.x[2 * n + i];
         if (field_cell(g, xi, yi, zi) != cell) return;
         const double m = a.m[i], ri = a.r[i];
         const double vx = a.v[i], vy = a.v[n + i], vz = a.v[2 * n + i];
         const double wx = a.w[i], wy = a.w[n + i], wz = a.w[2 * n + i];
-        const double qx = vx - ux, qy = vy - uy, qz = vz - uz;
-        kin[0] += m * qx * qx;
-        kin[1] += m * qx * qy;
-        kin[2] += m * qx * qz;
-        kin[3] += m * qy * qy;
-        kin[4] += m * qy * qz;
-        kin[5] += m * qz * qz;
+        if (lane == 0) {
+            const double qx = vx - ux, qy = vy - uy, qz = vz - uz;
+            kin[0] += m * qx * qx;
+            kin[1] += m * qx * qy;
+            kin[2] += m * qx * qz;
+            kin[3] += m * qy * qy;
+            kin[4] += m * qy * qz;
+            kin[5] += m * qz * qz;
+        }
         const int ti = a.type[i];
         const int rowlen = L.cnt[i];
         const uint64_t mask = L.mask[i];
-        for (int q = 0; q < rowlen; ++q) {
+        for (int q = lane; q < rowlen; q += kFG) {
             const int32_t j = L.nbr[q * n + i];
             ContactIn c;
             c.dx = min_image(xi - a.x[j], sd.L[0], sd.hL[0], sd.periodic[0]);
@@ -289,7 +395,7 @@ __global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, double
             const int ksym[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
             for (int k = 0; k < 9; ++k) out[(DEM_F_STRESS + k) * nc + cell] = (v[k] + v[9 + ksym[k]]) / g.vol;
         } else {
-            for (int k = 0; k < kP2; ++k) part[(cell * S + b) * kP2 + k] = v[k];
+            for (int k = 0; k < kP2; ++k) part2[(cell * S + b) * kP2 + k] = v[k];
         }
     }
 }
@@ -307,18 +413,6 @@ __global__ void k_fields2_reduce(FGrid g, int S, const double *part, double *out
     }
 }
 
-// Every sphere of the system must lie within one bin width (per axis) of its
-// position at the last list build for the bin-row search above to find it.
-__global__ void k_fields_guard(KArgs a, int32_t sys) {
-    const SysDesc &sd = a.sys[sys];
-    const int64_t n = a.n;
-    bool bad = false;
-    for (int64_t i = sd.p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.pe;
-         i += (int64_t)gridDim.x * blockDim.x)
-        for (int ax = 0; ax < 3; ++ax)
-            if (!(fabs(a.disp[ax * n + i]) * sd.inv_w[ax] <= 1.0)) bad = true;
-    if (bad) atomicOr(&a.flags->err, kErrStale);
-}
 
 // PI update per transition cell: e = n.sigma_coarse.n - n.sigma_fine.n,
 // integral += e interval, u = kp e + ki integral.
@@ -449,42 +543,55 @@ int enable_fext(dem_ctx *c, const KArgs &a) {
     return DEM_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int dem_cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double *fields) {
+// Both field calls: pass 1 with the guard in the same launch; with `stress`
+// pass 2, which also completes pass 1 (S > 1), then the pass-2 slices.
+int cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double *fields, bool stress) {
     int rc = check_state(c, s);
     if (rc) return rc;
     FGrid g;
     if ((rc = make_fgrid(c, grid, g))) return rc;
     if (!fields) return fail(c, DEM_ERR_ARG, "fields is NULL");
-    if (!c->list_current) return fail(c, DEM_ERR_STATE, "dem_cell_fields needs a neighbour list for the current order");
+    if (!c->list_current) return fail(c, DEM_ERR_STATE, "the cell fields need a neighbour list for the current order");
     KArgs a = kargs(c, s);
     HIPCALL(c, hipGetLastError());
     const SysDesc &sd = c->geo.sys[g.sys];
-    k_fields_guard<<<grid_blocks(sd.pe - sd.p0, 256), 256, 0, c->stream>>>(a, g.sys);
-    // slices per cell: enough blocks to fill the device when cells are few, no
-    // more than a cell has bin rows (a function of the grid, the system's
-    // binning and the workspace only, so the sums' order is too); S = 1 writes
-    // the fields directly
+    // slices per cell: about eight bin rows each (a row of bins holds some tens
+    // of candidates), but no more than 4096 workgroups in all (a function of
+    // the grid, the system's binning and the workspace only, so the sums'
+    // order is too); S = 1 writes the fields directly
     const size_t scratch = (size_t)kShadowD * c->geo.n * 8;
     int64_t rows = 1;
     for (int ax = 1; ax < 3; ++ax) {
         const double w = sd.L[ax] / (double)sd.nc[ax];
         rows *= std::min<int64_t>(sd.nc[ax], (int64_t)std::floor(g.h[ax] / w) + 3);
     }
-    int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(256, 4096 / g.ncell), rows));
-    while (S > 1 && (size_t)g.ncell * S * kP2 * 8 > scratch) S /= 2;
-    double *part = (double *)(c->ws + c->lay.shadow_d);
-    const int64_t blocks = g.ncell * S;
-    if (blocks > INT32_MAX) return fail(c, DEM_ERR_ARG, "grid too large");
-    k_fields1<<<(int)blocks, kFB, 0, c->stream>>>(a, g, S, part, fields);
-    if (S > 1) k_fields1_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part, fields);
-    k_fields2<<<(int)blocks, kFB, 0, c->stream>>>(a, g, S, part, fields);
-    if (S > 1) k_fields2_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part, fields);
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(256, 4096 / g.ncell), rows / 8));
+    while (S > 1 && (size_t)g.ncell * S * (kP1 + kP2) * 8 > scratch) S /= 2;
+    double *part1 = (double *)(c->ws + c->lay.shadow_d);
+    double *part2 = part1 + (size_t)g.ncell * S * kP1;
+    const int64_t blocks = g.ncell * S, guard = grid_blocks(sd.pe - sd.p0, 256);
+    if (blocks + guard > INT32_MAX) return fail(c, DEM_ERR_ARG, "grid too large");
+    k_fields1<<<(int)(blocks + guard), kFB, 0, c->stream>>>(a, g, S, part1, fields);
+    if (stress) {
+        k_fields2<<<(int)blocks, kFB, 0, c->stream>>>(a, g, S, part1, part2, fields);
+        if (S > 1) k_fields2_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part2, fields);
+    } else if (S > 1) {
+        k_fields1_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part1, fields);
+    }
     HIPCALL(c, hipGetLastError());
     return DEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dem_cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double *fields) {
+    return cell_fields(c, s, grid, fields, true);
+}
+
+int dem_cell_mass_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double *fields) {
+    return cell_fields(c, s, grid, fields, false);
 }
 
 int dem_pi_control(dem_ctx *c, const dem_state *s, const dem_pi_params *p, const double *fine, const double *coarse,

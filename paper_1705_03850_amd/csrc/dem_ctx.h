@@ -58,6 +58,7 @@ struct dem_ctx {
     dem::PairCoef *d_coef = nullptr;
     double *d_rho = nullptr;
     dem::Flags *d_flags = nullptr;
+    dem::Flags *h_flags = nullptr;   // pinned host copy for read_flags (null: a pageable copy)
     dem::List lists[2];
     // host-side state machine
     bool masses = false, have_list = false, list_current = false, binned = false, frame_identity = true;

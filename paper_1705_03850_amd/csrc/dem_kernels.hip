@@ -1036,7 +1036,6 @@ __global__ void __launch_bounds__(256, 4) k_step(KArgs a, int src, int k, int up
             send = a.flags->step_end;
         }
     }
-    const int64_t n = a.n;
     const int g = threadIdx.x % G;
     const int ppb = blockDim.x / G;                        // particles per tile
     const int gbase = (threadIdx.x % warpSize) / G * G;    // first lane of the group in the wave
@@ -1248,7 +1247,6 @@ hipError_t launch_unpack(const KArgs &a, int src, int selected, hipStream_t st, 
 
 template <int G>
 static hipError_t launch_step_g(const KArgs &a, int src, int mode, int k, int update, int count, hipStream_t st) {
-    const int ppb = a.block / G;
     const int64_t ntiles = a.ntiles_b;
     const int g = grid_for(ntiles * a.block, a.block, a.grid_cap);
     const int B = a.block;

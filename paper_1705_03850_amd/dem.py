@@ -107,7 +107,7 @@ _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_b
             "dem_stats", "dem_set_timing", "dem_kernel_times", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
             "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
             "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
-            "dem_adjoint_destroy", "dem_cell_fields", "dem_pi_control", "dem_p_control", "dem_set_external_force",
+            "dem_adjoint_destroy", "dem_cell_fields", "dem_cell_mass_fields", "dem_pi_control", "dem_p_control", "dem_set_external_force",
             "dem_set_multirate", "dem_exchange", "dem_live_count", "dem_set_surfaces"]
 
 
@@ -163,6 +163,7 @@ def load(path: str = LIB_PATH):
     L.dem_adjoint_info.argtypes = [vp, P(i64)]
     L.dem_adjoint_destroy.argtypes = [vp]
     L.dem_cell_fields.argtypes = [vp, P(State), P(Grid), vp]
+    L.dem_cell_mass_fields.argtypes = [vp, P(State), P(Grid), vp]
     L.dem_pi_control.argtypes = [vp, P(State), P(PIParams), vp, vp, vp, vp]
     L.dem_p_control.argtypes = [vp, P(State), P(PParams), vp, vp]
     L.dem_set_external_force.argtypes = [vp, P(State), vp]
@@ -476,14 +477,20 @@ class DemSystem:
         return a, xi
 
     # ------------------------------------------------------------ coupling (Sec. 2.3)
-    def cell_fields(self, grid: Grid):
+    def cell_fields(self, grid: Grid, stress: bool = True, out=None):
         """Fields of the cells of `grid` at the current state: device tensor
         (NFIELDS, ncell) with rows F_COUNT, F_MASS, F_MOM..+2, F_VOLUME, F_VMAX,
-        F_STRESS..+8 (sigma_ab of Eq. 7 at row F_STRESS + 3 a + b)."""
+        F_STRESS..+8 (sigma_ab of Eq. 7 at row F_STRESS + 3 a + b).  Without
+        `stress` (dem_cell_mass_fields) the stress rows are left as they are.
+        `out`: a contiguous float64 device tensor of that shape to reuse."""
         ncell = grid.n[0] * grid.n[1] * grid.n[2]
-        out = self.torch.empty((NFIELDS, ncell), dtype=self.torch.float64, device=self.device)
+        if out is None:
+            out = self.torch.empty((NFIELDS, ncell), dtype=self.torch.float64, device=self.device)
+        elif out.shape != (NFIELDS, ncell) or out.dtype != self.torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of shape (NFIELDS, ncell)")
         self._enter(out)
-        self._rc(self.L.dem_cell_fields(self.ctx, self._state, ctypes.byref(grid), _ptr(out)))
+        fn = self.L.dem_cell_fields if stress else self.L.dem_cell_mass_fields
+        self._rc(fn(self.ctx, self._state, ctypes.byref(grid), _ptr(out)))
         self._leave()
         return out
 
@@ -492,13 +499,17 @@ class DemSystem:
     # blocking the host.
     def _enter(self, *tensors):
         cur = self.torch.cuda.current_stream(self.device)
+        if cur == self.stream:
+            return
         self.stream.wait_stream(cur)
         for t in tensors:
             if t is not None:
                 t.record_stream(self.stream)
 
     def _leave(self):
-        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
 
     def pi_control(self, params: PIParams, fine, coarse, integral, u=None):
         """PI controller of the transition layer (fine system params.grid.sys):

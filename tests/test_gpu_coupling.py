@@ -213,6 +213,12 @@ def test_cell_fields_against_oracle(stepped):
             f, scale = fields_scale(s, oracles[k], spec)
             gf = g.cell_fields(grid(spec, k))
             compare_fields(gf, f, scale, (s.name, spec))
+            # without the stress: the other rows bit for bit, the stress rows untouched
+            mf = torch.full_like(gf, float("nan"))
+            g.cell_fields(grid(spec, k), stress=False, out=mf)
+            d = dem()
+            assert torch.equal(mf[:d.F_STRESS], gf[:d.F_STRESS]), (s.name, spec)
+            assert torch.isnan(mf[d.F_STRESS:]).all(), (s.name, spec)
 
 
 def test_controllers_against_oracle(stepped):
@@ -319,6 +325,57 @@ def test_coupled_two_level_run_against_oracle():
             L = s.hi[ax] - s.lo[ax]
             d[:, ax] -= L * np.round(d[:, ax] / L)
         assert np.max(np.abs(d)) <= 1e-9 * max(s.hi), (k, np.max(np.abs(d)))
+
+
+def test_coupling_interval_replayed_as_a_graph():
+    """The calls of a coupling interval (four field reductions, PI and P)
+    captured once in a HIP graph and replayed every interval, with steps,
+    host reads and insertion-free eager work in between, give bit for bit
+    what the same calls made one by one give on a twin context."""
+    coarse, fine = two_level()
+    dt = fine.dt
+    twins = [dem().DemSystem([coarse, fine], use_graph=True, chunk=16) for _ in range(2)]
+    bufs = []
+    for g in twins:
+        g.prime()
+        bufs.append({"pf": torch.empty((16, 2), dtype=torch.float64, device=g.device),
+                     "pc": torch.empty((16, 2), dtype=torch.float64, device=g.device),
+                     "qf": torch.empty((16, 8), dtype=torch.float64, device=g.device),
+                     "qc": torch.empty((16, 8), dtype=torch.float64, device=g.device),
+                     "I": torch.full((2,), 0.01, dtype=torch.float64, device=g.device),
+                     "u": torch.empty(2, dtype=torch.float64, device=g.device)})
+    pi, pp = pi_params(1, 15 * dt), p_params(0, True)
+
+    def couple(g, b):
+        g.pi_control(pi, g.cell_fields(grid(PI_GRID, 1), out=b["pf"]), g.cell_fields(grid(PI_GRID, 0), out=b["pc"]),
+                     b["I"], b["u"])
+        g.p_control(pp, g.cell_fields(grid(P_GRID, 1), stress=False, out=b["qf"]),
+                    g.cell_fields(grid(P_GRID, 0), stress=False, out=b["qc"]))
+
+    eager, replayed = twins
+    for g, b in zip(twins, bufs):
+        with torch.cuda.stream(g.stream):
+            couple(g, b)                         # first use: the external forces start at zero
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=replayed.stream):
+        couple(replayed, bufs[1])
+    for it in range(5):
+        for g in twins:
+            g.step(15)
+        with torch.cuda.stream(eager.stream):
+            couple(eager, bufs[0])
+        with torch.cuda.stream(replayed.stream):
+            graph.replay()
+        torch.cuda.synchronize()
+        for key in ("pf", "pc", "I", "u"):
+            assert torch.equal(bufs[0][key], bufs[1][key]), (it, key)
+        for key in ("qf", "qc"):
+            assert torch.equal(bufs[0][key][:dem().F_STRESS], bufs[1][key][:dem().F_STRESS]), (it, key)
+        h0, h1 = eager.host(), replayed.host()
+        for key in ("x", "v", "w", "f", "t"):
+            assert np.array_equal(h0[key], h1[key]), (it, key)
+    assert eager.stats()["builds"] == replayed.stats()["builds"]
 
 
 def test_coupling_errors():

@@ -184,6 +184,9 @@ def coupled_run(g, cpl, steps):
     n_p = p_f.n[0] * p_f.n[1] * p_f.n[2]
     buf = [torch.empty((dem.NFIELDS, n), dtype=torch.float64, device=g.device) for n in (n_pi, n_pi, n_p, n_p)]
     t_ctl = 0.0
+    # external forces switched on (all zero) before the capture, so that the
+    # graph holds only the coupling
+    g.set_external_force(torch.zeros((3, g.n), dtype=torch.float64, device=g.device))
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=g.stream):
@@ -544,7 +547,9 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
     t_cpl = t_ex = 0.0
     # the interval's coupling calls captured once in a graph that every
     # interval replays: the calls read everything that changes (positions,
-    # binning, live counts, list buffer) from the device
+    # binning, live counts, list buffer) from the device; external forces
+    # switched on (all zero) first, so that the graph holds only the coupling
+    g.set_external_force(torch.zeros((3, g.n), dtype=torch.float64, device=g.device))
     torch.cuda.synchronize()
     cpl_graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(cpl_graph, stream=g.stream):

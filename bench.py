@@ -458,7 +458,7 @@ def silo_run(label, r, dt, fill, settle_s, discharge_s, sample_s, chunk):
     return out
 
 
-def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, sample_s=0.01):
+def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, sample_s=0.01, multirate=False):
     """The multi-level silo (Sec. 2.3 on the silo of Sec. 3, Table 2's MLCG
     rows): the coarse level (alpha = 2, d = 5.6 mm) fills the silo as in the
     coarse-grain run; the fine level (d = 2.8 mm) fills its lower quarter
@@ -472,7 +472,10 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
     the face (the coarse fields of the 2 cm slab above it), candidates are
     drawn in the top centimetre of the region and fine spheres above the face
     are removed.  Both levels discharge through the orifice; each level's
-    rate is its mass removed 1 cm below the orifice per 10 ms."""
+    rate is its mass removed 1 cm below the orifice per 10 ms.  With
+    `multirate` the coarse level steps at 2 dt in one multi-rate schedule
+    (Sec. 3: the time step may grow with the coarse-grain factor) and
+    `interval` counts fine substeps (even, so that both levels meet)."""
     import math
 
     import numpy as np
@@ -483,13 +486,18 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
 
     dt = 1e-6
     mat, muw = W.MAT_SILO, W.MU_WALL_SILO
-    coarse = W.silo_system(scale=1.0, r=2.8e-3, fill=0.53, dt=dt, mat=mat, mu_wall=muw, seed=9)
+    if multirate and interval % 2:
+        raise ValueError("a multi-rate coupling interval must be even")
+    coarse = W.silo_system(scale=1.0, r=2.8e-3, fill=0.53, dt=2 * dt if multirate else dt, mat=mat, mu_wall=muw,
+                           seed=9)
     coarse.alpha = 2.0
     fine = W.silo_system(scale=1.0, r=1.4e-3, fill=0.25, dt=dt, mat=mat, mu_wall=muw, seed=10)
     log(f"multi-level silo: {coarse.n} coarse spheres (d = 5.6 mm), {fine.n} fine (d = 2.8 mm) below z = 10 cm")
     closed = W.silo_surfaces(1.0, mu_wall=muw)
     g = dem.DemSystem([coarse, fine], surfaces=[closed, closed], capacity=[coarse.n, fine.n + 40_000],
                       use_graph=True, chunk=chunk)
+    if multirate:
+        g.set_multirate(True)
     g.prime()
     zf, h = 0.10, 0.02
     pi_grid = dem.make_grid((-0.08, -0.08, zf - h), (h, h, h), (8, 8, 1), sys=1)
@@ -629,13 +637,16 @@ def silo_suite(args):
             "paper": {"reference": 0.400, "cg_alpha2": 0.315, "cg_over_reference": 0.315 / 0.400,
                       "mlcg_fine": 0.390, "mlcg_coarse": 0.391},
             "device": torch.cuda.get_device_name(0)}
-    if not args.silo_mlcg_only:
+    if not (args.silo_mlcg_only or args.silo_mlcg_multirate_only):
         ref = silo_run("reference", 1.4e-3, 1e-6, 0.525, settle, args.silo_discharge, 0.01, args.chunk)
         cg = silo_run("CG alpha=2", 2.8e-3, 1e-6, 0.53, settle, args.silo_discharge, 0.01, args.chunk)
         line.update({"reference": ref, "cg_alpha2": cg,
                      "cg_over_reference": cg["rate_kg_s_mean"] / ref["rate_kg_s_mean"]})
     if args.silo_mlcg or args.silo_mlcg_only:
         line["mlcg"] = mlcg_silo_run(settle, args.silo_discharge, 16)
+    if args.silo_mlcg_multirate or args.silo_mlcg_multirate_only:
+        line["mlcg_multirate"] = dict(mlcg_silo_run(settle, args.silo_discharge, 16, interval=16, multirate=True),
+                                      coarse_dt=2e-6, fine_dt=1e-6)
     print(json.dumps(line), flush=True)
 
 
@@ -763,6 +774,10 @@ def main():
     ap.add_argument("--silo-discharge", type=float, default=1.0, help="silo suite: discharge time (s)")
     ap.add_argument("--silo-mlcg", action="store_true", help="silo suite: also the multi-level silo")
     ap.add_argument("--silo-mlcg-only", action="store_true", help="silo suite: the multi-level silo only")
+    ap.add_argument("--silo-mlcg-multirate", action="store_true",
+                    help="silo suite: also the multi-level silo with the coarse level at 2 dt (multi-rate)")
+    ap.add_argument("--silo-mlcg-multirate-only", action="store_true",
+                    help="silo suite: the multi-rate multi-level silo only")
     ap.add_argument("--suite", choices=("plain", "batch", "adjoint", "silo"), default="plain",
                     help="plain: the 1e6-sphere bed (default); batch: 64-system and two-level batches vs plain")
     ap.add_argument("--no-autotune", action="store_true", help="batch suite: default launch shape and skin")

@@ -32,7 +32,10 @@
  *     each system); compare results by id.
  *   - The library never allocates device memory.  Its device storage is one
  *     caller-provided workspace of dem_workspace_size() bytes that must stay
- *     allocated and untouched until dem_destroy.
+ *     allocated and untouched until dem_destroy.  dem_init and dem_batch_init
+ *     allocate one small pinned host buffer (the copy of the flag block that
+ *     synchronising calls read), freed by dem_destroy; dem_init_noalloc
+ *     allocates nothing.
  *   - Calls are enqueued on the stream given to dem_init (a hipStream_t passed
  *     as void*) and return before the GPU finishes, except where a call is
  *     documented as synchronising.

@@ -153,8 +153,9 @@ struct CandLds {
 
 // Calls visit(p, lane) for every candidate sphere p of slice b of S of the
 // cell's bin rows (rows b, b + S, ...), G lanes per candidate: the rows are
-// taken kFB at a time, their ranges laid end to end, and candidate q of the
-// chunk goes to the threads kFB / G apart from thread G (q mod kFB / G).
+// taken kFB at a time and their ranges laid end to end; candidate q of such a
+// chunk goes to the G threads that start at G (q mod kFB / G), as lanes 0 to
+// G - 1.
 template <int G, class F>
 __device__ inline void for_candidates(const KArgs &a, const SysDesc &sd, const Pieces &X, const Pieces &Y,
                                       const Pieces &Z, int b, int S, CandLds &sh, F visit) {

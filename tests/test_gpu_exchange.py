@@ -175,6 +175,46 @@ def test_other_system_of_batch_untouched():
         assert np.array_equal(runs[0][key], runs[1][key]), key
 
 
+def test_events_in_a_multirate_batch():
+    """Insertion events on the fine system of a multi-rate batch (the coarse
+    system at 2 dt, 16 substeps per interval): the fine system evolves bit
+    for bit as it does alone with the same events, the coarse one as it does
+    alone with 8 steps per interval."""
+    fine = bed(n=2000, seed=26)
+    coarse = bed(n=1500, seed=27).copy()
+    coarse.dt = 2 * fine.dt
+    zf = float(np.quantile(fine.x[:, 2], 0.8))
+    g = dem().DemSystem([coarse, fine], capacity=[None, fine.n + 400], use_graph=True, chunk=16)
+    g.set_multirate(True)
+    g.prime()
+    gf = dem().DemSystem(fine, capacity=fine.n + 400, use_graph=True, chunk=16)
+    gf.prime()
+    gc = dem().DemSystem(coarse, use_graph=True, chunk=16)
+    gc.prime()
+    total = 0
+    for k in range(3):
+        g.step(16)
+        gf.step(16)
+        gc.step(8)
+        ev = W.exchange_inputs(fine, zf + 4e-3, 200, seed=40 + k, budget_spheres=4.0, depth=5e-3)
+        ev["face"] = -zf
+        acc_b, bud_b, ins_b, rem_b = gpu_event(g, 1, ev)
+        acc_a, bud_a, ins_a, rem_a = gpu_event(gf, 0, ev)
+        assert acc_b.tolist() == acc_a.tolist() and (ins_b, rem_b) == (ins_a, rem_a), k
+        assert torch.equal(bud_a, bud_b), k
+        total += ins_a + rem_a
+    assert total > 0
+    g.step(32)
+    gf.step(32)
+    gc.step(16)
+    hb, ha = g.host(1), gf.host(0)
+    for key in ("x", "v", "w", "f", "t"):
+        assert np.array_equal(hb[key], ha[key]), key
+    hb, ha = g.host(0), gc.host(0)
+    for key in ("x", "v", "w", "f", "t", "id"):
+        assert np.array_equal(hb[key], ha[key]), ("coarse", key)
+
+
 def test_edge_cases():
     d = dem()
     s = bed(n=1500, seed=25)

@@ -575,6 +575,23 @@ int dem_rollout_backward(dem_adjoint *adj, const dem_state *s, const double *gx,
 int dem_forces_vjp(dem_adjoint *adj, const dem_state *s, const double *fb, const double *tb, double *xb, double *vb,
                    double *wb, double *grad);
 
+/* Reverse mode of dem_integrate (the velocity-Verlet halves of Eq. (1)-(2)):
+ * from the adjoints xb, vb, wb of the positions, velocities and spins that
+ * dem_integrate(ctx, s, phase) writes, the adjoints of its inputs, per live
+ * particle with dt of its system and m, I as fixed at dem_reset:
+ *   phase 0 (v' = v + dt/2 f/m, w' = w + dt/2 t/I, x' = x + dt v' wrapped
+ *   into the box): x_in = xb, v_in = vb + dt xb, w_in = wb,
+ *   f_in = dt/2 (v_in / m), t_in = dt/2 (wb / I);
+ *   phase 1 (v' = v + dt/2 f/m, w' = w + dt/2 t/I): x_in = xb, v_in = vb,
+ *   w_in = wb, f_in = dt/2 (vb / m), t_in = dt/2 (wb / I).
+ * The wrap shifts by a box length and passes the adjoint through; no material
+ * parameter enters the integration, so there is no parameter gradient.  All
+ * arrays device [3][n] in the context's current order; free slots get zeros;
+ * outputs must not overlap inputs.  DEM_ERR_STATE before dem_reset,
+ * DEM_ERR_ARG for another phase or a NULL array.  Enqueued. */
+int dem_integrate_vjp(dem_ctx *ctx, const dem_state *s, int32_t phase, const double *xb, const double *vb,
+                      const double *wb, double *x_in, double *v_in, double *w_in, double *f_in, double *t_in);
+
 /* Threads per particle in the evaluation and reverse kernels: 4 (default) or
  * 8.  Sums over a particle's row are taken per lane and then over the lanes
  * in order, so results are reproducible for a given choice. */

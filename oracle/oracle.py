@@ -179,6 +179,22 @@ class Oracle:
     def drift(self):
         self.L.orc_drift(self.h)
 
+    def integrate_vjp(self, phase: int, xb, vb, wb) -> dict:
+        """Reverse mode of one half of the velocity-Verlet step (Eq. (1)-(2)):
+        phase 0 is kick() then drift() (v' = v + dt/2 f/m, w' = w + dt/2 t/I,
+        x' = x + dt v' wrapped into the box), phase 1 is kick().  Given the
+        adjoints of the outputs x', v', w' ((n, 3) in input order), returns
+        those of the inputs x, v, w, f, t.  Written from the map itself: it is
+        linear in its inputs and the wrap is a shift by a box length, so
+        x_in = x', v_in = v' + dt x' (phase 0) or v' (phase 1), w_in = w',
+        f_in = dt/2 v_in / m, t_in = dt/2 w' / I."""
+        m, inertia = self.mass()
+        dt = self.cfg.dt
+        xb, vb, wb = (np.asarray(q, dtype=np.float64) for q in (xb, vb, wb))
+        uv = vb + dt * xb if phase == 0 else vb.copy()
+        return {"x": xb.copy(), "v": uv, "w": wb.copy(), "f": 0.5 * dt * uv / m[:, None],
+                "t": 0.5 * dt * wb / inertia[:, None]}
+
     def history(self):
         """Unordered pair history: (id_lo, id_hi, xi (k,3)) with xi seen from id_lo."""
         k = self.L.orc_history(self.h, None, None, None, 0)

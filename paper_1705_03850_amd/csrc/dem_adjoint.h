@@ -67,6 +67,11 @@ hipError_t launch_adj_compress(const AArgs &a, const D4 *hin, const D4 *hwin, D4
                                hipStream_t st);
 // Longest row of a list (cnt[n]) -> atomic maximum into *out (cleared by the caller).
 hipError_t launch_adj_row_max(const int32_t *cnt, int64_t n, int32_t *out, hipStream_t st);
+// Reverse of dem_integrate's phase 0 or 1: output adjoints (xb, vb, wb) ->
+// input adjoints (xo, vo, wo) and force and torque adjoints (fo, to), [3][n].
+hipError_t launch_integrate_vjp(const SysDesc *sys, int nsys, int64_t n, const double *inv_m, const double *inv_I,
+                                int phase, const double *xb, const double *vb, const double *wb, double *xo,
+                                double *vo, double *wo, double *fo, double *to, hipStream_t st);
 // Packed pos/vel/spin -> caller arrays x, v, w.
 hipError_t launch_adj_unpack(const AArgs &a, double *x, double *v, double *w, hipStream_t st);
 // Records of the last evaluation from the adjoints of the final x, v, w.

@@ -537,6 +537,45 @@ hipError_t launch_adj_unpack(const AArgs &a, double *x, double *v, double *w, hi
     CHECK_LAUNCH();
 }
 
+// Reverse of one half of the velocity-Verlet step (dem_integrate), one
+// thread per slot: phase 0 (kick, drift, wrap) and phase 1 (kick).  The wrap
+// is a shift by a box length, so the position adjoint passes through it.
+__global__ void k_integrate_vjp(const SysDesc *sys, int nsys, int64_t n, const double *inv_m, const double *inv_I,
+                                int phase, const double *xb, const double *vb, const double *wb, double *xo,
+                                double *vo, double *wo, double *fo, double *to) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int k = 0;
+        while (k + 1 < nsys && i >= sys[k + 1].p0) ++k;
+        const SysDesc &s = sys[k];
+        const bool live = i >= s.p0 && i < s.pe;
+        const double im = live ? inv_m[i] : 0.0, iI = live ? inv_I[i] : 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const int64_t j = c * n + i;
+            if (!live) {
+                xo[j] = vo[j] = wo[j] = fo[j] = to[j] = 0.0;
+                continue;
+            }
+            const double ux = xb[j];
+            const double uv = phase == 0 ? vb[j] + s.dt * ux : vb[j];   // v' also moves x' in phase 0
+            const double uw = wb[j];
+            xo[j] = ux;
+            vo[j] = uv;
+            wo[j] = uw;
+            fo[j] = s.hdt * (uv * im);
+            to[j] = s.hdt * (uw * iI);
+        }
+    }
+}
+
+hipError_t launch_integrate_vjp(const SysDesc *sys, int nsys, int64_t n, const double *inv_m, const double *inv_I,
+                                int phase, const double *xb, const double *vb, const double *wb, double *xo,
+                                double *vo, double *wo, double *fo, double *to, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_integrate_vjp<<<flat_grid(n), kABlock, 0, st>>>(sys, nsys, n, inv_m, inv_I, phase, xb, vb, wb, xo, vo, wo,
+                                                      fo, to);
+    CHECK_LAUNCH();
+}
+
 hipError_t launch_adj_seed(const AArgs &a, const double *gx, const double *gv, const double *gw, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
     k_adj_seed<<<flat_grid(a.n), kABlock, 0, st>>>(a, gx, gv, gw);

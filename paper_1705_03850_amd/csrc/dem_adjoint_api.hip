@@ -610,6 +610,20 @@ int dem_forces_vjp(dem_adjoint *A, const dem_state *s, const double *fb, const d
     return finish_grad(A, grad);
 }
 
+int dem_integrate_vjp(dem_ctx *c, const dem_state *s, int32_t phase, const double *xb, const double *vb,
+                      const double *wb, double *x_in, double *v_in, double *w_in, double *f_in, double *t_in) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (phase != 0 && phase != 1) return fail(c, DEM_ERR_ARG, "phase must be 0 or 1");
+    if (c->geo.n > 0 && (!xb || !vb || !wb || !x_in || !v_in || !w_in || !f_in || !t_in))
+        return fail(c, DEM_ERR_ARG, "an adjoint array is NULL");
+    if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first (the masses)");
+    const KArgs a = kargs(c, s);
+    HIPCALL(c, launch_integrate_vjp(c->d_sys, (int)c->geo.sys.size(), c->geo.n, a.inv_m, a.inv_I, phase, xb, vb, wb,
+                                    x_in, v_in, w_in, f_in, t_in, c->stream));
+    return DEM_OK;
+}
+
 int dem_adjoint_set_lanes(dem_adjoint *A, int32_t lanes) {
     if (!A) return DEM_ERR_ARG;
     if (lanes != 4 && lanes != 8) return fail(A->ctx, DEM_ERR_ARG, "lanes must be 4 or 8");

@@ -106,7 +106,7 @@ _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_b
             "dem_neighbors", "dem_forces", "dem_integrate", "dem_step", "dem_declare_forces", "dem_set_step_options", "dem_set_launch", "dem_check",
             "dem_stats", "dem_set_timing", "dem_kernel_times", "dem_export_neighbors", "dem_export_contacts", "dem_export_wall", "dem_import_history",
             "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
-            "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
+            "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_integrate_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
             "dem_adjoint_destroy", "dem_cell_fields", "dem_cell_mass_fields", "dem_pi_control", "dem_p_control", "dem_set_external_force",
             "dem_set_multirate", "dem_exchange", "dem_live_count", "dem_set_surfaces"]
 
@@ -159,6 +159,7 @@ def load(path: str = LIB_PATH):
     L.dem_rollout_forward.argtypes = [vp, P(State)]
     L.dem_rollout_backward.argtypes = [vp, P(State), vp, vp, vp, vp, vp, vp, vp, dp]
     L.dem_forces_vjp.argtypes = [vp, P(State), vp, vp, vp, vp, vp, dp]
+    L.dem_integrate_vjp.argtypes = [vp, P(State), ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
     L.dem_adjoint_set_lanes.argtypes = [vp, i32]
     L.dem_adjoint_info.argtypes = [vp, P(i64)]
     L.dem_adjoint_destroy.argtypes = [vp]
@@ -390,6 +391,19 @@ class DemSystem:
 
     def integrate(self, phase: int):
         self._rc(self.L.dem_integrate(self.ctx, self._state, int(phase)))
+
+    def integrate_vjp(self, phase: int, xb, vb, wb) -> dict:
+        """Reverse of integrate(phase) (dem_integrate_vjp): the adjoints of its
+        outputs x, v, w ((3, n) device, current order) -> the adjoints of its
+        inputs x, v, w, f, t (a dict of new (3, n) device tensors)."""
+        t = self.torch
+        xb, vb, wb = (q.to(t.float64).contiguous() for q in (xb, vb, wb))
+        out = {k: t.empty((3, self.n), dtype=t.float64, device=self.device) for k in ("x", "v", "w", "f", "t")}
+        self._enter(xb, vb, wb, *out.values())
+        self._rc(self.L.dem_integrate_vjp(self.ctx, self._state, int(phase), _ptr(xb), _ptr(vb), _ptr(wb),
+                                          *[_ptr(out[k]) for k in ("x", "v", "w", "f", "t")]))
+        self._leave()
+        return out
 
     def step(self, nsteps: int):
         self._rc(self.L.dem_step(self.ctx, self._state, int(nsteps)))

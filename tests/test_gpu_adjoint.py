@@ -161,6 +161,33 @@ def test_kslots_shrinks_the_workspace_and_changes_nothing(keep):
 
 # ------------------------------------------------------------ one force evaluation
 
+def test_integrate_vjp_matches_oracle():
+    """dem_integrate_vjp for both halves of the step against the oracle's
+    reverse mode of kick and drift (pinned on the CPU by the adjoint
+    identity): x and w adjoints bit for bit, the others to rounding."""
+    d = dem()
+    s = chute(n=600)
+    g = d.DemSystem(s)
+    g.prime()
+    o = O.Oracle(s)
+    rng = np.random.default_rng(11)
+    ys = {k: rng.normal(size=(s.n, 3)) for k in ("x", "v", "w")}       # rows by id
+    per = np.argsort(g.id.long().cpu().numpy(), kind="stable")
+    for phase in (0, 1):
+        back = g.integrate_vjp(phase, *(device_by_id(g, ys[k]) for k in ("x", "v", "w")))
+        ref = o.integrate_vjp(phase, *(ys[k][s.id] for k in ("x", "v", "w")))   # input rows
+        for k in ("x", "v", "w", "f", "t"):
+            got = back[k].cpu().numpy().T[per]
+            want = ref[k][np.argsort(s.id, kind="stable")]
+            if k in ("x", "w"):
+                assert np.array_equal(got, want), (phase, k)
+            else:
+                np.testing.assert_allclose(got, want, rtol=4e-16 * 8, atol=0, err_msg=f"{phase} {k}")
+    with pytest.raises(d.DemError) as e:
+        g.integrate_vjp(2, *(device_by_id(g, ys[k]) for k in ("x", "v", "w")))
+    assert e.value.code == d.DEM_ERR_ARG
+
+
 def test_forces_vjp_matches_oracle_tangent():
     s = chute(n=600)
     rng = np.random.default_rng(5)

@@ -1234,6 +1234,75 @@ int dem_import_history(dem_ctx *c, const dem_state *s, int64_t npairs, const int
     return DEM_OK;
 }
 
+int dem_export_surface_history(dem_ctx *c, const dem_state *s, int32_t *id, int32_t *surf, double *xi, int64_t cap,
+                               int64_t *count) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!count) return fail(c, DEM_ERR_ARG, "count is NULL");
+    *count = 0;
+    const int64_t n = c->geo.n;
+    const int S = c->geo.nsurf_slots;
+    if (S == 0 || n == 0) return DEM_OK;
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    std::vector<uint32_t> mask((size_t)n);
+    std::vector<D4> h((size_t)S * n);
+    std::vector<int32_t> ids((size_t)n);
+    HIPCALL(c, hipMemcpy(mask.data(), c->ws + c->lay.smask, (size_t)n * 4, hipMemcpyDeviceToHost));
+    HIPCALL(c, hipMemcpy(h.data(), c->ws + c->lay.sxi, (size_t)S * n * sizeof(D4), hipMemcpyDeviceToHost));
+    HIPCALL(c, hipMemcpy(ids.data(), s->id, (size_t)n * 4, hipMemcpyDeviceToHost));
+    struct Rec { int32_t a, k; double x, y, z; };
+    std::vector<Rec> out;
+    for (int64_t i = 0; i < n; ++i) {
+        const SysDesc &sd = c->geo.sys[sys_index(c->geo, i)];
+        if (i >= sd.pe) continue;
+        for (int k = 0; k < sd.nsurf; ++k)
+            if ((mask[i] >> k) & 1u) {
+                const D4 &v = h[(size_t)k * n + i];
+                out.push_back(Rec{ids[i], k, v.x, v.y, v.z});
+            }
+    }
+    std::sort(out.begin(), out.end(), [](const Rec &p, const Rec &q) { return p.a != q.a ? p.a < q.a : p.k < q.k; });
+    *count = (int64_t)out.size();
+    for (int64_t k = 0; k < *count && k < cap; ++k) {
+        if (id) id[k] = out[k].a;
+        if (surf) surf[k] = out[k].k;
+        if (xi) { xi[3 * k] = out[k].x; xi[3 * k + 1] = out[k].y; xi[3 * k + 2] = out[k].z; }
+    }
+    return DEM_OK;
+}
+
+int dem_import_surface_history(dem_ctx *c, const dem_state *s, int64_t count, const int32_t *id, const int32_t *surf,
+                               const double *xi) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (count < 0 || (count && (!id || !surf || !xi))) return fail(c, DEM_ERR_ARG, "bad surface history arrays");
+    const int64_t n = c->geo.n;
+    const int S = c->geo.nsurf_slots;
+    if (S == 0 || n == 0) return count ? fail(c, DEM_ERR_ARG, "no surfaces reserved") : DEM_OK;
+    HIPCALL(c, hipStreamSynchronize(c->stream));
+    std::vector<int32_t> ids((size_t)n);
+    HIPCALL(c, hipMemcpy(ids.data(), s->id, (size_t)n * 4, hipMemcpyDeviceToHost));
+    std::unordered_map<int32_t, int64_t> where;
+    for (int64_t i = 0; i < n; ++i)
+        if (i < c->geo.sys[sys_index(c->geo, i)].pe) where[ids[i]] = i;
+    std::vector<uint32_t> mask((size_t)n, 0u);
+    std::vector<D4> h((size_t)S * n, D4{0.0, 0.0, 0.0, 0.0});
+    for (int64_t r = 0; r < count; ++r) {
+        auto it = where.find(id[r]);
+        if (it == where.end()) return fail(c, DEM_ERR_ARG, "surface history of an id that is not live");
+        const int64_t i = it->second;
+        const int k = surf[r];
+        if (k < 0 || k >= c->geo.sys[sys_index(c->geo, i)].nsurf)
+            return fail(c, DEM_ERR_ARG, "surface index out of range for the sphere's system");
+        const double x = xi[3 * r], y = xi[3 * r + 1], z = xi[3 * r + 2];
+        h[(size_t)k * n + i] = D4{x, y, z, 0.0};
+        if (x != 0.0 || y != 0.0 || z != 0.0) mask[i] |= 1u << k;
+    }
+    HIPCALL(c, hipMemcpy(c->ws + c->lay.sxi, h.data(), (size_t)S * n * sizeof(D4), hipMemcpyHostToDevice));
+    HIPCALL(c, hipMemcpy(c->ws + c->lay.smask, mask.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    return DEM_OK;
+}
+
 const char *dem_last_error(const dem_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 
 int dem_destroy(dem_ctx *c) {

@@ -108,7 +108,8 @@ _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_b
             "dem_last_error", "dem_destroy", "dem_set_materials", "dem_adjoint_workspace_size", "dem_adjoint_init",
             "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_integrate_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
             "dem_adjoint_destroy", "dem_cell_fields", "dem_cell_mass_fields", "dem_pi_control", "dem_p_control", "dem_set_external_force",
-            "dem_set_multirate", "dem_exchange", "dem_live_count", "dem_set_surfaces"]
+            "dem_set_multirate", "dem_exchange", "dem_live_count", "dem_set_surfaces", "dem_export_surface_history",
+            "dem_import_surface_history"]
 
 
 def load(path: str = LIB_PATH):
@@ -171,6 +172,8 @@ def load(path: str = LIB_PATH):
     L.dem_exchange.argtypes = [vp, P(State), i32, P(ExchangeParams), vp, vp, i64, vp, vp, vp, vp, vp, P(i64)]
     L.dem_live_count.argtypes = [vp, i32, P(i64)]
     L.dem_set_surfaces.argtypes = [vp, i32, i32, P(Surface)]
+    L.dem_export_surface_history.argtypes = [vp, P(State), vp, vp, vp, i64, P(i64)]
+    L.dem_import_surface_history.argtypes = [vp, P(State), i64, vp, vp, vp]
     for name in _SYMBOLS:
         if name != "dem_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -297,6 +300,7 @@ class DemSystem:
         self._rc(self.L.dem_set_step_options(self.ctx, int(use_graph), int(chunk)))
         self._rc(self.L.dem_set_launch(self.ctx, int(lanes), int(max_blocks)))
         self.reset()
+        self.surfaces = [[] for _ in range(self.nsys)]
         for k, sf in enumerate(surfs):
             if sf:
                 self.set_surfaces(k, sf)
@@ -304,6 +308,21 @@ class DemSystem:
     def set_surfaces(self, sys: int, records):
         """Static wall surfaces of system `sys` (dem_set_surfaces)."""
         self._rc(self.L.dem_set_surfaces(self.ctx, int(sys), len(records), make_surfaces(records)))
+        self.surfaces[int(sys)] = [tuple(r) for r in records]
+
+    def export_surface_history(self):
+        """(id, surface index, xi (k, 3)) of every non-zero surface history."""
+        cnt = ctypes.c_int64()
+        self._rc(self.L.dem_export_surface_history(self.ctx, self._state, None, None, None, 0, ctypes.byref(cnt)))
+        a = np.empty(cnt.value, np.int32); k = np.empty(cnt.value, np.int32); xi = np.empty((cnt.value, 3))
+        self._rc(self.L.dem_export_surface_history(self.ctx, self._state, _i32p(a), _i32p(k), _dp(xi), cnt.value,
+                                                   ctypes.byref(cnt)))
+        return a, k, xi
+
+    def import_surface_history(self, ids, surf, xi):
+        ids = np.ascontiguousarray(ids, np.int32); surf = np.ascontiguousarray(surf, np.int32)
+        xi = np.ascontiguousarray(xi, np.float64).reshape(-1, 3)
+        self._rc(self.L.dem_import_surface_history(self.ctx, self._state, len(ids), _i32p(ids), _i32p(surf), _dp(xi)))
 
     # ------------------------------------------------------------ helpers
     def _rc(self, rc):
@@ -602,8 +621,8 @@ class DemSystem:
         """Host snapshot from which from_checkpoint resumes bit for bit: per
         system its live particles (positions, velocities, spins, radii, types,
         ids relative to the system's slot offset), forces and torques, plus the
-        tangential history of every pair in contact and of every wall contact
-        (by id).  The list itself is not saved: the step's results do not
+        tangential history of every pair in contact, of every wall contact
+        and of every surface contact (by id), and the current surfaces.  The list itself is not saved: the step's results do not
         depend on when it was built."""
         from .inputs.workloads import System
 
@@ -619,17 +638,24 @@ class DemSystem:
         wid, wxi = self.export_wall()
         return {"systems": systems, "f": np.concatenate([q["f"] for q in h]), "t": np.concatenate([q["t"] for q in h]),
                 "pairs": (a, b, xi), "wall": (wid, wxi), "capacity": list(self.counts),
+                "surfaces": [list(sf) for sf in self.surfaces], "surface_history": self.export_surface_history(),
                 "steps": self.stats()["steps"]}
 
     @classmethod
     def from_checkpoint(cls, ckpt: dict, **kwargs) -> "DemSystem":
         """A new context resumed from checkpoint(): same slot capacities, the
         state and history loaded, the saved forces declared current."""
+        surfs = ckpt.get("surfaces")
+        if surfs and any(surfs) and "surfaces" not in kwargs:
+            kwargs["surfaces"] = surfs
         g = cls(ckpt["systems"], capacity=ckpt["capacity"], **kwargs)
         g.load_state(f=ckpt["f"], t=ckpt["t"])
         g.reset()
         g.build_list()
         g.import_history(*ckpt["pairs"], *ckpt["wall"])
+        sh = ckpt.get("surface_history")
+        if sh is not None and len(sh[0]):
+            g.import_surface_history(*sh)
         g.declare_forces()
         return g
 

@@ -15,6 +15,11 @@ times (4 lanes per particle, 256-thread blocks, resident grid, graph replay).
   * 64-system batch (3.8e6 spheres): bit for bit equal to each system stepped
     alone over 300 steps (with list rebuilds), and two systems against the
     oracle.
+  * the reference silo of the discharge runs (188,621 spheres, the paper's
+    walls and material table): settled on the GPU for 0.02 s, its state and
+    every history (pairs and surfaces) handed to the oracle, then 10 steps
+    closed and 10 steps with the orifice open on both sides (positions within
+    1e-9 of the box, surface histories within 1e-9 of the box).
   * 5e4-sphere adjoint chute: 40 steps against the oracle's dual-number
     tangent (1e-9), with and without list rebuilds between windows, and in
     kept mode; the 200-step, 10-window flux-loss gradient against the
@@ -468,3 +473,46 @@ def test_full_adjoint_chute_200_steps():
 # mu 1.8e-3 and 1.3e-1 -- the second type (e = 0.7, mu = 0.3) has the most
 # contacts that switch between sticking and sliding inside the difference step.
 DIFF_TOL = {"E": 2e-2, "e": 2e-1, "mu": 2.5e-1}
+
+
+def test_full_silo_against_oracle():
+    s = W.silo_system(scale=1.0, r=1.4e-3, fill=0.525, dt=1e-6, mat=W.MAT_SILO, mu_wall=W.MU_WALL_SILO)
+    assert s.n == 188621
+    g = bench_system(s, surfaces=s.meta["surfaces"], capacity=s.n)
+    g.prime()
+    g.step(20000)                                   # spheres settle onto each other and the walls
+    ck = g.checkpoint()
+    s0 = ck["systems"][0]
+    ids, ks, sxi = ck["surface_history"]
+    a, b, xi = ck["pairs"]
+    assert len(ids) > 500 and len(a) > 5000, (len(ids), len(a))   # 1,585 and 13,742 after the 0.02 s
+    o = O.Oracle(s0)
+    o.set_surfaces(s.meta["surfaces"])
+    o.set_state(f=ck["f"], t=ck["t"])
+    up = a < b
+    o.set_history(a[up], b[up], xi[up])
+    wid, wxi = ck["wall"]
+    if len(wid):
+        o.set_wall_history(wid, wxi)
+    o.set_surface_history(ids, ks, sxi)
+    edge = max(s.hi[k] - s.lo[k] for k in range(3))
+
+    def compare(tag):
+        h = g.host(0)
+        d = h["x"] - by_id(s0, o.state()["x"])
+        assert np.max(np.abs(d)) <= 1e-9 * edge, (tag, np.max(np.abs(d)))
+        gi, gk, gx = g.export_surface_history()
+        oi, ok_, ox = o.surface_history()
+        order = np.lexsort((ok_, oi))
+        assert np.array_equal(gi, oi[order]) and np.array_equal(gk, ok_[order]), tag
+        assert np.max(np.abs(gx - ox[order])) <= 1e-9 * edge, (tag, np.max(np.abs(gx - ox[order])))
+
+    g.step(10)
+    o.step(10)
+    compare("closed")
+    opened = W.silo_surfaces(1.0, open_orifice=True, mu_wall=W.MU_WALL_SILO)
+    g.set_surfaces(0, opened)
+    o.set_surfaces(opened)
+    g.step(10)
+    o.step(10)
+    compare("open")

@@ -4,8 +4,9 @@ over the orifice, the orifice's rim) on the GPU against the oracle.
   * a small silo (the paper's shape at a tenth of its size, 4,635 spheres of
     r = 0.4 mm +- 10 % thrown at 0.2 m/s): 300 steps with the orifice closed,
     then the plug removed and the rim enabled on both sides, 300 more steps;
-    positions within 1e-9 of the box; the first forces within 1e-12 of the
-    largest;
+    positions within 1e-9 of the box, and the surface contact histories (the
+    same (id, surface) pairs, values within 1e-9 of the box); the first
+    forces within 1e-12 of the largest;
   * a silo and its coarse-grain twin (alpha = 2, dt = 2e-6 s) as one batch,
     single-rate and multi-rate, bit for bit equal to each system alone;
   * the outlet of an insertion event removes what has left through the
@@ -71,6 +72,13 @@ def test_silo_against_oracle_closed_then_open():
     g.step(300)
     o.step(300)
     compare(g, s, o)
+    # the surface contact histories, by (id, surface)
+    ids, ks, xi = g.export_surface_history()
+    oid, ok_, oxi = o.surface_history()
+    order = np.lexsort((ok_, oid))
+    assert np.array_equal(ids, oid[order]) and np.array_equal(ks, ok_[order]) and len(ids) >= 10
+    edge = max(s.hi[a] - s.lo[a] for a in range(3))
+    assert np.max(np.abs(xi - oxi[order])) <= 1e-9 * edge, np.max(np.abs(xi - oxi[order]))
     st = g.stats()
     assert st["wall_contacts"] > 0
 

@@ -74,7 +74,7 @@ def test_hertz_duration_elastic_monodisperse():
     mass = sphere_mass(1e-3, m.rho)
     tc, dmax = hertz_duration(mass / 2.0, 0.5e-3, e_star(m, m), 1.0)
     assert abs((t_out - t_in) / tc - 1.0) < 1e-4
-    assert abs(tc - 2.722935e-4) < 1e-9          # value recomputed in the design survey
+    assert abs(tc - 2.722935e-4) < 1e-9          # the closed form evaluated by hand for these values
     assert abs(dmax - 9.251379e-5) < 1e-10
     assert abs(ratio - 1.0) < 1e-6               # no dissipation at e = 1
 

@@ -469,7 +469,9 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
     mode on the coarse spheres of the four layers below.  Every
     `exchange_every` intervals an insertion event on the fine level: the
     budget of each 2 x 2 cm boundary cell grows by the coarse inflow through
-    the face (the coarse fields of the 2 cm slab above it), candidates are
+    the face (the coarse fields of the 2 cm slab above it, averaged over the
+    couplings since the last event, so that the inserted spheres move with
+    the Favre-averaged velocity of the period), candidates are
     drawn in the top centimetre of the region and fine spheres above the face
     are removed.  Both levels discharge through the orifice; each level's
     rate is its mass removed 1 cm below the orifice per 10 ms.  With
@@ -541,15 +543,20 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
 
     # the loop runs on the library's stream with its buffers allocated once;
     # the P controller and the insertion budget read no stress
-    buf = {k: torch.empty((dem.NFIELDS, 64 * n), dtype=torch.float64, device=g.device)
+    buf = {k: torch.zeros((dem.NFIELDS, 64 * n), dtype=torch.float64, device=g.device)
            for k, n in (("pi", 1), ("pi_c", 1), ("p", 4), ("p_c", 4), ("in_c", 1))}
     u = torch.empty(64, dtype=torch.float64, device=g.device)
+    in_sum = torch.zeros((dem.NFIELDS, 64), dtype=torch.float64, device=g.device)
 
     def interval_coupling():
         g.pi_control(pp, g.cell_fields(pi_grid, out=buf["pi"]), g.cell_fields(pi_grid_c, out=buf["pi_c"]),
                      integral, u)
         g.p_control(qp, g.cell_fields(p_grid_f, stress=False, out=buf["p"]),
                     g.cell_fields(p_grid_c, stress=False, out=buf["p_c"]))
+        # the coarse level on the boundary cells, summed at every coupling
+        # between insertion events: their mean is the Favre average over the
+        # period (momentum over mass) and the mean inflow
+        in_sum.add_(g.cell_fields(in_grid_c, stress=False, out=buf["in_c"]))
 
     inserted = removed_top = 0
     t_cpl = t_ex = 0.0
@@ -575,7 +582,8 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
             g.step(interval)
             if (k + 1) % exchange_every == 0:
                 te = time.perf_counter()
-                fields = g.cell_fields(in_grid_c, stress=False, out=buf["in_c"])
+                fields = in_sum / exchange_every
+                in_sum.zero_()
                 _, i, r = g.exchange(1, ex, fields, budget, *candidates())
                 inserted += i
                 removed_top += r

@@ -458,7 +458,8 @@ def silo_run(label, r, dt, fill, settle_s, discharge_s, sample_s, chunk):
     return out
 
 
-def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, sample_s=0.01, multirate=False):
+def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, sample_s=0.01, multirate=False,
+                  stepper="coupled", group=5):
     """The multi-level silo (Sec. 2.3 on the silo of Sec. 3, Table 2's MLCG
     rows): the coarse level (alpha = 2, d = 5.6 mm) fills the silo as in the
     coarse-grain run; the fine level (d = 2.8 mm) fills its lower quarter
@@ -477,7 +478,10 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
     rate is its mass removed 1 cm below the orifice per 10 ms.  With
     `multirate` the coarse level steps at 2 dt in one multi-rate schedule
     (Sec. 3: the time step may grow with the coarse-grain factor) and
-    `interval` counts fine substeps (even, so that both levels meet)."""
+    `interval` counts fine substeps (even, so that both levels meet).
+    stepper "coupled": dem_step_coupled runs `group` intervals (coupling and
+    steps) per synchronisation; "calls": per interval the coupling calls
+    replayed as one graph, then dem_step."""
     import math
 
     import numpy as np
@@ -566,12 +570,58 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
     # switched on (all zero) first, so that the graph holds only the coupling
     g.set_external_force(torch.zeros((3, g.n), dtype=torch.float64, device=g.device))
     torch.cuda.synchronize()
-    cpl_graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(cpl_graph, stream=g.stream):
-        interval_coupling()
+    if stepper == "calls":
+        cpl_graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cpl_graph, stream=g.stream):
+            interval_coupling()
+
+    plan = g.coupling_plan(pp, 0, qp, 1, interval, group=group, integral=integral, sum_grid=in_grid_c)
+
+    def insertion_event():
+        nonlocal inserted, removed_top, t_ex
+        te = time.perf_counter()
+        acc = plan.buffers["sum"] if stepper == "coupled" else in_sum
+        fields = acc / exchange_every
+        acc.zero_()
+        _, i, r = g.exchange(1, ex, fields, budget, *candidates())
+        inserted += i
+        removed_top += r
+        t_ex += time.perf_counter() - te
+
+    def run_coupled(seconds, sampling):
+        # blocks of whole insertion periods; a rate sample at the first block
+        # end at least sample_s after the last one, over the time elapsed
+        nonlocal t_cpl
+        rates_f, rates_c = [], []
+        per_sample = int(round(sample_s / (interval * dt)))
+        n_int = int(round(seconds / (interval * dt)))
+        k = last = 0
+        next_log = 5 * per_sample
+        while k < n_int:
+            nb = min(exchange_every - k % exchange_every, n_int - k)
+            tc = time.perf_counter()
+            g.step_coupled(nb, plan)
+            t_cpl += time.perf_counter() - tc
+            k += nb
+            if k % exchange_every == 0:
+                insertion_event()
+            if sampling and k - last >= per_sample:
+                _, _, rf_ = g.exchange(1, out, zero_f, zero_b)
+                _, _, rc_ = g.exchange(0, out, zero_f, zero_b)
+                rates_f.append(rf_ * mf / ((k - last) * interval * dt))
+                rates_c.append(rc_ * mc / ((k - last) * interval * dt))
+                last = k
+            if k >= next_log:
+                next_log += 5 * per_sample
+                log(f"multi-level silo: {k * interval * dt:.2f} s of {seconds:.2f} s"
+                    f"{' (discharge)' if sampling else ' (settling)'}; fine {g.live(1)}, coarse {g.live(0)}, "
+                    f"inserted {inserted}")
+        return np.array(rates_f), np.array(rates_c)
 
     def run(seconds, sampling):
-        nonlocal inserted, removed_top, t_cpl, t_ex
+        if stepper == "coupled":
+            return run_coupled(seconds, sampling)
+        nonlocal t_cpl
         rates_f, rates_c = [], []
         per_sample = int(round(sample_s / (interval * dt)))
         n_int = int(round(seconds / (interval * dt)))
@@ -581,13 +631,7 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
             t_cpl += time.perf_counter() - tc
             g.step(interval)
             if (k + 1) % exchange_every == 0:
-                te = time.perf_counter()
-                fields = in_sum / exchange_every
-                in_sum.zero_()
-                _, i, r = g.exchange(1, ex, fields, budget, *candidates())
-                inserted += i
-                removed_top += r
-                t_ex += time.perf_counter() - te
+                insertion_event()
             if sampling and (k + 1) % per_sample == 0:
                 _, _, rf_ = g.exchange(1, out, zero_f, zero_b)
                 _, _, rc_ = g.exchange(0, out, zero_f, zero_b)
@@ -620,7 +664,9 @@ def mlcg_silo_run(settle_s, discharge_s, chunk, interval=15, exchange_every=10, 
            "inserted": inserted, "removed_above_face": removed_top,
            "rate_fine_kg_s_mean": float(sf.mean()), "rate_fine_kg_s_std": float(sf.std()),
            "rate_coarse_kg_s_mean": float(sc.mean()), "rate_coarse_kg_s_std": float(sc.std()),
-           "settle_wall_s": t_settle, "discharge_wall_s": t_dis, "coupling_wall_s": t_cpl, "exchange_wall_s": t_ex,
+           "settle_wall_s": t_settle, "discharge_wall_s": t_dis, "stepper": stepper,
+           "group": group if stepper == "coupled" else 1,
+           "coupled_steps_wall_s" if stepper == "coupled" else "coupling_wall_s": t_cpl, "exchange_wall_s": t_ex,
            "rates_fine_kg_s": [round(float(q), 4) for q in rates_f],
            "rates_coarse_kg_s": [round(float(q), 4) for q in rates_c]}
     log(f"multi-level silo: fine {res['rate_fine_kg_s_mean']:.3f} +- {res['rate_fine_kg_s_std']:.3f} kg/s, coarse "
@@ -650,11 +696,12 @@ def silo_suite(args):
         cg = silo_run("CG alpha=2", 2.8e-3, 1e-6, 0.53, settle, args.silo_discharge, 0.01, args.chunk)
         line.update({"reference": ref, "cg_alpha2": cg,
                      "cg_over_reference": cg["rate_kg_s_mean"] / ref["rate_kg_s_mean"]})
+    stepper = "calls" if args.silo_mlcg_calls else "coupled"
     if args.silo_mlcg or args.silo_mlcg_only:
-        line["mlcg"] = mlcg_silo_run(settle, args.silo_discharge, 16)
+        line["mlcg"] = mlcg_silo_run(settle, args.silo_discharge, 16, stepper=stepper)
     if args.silo_mlcg_multirate or args.silo_mlcg_multirate_only:
-        line["mlcg_multirate"] = dict(mlcg_silo_run(settle, args.silo_discharge, 16, interval=16, multirate=True),
-                                      coarse_dt=2e-6, fine_dt=1e-6)
+        line["mlcg_multirate"] = dict(mlcg_silo_run(settle, args.silo_discharge, 16, interval=16, multirate=True,
+                                                    stepper=stepper), coarse_dt=2e-6, fine_dt=1e-6)
     print(json.dumps(line), flush=True)
 
 
@@ -784,6 +831,9 @@ def main():
     ap.add_argument("--silo-mlcg-only", action="store_true", help="silo suite: the multi-level silo only")
     ap.add_argument("--silo-mlcg-multirate", action="store_true",
                     help="silo suite: also the multi-level silo with the coarse level at 2 dt (multi-rate)")
+    ap.add_argument("--silo-mlcg-calls", action="store_true",
+                    help="silo suite: multi-level runs by per-interval calls (coupling graph + dem_step) instead of "
+                         "dem_step_coupled")
     ap.add_argument("--silo-mlcg-multirate-only", action="store_true",
                     help="silo suite: the multi-rate multi-level silo only")
     ap.add_argument("--suite", choices=("plain", "batch", "adjoint", "silo"), default="plain",

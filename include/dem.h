@@ -383,6 +383,43 @@ typedef struct dem_p_params {
 int dem_p_control(dem_ctx *ctx, const dem_state *s, const dem_p_params *p, const double *fine,
                   const double *coarse);
 
+/* Coupled stepping: nintervals coupling intervals of the multi-level model
+ * (Sec. 2.3: fields, PI and P controllers every interval_steps steps), each
+ * bit for bit the same as the calls
+ *   dem_cell_fields(pi.grid -> pi_fine);
+ *   dem_cell_fields(pi.grid with sys = pi_setpoint_sys -> pi_coarse);
+ *   dem_pi_control(pi, pi_fine, pi_coarse, integral, u);
+ *   dem_cell_mass_fields(p.grid with sys = p_target_sys -> p_fine);
+ *   dem_cell_mass_fields(p.grid -> p_coarse);
+ *   dem_p_control(p, p_fine, p_coarse);
+ *   if sum: dem_cell_mass_fields(sum_grid -> sum_tmp), then sum += sum_tmp;
+ *   dem_step(interval_steps);
+ * but with one synchronisation per `group` intervals instead of one per
+ * interval: the intervals of a group are enqueued together, a drift that asks
+ * for a list rebuild stops every later kernel of the group (the coupling
+ * kernels and steps skip their work while a rebuild is pending), and the call
+ * rebuilds, finishes the interrupted interval and issues the skipped
+ * intervals again.  Field arrays: device, DEM_NFIELDS rows of the grid's
+ * cells (the stress rows of p_fine, p_coarse and sum_tmp are not written).
+ * Same requirements and errors as those calls (DEM_ERR_STATE without the
+ * forces of the current state, DEM_ERR_ARG for a bad plan; with multi-rate
+ * stepping interval_steps must be a multiple of the largest stride).
+ * Synchronises once per group. */
+typedef struct dem_coupling_plan {
+    dem_pi_params pi;          /* PI controller; pi.grid: transition cells of the fine system    */
+    int32_t pi_setpoint_sys;   /* coarse system whose fields on pi.grid's cells are the setpoint */
+    int32_t p_target_sys;      /* fine system whose fields on p.grid's cells are the target      */
+    dem_p_params p;            /* P controller; p.grid: cells of the coarse system               */
+    double *pi_fine, *pi_coarse, *p_fine, *p_coarse;   /* fields written every interval      */
+    double *integral, *u;      /* PI state (in/out) and output, [cells of pi.grid]                */
+    dem_grid sum_grid;         /* cells whose fields (without stress) are summed every interval   */
+    double *sum, *sum_tmp;     /* running sum (in/out) and scratch; sum NULL: no summing          */
+    int64_t interval_steps;    /* steps per interval, >= 1                                        */
+    int32_t group;             /* intervals per synchronisation, >= 1                             */
+    int32_t pad;
+} dem_coupling_plan;
+int dem_step_coupled(dem_ctx *ctx, const dem_state *s, int64_t nintervals, const dem_coupling_plan *plan);
+
 /* Set the external forces of all spheres from a device array [3][n] in the
  * current order (copied), or clear them (fext NULL).  They are added to every
  * later force evaluation (after gravity, the contacts and the wall) and move

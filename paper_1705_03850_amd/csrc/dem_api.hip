@@ -458,6 +458,130 @@ int capture_graph(dem_ctx *c, const dem_state *s, GraphSlot &gs, int len) {
     return DEM_OK;
 }
 
+// Running estimate of the steps between rebuilds (it sets the group length).
+void note_rebuild(dem_ctx *c, int64_t ran) {
+    const double gap = (double)(c->since_rebuild + ran);
+    c->gap_avg = 0.5 * (c->gap_avg < 1e8 ? c->gap_avg : gap) + 0.5 * gap;
+    c->since_rebuild = 0;
+}
+
+void note_steps(dem_ctx *c, int64_t ran) {
+    c->since_rebuild += ran;
+    if ((double)c->since_rebuild > c->gap_avg) c->gap_avg = (double)c->since_rebuild;
+}
+
+// The drift into step qa (1-based within the current call) asked for a new
+// list: the systems that asked for it are unpacked, rebuilt and repacked into
+// the same buffer, by kernels over the index window of those systems.
+int rebuild_at(dem_ctx *c, const dem_state *s, int64_t qa) {
+    const int buf = (int)((qa - 1) & 1);
+    int rc;
+    if ((rc = tic(c, 3))) return rc;
+    if (c->geo.sys.size() > 1 && (rc = set_rebuild_window(c))) return rc;
+    KArgs a = kargs(c, s);
+    HIPCALL(c, launch_unpack(a, buf, 1, c->stream, qa));
+    c->binned = false;
+    if ((rc = do_bin(c, s, false)) || (rc = do_neighbors(c, s, false))) return rc;
+    KArgs b = kargs(c, s);
+    HIPCALL(c, launch_pack(b, buf, 2, 0, 0, c->stream, qa));
+    c->win_on = false;
+    HIPCALL(c, launch_fill_i32(b.sel, (int64_t)c->geo.sys.size(), 0, c->stream));
+    return toc(c);
+}
+
+// Steps q..nsteps of a call whose first step is global step base + 1.  On
+// entry the state of step q after its drift is in packed buffer (q - 1) & 1
+// and the flag block's step base is base + q.  Steps are numbered
+// 1..nsteps; the fused kernel of step q computes its forces and kicks, then
+// drifts into q + 1.  Groups of launches run between synchronisations; a
+// group that needs a rebuild stops at the step whose drift asked for it.
+// The call's last step writes the caller's arrays.  h: the flags read after
+// the last group.
+int step_loop(dem_ctx *c, const dem_state *s, int64_t nsteps, int64_t base, int64_t q, Flags &h) {
+    int rc;
+    const int cnt = c->count ? 1 : 0;
+    int64_t q0 = q;
+    while (q <= nsteps) {
+        KArgs a = kargs(c, s);
+        // group length: the full chunk, or shorter while rebuilds come often (a
+        // rebuild stops the group; the rest of it would run as empty launches)
+        int len = c->chunk;
+        if (c->gap_avg < 2.0 * c->chunk) {
+            len = 8;
+            while (2 * len <= c->chunk && 2 * len <= c->gap_avg / 2) len *= 2;
+            if (len > c->chunk) len = c->chunk;
+        }
+        int slot = 0;
+        while ((8 << slot) < len && slot < 7) ++slot;
+        int pair1 = -1, pair2 = -1;   // timed event pairs of this group (fused steps, last step)
+        if (c->use_graph && !c->timing && (8 << slot) == len && q == q0 && ((q - 1) & 1) == 0 &&
+            q + len - 1 <= nsteps - 1) {
+            GraphSlot &gs = c->graphs[slot];
+            const void *key[10] = {c->ws, c->fext_on ? (const void *)c->lay.fext : nullptr,
+                             c->multirate ? (const void *)c->lay.sys : nullptr};
+            if (!gs.exec || memcmp(gs.key, key, sizeof key) || gs.chunk != len || gs.count != cnt)
+                if ((rc = capture_graph(c, s, gs, len))) return rc;
+            HIPCALL(c, hipGraphLaunch(gs.exec, c->stream));
+            q += len;
+        } else {
+            // with timing on, one pair of events brackets each run of fused
+            // steps (the last step of a call gets a pair of its own), so the
+            // events add no gaps between the kernels they time
+            int open = 0;
+            while (q <= nsteps && q - q0 < len) {
+                const int last = q == nsteps;
+                if (last && open) {
+                    if ((rc = toc(c, open))) return rc;
+                    open = 0;
+                }
+                if (last) {
+                    pair2 = c->ev_used;
+                    if ((rc = tic(c, 2))) return rc;
+                } else if (!open) {
+                    pair1 = c->ev_used;
+                    if ((rc = tic(c, 1))) return rc;
+                }
+                KArgs al = a;
+                if (last) al.call_steps = nsteps;
+                HIPCALL(c, launch_step(al, (int)((q - 1) & 1), last ? 2 : 1, (int)(q - q0), 1, cnt, c->stream));
+                if (last) {
+                    if ((rc = toc(c))) return rc;
+                } else {
+                    ++open;
+                }
+                ++q;
+            }
+            if (open && (rc = toc(c, open))) return rc;
+        }
+        if ((rc = read_flags(c, h))) return rc;
+        if (c->timing && h.abort_at != INT64_MAX) {
+            // launches at or after the rebuild request did no work: count only
+            // the fused steps that ran (their near-empty launches stay inside
+            // the timed interval, a few microseconds each)
+            const int64_t ran = h.abort_at - base - q0;
+            if (pair1 >= 0 && c->ev_count[pair1] > ran) c->ev_count[pair1] = (int)(ran > 0 ? ran : 0);
+            if (pair2 >= 0 && h.abort_at - base <= nsteps) c->ev_count[pair2] = 0;
+        }
+        if ((rc = collect_times(c))) return rc;
+        if ((rc = flag_error(c, h))) return rc;
+        if (h.abort_at != INT64_MAX) {
+            // the drift into step q_a asked for a new list: rebuild on the caller's
+            // arrays and repack into the same buffer
+            const int64_t qa = h.abort_at - base;
+            if ((rc = rebuild_at(c, s, qa))) return rc;
+            note_rebuild(c, qa - q0);
+            q = qa;
+        } else {
+            note_steps(c, q - q0);
+        }
+        if (q <= nsteps) {
+            HIPCALL(c, launch_ctrl(c->d_flags, 0, base + q, c->stream));
+            q0 = q;
+        }
+    }
+    return DEM_OK;
+}
+
 }  // namespace host
 }  // namespace dem
 
@@ -837,14 +961,7 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
         // binned but no list yet: build it (f and t were permuted with the particles)
         if ((rc = do_bin(c, s, true)) || (rc = do_neighbors(c, s))) return rc;
     }
-    // Steps are numbered 1..nsteps.  The state of step q after its drift lives
-    // in packed buffer (q-1)&1; the fused kernel of step q computes its forces
-    // and kicks, then drifts into q+1.  Groups of launches run between
-    // synchronisations; a group that needs a rebuild stops at the step whose
-    // drift asked for it.
     const int64_t base = c->step_counter;
-    const int cnt = c->count ? 1 : 0;
-    int64_t q = 1, q0 = 1;
     Flags h;
     HIPCALL(c, launch_ctrl(c->d_flags, 0, base + 1, c->stream));
     if (c->multirate) {
@@ -857,100 +974,7 @@ int dem_step(dem_ctx *c, const dem_state *s, int64_t nsteps) {
         HIPCALL(c, launch_pack(a, 0, 1, 0, 1, c->stream));
         if ((rc = toc(c))) return rc;
     }
-    while (q <= nsteps) {
-        KArgs a = kargs(c, s);
-        // group length: the full chunk, or shorter while rebuilds come often (a
-        // rebuild stops the group; the rest of it would run as empty launches)
-        int len = c->chunk;
-        if (c->gap_avg < 2.0 * c->chunk) {
-            len = 8;
-            while (2 * len <= c->chunk && 2 * len <= c->gap_avg / 2) len *= 2;
-            if (len > c->chunk) len = c->chunk;
-        }
-        int slot = 0;
-        while ((8 << slot) < len && slot < 7) ++slot;
-        int pair1 = -1, pair2 = -1;   // timed event pairs of this group (fused steps, last step)
-        if (c->use_graph && !c->timing && (8 << slot) == len && q == q0 && ((q - 1) & 1) == 0 &&
-            q + len - 1 <= nsteps - 1) {
-            GraphSlot &gs = c->graphs[slot];
-            const void *key[10] = {c->ws, c->fext_on ? (const void *)c->lay.fext : nullptr,
-                             c->multirate ? (const void *)c->lay.sys : nullptr};
-            if (!gs.exec || memcmp(gs.key, key, sizeof key) || gs.chunk != len || gs.count != cnt)
-                if ((rc = capture_graph(c, s, gs, len))) return rc;
-            HIPCALL(c, hipGraphLaunch(gs.exec, c->stream));
-            q += len;
-        } else {
-            // with timing on, one pair of events brackets each run of fused
-            // steps (the last step of a call gets a pair of its own), so the
-            // events add no gaps between the kernels they time
-            int open = 0;
-            while (q <= nsteps && q - q0 < len) {
-                const int last = q == nsteps;
-                if (last && open) {
-                    if ((rc = toc(c, open))) return rc;
-                    open = 0;
-                }
-                if (last) {
-                    pair2 = c->ev_used;
-                    if ((rc = tic(c, 2))) return rc;
-                } else if (!open) {
-                    pair1 = c->ev_used;
-                    if ((rc = tic(c, 1))) return rc;
-                }
-                KArgs al = a;
-                if (last) al.call_steps = nsteps;
-                HIPCALL(c, launch_step(al, (int)((q - 1) & 1), last ? 2 : 1, (int)(q - q0), 1, cnt, c->stream));
-                if (last) {
-                    if ((rc = toc(c))) return rc;
-                } else {
-                    ++open;
-                }
-                ++q;
-            }
-            if (open && (rc = toc(c, open))) return rc;
-        }
-        if ((rc = read_flags(c, h))) return rc;
-        if (c->timing && h.abort_at != INT64_MAX) {
-            // launches at or after the rebuild request did no work: count only
-            // the fused steps that ran (their near-empty launches stay inside
-            // the timed interval, a few microseconds each)
-            const int64_t ran = h.abort_at - base - q0;
-            if (pair1 >= 0 && c->ev_count[pair1] > ran) c->ev_count[pair1] = (int)(ran > 0 ? ran : 0);
-            if (pair2 >= 0 && h.abort_at - base <= nsteps) c->ev_count[pair2] = 0;
-        }
-        if ((rc = collect_times(c))) return rc;
-        if ((rc = flag_error(c, h))) return rc;
-        if (h.abort_at != INT64_MAX) {
-            // the drift into step q_a asked for a new list: rebuild on the caller's
-            // arrays and repack into the same buffer
-            const int64_t qa = h.abort_at - base;
-            const int buf = (int)((qa - 1) & 1);
-            // only the systems that asked for it are unpacked, rebuilt and repacked,
-            // by kernels over the index window of those systems
-            if ((rc = tic(c, 3))) return rc;
-            if (c->geo.sys.size() > 1 && (rc = set_rebuild_window(c))) return rc;
-            a = kargs(c, s);
-            HIPCALL(c, launch_unpack(a, buf, 1, c->stream, qa));
-            c->binned = false;
-            if ((rc = do_bin(c, s, false)) || (rc = do_neighbors(c, s, false))) return rc;
-            KArgs b = kargs(c, s);
-            HIPCALL(c, launch_pack(b, buf, 2, 0, 0, c->stream, qa));
-            c->win_on = false;
-            HIPCALL(c, launch_fill_i32(b.sel, (int64_t)c->geo.sys.size(), 0, c->stream));
-            if ((rc = toc(c))) return rc;
-            const double gap = (double)(c->since_rebuild + (qa - q0));
-            c->gap_avg = 0.5 * (c->gap_avg < 1e8 ? c->gap_avg : gap) + 0.5 * gap;
-            c->since_rebuild = 0;
-            q = qa;
-        } else {
-            c->since_rebuild += q - q0;
-            if ((double)c->since_rebuild > c->gap_avg) c->gap_avg = (double)c->since_rebuild;
-        }
-        if (q <= nsteps) {
-            HIPCALL(c, launch_ctrl(c->d_flags, 0, base + q, c->stream));
-            q0 = q;
-        }
-    }
+    if ((rc = step_loop(c, s, nsteps, base, 1, h))) return rc;
     // the flags read after the last group are final: its last launch counted the steps
     if ((rc = collect_times(c))) return rc;
     c->step_counter += nsteps;

@@ -36,6 +36,11 @@ struct FGrid {
 };
 
 constexpr int kFB = 256;   // threads per workgroup of the fields kernels
+
+// Coupled stepping (dem_step_coupled) enqueues several intervals at once: a
+// kernel given the flag block does nothing while a list rebuild is pending
+// (the call issues it again after the rebuild).  Null: always runs.
+__device__ inline bool skip_pending(const Flags *gate) { return gate && gate->abort_at != INT64_MAX; }
 constexpr int kFG = 4;     // threads per sphere where its contacts are summed
 
 // Cell of a centre: floor((x - lo) / h) per axis, -1 outside (or NaN).
@@ -234,9 +239,11 @@ __device__ inline void fields_guard(const KArgs &a, int32_t sys, int64_t blk, in
 // Block (cell, b): slice b of S of the cell's rows.  S = 1 writes the cell's
 // rows of `out` directly; S > 1 writes the slice's sums to part[(cell S + b) kP1].
 // The blocks after the ncell S field blocks run the guard above.
-__global__ void __launch_bounds__(kFB) k_fields1(KArgs a, FGrid g, int S, double *part, double *out) {
+__global__ void __launch_bounds__(kFB) k_fields1(KArgs a, FGrid g, int S, double *part, double *out,
+                                                 const Flags *gate) {
     __shared__ double lds[kP1 * kFB];
     __shared__ CandLds sh;
+    if (skip_pending(gate)) return;
     const int64_t nfb = g.ncell * S;
     if ((int64_t)blockIdx.x >= nfb) {
         fields_guard(a, g.sys, (int64_t)blockIdx.x - nfb, (int64_t)gridDim.x - nfb);
@@ -291,7 +298,8 @@ __device__ inline void write_pass1(double *out, int64_t nc, int64_t cell, const 
 }
 
 // One thread per cell (the fields without stress): the slices' sums.
-__global__ void k_fields1_reduce(FGrid g, int S, const double *part, double *out) {
+__global__ void k_fields1_reduce(FGrid g, int S, const double *part, double *out, const Flags *gate) {
+    if (skip_pending(gate)) return;
     const int64_t nc = g.ncell;
     for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < nc;
          cell += (int64_t)gridDim.x * blockDim.x) {
@@ -305,9 +313,10 @@ __global__ void k_fields1_reduce(FGrid g, int S, const double *part, double *out
 // part1 by every block of the cell (block 0 also writes them to `out`), and
 // the slice's pass-2 sums go to part2[(cell S + b) kP2].
 __global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, const double *part1, double *part2,
-                                                 double *out) {
+                                                 double *out, const Flags *gate) {
     __shared__ double lds[kP2 * kFB];
     __shared__ CandLds sh;
+    if (skip_pending(gate)) return;
     const SysDesc sd = a.sys[g.sys];
     const int64_t n = a.n;
     const int64_t nc = g.ncell;
@@ -401,7 +410,8 @@ __global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, const 
     }
 }
 
-__global__ void k_fields2_reduce(FGrid g, int S, const double *part, double *out) {
+__global__ void k_fields2_reduce(FGrid g, int S, const double *part, double *out, const Flags *gate) {
+    if (skip_pending(gate)) return;
     const int64_t nc = g.ncell;
     const int ksym[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
     for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < nc;
@@ -418,7 +428,8 @@ __global__ void k_fields2_reduce(FGrid g, int S, const double *part, double *out
 // PI update per transition cell: e = n.sigma_coarse.n - n.sigma_fine.n,
 // integral += e interval, u = kp e + ki integral.
 __global__ void k_pi_cells(FGrid g, const double *fine, const double *coarse, double nx, double ny, double nz,
-                           double kp, double ki, double interval, double *integral, double *u) {
+                           double kp, double ki, double interval, double *integral, double *u, const Flags *gate) {
+    if (skip_pending(gate)) return;
     const int64_t nc = g.ncell;
     const double nn[3] = {nx, ny, nz};
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
@@ -439,7 +450,8 @@ __global__ void k_pi_cells(FGrid g, const double *fine, const double *coarse, do
 // inward normal in a transition cell (fade w over `fade` diameters below the
 // face), limited by the coarse cell's largest speed; zero elsewhere.
 __global__ void k_pi_particles(KArgs a, FGrid g, const double *coarse, const double *u, double nx, double ny,
-                               double nz, double face, double fade) {
+                               double nz, double face, double fade, const Flags *gate) {
+    if (skip_pending(gate)) return;
     const SysDesc &sd = a.sys[g.sys];
     const int64_t n = a.n;
     if (a.flags->err & kErrStale) return;   // fields from a stale list: forces left as they are
@@ -472,7 +484,9 @@ __global__ void k_pi_particles(KArgs a, FGrid g, const double *coarse, const dou
 
 // P controller force on every sphere of the coarse system: kp m (target - u_c)
 // in a cell where both levels hold mass, zero elsewhere.
-__global__ void k_p_particles(KArgs a, FGrid g, const double *fine, const double *coarse, double kp, int mass_flow) {
+__global__ void k_p_particles(KArgs a, FGrid g, const double *fine, const double *coarse, double kp, int mass_flow,
+                              const Flags *gate) {
+    if (skip_pending(gate)) return;
     const SysDesc &sd = a.sys[g.sys];
     const int64_t n = a.n, nc = g.ncell;
     if (a.flags->err & kErrStale) return;   // fields from a stale list: forces left as they are
@@ -496,6 +510,13 @@ __global__ void k_p_particles(KArgs a, FGrid g, const double *fine, const double
         a.fext_ws[n + i] = F[1];
         a.fext_ws[2 * n + i] = F[2];
     }
+}
+
+// sum += add over m values (the running sum of a fields array).
+__global__ void k_fields_add(double *sum, const double *add, int64_t m, const Flags *gate) {
+    if (skip_pending(gate)) return;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+        sum[k] += add[k];
 }
 
 int grid_blocks(int64_t work, int block) {
@@ -544,9 +565,54 @@ int enable_fext(dem_ctx *c, const KArgs &a) {
     return DEM_OK;
 }
 
+int pi_control(dem_ctx *c, const dem_state *s, const dem_pi_params *p, const double *fine, const double *coarse,
+               double *integral, double *u, const Flags *gate) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!p) return fail(c, DEM_ERR_ARG, "params is NULL");
+    FGrid g;
+    if ((rc = make_fgrid(c, &p->grid, g))) return rc;
+    if (!fine || !coarse || !integral || !u) return fail(c, DEM_ERR_ARG, "a fields or controller array is NULL");
+    const double nn = p->nrm[0] * p->nrm[0] + p->nrm[1] * p->nrm[1] + p->nrm[2] * p->nrm[2];
+    if (!(std::fabs(nn - 1.0) < 1e-12)) return fail(c, DEM_ERR_ARG, "nrm must be a unit vector");
+    if (!(p->fade >= 0.0) || !(p->interval >= 0.0) || !std::isfinite(p->kp) || !std::isfinite(p->ki) ||
+        !std::isfinite(p->face))
+        return fail(c, DEM_ERR_ARG, "need fade >= 0, interval >= 0 and finite gains and face");
+    KArgs a = kargs(c, s);
+    if ((rc = enable_fext(c, a))) return rc;
+    a = kargs(c, s);
+    k_pi_cells<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, fine, coarse, p->nrm[0], p->nrm[1], p->nrm[2],
+                                                                  p->kp, p->ki, p->interval, integral, u, gate);
+    const SysDesc &sd = c->geo.sys[g.sys];
+    k_pi_particles<<<grid_blocks(sd.pe - sd.p0, 256), 256, 0, c->stream>>>(a, g, coarse, u, p->nrm[0], p->nrm[1],
+                                                                          p->nrm[2], p->face, p->fade, gate);
+    HIPCALL(c, hipGetLastError());
+    return DEM_OK;
+}
+
+int p_control(dem_ctx *c, const dem_state *s, const dem_p_params *p, const double *fine, const double *coarse,
+              const Flags *gate) {
+    int rc = check_state(c, s);
+    if (rc) return rc;
+    if (!p) return fail(c, DEM_ERR_ARG, "params is NULL");
+    FGrid g;
+    if ((rc = make_fgrid(c, &p->grid, g))) return rc;
+    if (!fine || !coarse) return fail(c, DEM_ERR_ARG, "a fields array is NULL");
+    if (!std::isfinite(p->kp)) return fail(c, DEM_ERR_ARG, "kp must be finite");
+    KArgs a = kargs(c, s);
+    if ((rc = enable_fext(c, a))) return rc;
+    a = kargs(c, s);
+    const SysDesc &sd = c->geo.sys[g.sys];
+    k_p_particles<<<grid_blocks(sd.pe - sd.p0, 256), 256, 0, c->stream>>>(a, g, fine, coarse, p->kp,
+                                                                         p->mass_flow ? 1 : 0, gate);
+    HIPCALL(c, hipGetLastError());
+    return DEM_OK;
+}
+
 // Both field calls: pass 1 with the guard in the same launch; with `stress`
 // pass 2, which also completes pass 1 (S > 1), then the pass-2 slices.
-int cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double *fields, bool stress) {
+int cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double *fields, bool stress,
+                const Flags *gate = nullptr) {
     int rc = check_state(c, s);
     if (rc) return rc;
     FGrid g;
@@ -572,14 +638,64 @@ int cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double *fi
     double *part2 = part1 + (size_t)g.ncell * S * kP1;
     const int64_t blocks = g.ncell * S, guard = grid_blocks(sd.pe - sd.p0, 256);
     if (blocks + guard > INT32_MAX) return fail(c, DEM_ERR_ARG, "grid too large");
-    k_fields1<<<(int)(blocks + guard), kFB, 0, c->stream>>>(a, g, S, part1, fields);
+    k_fields1<<<(int)(blocks + guard), kFB, 0, c->stream>>>(a, g, S, part1, fields, gate);
     if (stress) {
-        k_fields2<<<(int)blocks, kFB, 0, c->stream>>>(a, g, S, part1, part2, fields);
-        if (S > 1) k_fields2_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part2, fields);
+        k_fields2<<<(int)blocks, kFB, 0, c->stream>>>(a, g, S, part1, part2, fields, gate);
+        if (S > 1) k_fields2_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part2, fields, gate);
     } else if (S > 1) {
-        k_fields1_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part1, fields);
+        k_fields1_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part1, fields, gate);
     }
     HIPCALL(c, hipGetLastError());
+    return DEM_OK;
+}
+
+// One interval's coupling calls of a plan, gated by the flag block.
+int couple(dem_ctx *c, const dem_state *s, const dem_coupling_plan *p, const dem_grid &pi_set, const dem_grid &p_tgt,
+           const Flags *gate) {
+    int rc;
+    if ((rc = cell_fields(c, s, &p->pi.grid, p->pi_fine, true, gate)) ||
+        (rc = cell_fields(c, s, &pi_set, p->pi_coarse, true, gate)) ||
+        (rc = pi_control(c, s, &p->pi, p->pi_fine, p->pi_coarse, p->integral, p->u, gate)) ||
+        (rc = cell_fields(c, s, &p_tgt, p->p_fine, false, gate)) ||
+        (rc = cell_fields(c, s, &p->p.grid, p->p_coarse, false, gate)) ||
+        (rc = p_control(c, s, &p->p, p->p_fine, p->p_coarse, gate)))
+        return rc;
+    if (p->sum) {
+        FGrid g;
+        if ((rc = make_fgrid(c, &p->sum_grid, g))) return rc;
+        if ((rc = cell_fields(c, s, &p->sum_grid, p->sum_tmp, false, gate))) return rc;
+        const int64_t m = (int64_t)DEM_F_STRESS * g.ncell;   // the rows without stress
+        k_fields_add<<<grid_blocks(m, 256), 256, 0, c->stream>>>(p->sum, p->sum_tmp, m, gate);
+        HIPCALL(c, hipGetLastError());
+    }
+    return DEM_OK;
+}
+
+// The plan's grids and parameters, checked once before anything is enqueued.
+int plan_ok(dem_ctx *c, const dem_coupling_plan *p, dem_grid &pi_set, dem_grid &p_tgt) {
+    if (p->interval_steps < 1 || p->group < 1) return fail(c, DEM_ERR_ARG, "need interval_steps >= 1 and group >= 1");
+    if (!p->pi_fine || !p->pi_coarse || !p->p_fine || !p->p_coarse || !p->integral || !p->u)
+        return fail(c, DEM_ERR_ARG, "a fields or controller array of the plan is NULL");
+    if (p->sum && !p->sum_tmp) return fail(c, DEM_ERR_ARG, "sum needs sum_tmp");
+    pi_set = p->pi.grid;
+    pi_set.sys = p->pi_setpoint_sys;
+    p_tgt = p->p.grid;
+    p_tgt.sys = p->p_target_sys;
+    FGrid g;
+    int rc;
+    if ((rc = make_fgrid(c, &p->pi.grid, g)) || (rc = make_fgrid(c, &pi_set, g)) ||
+        (rc = make_fgrid(c, &p->p.grid, g)) || (rc = make_fgrid(c, &p_tgt, g)) ||
+        (p->sum && (rc = make_fgrid(c, &p->sum_grid, g))))
+        return rc;
+    const dem_pi_params &q = p->pi;
+    const double nn = q.nrm[0] * q.nrm[0] + q.nrm[1] * q.nrm[1] + q.nrm[2] * q.nrm[2];
+    if (!(std::fabs(nn - 1.0) < 1e-12)) return fail(c, DEM_ERR_ARG, "nrm must be a unit vector");
+    if (!(q.fade >= 0.0) || !(q.interval >= 0.0) || !std::isfinite(q.kp) || !std::isfinite(q.ki) ||
+        !std::isfinite(q.face))
+        return fail(c, DEM_ERR_ARG, "need fade >= 0, interval >= 0 and finite gains and face");
+    if (!std::isfinite(p->p.kp)) return fail(c, DEM_ERR_ARG, "kp must be finite");
+    if (c->multirate && p->interval_steps % c->max_stride)
+        return fail(c, DEM_ERR_ARG, "multi-rate stepping needs interval_steps to be a multiple of the largest stride");
     return DEM_OK;
 }
 
@@ -597,44 +713,82 @@ int dem_cell_mass_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, d
 
 int dem_pi_control(dem_ctx *c, const dem_state *s, const dem_pi_params *p, const double *fine, const double *coarse,
                    double *integral, double *u) {
-    int rc = check_state(c, s);
-    if (rc) return rc;
-    if (!p) return fail(c, DEM_ERR_ARG, "params is NULL");
-    FGrid g;
-    if ((rc = make_fgrid(c, &p->grid, g))) return rc;
-    if (!fine || !coarse || !integral || !u) return fail(c, DEM_ERR_ARG, "a fields or controller array is NULL");
-    const double nn = p->nrm[0] * p->nrm[0] + p->nrm[1] * p->nrm[1] + p->nrm[2] * p->nrm[2];
-    if (!(std::fabs(nn - 1.0) < 1e-12)) return fail(c, DEM_ERR_ARG, "nrm must be a unit vector");
-    if (!(p->fade >= 0.0) || !(p->interval >= 0.0) || !std::isfinite(p->kp) || !std::isfinite(p->ki) ||
-        !std::isfinite(p->face))
-        return fail(c, DEM_ERR_ARG, "need fade >= 0, interval >= 0 and finite gains and face");
-    KArgs a = kargs(c, s);
-    if ((rc = enable_fext(c, a))) return rc;
-    a = kargs(c, s);
-    k_pi_cells<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, fine, coarse, p->nrm[0], p->nrm[1], p->nrm[2],
-                                                                  p->kp, p->ki, p->interval, integral, u);
-    const SysDesc &sd = c->geo.sys[g.sys];
-    k_pi_particles<<<grid_blocks(sd.pe - sd.p0, 256), 256, 0, c->stream>>>(a, g, coarse, u, p->nrm[0], p->nrm[1],
-                                                                          p->nrm[2], p->face, p->fade);
-    HIPCALL(c, hipGetLastError());
-    return DEM_OK;
+    return pi_control(c, s, p, fine, coarse, integral, u, nullptr);
 }
 
 int dem_p_control(dem_ctx *c, const dem_state *s, const dem_p_params *p, const double *fine, const double *coarse) {
+    return p_control(c, s, p, fine, coarse, nullptr);
+}
+
+int dem_step_coupled(dem_ctx *c, const dem_state *s, int64_t nintervals, const dem_coupling_plan *plan) {
     int rc = check_state(c, s);
     if (rc) return rc;
-    if (!p) return fail(c, DEM_ERR_ARG, "params is NULL");
-    FGrid g;
-    if ((rc = make_fgrid(c, &p->grid, g))) return rc;
-    if (!fine || !coarse) return fail(c, DEM_ERR_ARG, "a fields array is NULL");
-    if (!std::isfinite(p->kp)) return fail(c, DEM_ERR_ARG, "kp must be finite");
-    KArgs a = kargs(c, s);
-    if ((rc = enable_fext(c, a))) return rc;
-    a = kargs(c, s);
-    const SysDesc &sd = c->geo.sys[g.sys];
-    k_p_particles<<<grid_blocks(sd.pe - sd.p0, 256), 256, 0, c->stream>>>(a, g, fine, coarse, p->kp,
-                                                                         p->mass_flow ? 1 : 0);
-    HIPCALL(c, hipGetLastError());
+    if (!plan) return fail(c, DEM_ERR_ARG, "plan is NULL");
+    if (nintervals < 0) return fail(c, DEM_ERR_ARG, "nintervals < 0");
+    dem_grid pi_set, p_tgt;
+    if ((rc = plan_ok(c, plan, pi_set, p_tgt))) return rc;
+    if (!c->masses) return fail(c, DEM_ERR_STATE, "dem_reset first");
+    if (!c->forces_valid)
+        return fail(c, DEM_ERR_STATE,
+                    "dem_step_coupled needs the forces of the current state: call dem_forces(ctx, s, 0) or "
+                    "dem_declare_forces");
+    if (nintervals == 0 || c->geo.n == 0) return DEM_OK;
+    if (!c->list_current)
+        if ((rc = do_bin(c, s, true)) || (rc = do_neighbors(c, s))) return rc;
+    {
+        KArgs a = kargs(c, s);
+        if ((rc = enable_fext(c, a))) return rc;
+    }
+    const int64_t I = plan->interval_steps;
+    const Flags *gate = c->d_flags;
+    const int cnt = c->count ? 1 : 0;
+    Flags h;
+    int64_t done = 0;
+    while (done < nintervals) {
+        // a group of intervals, enqueued together; steps numbered from base + 1
+        const int64_t G = std::min<int64_t>(plan->group, nintervals - done);
+        const int64_t base = c->step_counter;
+        HIPCALL(c, launch_ctrl(c->d_flags, 0, base + 1, c->stream));
+        for (int64_t j = 0; j < G; ++j) {
+            if ((rc = couple(c, s, plan, pi_set, p_tgt, gate))) return rc;
+            const KArgs a = kargs(c, s);
+            if (c->multirate) {
+                HIPCALL(c, launch_ctrl(c->d_flags, 5, base + I * j, c->stream));
+                HIPCALL(c, launch_ctrl(c->d_flags, 6, base + I * (j + 1), c->stream));
+            }
+            HIPCALL(c, launch_pack(a, 0, 1, (int)(I * j), 1, c->stream));
+            for (int64_t q = 1; q <= I; ++q) {
+                KArgs al = a;
+                if (q == I) al.call_steps = I;
+                HIPCALL(c, launch_step(al, (int)((q - 1) & 1), q == I ? 2 : 1, (int)(I * j + q - 1), 1, cnt,
+                                       c->stream));
+            }
+        }
+        if ((rc = read_flags(c, h)) || (rc = collect_times(c)) || (rc = flag_error(c, h))) return rc;
+        if (h.abort_at == INT64_MAX) {
+            note_steps(c, G * I);
+            c->step_counter = base + G * I;
+            done += G;
+            continue;
+        }
+        // the drift into step qa of interval jr asked for a new list; every
+        // later kernel of the group did nothing: rebuild, finish interval jr
+        // as dem_step would, and issue the rest again
+        const int64_t qg = h.abort_at - base;
+        const int64_t jr = (qg - 1) / I, qa = qg - jr * I, bj = base + jr * I;
+        if ((rc = rebuild_at(c, s, qa))) return rc;
+        note_rebuild(c, qg - 1);
+        HIPCALL(c, launch_ctrl(c->d_flags, 0, bj + qa, c->stream));
+        if (c->multirate) {
+            HIPCALL(c, launch_ctrl(c->d_flags, 5, bj, c->stream));
+            HIPCALL(c, launch_ctrl(c->d_flags, 6, bj + I, c->stream));
+        }
+        if ((rc = step_loop(c, s, I, bj, qa, h)) || (rc = collect_times(c)) || (rc = flag_error(c, h))) return rc;
+        c->step_counter = bj + I;
+        done += jr + 1;
+    }
+    c->binned = false;
+    c->forces_valid = true;
     return DEM_OK;
 }
 

@@ -111,6 +111,12 @@ int do_bin(dem_ctx *c, const dem_state *s, bool all);
 int do_neighbors(dem_ctx *c, const dem_state *s, bool clear_sel = true);
 // The current list buffer of system sy (reads the device's choice; synchronises).
 int live_list(dem_ctx *c, int sy, List &out);
+// Stepping pieces shared by dem_step and dem_step_coupled (dem_api.hip).
+int rebuild_at(dem_ctx *c, const dem_state *s, int64_t qa);
+int step_loop(dem_ctx *c, const dem_state *s, int64_t nsteps, int64_t base, int64_t q, Flags &h);
+int collect_times(dem_ctx *c);
+void note_rebuild(dem_ctx *c, int64_t ran);
+void note_steps(dem_ctx *c, int64_t ran);
 // E > 0, -1 < nu < 0.5, rho > 0, 0 < e <= 1, mu >= 0, all finite.
 bool material_ok(const dem_material &m);
 // Folded Eq. (6) coefficients of a pair of materials.

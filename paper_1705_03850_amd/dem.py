@@ -79,6 +79,16 @@ class PParams(ctypes.Structure):
     _fields_ = [("grid", Grid), ("kp", ctypes.c_double), ("mass_flow", ctypes.c_int32)]
 
 
+class CouplingPlan(ctypes.Structure):
+    """dem_coupling_plan: one coupling interval (fields, PI and P controllers,
+    an optional running sum of fields) repeated by dem_step_coupled."""
+    _fields_ = [("pi", PIParams), ("pi_setpoint_sys", ctypes.c_int32), ("p_target_sys", ctypes.c_int32),
+                ("p", PParams), ("pi_fine", ctypes.c_void_p), ("pi_coarse", ctypes.c_void_p),
+                ("p_fine", ctypes.c_void_p), ("p_coarse", ctypes.c_void_p), ("integral", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("sum_grid", Grid), ("sum", ctypes.c_void_p), ("sum_tmp", ctypes.c_void_p),
+                ("interval_steps", ctypes.c_int64), ("group", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class ExchangeParams(ctypes.Structure):
     """dem_exchange_params: boundary face (region x . nrm >= face), inflow slab
     and interval, number of boundary cells, an optional outlet half-space
@@ -109,7 +119,7 @@ _SYMBOLS = ["dem_workspace_size", "dem_batch_workspace_size", "dem_init", "dem_b
             "dem_rollout_forward", "dem_rollout_backward", "dem_forces_vjp", "dem_integrate_vjp", "dem_adjoint_set_lanes", "dem_adjoint_info",
             "dem_adjoint_destroy", "dem_cell_fields", "dem_cell_mass_fields", "dem_pi_control", "dem_p_control", "dem_set_external_force",
             "dem_set_multirate", "dem_exchange", "dem_live_count", "dem_set_surfaces", "dem_export_surface_history",
-            "dem_import_surface_history"]
+            "dem_import_surface_history", "dem_step_coupled"]
 
 
 def load(path: str = LIB_PATH):
@@ -173,6 +183,7 @@ def load(path: str = LIB_PATH):
     L.dem_live_count.argtypes = [vp, i32, P(i64)]
     L.dem_set_surfaces.argtypes = [vp, i32, i32, P(Surface)]
     L.dem_export_surface_history.argtypes = [vp, P(State), vp, vp, vp, i64, P(i64)]
+    L.dem_step_coupled.argtypes = [vp, P(State), i64, P(CouplingPlan)]
     L.dem_import_surface_history.argtypes = [vp, P(State), i64, vp, vp, vp]
     for name in _SYMBOLS:
         if name != "dem_last_error":
@@ -562,6 +573,36 @@ class DemSystem:
         fine, coarse = fine.contiguous(), coarse.contiguous()
         self._enter(fine, coarse)
         self._rc(self.L.dem_p_control(self.ctx, self._state, ctypes.byref(params), _ptr(fine), _ptr(coarse)))
+        self._leave()
+
+    def coupling_plan(self, pi: PIParams, pi_setpoint_sys: int, p: PParams, p_target_sys: int, interval_steps: int,
+                      group: int = 4, integral=None, sum_grid: Grid | None = None):
+        """A dem_coupling_plan with its device buffers (kept on the returned
+        object: pi_fine, pi_coarse, p_fine, p_coarse, integral, u, and with
+        sum_grid the running sum `sum` and its scratch)."""
+        t = self.torch
+        f64 = dict(dtype=t.float64, device=self.device)
+        cells = lambda g: g.n[0] * g.n[1] * g.n[2]  # noqa: E731
+        plan = CouplingPlan()
+        plan.pi, plan.pi_setpoint_sys, plan.p, plan.p_target_sys = pi, int(pi_setpoint_sys), p, int(p_target_sys)
+        plan.interval_steps, plan.group = int(interval_steps), int(group)
+        bufs = {"pi_fine": t.zeros((NFIELDS, cells(pi.grid)), **f64), "pi_coarse": t.zeros((NFIELDS, cells(pi.grid)), **f64),
+                "p_fine": t.zeros((NFIELDS, cells(p.grid)), **f64), "p_coarse": t.zeros((NFIELDS, cells(p.grid)), **f64),
+                "integral": t.zeros(cells(pi.grid), **f64) if integral is None else integral,
+                "u": t.zeros(cells(pi.grid), **f64)}
+        if sum_grid is not None:
+            plan.sum_grid = sum_grid
+            bufs["sum"] = t.zeros((NFIELDS, cells(sum_grid)), **f64)
+            bufs["sum_tmp"] = t.zeros((NFIELDS, cells(sum_grid)), **f64)
+        for k, v in bufs.items():
+            setattr(plan, k, v.data_ptr())
+        plan.buffers = bufs
+        return plan
+
+    def step_coupled(self, nintervals: int, plan: CouplingPlan):
+        """nintervals coupling intervals (dem_step_coupled)."""
+        self._enter(*plan.buffers.values())
+        self._rc(self.L.dem_step_coupled(self.ctx, self._state, int(nintervals), ctypes.byref(plan)))
         self._leave()
 
     def set_external_force(self, fext=None):

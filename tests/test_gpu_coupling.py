@@ -378,6 +378,59 @@ def test_coupling_interval_replayed_as_a_graph():
     assert eager.stats()["builds"] == replayed.stats()["builds"]
 
 
+@pytest.mark.parametrize("multirate", [False, True])
+def test_step_coupled_equals_the_calls(multirate):
+    """dem_step_coupled (three intervals per synchronisation) against the
+    same calls made one by one, on twin contexts: with a small skin the list
+    is rebuilt inside intervals and groups, so intervals are interrupted and
+    issued again; states, PI state, fields and the running sum bit for bit.
+    Multi-rate: the coarse level at 2 dt, 16 substeps per interval."""
+    d = dem()
+    coarse, fine = (s.copy() for s in two_level())
+    rng = np.random.default_rng(17)
+    for s in (coarse, fine):                       # moving spheres: rebuilds every 20 steps or so
+        s.v = rng.normal(0.0, 0.05, (s.n, 3))
+    if multirate:
+        coarse.dt = 2 * fine.dt
+    interval = 16 if multirate else 15
+    skin = [2e-6, 2e-6]
+    twins = [d.DemSystem([coarse, fine], skin=skin, use_graph=True, chunk=16) for _ in range(2)]
+    for g in twins:
+        if multirate:
+            g.set_multirate(True)
+        g.prime()
+    pi, pp = pi_params(1, interval * fine.dt), p_params(0, True)
+    sum_spec = ((0.0, 0.0, 0.10), (0.02, 0.02, 0.01), (2, 1, 1))
+    plans = [g.coupling_plan(pi, 0, pp, 1, interval, group=3, sum_grid=grid(sum_spec, 0)) for g in twins]
+    eager, coupled = twins
+    b = plans[0].buffers
+    pf, pc = grid(P_GRID, 1), grid(P_GRID, 0)
+    nint = 7
+    for _ in range(nint):
+        eager.pi_control(pi, eager.cell_fields(grid(PI_GRID, 1), out=b["pi_fine"]),
+                         eager.cell_fields(grid(PI_GRID, 0), out=b["pi_coarse"]), b["integral"], b["u"])
+        eager.p_control(pp, eager.cell_fields(pf, stress=False, out=b["p_fine"]),
+                        eager.cell_fields(pc, stress=False, out=b["p_coarse"]))
+        b["sum"][:d.F_STRESS] += eager.cell_fields(grid(sum_spec, 0), stress=False, out=b["sum_tmp"])[:d.F_STRESS]
+        eager.step(interval)
+    coupled.step_coupled(nint, plans[1])
+    torch.cuda.synchronize()
+    builds = [g.stats()["builds"] for g in twins]
+    assert builds[0] == builds[1] and builds[0] >= 3, builds
+    for key in ("integral", "u", "pi_fine", "pi_coarse", "sum"):
+        assert torch.equal(plans[0].buffers[key], plans[1].buffers[key]), key
+    for key in ("p_fine", "p_coarse"):
+        assert torch.equal(plans[0].buffers[key][:d.F_STRESS], plans[1].buffers[key][:d.F_STRESS]), key
+    for k in range(2):
+        h0, h1 = eager.host(k), coupled.host(k)
+        for key in ("x", "v", "w", "f", "t", "id"):
+            assert np.array_equal(h0[key], h1[key]), (k, key)
+    # and both continue alike
+    eager.step(interval)
+    coupled.step(interval)
+    assert np.array_equal(eager.host()["x"], coupled.host()["x"])
+
+
 def test_coupling_errors():
     d = dem()
     s = W.plain_fcc()

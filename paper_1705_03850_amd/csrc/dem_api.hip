@@ -1340,6 +1340,7 @@ int dem_destroy(dem_ctx *c) {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (GraphSlot &g : c->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (c->cpl_exec) (void)hipGraphExecDestroy(c->cpl_exec);
     if (c->h_flags) {
         (void)hipStreamSynchronize(c->stream);
         (void)hipHostFree(c->h_flags);

@@ -699,6 +699,66 @@ int plan_ok(dem_ctx *c, const dem_coupling_plan *p, dem_grid &pi_set, dem_grid &
     return DEM_OK;
 }
 
+// The kernels of one coupled interval, in stream order: the coupling, the
+// first kick and drift from the caller's arrays, the interval's steps (the
+// last writes the caller's arrays), then the step base advanced by the
+// interval, so that the same sequence serves every interval of a group.
+int enqueue_interval(dem_ctx *c, const dem_state *s, const dem_coupling_plan *p, const dem_grid &pi_set,
+                     const dem_grid &p_tgt) {
+    int rc;
+    const Flags *gate = c->d_flags;
+    if ((rc = couple(c, s, p, pi_set, p_tgt, gate))) return rc;
+    const KArgs a = kargs(c, s);
+    const int64_t I = p->interval_steps;
+    HIPCALL(c, launch_pack(a, 0, 1, 0, 1, c->stream));
+    for (int64_t q = 1; q <= I; ++q) {
+        KArgs al = a;
+        if (q == I) al.call_steps = I;
+        HIPCALL(c, launch_step(al, (int)((q - 1) & 1), q == I ? 2 : 1, (int)(q - 1), 1, c->count ? 1 : 0,
+                               c->stream));
+    }
+    HIPCALL(c, launch_ctrl(c->d_flags, 1, I, c->stream));
+    return DEM_OK;
+}
+
+// The interval as one graph, captured again when the plan or the context's
+// stepping options changed.  Everything that changes between intervals
+// (positions, lists, live counts, tiles, surfaces) is read from the device.
+int interval_graph(dem_ctx *c, const dem_state *s, const dem_coupling_plan *p, const dem_grid &pi_set,
+                   const dem_grid &p_tgt) {
+    std::vector<char> key(sizeof(dem_coupling_plan) + sizeof(dem_state) + 4 * sizeof(void *));
+    char *k = key.data();
+    memcpy(k, p, sizeof(dem_coupling_plan));
+    k += sizeof(dem_coupling_plan);
+    memcpy(k, s, sizeof(dem_state));
+    k += sizeof(dem_state);
+    const void *more[4] = {c->ws, c->fext_on ? (const void *)c->lay.fext : nullptr,
+                           (const void *)(intptr_t)(c->multirate ? 1 : 0), (const void *)(intptr_t)(c->count ? 1 : 0)};
+    memcpy(k, more, sizeof more);
+    if (c->cpl_exec && key == c->cpl_key) return DEM_OK;
+    if (c->cpl_exec) {
+        (void)hipGraphExecDestroy(c->cpl_exec);
+        c->cpl_exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    HIPCALL(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_interval(c, s, p, pi_set, p_tgt);
+    const hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+    const hipError_t e3 = hipGraphInstantiate(&c->cpl_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+        c->cpl_exec = nullptr;
+        return hip_fail(c, e3, "hipGraphInstantiate");
+    }
+    c->cpl_key = key;
+    return DEM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -740,29 +800,21 @@ int dem_step_coupled(dem_ctx *c, const dem_state *s, int64_t nintervals, const d
         if ((rc = enable_fext(c, a))) return rc;
     }
     const int64_t I = plan->interval_steps;
-    const Flags *gate = c->d_flags;
-    const int cnt = c->count ? 1 : 0;
     Flags h;
     int64_t done = 0;
     while (done < nintervals) {
         // a group of intervals, enqueued together; steps numbered from base + 1
         const int64_t G = std::min<int64_t>(plan->group, nintervals - done);
         const int64_t base = c->step_counter;
+        if (c->use_graph && !c->timing && (rc = interval_graph(c, s, plan, pi_set, p_tgt))) return rc;
         HIPCALL(c, launch_ctrl(c->d_flags, 0, base + 1, c->stream));
         for (int64_t j = 0; j < G; ++j) {
-            if ((rc = couple(c, s, plan, pi_set, p_tgt, gate))) return rc;
-            const KArgs a = kargs(c, s);
             if (c->multirate) {
                 HIPCALL(c, launch_ctrl(c->d_flags, 5, base + I * j, c->stream));
                 HIPCALL(c, launch_ctrl(c->d_flags, 6, base + I * (j + 1), c->stream));
             }
-            HIPCALL(c, launch_pack(a, 0, 1, (int)(I * j), 1, c->stream));
-            for (int64_t q = 1; q <= I; ++q) {
-                KArgs al = a;
-                if (q == I) al.call_steps = I;
-                HIPCALL(c, launch_step(al, (int)((q - 1) & 1), q == I ? 2 : 1, (int)(I * j + q - 1), 1, cnt,
-                                       c->stream));
-            }
+            if (c->use_graph && !c->timing) HIPCALL(c, hipGraphLaunch(c->cpl_exec, c->stream));
+            else if ((rc = enqueue_interval(c, s, plan, pi_set, p_tgt))) return rc;
         }
         if ((rc = read_flags(c, h)) || (rc = collect_times(c)) || (rc = flag_error(c, h))) return rc;
         if (h.abort_at == INT64_MAX) {

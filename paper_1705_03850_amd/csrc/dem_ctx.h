@@ -77,6 +77,8 @@ struct dem_ctx {
     int cus = 256;
     int64_t ntiles_b = 0;            // tiles of the batch step (each within one system)
     dem::host::GraphSlot graphs[8];          // replay graphs of 2^(k+3) fused steps
+    hipGraphExec_t cpl_exec = nullptr;       // one coupled interval (dem_step_coupled)
+    std::vector<char> cpl_key;               // what it was captured for
     double gap_avg = 1e9;         // running estimate of steps between rebuilds
     int64_t since_rebuild = 0;
     // per-kernel timing with HIP events (non-graph stepping only)

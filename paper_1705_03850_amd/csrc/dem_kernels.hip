@@ -933,39 +933,53 @@ __device__ __forceinline__ void step_particle(const KArgs &a, const SysDesc &s, 
                 }
             }
         }
-        // the system's static surfaces, in table order (every lane computes them;
-        // lane 0 stores)
+        // the system's static surfaces: lane g of the group takes surfaces g, g + G,
+        // ..., stores its own histories, and the contributions are added in table
+        // order as the neighbour chunks are
         if (SURF && s.nsurf > 0) {
             const uint32_t sm = a.smask[i];
             uint32_t nsm = 0;
-            for (int k = 0; k < s.nsurf; ++k) {
-                const Surf w = a.surf[s.surf0 + k];
+            for (int k0 = 0; k0 < s.nsurf; k0 += G) {   // (uniform over the block)
+                const int k = k0 + g;
+                double fx = 0.0, fy = 0.0, fz = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
+                bool hit = false;
                 double dist, wnx, wny, wnz;
-                if (!w.enabled || !surf_gap(w, pi.x, pi.y, pi.z, ri, dist, wnx, wny, wnz)) continue;
-                PairCoef pc = coef[ti * s.ntypes + ti];
-                if (w.mu >= 0.0) pc.mu = w.mu;
-                ContactIn c;
-                c.dx = 0.0; c.dy = 0.0; c.dz = dist;
-                c.ra = ri; c.rb = 0.0; c.ma = mi; c.mb = 0.0;
-                c.vrx = vi.x; c.vry = vi.y; c.vrz = vi.z;
-                c.wsx = ri * si.x; c.wsy = ri * si.y; c.wsz = ri * si.z;
-                double hx = 0.0, hy = 0.0, hz = 0.0;
-                if ((sm >> k) & 1u) {
-                    const D4 h = a.sxi[k * n + i];
-                    hx = h.x; hy = h.y; hz = h.z;
-                }
-                double fx, fy, fz, ftx, fty, ftz, nx, ny, nz, fn;
-                if (contact_force_n(c, true, wnx, wny, wnz, pc, s.dt, update != 0, hx, hy, hz, fx, fy, fz, ftx, fty,
-                                    ftz, nx, ny, nz, fn)) {
-                    if (COUNT && g == 0) ++nwall;
-                    Fx = Fx + fx; Fy = Fy + fy; Fz = Fz + fz;
-                    Tx = Tx + -(ri * (ny * ftz - nz * fty));
-                    Ty = Ty + -(ri * (nz * ftx - nx * ftz));
-                    Tz = Tz + -(ri * (nx * fty - ny * ftx));
-                    if (update) {
-                        if (g == 0) a.sxi[k * n + i] = D4{hx, hy, hz, 0.0};
-                        nsm |= 1u << k;
+                const Surf *w = a.surf + s.surf0 + (k < s.nsurf ? k : 0);
+                if (k < s.nsurf && w->enabled && surf_gap(*w, pi.x, pi.y, pi.z, ri, dist, wnx, wny, wnz)) {
+                    PairCoef pc = coef[ti * s.ntypes + ti];
+                    if (w->mu >= 0.0) pc.mu = w->mu;
+                    ContactIn c;
+                    c.dx = 0.0; c.dy = 0.0; c.dz = dist;
+                    c.ra = ri; c.rb = 0.0; c.ma = mi; c.mb = 0.0;
+                    c.vrx = vi.x; c.vry = vi.y; c.vrz = vi.z;
+                    c.wsx = ri * si.x; c.wsy = ri * si.y; c.wsz = ri * si.z;
+                    double hx = 0.0, hy = 0.0, hz = 0.0;
+                    if ((sm >> k) & 1u) {
+                        const D4 h = a.sxi[k * n + i];
+                        hx = h.x; hy = h.y; hz = h.z;
                     }
+                    double ftx, fty, ftz, nx, ny, nz, fn;
+                    if (contact_force_n(c, true, wnx, wny, wnz, pc, s.dt, update != 0, hx, hy, hz, fx, fy, fz, ftx,
+                                        fty, ftz, nx, ny, nz, fn)) {
+                        if (COUNT) ++nwall;
+                        hit = true;
+                        tx = -(ri * (ny * ftz - nz * fty));
+                        ty = -(ri * (nz * ftx - nx * ftz));
+                        tz = -(ri * (nx * fty - ny * ftx));
+                        if (update) a.sxi[k * n + i] = D4{hx, hy, hz, 0.0};
+                    }
+                }
+                uint64_t b = (__ballot(hit) >> gbase) & gmask;
+                if (update) nsm |= (uint32_t)b << k0;
+                while (b) {
+                    const int src_lane = gbase + __builtin_ctzll(b);
+                    b &= b - 1;
+                    Fx = Fx + __shfl(fx, src_lane);
+                    Fy = Fy + __shfl(fy, src_lane);
+                    Fz = Fz + __shfl(fz, src_lane);
+                    Tx = Tx + __shfl(tx, src_lane);
+                    Ty = Ty + __shfl(ty, src_lane);
+                    Tz = Tz + __shfl(tz, src_lane);
                 }
             }
             if (update && g == 0 && nsm != sm) a.smask[i] = nsm;

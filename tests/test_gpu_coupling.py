@@ -460,3 +460,59 @@ def test_coupling_errors():
     with pytest.raises(d.DemError) as e:
         adj.forward()
     assert e.value.code == d.DEM_ERR_STATE
+
+
+def test_step_coupled_errors():
+    """dem_step_coupled refuses a plan it cannot run, before enqueuing any
+    work: the state is left as it was; zero intervals do nothing; a valid
+    plan then runs on the same context."""
+    d = dem()
+    coarse, fine = two_level()
+    interval = 15
+    pi, pp = pi_params(1, interval * fine.dt), p_params(0, True)
+    g = d.DemSystem([coarse, fine], use_graph=True, chunk=16)
+    g.build_list()
+    plan = g.coupling_plan(pi, 0, pp, 1, interval, group=2)
+    with pytest.raises(d.DemError) as e:
+        g.step_coupled(1, plan)                  # no forces of the current state yet
+    assert e.value.code == d.DEM_ERR_STATE
+    g.forces(False)
+    before = g.host()
+
+    def refused(plan, nint=1):
+        with pytest.raises(d.DemError) as e:
+            g.step_coupled(nint, plan)
+        return e.value.code
+
+    assert refused(plan, -1) == d.DEM_ERR_ARG
+    for field in ("interval_steps", "group", "u", "pi_fine"):
+        bad = g.coupling_plan(pi, 0, pp, 1, interval)
+        setattr(bad, field, 0 if field in ("interval_steps", "group") else None)
+        assert refused(bad) == d.DEM_ERR_ARG, field
+    bad = g.coupling_plan(pi, 0, pp, 1, interval, sum_grid=grid(PI_GRID, 0))
+    bad.sum_tmp = None
+    assert refused(bad) == d.DEM_ERR_ARG
+    bad = g.coupling_plan(pi, 0, pp, 1, interval)
+    bad.pi.nrm[2] = -0.5                         # not a unit vector
+    assert refused(bad) == d.DEM_ERR_ARG
+    bad = g.coupling_plan(pi, 0, pp, 1, interval)
+    bad.pi_setpoint_sys = 2                      # no such system
+    assert refused(bad) == d.DEM_ERR_ARG
+    g.step_coupled(0, plan)
+    after = g.host()
+    for key in ("x", "v", "w", "f", "t"):
+        assert np.array_equal(before[key], after[key]), key
+    assert g.stats()["steps"] == 0
+    g.step_coupled(3, plan)
+    assert g.stats()["steps"] == 3 * interval
+    # multi-rate: the interval must be a whole number of the coarse level's steps
+    c2 = coarse.copy()
+    c2.dt = 2 * fine.dt
+    m = d.DemSystem([c2, fine], use_graph=True, chunk=16)
+    m.set_multirate(True)
+    m.prime()
+    with pytest.raises(d.DemError) as e:
+        m.step_coupled(1, m.coupling_plan(pi, 0, pp, 1, interval))
+    assert e.value.code == d.DEM_ERR_ARG
+    m.step_coupled(1, m.coupling_plan(pi, 0, pp, 1, 2 * 8))
+    assert m.stats()["steps"] == 16

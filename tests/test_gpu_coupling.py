@@ -378,13 +378,14 @@ def test_coupling_interval_replayed_as_a_graph():
     assert eager.stats()["builds"] == replayed.stats()["builds"]
 
 
-@pytest.mark.parametrize("multirate", [False, True])
-def test_step_coupled_equals_the_calls(multirate):
+@pytest.mark.parametrize("multirate,graph", [(False, True), (True, True), (False, False)])
+def test_step_coupled_equals_the_calls(multirate, graph):
     """dem_step_coupled (three intervals per synchronisation) against the
     same calls made one by one, on twin contexts: with a small skin the list
     is rebuilt inside intervals and groups, so intervals are interrupted and
     issued again; states, PI state, fields and the running sum bit for bit.
-    Multi-rate: the coarse level at 2 dt, 16 substeps per interval."""
+    Multi-rate: the coarse level at 2 dt, 16 substeps per interval.  Without
+    graphs the coupled context enqueues each interval kernel by kernel."""
     d = dem()
     coarse, fine = (s.copy() for s in two_level())
     rng = np.random.default_rng(17)
@@ -394,7 +395,7 @@ def test_step_coupled_equals_the_calls(multirate):
         coarse.dt = 2 * fine.dt
     interval = 16 if multirate else 15
     skin = [2e-6, 2e-6]
-    twins = [d.DemSystem([coarse, fine], skin=skin, use_graph=True, chunk=16) for _ in range(2)]
+    twins = [d.DemSystem([coarse, fine], skin=skin, use_graph=use, chunk=16) for use in (True, graph)]
     for g in twins:
         if multirate:
             g.set_multirate(True)

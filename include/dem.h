@@ -470,12 +470,13 @@ typedef struct dem_surface {
 int dem_set_surfaces(dem_ctx *ctx, int32_t sys, int32_t count, const dem_surface *surf);
 
 /* Surface contact history, for checking and for resuming a run (synchronise;
- * host arrays).  Export: every live sphere's non-zero tangential history
- * with a surface of its system, as (id, surface index k < count of its
- * system, xi [3]) sorted by (id, k); *count receives the total even when it
- * exceeds cap.  Import: replaces every sphere's surface history with the
- * given records (the others zero); an id that is not live or an index beyond
- * its system's surfaces is DEM_ERR_ARG. */
+ * host arrays).  Export: the tangential history that every live sphere
+ * stored with a surface of its system (its surface contacts of the last
+ * force evaluation), as (id, surface index k < count of its system, xi [3])
+ * sorted by (id, k); *count receives the total even when it exceeds cap.
+ * Import: replaces every sphere's surface history with the given records
+ * (the others zero; a record of zeros is the same as none); an id that is
+ * not live or an index beyond its system's surfaces is DEM_ERR_ARG. */
 int dem_export_surface_history(dem_ctx *ctx, const dem_state *s, int32_t *id, int32_t *surf, double *xi, int64_t cap,
                                int64_t *count);
 int dem_import_surface_history(dem_ctx *ctx, const dem_state *s, int64_t count, const int32_t *id,

@@ -322,7 +322,8 @@ class DemSystem:
         self.surfaces[int(sys)] = [tuple(r) for r in records]
 
     def export_surface_history(self):
-        """(id, surface index, xi (k, 3)) of every non-zero surface history."""
+        """(id, surface index, xi (k, 3)) of every stored surface history (the
+        surface contacts of the last force evaluation)."""
         cnt = ctypes.c_int64()
         self._rc(self.L.dem_export_surface_history(self.ctx, self._state, None, None, None, 0, ctypes.byref(cnt)))
         a = np.empty(cnt.value, np.int32); k = np.empty(cnt.value, np.int32); xi = np.empty((cnt.value, 3))

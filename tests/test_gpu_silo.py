@@ -9,6 +9,7 @@ over the orifice, the orifice's rim) on the GPU against the oracle.
     forces within 1e-12 of the largest;
   * a silo and its coarse-grain twin (alpha = 2, dt = 2e-6 s) as one batch,
     single-rate and multi-rate, bit for bit equal to each system alone;
+  * 4, 8 and 16 lanes per sphere bit for bit alike;
   * the outlet of an insertion event removes what has left through the
     orifice.
 """
@@ -81,6 +82,31 @@ def test_silo_against_oracle_closed_then_open():
     assert np.max(np.abs(xi - oxi[order])) <= 1e-9 * edge, np.max(np.abs(xi - oxi[order]))
     st = g.stats()
     assert st["wall_contacts"] > 0
+
+
+@pytest.mark.parametrize("lanes", [8, 16])
+def test_silo_lanes_do_not_change_results(lanes):
+    """A sphere's surface terms are dealt to its lanes (lane g takes surface
+    g) and added in table order, so 4, 8 or 16 lanes give the same silo bit
+    for bit, orifice closed and then open: states, surface histories and the
+    count of surface contacts."""
+    s = small_silo(seed=13)
+    surf = s.meta["surfaces"]
+    opened = W.silo_surfaces(scale=0.1, open_orifice=True)
+    out = []
+    for ln in (4, lanes):
+        g = dem().DemSystem(s, surfaces=surf, lanes=ln, use_graph=True, chunk=16)
+        g.prime()
+        g.step(150)
+        g.set_surfaces(0, opened)
+        g.step(150)
+        out.append((g.host(), g.export_surface_history(), g.stats()["wall_contacts"]))
+    (h0, e0, c0), (h1, e1, c1) = out
+    for key in ("x", "v", "w", "f", "t"):
+        assert np.array_equal(h0[key], h1[key]), key
+    for a, b in zip(e0, e1):
+        assert np.array_equal(a, b)
+    assert len(e0[0]) >= 10 and c0 == c1 > 0
 
 
 def test_silo_batch_bitwise_and_multirate():

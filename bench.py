@@ -155,6 +155,39 @@ def timed_steps(g, steps, warm):
     return time.perf_counter() - t0
 
 
+def chute_controllers(g, cpl):
+    """PI parameters on the fine level's transition layer and P parameters on
+    the coarse spheres inside the fine region, for the two-level chute."""
+    from paper_1705_03850_amd import dem
+
+    pp = dem.PIParams()
+    pp.grid = dem.make_grid(*cpl["pi_grid"], sys=1)
+    for a in range(3):
+        pp.nrm[a] = cpl["normal"][a]
+    pp.face, pp.kp, pp.ki, pp.fade = cpl["face"], cpl["kp"], cpl["ki"], cpl["fade"]
+    pp.interval = cpl["interval_steps"] * g.systems[1].dt
+    qp = dem.PParams()
+    qp.grid, qp.kp, qp.mass_flow = dem.make_grid(*cpl["p_grid"], sys=0), cpl["kp_coarse"], 1
+    return pp, qp
+
+
+def coupled_grouped_run(g, cpl, steps, group):
+    """The same coupled chute stepped by dem_step_coupled: `group` intervals
+    (coupling and steps, one captured graph per interval) per synchronisation.
+    The first interval (graph capture) is left out of the timing."""
+    import torch
+
+    k = cpl["interval_steps"]
+    pp, qp = chute_controllers(g, cpl)
+    plan = g.coupling_plan(pp, 0, qp, 1, k, group=group)
+    g.step_coupled(1, plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step_coupled(steps // k, plan)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
 def coupled_run(g, cpl, steps):
     """The two-level chute coupled (Sec. 2.3): every `interval_steps` steps the
     cell fields of both levels on the transition layer and on the grid inside
@@ -168,16 +201,9 @@ def coupled_run(g, cpl, steps):
     from paper_1705_03850_amd import dem
 
     k = cpl["interval_steps"]
+    pp, qp = chute_controllers(g, cpl)
     pi_f, pi_c = dem.make_grid(*cpl["pi_grid"], sys=1), dem.make_grid(*cpl["pi_grid"], sys=0)
     p_f, p_c = dem.make_grid(*cpl["p_grid"], sys=1), dem.make_grid(*cpl["p_grid"], sys=0)
-    pp = dem.PIParams()
-    pp.grid = pi_f
-    for a in range(3):
-        pp.nrm[a] = cpl["normal"][a]
-    pp.face, pp.kp, pp.ki, pp.fade = cpl["face"], cpl["kp"], cpl["ki"], cpl["fade"]
-    pp.interval = k * g.systems[1].dt
-    qp = dem.PParams()
-    qp.grid, qp.kp, qp.mass_flow = p_c, cpl["kp_coarse"], 1
     n_pi = pi_f.n[0] * pi_f.n[1] * pi_f.n[2]
     integral = torch.zeros(n_pi, dtype=torch.float64, device=g.device)
     u = torch.empty(n_pi, dtype=torch.float64, device=g.device)
@@ -361,6 +387,11 @@ def batch_suite(args, emit=True):
     steps_c = steps2 - steps2 % cpl["interval_steps"]
     t_cpl, t_ctl = coupled_run(g2c, cpl, steps_c)
     del g2c
+    group = 8
+    g2g = dem.DemSystem(two, use_graph=True, chunk=8)
+    g2g.prime()
+    t_grp = coupled_grouped_run(g2g, cpl, steps_c, group)
+    del g2g
     log("two-level chute, insertion events")
     exch = exchange_events(two, cpl, args.chunk)
     out = {
@@ -384,6 +415,8 @@ def batch_suite(args, emit=True):
                                         "particle_steps_per_s": n2 * steps_c / t_cpl,
                                         "coupled_vs_batched": (n2 * steps_c / t_cpl) / (n2 * steps2 / t_two),
                                         "coupling_issue_host_s": t_ctl,
+                                        "grouped": {"group": group, "particle_steps_per_s": n2 * steps_c / t_grp,
+                                                    "vs_batched": (n2 * steps_c / t_grp) / (n2 * steps2 / t_two)},
                                         "transition_cells": list(cpl["pi_grid"][2]),
                                         "fine_region_cells": list(cpl["p_grid"][2])},
                             "exchange": exch},

@@ -943,6 +943,7 @@ int dem_set_launch(dem_ctx *c, int32_t lanes, int32_t max_blocks) {
     c->grid_cap = max_blocks;
     c->lanes = lanes;
     for (GraphSlot &g : c->graphs) g.chunk = 0;  // re-capture with the new grid/lanes
+    c->cpl_key.clear();                          // and the coupled interval's graph
     return upload_tiles(c);
 }
 

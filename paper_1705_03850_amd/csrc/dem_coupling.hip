@@ -726,14 +726,18 @@ int enqueue_interval(dem_ctx *c, const dem_state *s, const dem_coupling_plan *p,
 // (positions, lists, live counts, tiles, surfaces) is read from the device.
 int interval_graph(dem_ctx *c, const dem_state *s, const dem_coupling_plan *p, const dem_grid &pi_set,
                    const dem_grid &p_tgt) {
-    std::vector<char> key(sizeof(dem_coupling_plan) + sizeof(dem_state) + 4 * sizeof(void *));
+    std::vector<char> key(sizeof(dem_coupling_plan) + sizeof(dem_state) + 7 * sizeof(void *));
     char *k = key.data();
     memcpy(k, p, sizeof(dem_coupling_plan));
     k += sizeof(dem_coupling_plan);
     memcpy(k, s, sizeof(dem_state));
     k += sizeof(dem_state);
-    const void *more[4] = {c->ws, c->fext_on ? (const void *)c->lay.fext : nullptr,
-                           (const void *)(intptr_t)(c->multirate ? 1 : 0), (const void *)(intptr_t)(c->count ? 1 : 0)};
+    // the launch shape too: the step kernels' lanes, block and grid cap must
+    // match the tile tables that dem_set_launch uploads
+    const void *more[7] = {c->ws, c->fext_on ? (const void *)c->lay.fext : nullptr,
+                           (const void *)(intptr_t)(c->multirate ? 1 : 0), (const void *)(intptr_t)(c->count ? 1 : 0),
+                           (const void *)(intptr_t)c->lanes, (const void *)(intptr_t)c->geo.block,
+                           (const void *)(intptr_t)c->grid_cap};
     memcpy(k, more, sizeof more);
     if (c->cpl_exec && key == c->cpl_key) return DEM_OK;
     if (c->cpl_exec) {

@@ -517,3 +517,35 @@ def test_step_coupled_errors():
     assert e.value.code == d.DEM_ERR_ARG
     m.step_coupled(1, m.coupling_plan(pi, 0, pp, 1, 2 * 8))
     assert m.stats()["steps"] == 16
+
+
+def test_step_coupled_after_launch_changes():
+    """The captured interval follows the launch shape: with dem_set_launch
+    (4, 8, 16 lanes) between dem_step_coupled calls, the coupled context stays
+    bit for bit equal to the same calls made one by one on a twin."""
+    d = dem()
+    coarse, fine = two_level()
+    interval = 15
+    twins = [d.DemSystem([coarse, fine], use_graph=True, chunk=16) for _ in range(2)]
+    for g in twins:
+        g.prime()
+    pi, pp = pi_params(1, interval * fine.dt), p_params(0, True)
+    plans = [g.coupling_plan(pi, 0, pp, 1, interval, group=2) for g in twins]
+    eager, coupled = twins
+    b = plans[0].buffers
+    for lanes in (4, 8, 16, 0):
+        coupled.set_launch(lanes)
+        coupled.step_coupled(3, plans[1])
+        for _ in range(3):
+            eager.pi_control(pi, eager.cell_fields(grid(PI_GRID, 1), out=b["pi_fine"]),
+                             eager.cell_fields(grid(PI_GRID, 0), out=b["pi_coarse"]), b["integral"], b["u"])
+            eager.p_control(pp, eager.cell_fields(grid(P_GRID, 1), stress=False, out=b["p_fine"]),
+                            eager.cell_fields(grid(P_GRID, 0), stress=False, out=b["p_coarse"]))
+            eager.step(interval)
+        torch.cuda.synchronize()
+        for k in range(2):
+            h0, h1 = eager.host(k), coupled.host(k)
+            for key in ("x", "v", "w", "f", "t"):
+                assert np.array_equal(h0[key], h1[key]), (lanes, k, key)
+        for key in ("integral", "u"):
+            assert torch.equal(plans[0].buffers[key], plans[1].buffers[key]), (lanes, key)

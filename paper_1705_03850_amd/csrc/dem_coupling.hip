@@ -281,15 +281,14 @@ __global__ void __launch_bounds__(kFB) k_fields1(KArgs a, FGrid g, int S, double
     }
 }
 
-// A cell's pass-1 sums: its S slices added in slice order (the maximum for
-// the last); the same order wherever it is taken.
-__device__ inline void pass1_total(const double *part, int64_t cell, int S, double (&v)[kP1]) {
-    for (int k = 0; k < kP1; ++k) v[k] = part[(cell * S) * kP1 + k];
-    for (int b = 1; b < S; ++b)
-        for (int k = 0; k < kP1; ++k) {
-            const double q = part[(cell * S + b) * kP1 + k];
-            v[k] = k == kP1 - 1 ? fmax(v[k], q) : v[k] + q;
-        }
+// A cell's pass-1 sums over its S <= kFB slices, taken by a whole block:
+// thread t loads slice t (zeros past S), then the block's fixed tree (the
+// maximum for the last); every thread gets the totals.  The same routine
+// wherever the totals are taken, so they agree bit for bit.
+__device__ inline void block_pass1_total(const double *part, int64_t cell, int S, double (&v)[kP1], double *lds) {
+    const int t = threadIdx.x;
+    for (int k = 0; k < kP1; ++k) v[k] = t < S ? part[(cell * S + t) * kP1 + k] : 0.0;
+    block_reduce_n<kP1, true>(v, lds);
 }
 
 __device__ inline void write_pass1(double *out, int64_t nc, int64_t cell, const double (&v)[kP1]) {
@@ -297,15 +296,16 @@ __device__ inline void write_pass1(double *out, int64_t nc, int64_t cell, const 
     for (int k = 0; k < kP1; ++k) out[rows[k] * nc + cell] = v[k];
 }
 
-// One thread per cell (the fields without stress): the slices' sums.
-__global__ void k_fields1_reduce(FGrid g, int S, const double *part, double *out, const Flags *gate) {
+// One block per cell (the fields without stress): the slices' sums.
+__global__ void __launch_bounds__(kFB) k_fields1_reduce(FGrid g, int S, const double *part, double *out,
+                                                        const Flags *gate) {
+    __shared__ double lds[kP1 * kFB];
     if (skip_pending(gate)) return;
     const int64_t nc = g.ncell;
-    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < nc;
-         cell += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t cell = blockIdx.x; cell < nc; cell += gridDim.x) {   // (uniform over the block)
         double v[kP1];
-        pass1_total(part, cell, S, v);
-        write_pass1(out, nc, cell, v);
+        block_pass1_total(part, cell, S, v, lds);
+        if (threadIdx.x == 0) write_pass1(out, nc, cell, v);
     }
 }
 
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, const 
     // the cell's Favre velocity from pass 1
     double p1[kP1];
     if (S > 1) {
-        pass1_total(part1, cell, S, p1);
+        block_pass1_total(part1, cell, S, p1, lds);
         if (b == 0 && threadIdx.x == 0) write_pass1(out, nc, cell, p1);
     } else {
         p1[1] = out[DEM_F_MASS * nc + cell];
@@ -410,17 +410,20 @@ __global__ void __launch_bounds__(kFB) k_fields2(KArgs a, FGrid g, int S, const 
     }
 }
 
-__global__ void k_fields2_reduce(FGrid g, int S, const double *part, double *out, const Flags *gate) {
+__global__ void __launch_bounds__(kFB) k_fields2_reduce(FGrid g, int S, const double *part, double *out,
+                                                        const Flags *gate) {
+    __shared__ double lds[kP2 * kFB];
     if (skip_pending(gate)) return;
     const int64_t nc = g.ncell;
     const int ksym[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
-    for (int64_t cell = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; cell < nc;
-         cell += (int64_t)gridDim.x * blockDim.x) {
+    const int t = threadIdx.x;
+    for (int64_t cell = blockIdx.x; cell < nc; cell += gridDim.x) {   // (uniform over the block)
+        // one block per cell: thread t loads slice t (S <= kFB), then the fixed tree
         double v[kP2];
-        for (int k = 0; k < kP2; ++k) v[k] = part[(cell * S) * kP2 + k];
-        for (int b = 1; b < S; ++b)
-            for (int k = 0; k < kP2; ++k) v[k] += part[(cell * S + b) * kP2 + k];
-        for (int k = 0; k < 9; ++k) out[(DEM_F_STRESS + k) * nc + cell] = (v[k] + v[9 + ksym[k]]) / g.vol;
+        for (int k = 0; k < kP2; ++k) v[k] = t < S ? part[(cell * S + t) * kP2 + k] : 0.0;
+        block_reduce_n<kP2, false>(v, lds);
+        if (t == 0)
+            for (int k = 0; k < 9; ++k) out[(DEM_F_STRESS + k) * nc + cell] = (v[k] + v[9 + ksym[k]]) / g.vol;
     }
 }
 
@@ -632,18 +635,19 @@ int cell_fields(dem_ctx *c, const dem_state *s, const dem_grid *grid, double *fi
         const double w = sd.L[ax] / (double)sd.nc[ax];
         rows *= std::min<int64_t>(sd.nc[ax], (int64_t)std::floor(g.h[ax] / w) + 3);
     }
-    int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(256, 4096 / g.ncell), rows / 8));
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kFB, 4096 / g.ncell), rows / 8));
     while (S > 1 && (size_t)g.ncell * S * (kP1 + kP2) * 8 > scratch) S /= 2;
     double *part1 = (double *)(c->ws + c->lay.shadow_d);
     double *part2 = part1 + (size_t)g.ncell * S * kP1;
     const int64_t blocks = g.ncell * S, guard = grid_blocks(sd.pe - sd.p0, 256);
+    const int reduce_blocks = (int)std::min<int64_t>(g.ncell, 4096);   // one per cell, looping beyond
     if (blocks + guard > INT32_MAX) return fail(c, DEM_ERR_ARG, "grid too large");
     k_fields1<<<(int)(blocks + guard), kFB, 0, c->stream>>>(a, g, S, part1, fields, gate);
     if (stress) {
         k_fields2<<<(int)blocks, kFB, 0, c->stream>>>(a, g, S, part1, part2, fields, gate);
-        if (S > 1) k_fields2_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part2, fields, gate);
+        if (S > 1) k_fields2_reduce<<<reduce_blocks, kFB, 0, c->stream>>>(g, S, part2, fields, gate);
     } else if (S > 1) {
-        k_fields1_reduce<<<grid_blocks(g.ncell, 256), 256, 0, c->stream>>>(g, S, part1, fields, gate);
+        k_fields1_reduce<<<reduce_blocks, kFB, 0, c->stream>>>(g, S, part1, fields, gate);
     }
     HIPCALL(c, hipGetLastError());
     return DEM_OK;

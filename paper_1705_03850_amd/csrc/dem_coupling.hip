@@ -11,11 +11,12 @@
 // workgroup lays its rows' candidates end to end (a scan of the row lengths
 // in LDS) and its threads take them in turn, G threads per sphere where the
 // sphere's contacts are summed.  Each thread sums its own terms, the block
-// adds the threads' sums in a fixed tree (all sums at once) and a second
-// kernel adds the S slices in order: the result depends on nothing but the
-// state, the grid, the binning and the workspace size.  A first pass gives mass and momentum, hence the Favre
-// velocity; the second the kinetic and contact parts of Eq. (7), the contact
-// forces evaluated as in a force pass without history update.
+// adds the threads' sums in a fixed tree (all sums at once), and one block
+// per cell adds the S slices in the same kind of tree: the result depends on
+// nothing but the state, the grid, the binning and the workspace size.  A
+// first pass gives mass and momentum, hence the Favre velocity; the second
+// the kinetic and contact parts of Eq. (7), the contact forces evaluated as
+// in a force pass without history update.
 // Controllers: one thread per cell updates the PI state; one thread per
 // sphere of the system writes its external force.
 #include <algorithm>

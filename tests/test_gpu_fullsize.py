@@ -10,8 +10,10 @@ times (4 lanes per particle, 256-thread blocks, resident grid, graph replay).
     stepping over 130 steps.
   * two-level chute (2e5 + 5e5 spheres): the 2-system batch bit for bit
     equal to each system stepped alone, and each system against the oracle
-    over 10 steps; one insertion and deletion event on the fine level against
-    the oracle's SSI, bit for bit.
+    over 10 steps; one coupling interval (fields, PI and P controllers)
+    against the oracle; 16 intervals of dem_step_coupled bit for bit equal
+    to the same calls made one by one; one insertion and deletion event on
+    the fine level against the oracle's SSI, bit for bit.
   * 64-system batch (3.8e6 spheres): bit for bit equal to each system stepped
     alone over 300 steps (with list rebuilds), and two systems against the
     oracle.
@@ -274,6 +276,46 @@ def test_two_level_chute_coupled_against_oracle():
             Lk = s.hi[ax] - s.lo[ax]
             d[:, ax] -= Lk * np.round(d[:, ax] / Lk)
         assert np.max(np.abs(d)) <= 1e-9 * max(s.hi[a] - s.lo[a] for a in range(3)), (k, np.max(np.abs(d)))
+
+
+def test_two_level_chute_step_coupled_at_full_size():
+    """The coupled chute as the bench steps it (dem_step_coupled, eight
+    intervals per synchronisation, interval graphs) against the same coupling
+    calls and steps made one by one on a twin context: states, PI state and
+    fields bit for bit after 16 intervals."""
+    coarse, fine = systems = W.chute_two_level()
+    cpl = W.chute_coupling(coarse, fine)
+    k_int, nrm = cpl["interval_steps"], cpl["normal"]
+    twins = [dem().DemSystem(systems, use_graph=True, chunk=8) for _ in range(2)]
+    for g in twins:
+        g.prime()
+    pp = dem().PIParams()
+    pp.grid = dem().make_grid(*cpl["pi_grid"], sys=1)
+    for a in range(3):
+        pp.nrm[a] = nrm[a]
+    pp.face, pp.kp, pp.ki, pp.fade, pp.interval = cpl["face"], cpl["kp"], cpl["ki"], cpl["fade"], k_int * fine.dt
+    qp = dem().PParams()
+    qp.grid, qp.kp, qp.mass_flow = dem().make_grid(*cpl["p_grid"], sys=0), cpl["kp_coarse"], 1
+    plans = [g.coupling_plan(pp, 0, qp, 1, k_int, group=8) for g in twins]
+    eager, coupled = twins
+    b = plans[0].buffers
+    pif, pic = dem().make_grid(*cpl["pi_grid"], sys=1), dem().make_grid(*cpl["pi_grid"], sys=0)
+    pf, pc = dem().make_grid(*cpl["p_grid"], sys=1), dem().make_grid(*cpl["p_grid"], sys=0)
+    nint = 16
+    for _ in range(nint):
+        eager.pi_control(pp, eager.cell_fields(pif, out=b["pi_fine"]), eager.cell_fields(pic, out=b["pi_coarse"]),
+                         b["integral"], b["u"])
+        eager.p_control(qp, eager.cell_fields(pf, stress=False, out=b["p_fine"]),
+                        eager.cell_fields(pc, stress=False, out=b["p_coarse"]))
+        eager.step(k_int)
+    coupled.step_coupled(nint, plans[1])
+    torch.cuda.synchronize()
+    for key in ("integral", "u", "pi_fine", "pi_coarse"):
+        assert torch.equal(plans[0].buffers[key], plans[1].buffers[key]), key
+    assert torch.count_nonzero(plans[1].buffers["u"]) > 0
+    h0, h1 = eager.host(), coupled.host()
+    for key in ("x", "v", "w", "f", "t"):
+        assert np.array_equal(h0[key], h1[key]), key
 
 
 def test_two_level_chute_exchange_at_full_size():
